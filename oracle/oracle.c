@@ -1,0 +1,531 @@
+/*
+ * Plain FP64 CPU oracle of the split-explicit barotropic subcycle
+ * (Banerjee et al., "Split-explicit external mode solver in finite volume sea
+ * ice ocean model FESOM2", arXiv 2311.08241).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the CPU
+ * baseline of the benchmark may load this file's library.  It shares no code
+ * with the GPU library and must stay slow, plain and obviously correct:
+ * loops in the order of the definitions, no blocking, no fusion.
+ * Build: gcc -O2 -ffp-contract=off -fno-fast-math -shared -fPIC.
+ *
+ * What is computed (readings of the paper fixed where it is silent):
+ *  - Continuous problem: the barotropic system of Sec. 2.2, eq. (eq4_5):
+ *      dU/dt + f e_z x U + g H grad(eta) = R,  d(eta)/dt + div U + W = 0,
+ *    H = H0 + eta, R frozen over the baroclinic step.
+ *  - Time stepping: the dissipative forward-backward substep of eq. (eq4_10):
+ *    U first with Crank-Nicolson Coriolis, then eta from the divergence of
+ *    (1+theta) U^{m+1} - theta U^m.  The printed "- g H grad(eta)" inside the
+ *    bracket with a leading minus would flip the pressure force against
+ *    eq. (eq4_5) and eq. (eq4_8); the sign of eq. (eq4_5) is used.  W is kept
+ *    in the eta line as in eq. (eq4_5).
+ *  - Space: scalars at vertices, transports on triangles (Sec. 2.1).  The
+ *    gradient is the P1 gradient on each triangle; the divergence is the
+ *    median-dual finite-volume divergence (edge midpoints joined to the
+ *    centroid), with no flux through coastlines.
+ *  - H at substep m is the triangle mean of H0 + eta^m (vertex values).
+ *  - Averaged transport: eq. (eq4_12), with the sum over m = 1..M and the
+ *    endpoint term theta/M (U^M - U^0), the only reading that makes the summed
+ *    elevation equation eq. (eq4_11) exact.
+ *  - Space-filling-curve reordering (not part of the paper's method): a
+ *    Hilbert index on a 2^16 x 2^16 quantisation of the coordinates, used to
+ *    check the GPU library's reordering integer for integer.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_PERIODIC_X 1u
+#define ORC_PERIODIC_Y 2u
+#define ORC_SPHERICAL 4u
+
+#define ORC_OK 0
+#define ORC_ERR_ARG 1
+#define ORC_ERR_MESH 2
+#define ORC_ERR_OOM 3
+
+/* ------------------------------------------------------------------------ */
+/* Hilbert curve index (Hilbert 1891; the iterative xy -> d formulation with
+ * quadrant code (3 rx) xor ry and a flip/transpose when ry == 0).            */
+/* ------------------------------------------------------------------------ */
+uint64_t orc_hilbert_d(uint32_t side, uint32_t x, uint32_t y)
+{
+    uint64_t d = 0;
+    for (uint32_t s = side / 2; s > 0; s /= 2) {
+        uint32_t rx = (x & s) ? 1u : 0u;
+        uint32_t ry = (y & s) ? 1u : 0u;
+        d += (uint64_t)s * (uint64_t)s * (uint64_t)((3u * rx) ^ ry);
+        if (ry == 0) {
+            if (rx == 1) {
+                x = side - 1 - x;
+                y = side - 1 - y;
+            }
+            uint32_t t = x;
+            x = y;
+            y = t;
+        }
+    }
+    return d;
+}
+
+/* Quantise one coordinate onto 0..65535 (scale 65535/range, floor, cap). */
+static uint32_t quantise(double v, double vmin, double scale)
+{
+    double q = floor((v - vmin) * scale);
+    if (q < 0.0) q = 0.0;
+    if (q > 65535.0) q = 65535.0;
+    return (uint32_t)q;
+}
+
+int orc_sfc_keys(int64_t nv, const double *x, const double *y, uint32_t *key)
+{
+    if (nv <= 0) return ORC_ERR_ARG;
+    double xmin = x[0], xmax = x[0], ymin = y[0], ymax = y[0];
+    for (int64_t i = 1; i < nv; ++i) {
+        if (x[i] < xmin) xmin = x[i];
+        if (x[i] > xmax) xmax = x[i];
+        if (y[i] < ymin) ymin = y[i];
+        if (y[i] > ymax) ymax = y[i];
+    }
+    double sx = (xmax > xmin) ? 65535.0 / (xmax - xmin) : 0.0;
+    double sy = (ymax > ymin) ? 65535.0 / (ymax - ymin) : 0.0;
+    for (int64_t i = 0; i < nv; ++i)
+        key[i] = (uint32_t)orc_hilbert_d(65536u, quantise(x[i], xmin, sx), quantise(y[i], ymin, sy));
+    return ORC_OK;
+}
+
+typedef struct { uint32_t key; int32_t idx; } vkey_t;
+typedef struct { int32_t v[3]; int32_t idx; } tkey_t;
+
+static int cmp_vkey(const void *a, const void *b)
+{
+    const vkey_t *p = (const vkey_t *)a, *q = (const vkey_t *)b;
+    if (p->key != q->key) return p->key < q->key ? -1 : 1;
+    return (p->idx > q->idx) - (p->idx < q->idx);
+}
+
+static int cmp_tkey(const void *a, const void *b)
+{
+    const tkey_t *p = (const tkey_t *)a, *q = (const tkey_t *)b;
+    for (int k = 0; k < 3; ++k)
+        if (p->v[k] != q->v[k]) return p->v[k] < q->v[k] ? -1 : 1;
+    return (p->idx > q->idx) - (p->idx < q->idx);
+}
+
+/*
+ * Reorder a mesh:
+ *  vperm[new] = old vertex (stable sort by Hilbert key, ties by old index);
+ *  each triangle renumbered and rotated cyclically so its smallest vertex is
+ *  first (orientation kept); eperm[new] = old triangle (lexicographic sort of
+ *  the rotated triples; a repeated triple is a mesh error);
+ *  row_ptr/col: per vertex, its incident triangles in ascending new index,
+ *  encoded (e << 2) | local slot.
+ */
+int orc_reorder(int64_t nv, int64_t ne, const double *x, const double *y,
+                const int32_t *tri, int32_t *vperm, int32_t *eperm,
+                int32_t *tri_new, int32_t *row_ptr, int32_t *col)
+{
+    if (nv <= 0 || ne <= 0) return ORC_ERR_ARG;
+    for (int64_t i = 0; i < 3 * ne; ++i)
+        if (tri[i] < 0 || tri[i] >= nv) return ORC_ERR_MESH;
+    uint32_t *key = (uint32_t *)malloc(sizeof(uint32_t) * nv);
+    vkey_t *vk = (vkey_t *)malloc(sizeof(vkey_t) * nv);
+    int32_t *vinv = (int32_t *)malloc(sizeof(int32_t) * nv);
+    tkey_t *tk = (tkey_t *)malloc(sizeof(tkey_t) * ne);
+    if (!key || !vk || !vinv || !tk) {
+        free(key); free(vk); free(vinv); free(tk);
+        return ORC_ERR_OOM;
+    }
+    orc_sfc_keys(nv, x, y, key);
+    for (int64_t i = 0; i < nv; ++i) { vk[i].key = key[i]; vk[i].idx = (int32_t)i; }
+    qsort(vk, (size_t)nv, sizeof(vkey_t), cmp_vkey);
+    for (int64_t i = 0; i < nv; ++i) { vperm[i] = vk[i].idx; vinv[vk[i].idx] = (int32_t)i; }
+
+    for (int64_t e = 0; e < ne; ++e) {
+        int32_t a = vinv[tri[3 * e]], b = vinv[tri[3 * e + 1]], c = vinv[tri[3 * e + 2]];
+        int32_t r0, r1, r2;
+        if (a <= b && a <= c) { r0 = a; r1 = b; r2 = c; }
+        else if (b <= a && b <= c) { r0 = b; r1 = c; r2 = a; }
+        else { r0 = c; r1 = a; r2 = b; }
+        tk[e].v[0] = r0; tk[e].v[1] = r1; tk[e].v[2] = r2; tk[e].idx = (int32_t)e;
+    }
+    qsort(tk, (size_t)ne, sizeof(tkey_t), cmp_tkey);
+    int status = ORC_OK;
+    for (int64_t e = 0; e < ne; ++e) {
+        if (e > 0 && tk[e].v[0] == tk[e - 1].v[0] && tk[e].v[1] == tk[e - 1].v[1] &&
+            tk[e].v[2] == tk[e - 1].v[2]) status = ORC_ERR_MESH;
+        if (tk[e].v[0] == tk[e].v[1] || tk[e].v[1] == tk[e].v[2] || tk[e].v[0] == tk[e].v[2])
+            status = ORC_ERR_MESH;
+        eperm[e] = tk[e].idx;
+        for (int k = 0; k < 3; ++k) tri_new[3 * e + k] = tk[e].v[k];
+    }
+    /* CSR by counting; triangles visited in ascending new index */
+    for (int64_t v = 0; v <= nv; ++v) row_ptr[v] = 0;
+    for (int64_t e = 0; e < ne; ++e)
+        for (int k = 0; k < 3; ++k) row_ptr[tri_new[3 * e + k] + 1] += 1;
+    for (int64_t v = 0; v < nv; ++v) row_ptr[v + 1] += row_ptr[v];
+    int32_t *fill = vinv; /* reuse as cursor */
+    for (int64_t v = 0; v < nv; ++v) fill[v] = row_ptr[v];
+    for (int64_t e = 0; e < ne; ++e)
+        for (int k = 0; k < 3; ++k) {
+            int32_t v = tri_new[3 * e + k];
+            col[fill[v]++] = (int32_t)((e << 2) | k);
+        }
+    free(key); free(vk); free(vinv); free(tk);
+    return status;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Geometry                                                                  */
+/* ------------------------------------------------------------------------ */
+static double wrap_half(double d, double period)
+{
+    /* into (-period/2, period/2] */
+    if (d > 0.5 * period) d -= period;
+    else if (d <= -0.5 * period) d += period;
+    return d;
+}
+
+/*
+ * Per triangle e = (a, b, c): area A_e and P1 basis gradients gN[e][k][2]
+ * (k = local slot).  Per vertex: median-dual area A_v = sum_e A_e / 3.
+ * Planar coordinates: differences wrapped across periodic seams.
+ * Spherical coordinates (lon, lat in radians): dx = R cos(mean lat) dlon,
+ * dy = R dlat, with dlon wrapped into (-pi, pi].
+ */
+int orc_geometry(int64_t nv, int64_t ne, const double *x, const double *y,
+                 const int32_t *tri, uint32_t flags, double period_x, double period_y,
+                 double radius, double *Ae, double *gN, double *Av)
+{
+    for (int64_t v = 0; v < nv; ++v) Av[v] = 0.0;
+    for (int64_t e = 0; e < ne; ++e) {
+        int32_t a = tri[3 * e], b = tri[3 * e + 1], c = tri[3 * e + 2];
+        double abx = x[b] - x[a], aby = y[b] - y[a];
+        double acx = x[c] - x[a], acy = y[c] - y[a];
+        if (flags & ORC_SPHERICAL) {
+            double pi = 3.14159265358979323846;
+            abx = wrap_half(abx, 2.0 * pi);
+            acx = wrap_half(acx, 2.0 * pi);
+            double latm = (y[a] + y[b] + y[c]) / 3.0;
+            double cl = cos(latm);
+            abx = radius * cl * abx;
+            acx = radius * cl * acx;
+            aby = radius * aby;
+            acy = radius * acy;
+        } else {
+            if (flags & ORC_PERIODIC_X) { abx = wrap_half(abx, period_x); acx = wrap_half(acx, period_x); }
+            if (flags & ORC_PERIODIC_Y) { aby = wrap_half(aby, period_y); acy = wrap_half(acy, period_y); }
+        }
+        double twoA = abx * acy - aby * acx;
+        if (!(twoA > 0.0)) return ORC_ERR_MESH;
+        Ae[e] = 0.5 * twoA;
+        double gbx = acy / twoA, gby = -acx / twoA;
+        double gcx = -aby / twoA, gcy = abx / twoA;
+        gN[6 * e + 0] = -(gbx + gcx);
+        gN[6 * e + 1] = -(gby + gcy);
+        gN[6 * e + 2] = gbx;
+        gN[6 * e + 3] = gby;
+        gN[6 * e + 4] = gcx;
+        gN[6 * e + 5] = gcy;
+        Av[a] += Ae[e] / 3.0;
+        Av[b] += Ae[e] / 3.0;
+        Av[c] += Ae[e] / 3.0;
+    }
+    for (int64_t v = 0; v < nv; ++v)
+        if (!(Av[v] > 0.0)) return ORC_ERR_MESH;
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Forward substep                                                           */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int64_t nv, ne;
+    const int32_t *tri;
+    const double *Ae, *gN, *Av;
+} orc_mesh;
+
+/* Triangle-local quantities of one substep, kept so that the derivative code
+ * can reuse them without re-deriving anything. */
+typedef struct {
+    double gx, gy;   /* P1 gradient of eta on the triangle           */
+    double He;       /* mean of H0 + eta (or of H0) over the vertices */
+    double al;       /* f dt_s / 2                                   */
+} orc_elem;
+
+static void elem_quantities(const orc_mesh *m, int64_t e, const double *eta,
+                            const double *H0, double f, double dts, int linear_h,
+                            orc_elem *q)
+{
+    const int32_t *t = m->tri + 3 * e;
+    const double *g = m->gN + 6 * e;
+    /* difference form: constant eta has an exactly zero gradient */
+    double db = eta[t[1]] - eta[t[0]], dc = eta[t[2]] - eta[t[0]];
+    q->gx = db * g[2] + dc * g[4];
+    q->gy = db * g[3] + dc * g[5];
+    if (linear_h)
+        q->He = (H0[t[0]] + H0[t[1]] + H0[t[2]]) / 3.0;
+    else
+        q->He = ((H0[t[0]] + eta[t[0]]) + (H0[t[1]] + eta[t[1]]) + (H0[t[2]] + eta[t[2]])) / 3.0;
+    q->al = 0.5 * f * dts;
+}
+
+/* Ub' = (I + al J)^-1 [ (I - al J) Ub + dts (-g He grad eta + R) ],  J(x,y) = (-y,x) */
+static void transport_update(const orc_elem *q, double g, double dts, const double *U,
+                             const double *R, double *Un)
+{
+    double rx = U[0] + q->al * U[1] + dts * (-g * q->He * q->gx + R[0]);
+    double ry = U[1] - q->al * U[0] + dts * (-g * q->He * q->gy + R[1]);
+    double den = 1.0 + q->al * q->al;
+    Un[0] = (rx + q->al * ry) / den;
+    Un[1] = (ry - q->al * rx) / den;
+}
+
+/* outward flux of F through the sub-cell boundary of slot k inside triangle e:
+ * F . S_{e,k}, S_{e,k} = -A_e gN_{e,k} */
+static double slot_flux(const orc_mesh *m, int64_t e, int k, const double *F)
+{
+    const double *g = m->gN + 6 * e + 2 * k;
+    double Sx = -m->Ae[e] * g[0], Sy = -m->Ae[e] * g[1];
+    return F[0] * Sx + F[1] * Sy;
+}
+
+static double volume_of(const orc_mesh *m, const double *eta)
+{
+    double V = 0.0;
+    for (int64_t v = 0; v < m->nv; ++v) V += m->Av[v] * eta[v];
+    return V;
+}
+
+/*
+ * One baroclinic step: nsub substeps of length tau/nsub from (eta, U) in place.
+ * Uavg [ne][2] receives the averaged transport, volume [nsub+1] (optional)
+ * the volume sum_v A_v eta_v after each substep (entry 0: initial state).
+ */
+int orc_subcycle(int64_t nv, int64_t ne, const int32_t *tri, const double *Ae,
+                 const double *gN, const double *Av, double g, double theta,
+                 int linear_h, const double *H0, const double *f, const double *R,
+                 const double *W, int32_t nsub, double tau, double *eta, double *U,
+                 double *Uavg, double *volume)
+{
+    if (nsub <= 0 || nv <= 0 || ne <= 0) return ORC_ERR_ARG;
+    orc_mesh m = {nv, ne, tri, Ae, gN, Av};
+    double dts = tau / (double)nsub;
+    double *Un = (double *)malloc(sizeof(double) * 2 * ne);
+    double *F = (double *)malloc(sizeof(double) * 2 * ne);
+    double *U0 = (double *)malloc(sizeof(double) * 2 * ne);
+    double *sum = (double *)calloc((size_t)(2 * ne), sizeof(double));
+    double *div = (double *)malloc(sizeof(double) * nv);
+    if (!Un || !F || !U0 || !sum || !div) {
+        free(Un); free(F); free(U0); free(sum); free(div);
+        return ORC_ERR_OOM;
+    }
+    memcpy(U0, U, sizeof(double) * 2 * ne);
+    if (volume) volume[0] = volume_of(&m, eta);
+    for (int32_t s = 0; s < nsub; ++s) {
+        for (int64_t e = 0; e < ne; ++e) {
+            orc_elem q;
+            elem_quantities(&m, e, eta, H0, f[e], dts, linear_h, &q);
+            transport_update(&q, g, dts, U + 2 * e, R + 2 * e, Un + 2 * e);
+            F[2 * e] = (1.0 + theta) * Un[2 * e] - theta * U[2 * e];
+            F[2 * e + 1] = (1.0 + theta) * Un[2 * e + 1] - theta * U[2 * e + 1];
+        }
+        for (int64_t v = 0; v < nv; ++v) div[v] = 0.0;
+        for (int64_t e = 0; e < ne; ++e)
+            for (int k = 0; k < 3; ++k) div[tri[3 * e + k]] += slot_flux(&m, e, k, F + 2 * e);
+        for (int64_t v = 0; v < nv; ++v)
+            eta[v] = eta[v] - dts * (div[v] / Av[v] + (W ? W[v] : 0.0));
+        for (int64_t i = 0; i < 2 * ne; ++i) {
+            U[i] = Un[i];
+            sum[i] += Un[i];
+        }
+        if (volume) volume[s + 1] = volume_of(&m, eta);
+    }
+    for (int64_t i = 0; i < 2 * ne; ++i)
+        Uavg[i] = sum[i] / (double)nsub + theta / (double)nsub * (U[i] - U0[i]);
+    free(Un); free(F); free(U0); free(sum); free(div);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Tangent-linear model: derivative of the subcycle map along                */
+/* (d_eta0, d_U0, d_R, d_H0); the state is advanced alongside.               */
+/* ------------------------------------------------------------------------ */
+int orc_tlm(int64_t nv, int64_t ne, const int32_t *tri, const double *Ae,
+            const double *gN, const double *Av, double g, double theta, int linear_h,
+            const double *H0, const double *f, const double *R, const double *W,
+            int32_t nsub, double tau, const double *eta0, const double *U0,
+            const double *d_eta0, const double *d_U0, const double *d_R,
+            const double *d_H0, double *d_eta, double *d_U, double *d_Uavg)
+{
+    if (nsub <= 0) return ORC_ERR_ARG;
+    orc_mesh m = {nv, ne, tri, Ae, gN, Av};
+    double dts = tau / (double)nsub;
+    size_t nb2 = sizeof(double) * 2 * ne;
+    double *eta = (double *)malloc(sizeof(double) * nv);
+    double *U = (double *)malloc(nb2), *Un = (double *)malloc(nb2), *F = (double *)malloc(nb2);
+    double *dUn = (double *)malloc(nb2), *dF = (double *)malloc(nb2);
+    double *dsum = (double *)calloc((size_t)(2 * ne), sizeof(double));
+    double *div = (double *)malloc(sizeof(double) * nv), *ddiv = (double *)malloc(sizeof(double) * nv);
+    if (!eta || !U || !Un || !F || !dUn || !dF || !dsum || !div || !ddiv) return ORC_ERR_OOM;
+    memcpy(eta, eta0, sizeof(double) * nv);
+    memcpy(U, U0, nb2);
+    memcpy(d_eta, d_eta0, sizeof(double) * nv);
+    memcpy(d_U, d_U0, nb2);
+    for (int32_t s = 0; s < nsub; ++s) {
+        for (int64_t e = 0; e < ne; ++e) {
+            const int32_t *t = tri + 3 * e;
+            const double *gg = gN + 6 * e;
+            orc_elem q, dq;
+            elem_quantities(&m, e, eta, H0, f[e], dts, linear_h, &q);
+            /* tangent of the triangle quantities */
+            double db = d_eta[t[1]] - d_eta[t[0]], dc = d_eta[t[2]] - d_eta[t[0]];
+            dq.gx = db * gg[2] + dc * gg[4];
+            dq.gy = db * gg[3] + dc * gg[5];
+            if (linear_h)
+                dq.He = (d_H0[t[0]] + d_H0[t[1]] + d_H0[t[2]]) / 3.0;
+            else
+                dq.He = ((d_H0[t[0]] + d_eta[t[0]]) + (d_H0[t[1]] + d_eta[t[1]]) +
+                         (d_H0[t[2]] + d_eta[t[2]])) / 3.0;
+            transport_update(&q, g, dts, U + 2 * e, R + 2 * e, Un + 2 * e);
+            double al = q.al, den = 1.0 + al * al;
+            const double *dU = d_U + 2 * e;
+            double drx = dU[0] + al * dU[1] + dts * (-g * (dq.He * q.gx + q.He * dq.gx) + d_R[2 * e]);
+            double dry = dU[1] - al * dU[0] + dts * (-g * (dq.He * q.gy + q.He * dq.gy) + d_R[2 * e + 1]);
+            dUn[2 * e] = (drx + al * dry) / den;
+            dUn[2 * e + 1] = (dry - al * drx) / den;
+            for (int k = 0; k < 2; ++k) {
+                F[2 * e + k] = (1.0 + theta) * Un[2 * e + k] - theta * U[2 * e + k];
+                dF[2 * e + k] = (1.0 + theta) * dUn[2 * e + k] - theta * d_U[2 * e + k];
+            }
+        }
+        for (int64_t v = 0; v < nv; ++v) { div[v] = 0.0; ddiv[v] = 0.0; }
+        for (int64_t e = 0; e < ne; ++e)
+            for (int k = 0; k < 3; ++k) {
+                div[tri[3 * e + k]] += slot_flux(&m, e, k, F + 2 * e);
+                ddiv[tri[3 * e + k]] += slot_flux(&m, e, k, dF + 2 * e);
+            }
+        for (int64_t v = 0; v < nv; ++v) {
+            eta[v] = eta[v] - dts * (div[v] / Av[v] + (W ? W[v] : 0.0));
+            d_eta[v] = d_eta[v] - dts * (ddiv[v] / Av[v]);
+        }
+        for (int64_t i = 0; i < 2 * ne; ++i) {
+            U[i] = Un[i];
+            d_U[i] = dUn[i];
+            dsum[i] += dUn[i];
+        }
+    }
+    for (int64_t i = 0; i < 2 * ne; ++i)
+        d_Uavg[i] = dsum[i] / (double)nsub + theta / (double)nsub * (d_U[i] - d_U0[i]);
+    free(eta); free(U); free(Un); free(F); free(dUn); free(dF); free(dsum); free(div); free(ddiv);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Adjoint: gradients of  <lam_eta, eta^M> + <lam_U, U^M> + <lam_Uavg, Uavg>  */
+/* with respect to eta^0, U^0, R and H0.  The whole forward trajectory is    */
+/* stored (no checkpointing in the oracle).  NULL seeds count as zero.       */
+/* ------------------------------------------------------------------------ */
+int orc_adjoint(int64_t nv, int64_t ne, const int32_t *tri, const double *Ae,
+                const double *gN, const double *Av, double g, double theta, int linear_h,
+                const double *H0, const double *f, const double *R, const double *W,
+                int32_t nsub, double tau, const double *eta0, const double *U0,
+                const double *lam_eta, const double *lam_U, const double *lam_Uavg,
+                double *g_eta0, double *g_U0, double *g_R, double *g_H0)
+{
+    if (nsub <= 0) return ORC_ERR_ARG;
+    orc_mesh m = {nv, ne, tri, Ae, gN, Av};
+    double dts = tau / (double)nsub;
+    double rM = 1.0 / (double)nsub;
+    size_t nb2 = sizeof(double) * 2 * ne;
+    double *etas = (double *)malloc(sizeof(double) * nv * (size_t)(nsub + 1));
+    double *Us = (double *)malloc(nb2 * (size_t)(nsub + 1));
+    double *F = (double *)malloc(nb2), *div = (double *)malloc(sizeof(double) * nv);
+    double *le = (double *)malloc(sizeof(double) * nv), *le_new = (double *)malloc(sizeof(double) * nv);
+    double *lU = (double *)malloc(nb2), *lU_new = (double *)malloc(nb2);
+    if (!etas || !Us || !F || !div || !le || !le_new || !lU || !lU_new) return ORC_ERR_OOM;
+
+    /* forward, storing every state */
+    memcpy(etas, eta0, sizeof(double) * nv);
+    memcpy(Us, U0, nb2);
+    for (int32_t s = 0; s < nsub; ++s) {
+        const double *eta = etas + (size_t)s * nv;
+        const double *U = Us + (size_t)s * 2 * ne;
+        double *etan = etas + (size_t)(s + 1) * nv;
+        double *Un = Us + (size_t)(s + 1) * 2 * ne;
+        for (int64_t e = 0; e < ne; ++e) {
+            orc_elem q;
+            elem_quantities(&m, e, eta, H0, f[e], dts, linear_h, &q);
+            transport_update(&q, g, dts, U + 2 * e, R + 2 * e, Un + 2 * e);
+            F[2 * e] = (1.0 + theta) * Un[2 * e] - theta * U[2 * e];
+            F[2 * e + 1] = (1.0 + theta) * Un[2 * e + 1] - theta * U[2 * e + 1];
+        }
+        for (int64_t v = 0; v < nv; ++v) div[v] = 0.0;
+        for (int64_t e = 0; e < ne; ++e)
+            for (int k = 0; k < 3; ++k) div[tri[3 * e + k]] += slot_flux(&m, e, k, F + 2 * e);
+        for (int64_t v = 0; v < nv; ++v)
+            etan[v] = eta[v] - dts * (div[v] / Av[v] + (W ? W[v] : 0.0));
+    }
+
+    /* seeds at m = M; Uavg = (1/M) sum_{m=1..M} U^m + (theta/M)(U^M - U^0) */
+    for (int64_t v = 0; v < nv; ++v) le[v] = lam_eta ? lam_eta[v] : 0.0;
+    for (int64_t i = 0; i < 2 * ne; ++i)
+        lU[i] = (lam_U ? lam_U[i] : 0.0) + (lam_Uavg ? theta * rM * lam_Uavg[i] : 0.0);
+    for (int64_t i = 0; i < 2 * ne; ++i) g_R[i] = 0.0;
+    for (int64_t v = 0; v < nv; ++v) g_H0[v] = 0.0;
+
+    for (int32_t s = nsub - 1; s >= 0; --s) {
+        const double *eta = etas + (size_t)s * nv;
+        const double *U = Us + (size_t)s * 2 * ne;
+        /* U^{s+1} enters the running sum */
+        if (lam_Uavg)
+            for (int64_t i = 0; i < 2 * ne; ++i) lU[i] += rM * lam_Uavg[i];
+        /* eta^{s+1} = eta^s - dts (D F + W): identity part */
+        for (int64_t v = 0; v < nv; ++v) le_new[v] = le[v];
+        for (int64_t i = 0; i < 2 * ne; ++i) lU_new[i] = 0.0;
+        for (int64_t e = 0; e < ne; ++e) {
+            const int32_t *t = tri + 3 * e;
+            const double *gg = gN + 6 * e;
+            orc_elem q;
+            elem_quantities(&m, e, eta, H0, f[e], dts, linear_h, &q);
+            /* lam_F = -dts sum_k (lam_eta_k / A_k) S_{e,k} */
+            double lFx = 0.0, lFy = 0.0;
+            for (int k = 0; k < 3; ++k) {
+                double w = -dts * le[t[k]] / Av[t[k]];
+                lFx += w * (-Ae[e] * gg[2 * k]);
+                lFy += w * (-Ae[e] * gg[2 * k + 1]);
+            }
+            /* F = (1+theta) U' - theta U */
+            double lUnx = lU[2 * e] + (1.0 + theta) * lFx;
+            double lUny = lU[2 * e + 1] + (1.0 + theta) * lFy;
+            double lUox = -theta * lFx, lUoy = -theta * lFy;
+            /* U' = C r,  C = (I + al J)^-1;  C^T = (I + al J) / (1 + al^2) */
+            double al = q.al, den = 1.0 + al * al;
+            double lrx = (lUnx - al * lUny) / den;
+            double lry = (lUny + al * lUnx) / den;
+            /* r = (I - al J) U + dts(-g He grad + R); (I - al J)^T = I + al J */
+            lUox += lrx - al * lry;
+            lUoy += lry + al * lrx;
+            g_R[2 * e] += dts * lrx;
+            g_R[2 * e + 1] += dts * lry;
+            double lgx = -dts * g * q.He * lrx, lgy = -dts * g * q.He * lry;
+            double lHe = -dts * g * (q.gx * lrx + q.gy * lry);
+            for (int k = 0; k < 3; ++k) {
+                le_new[t[k]] += gg[2 * k] * lgx + gg[2 * k + 1] * lgy;
+                if (!linear_h) le_new[t[k]] += lHe / 3.0;
+                g_H0[t[k]] += lHe / 3.0;
+            }
+            lU_new[2 * e] = lUox;
+            lU_new[2 * e + 1] = lUoy;
+        }
+        memcpy(le, le_new, sizeof(double) * nv);
+        memcpy(lU, lU_new, nb2);
+    }
+    if (lam_Uavg)
+        for (int64_t i = 0; i < 2 * ne; ++i) lU[i] -= theta * rM * lam_Uavg[i];
+    memcpy(g_eta0, le, sizeof(double) * nv);
+    memcpy(g_U0, lU, nb2);
+    free(etas); free(Us); free(F); free(div); free(le); free(le_new); free(lU); free(lU_new);
+    return ORC_OK;
+}
