@@ -1,0 +1,254 @@
+"""Benchmark of the barotropic subcycle on one MI355X.
+
+A step is one baroclinic step of the global-scale lat-lon workload: 80
+dissipative forward-backward substeps on the 2048 x 1536 lat-lon mesh with a
+30% land mask (about 2.2M wet vertices, 4.3M triangles), FP32 bulk with FP64
+volume and averaged transport, followed by the averaged transport.  Inputs are
+seeded and synthetic and resident in HBM before timing starts.
+
+Prints one JSON line with: throughput in vertex-substeps/s, the roofline
+position of the dominant kernel (algorithmic bytes per vertex-substep x
+vertex-substeps per launch / average launch time, against 8 TB/s), the plain
+FP64 GPU path and the FP64 fused path on the same workload, errors of the
+timed configuration against the FP64 oracle after one step, and the oracle
+timed on this host's cores.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("vertex-substeps/s + HBM GB/s, FP32/batched vs FP64 plain at stated η error")
+HBM_PEAK_GBS = 8000.0
+# Algorithmic bytes per vertex-substep of one streaming pass with no on-chip
+# reuse across substeps (r = triangles per vertex ~ 2):
+#   vertex: eta r+w, H0, 1/A_v, row pointer; triangle: U r+w, R, f, geometry,
+#   connectivity, running sum r+w, CSR column.
+B_ALG = {"f32": 236.0, "f64": 356.0}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    with open(os.path.join(ROOT, "paper_2311_08241_amd", "csrc", "kernels.hip"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(workload_tag):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if current."""
+    path = os.path.join(ROOT, "profiles", f"pmc_k_tile_{workload_tag}.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernels_hip_sha256_16") != kernel_source_hash():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--precision", default="f32", choices=["f32", "f64"])
+    ap.add_argument("--plan", default="", help="tile,k_fused,block (default: autotuned/default)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
+    ap.add_argument("--no-extra", action="store_true", help="skip the FP64 comparison runs")
+    ap.add_argument("--small", action="store_true", help="reduced mesh (testing the script)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only; multi-GPU sharding is designed "
+              "but not implemented, so --gpus must be 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import sesynth
+    from paper_2311_08241_amd import Mesh, Params, device_inputs
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    if args.small:
+        case = sesynth.latlon_c3(nlon=512, nlat=384, nsteps=args.steps)
+        case["tau"] = case["nsub"] * 45.0
+        tag = "C3small"
+    else:
+        case = sesynth.latlon_c3(nsteps=args.steps)
+        tag = "C3"
+    log(f"[bench] generated {case['name']}: nv={case['x'].size} ne={case['tri'].shape[0]} "
+        f"in {time.time() - t0:.1f}s")
+    t0 = time.time()
+    mesh = Mesh.from_dict(case, device=0)
+    log(f"[bench] mesh create {time.time() - t0:.1f}s, mu_max={mesh.mu_max:.3e}")
+    t0 = time.time()
+    nsub, tau = case["nsub"], case["tau"]
+    prec = args.precision
+    params = Params(g=case["g"], theta=case["theta"], precision=prec,
+                    eta_ref=case["eta_ref"] if prec == "f32" else 0.0, track_volume=True)
+    d = device_inputs(mesh, case, params)
+    Uavg = torch.empty((mesh.ne, 2), dtype=torch.float64, device=dev)
+    vol = torch.empty(nsub + 1, dtype=torch.float64, device=dev)
+    ws = mesh.workspace(params, nsub)
+
+    def step(dd=d, p=params, w=ws, plain=False):
+        mesh.subcycle(dd["eta"], dd["U"], R=dd["R"], f=dd["f"], H0=dd["H0"], nsub=nsub, dt=tau,
+                      params=p, Uavg=Uavg, volume=vol, workspace=w, plain=plain)
+
+    tune = None
+    if args.plan:
+        mesh.set_plan(*[int(v) for v in args.plan.split(",")])
+    else:
+        from paper_2311_08241_amd.autotune import autotune
+        scratch = {k: (v.clone() if v is not None else None) for k, v in d.items()}
+        tune = autotune(mesh, lambda: step(scratch), prec, nsub, log=log)
+        del scratch
+        log(f"[bench] autotuned plan {tune['plan']} ({tune['ms']:.3f} ms/step, "
+            f"cached={tune['cached']})")
+    plan = mesh.get_plan()
+
+    # one step from the initial state, for the error report
+    step()
+    torch.cuda.synchronize()
+    if mesh.check_faults():
+        raise RuntimeError("kernel fault flags set")
+    eta_1 = d["eta"].double().cpu().numpy() + (params.eta_ref if prec == "f32" else 0.0)
+    Uavg_1 = Uavg.cpu().numpy()
+    log(f"[bench] plan tile,k,block={plan}; first step done ({time.time() - t0:.1f}s)")
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(args.steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    if mesh.check_faults():
+        raise RuntimeError("kernel fault flags set")
+    vsub = float(mesh.nv) * nsub * args.steps
+    value = vsub / (ms * 1e-3)
+    log(f"[bench] timed {args.steps} steps: {ms:.2f} ms, {value:.3e} vertex-substeps/s")
+
+    # roofline of the dominant kernel: the tile kernel runs ceil(nsub/k) launches per step
+    nlaunch = -(-nsub // plan[1]) * args.steps
+    avg_launch_s = ms * 1e-3 / nlaunch
+    units_per_launch = float(mesh.nv) * nsub / -(-nsub // plan[1])
+    achieved = B_ALG[prec] * units_per_launch / avg_launch_s / 1e9
+    traffic = read_traffic(f"{tag}_{prec}")
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic, "kernel": "k_tile",
+                "avg_launch_us": round(avg_launch_s * 1e6, 2),
+                "bytes_per_unit": B_ALG[prec], "units_per_launch": units_per_launch}
+
+    extra = {}
+    if not args.no_extra:
+        # FP64: the plain two-kernel path and the fused path, same workload and state
+        p64 = Params(g=case["g"], theta=case["theta"], precision="f64", track_volume=True)
+        d64 = device_inputs(mesh, case, p64)
+        ws64 = mesh.workspace(p64, nsub)
+        if prec != "f64":
+            from paper_2311_08241_amd.autotune import autotune
+            t64 = autotune(mesh, lambda: step(d64, p64, ws64), "f64", nsub, log=log)
+            extra["fp64_plan"] = t64["plan"]
+        for label, plain in (("fp64_plain", True), ("fp64_fused", False)):
+            def s64():
+                step(d64, p64, ws64, plain)
+            s64()
+            torch.cuda.synchronize()
+            n = max(2, args.steps // 4)
+            e0.record(stream)
+            for _ in range(n):
+                s64()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            t = e0.elapsed_time(e1)
+            extra[label] = {"value": float(mesh.nv) * nsub * n / (t * 1e-3),
+                            "ms_per_step": t / n}
+            log(f"[bench] {label}: {extra[label]['value']:.3e} vertex-substeps/s")
+        extra["speedup_vs_fp64_plain"] = value / extra["fp64_plain"]["value"]
+        del d64, ws64
+
+    cpu = None
+    errors = None
+    if not args.no_cpu:
+        import oracle
+        t0 = time.time()
+        om = oracle.Mesh(case, reordered=True)
+        log(f"[bench] oracle mesh {time.time() - t0:.1f}s")
+        H0, f, R = om.v_in(case["H0"]), om.e_in(case["f"]), om.e_in(case["R"])
+        eta, U = om.v_in(case["eta0"]), om.e_in(case["U0"])
+        t0 = time.perf_counter()
+        eta_o, U_o, Uavg_o, _ = om.subcycle(eta, U, H0=H0, f=f, R=R, g=case["g"],
+                                            theta=case["theta"], nsub=nsub, tau=tau,
+                                            linear_h=False, volume=True)
+        tcpu = time.perf_counter() - t0
+        cpu = {"value": om.nv * nsub / tcpu, "unit": "vertex-substeps/s", "cores": 1,
+               "kind": "oracle",
+               "sample": f"one baroclinic step ({nsub} substeps) of the same mesh, FP64, "
+                         f"1 thread, {tcpu:.1f} s"}
+        log(f"[bench] oracle: {tcpu:.1f}s, {cpu['value']:.3e} vertex-substeps/s")
+        # errors of the benchmarked configuration after one step
+        eta_g = mesh.v_out(eta_1)
+        eta_r = om.v_out(eta_o)
+        ua_g = mesh.e_out(Uavg_1)
+        ua_r = om.e_out(Uavg_o)
+        Av = om.v_out(om.Av)
+        Ae = om.e_out(om.Ae)
+        ref = case["eta_ref"] if prec == "f32" else 0.0
+        den = np.abs(eta_r - ref).max()
+        errors = {
+            "after_substeps": nsub,
+            "eta_max": float(np.abs(eta_g - eta_r).max() / den),
+            "eta_rms": float(np.sqrt(np.sum(Av * (eta_g - eta_r) ** 2) /
+                                     np.sum(Av * (eta_r - ref) ** 2))),
+            "Uavg_max": float(np.abs(ua_g - ua_r).max() / np.abs(ua_r).max()),
+            "Uavg_rms": float(np.sqrt(np.sum(Ae[:, None] * (ua_g - ua_r) ** 2) /
+                                      np.sum(Ae[:, None] * ua_r ** 2))),
+        }
+        log(f"[bench] errors vs oracle: {errors}")
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "vertex-substeps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": prec, "data": "synthetic",
+        "config": {"workload": f"{case['name']} lat-lon, 30% land, {nsub} substeps/step",
+                   "nv": mesh.nv, "ne": mesh.ne, "substeps_per_step": nsub,
+                   "precision": ("FP32 bulk, FP64 volume and averaged transport"
+                                 if prec == "f32" else "FP64"),
+                   "plan": {"tile": plan[0], "k_fused": plan[1], "block": plan[2]}},
+        "roofline": roofline, "cpu_baseline": cpu, "errors": errors,
+        "hbm_gbs_algorithmic": round(achieved, 1),
+    }
+    out.update(extra)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,8 @@
+"""MI355X-native split-explicit barotropic subcycle (arXiv 2311.08241).
+
+The compute path is the HIP library libsesub.so (gfx950) behind the C ABI of
+include/sesub.h; this package marshals arguments to it.  Importing the
+package does not load the library; the first call does, and fails with
+ImportError if it has not been built.
+"""
+from .api import Mesh, Params, device_inputs  # noqa: F401

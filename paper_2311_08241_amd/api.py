@@ -1,0 +1,236 @@
+"""Python face of the C ABI: the same entry points, argument marshalling only.
+
+torch provides device memory and streams; every step of the subcycle runs in
+libsesub.so.  Field tensors are in the mesh's internal (reordered) numbering;
+Mesh.v_in / e_in / v_out / e_out convert from and to the caller's numbering.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import _lib as L
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_ptr(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+@dataclass
+class Params:
+    """se_params: g, theta (eq. (eq4_10)), precision, flags, eta_ref, h_max."""
+    g: float = 9.81
+    theta: float = 0.14
+    precision: str = "f64"          # "f64" | "f32" (FP32 bulk, FP64 volume and average)
+    linear_h: bool = False
+    check_cfl: bool = False
+    track_volume: bool = True
+    eta_ref: float = 0.0
+    h_max: float = 0.0
+
+    @property
+    def dtype(self):
+        torch = _torch()
+        return torch.float64 if self.precision == "f64" else torch.float32
+
+    def c(self) -> L.Params:
+        if self.precision not in ("f64", "f32"):
+            raise ValueError("precision must be 'f64' or 'f32'")
+        flags = ((L.SE_LINEAR_H if self.linear_h else 0) |
+                 (L.SE_CHECK_CFL if self.check_cfl else 0) |
+                 (L.SE_TRACK_VOLUME if self.track_volume else 0))
+        return L.Params(self.g, self.theta,
+                        L.SE_F64 if self.precision == "f64" else L.SE_F32_MIXED, flags,
+                        self.eta_ref, self.h_max)
+
+
+class Mesh:
+    """A reordered mesh owned by the library (se_mesh_create)."""
+
+    def __init__(self, x, y, tri, *, periodic_x=False, periodic_y=False, period_x=0.0,
+                 period_y=0.0, spherical=False, radius=0.0, device: int = 0):
+        self._x = np.ascontiguousarray(x, np.float64)
+        self._y = np.ascontiguousarray(y, np.float64)
+        self._tri = np.ascontiguousarray(tri, np.int32)
+        flags = ((L.SE_PERIODIC_X if periodic_x else 0) | (L.SE_PERIODIC_Y if periodic_y else 0) |
+                 (L.SE_SPHERICAL if spherical else 0))
+        d = L.MeshDesc(self._x.size, self._tri.shape[0],
+                       self._x.ctypes.data_as(ctypes.c_void_p),
+                       self._y.ctypes.data_as(ctypes.c_void_p),
+                       self._tri.ctypes.data_as(ctypes.c_void_p), flags, float(period_x),
+                       float(period_y), float(radius))
+        h = ctypes.c_void_p()
+        L.check(L.lib().se_mesh_create(ctypes.byref(d), int(device), ctypes.byref(h)))
+        self._h = h
+        self.device = int(device)
+        nv, ne, nnz, mu = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_double()
+        L.check(L.lib().se_mesh_info(h, ctypes.byref(nv), ctypes.byref(ne), ctypes.byref(nnz),
+                                     ctypes.byref(mu)))
+        self.nv, self.ne, self.nnz, self.mu_max = nv.value, ne.value, nnz.value, mu.value
+        self.vperm = np.empty(self.nv, np.int32)
+        self.eperm = np.empty(self.ne, np.int32)
+        L.check(L.lib().se_mesh_perm(h, self.vperm.ctypes.data_as(ctypes.c_void_p),
+                                     self.eperm.ctypes.data_as(ctypes.c_void_p)))
+
+    @classmethod
+    def from_dict(cls, m: dict, device: int = 0):
+        return cls(m["x"], m["y"], m["tri"], periodic_x=m.get("periodic_x", False),
+                   periodic_y=m.get("periodic_y", False), period_x=m.get("period_x", 0.0),
+                   period_y=m.get("period_y", 0.0), spherical=m.get("spherical", False),
+                   radius=m.get("radius", 0.0), device=device)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            L.lib().se_mesh_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- host copies ----
+    def csr(self):
+        tri = np.empty((self.ne, 3), np.int32)
+        row = np.empty(self.nv + 1, np.int32)
+        col = np.empty(self.nnz, np.int32)
+        L.check(L.lib().se_mesh_csr(self._h, tri.ctypes.data_as(ctypes.c_void_p),
+                                    row.ctypes.data_as(ctypes.c_void_p),
+                                    col.ctypes.data_as(ctypes.c_void_p)))
+        return tri, row, col
+
+    def geometry(self):
+        Av = np.empty(self.nv)
+        Ae = np.empty(self.ne)
+        gN = np.empty((self.ne, 3, 2))
+        L.check(L.lib().se_mesh_geometry(self._h, Av.ctypes.data_as(ctypes.c_void_p),
+                                         Ae.ctypes.data_as(ctypes.c_void_p),
+                                         gN.ctypes.data_as(ctypes.c_void_p)))
+        return Av, Ae, gN
+
+    # ---- numbering helpers (caller numbering <-> internal) ----
+    def v_in(self, a):
+        return np.ascontiguousarray(np.asarray(a)[self.vperm])
+
+    def e_in(self, a):
+        return np.ascontiguousarray(np.asarray(a)[self.eperm])
+
+    def v_out(self, a):
+        out = np.empty_like(a)
+        out[self.vperm] = a
+        return out
+
+    def e_out(self, a):
+        out = np.empty_like(a)
+        out[self.eperm] = a
+        return out
+
+    # ---- plan ----
+    def set_plan(self, tile: int, k_fused: int, block: int = 256):
+        L.check(L.lib().se_set_plan(self._h, 0, int(tile), int(k_fused), int(block)))
+
+    def plan_stats(self, tile: int, k_fused: int, block: int = 256) -> dict:
+        st = L.PlanStats()
+        L.check(L.lib().se_plan_stats(self._h, 0, int(tile), int(k_fused), int(block),
+                                      ctypes.byref(st)))
+        return st.as_dict()
+
+    def get_plan(self):
+        t, k, b = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        L.check(L.lib().se_get_plan(self._h, 0, ctypes.byref(t), ctypes.byref(k), ctypes.byref(b)))
+        return t.value, k.value, b.value
+
+    # ---- compute ----
+    def workspace_bytes(self, params: Params, nsub: int, ckpt_every: int = 0) -> int:
+        n = ctypes.c_size_t()
+        pc = params.c()
+        L.check(L.lib().se_workspace_bytes(self._h, ctypes.byref(pc), int(nsub), int(ckpt_every),
+                                           ctypes.byref(n)))
+        return n.value
+
+    def workspace(self, params: Params, nsub: int, ckpt_every: int = 0):
+        torch = _torch()
+        n = self.workspace_bytes(params, nsub, ckpt_every)
+        # torch's caching allocator returns 256-byte aligned blocks
+        return torch.empty(max(n, 256), dtype=torch.uint8, device=f"cuda:{self.device}")
+
+    def _check_tensor(self, t, n, name, dtype, cols=None, allow_none=False):
+        if t is None:
+            if allow_none:
+                return
+            raise ValueError(f"{name} is required")
+        shape = (n,) if cols is None else (n, cols)
+        if tuple(t.shape) != shape or t.dtype != dtype or not t.is_contiguous() or not t.is_cuda:
+            raise ValueError(f"{name}: need a contiguous {dtype} CUDA tensor of shape {shape}, "
+                             f"got {tuple(t.shape)} {t.dtype} cuda={t.is_cuda}")
+
+    def subcycle(self, eta, U, *, R, f, H0, W=None, nsub: int, dt: float, params: Params,
+                 Uavg=None, volume=None, workspace=None, plain: bool = False, stream=None):
+        """se_subcycle (or se_subcycle_plain): eta, U updated in place; fills Uavg, volume."""
+        torch = _torch()
+        dt_ = params.dtype
+        self._check_tensor(eta, self.nv, "eta", dt_)
+        self._check_tensor(U, self.ne, "U", dt_, 2)
+        self._check_tensor(R, self.ne, "R", dt_, 2)
+        self._check_tensor(f, self.ne, "f", dt_)
+        self._check_tensor(H0, self.nv, "H0", dt_)
+        self._check_tensor(W, self.nv, "W", dt_, allow_none=True)
+        self._check_tensor(Uavg, self.ne, "Uavg", torch.float64, 2, allow_none=True)
+        nvol = nsub + 1 if params.track_volume else 2
+        self._check_tensor(volume, nvol, "volume", torch.float64, allow_none=True)
+        if workspace is None:
+            workspace = self.workspace(params, nsub)
+        st = L.State(_ptr(eta), _ptr(U), _ptr(Uavg), _ptr(volume))
+        fo = L.Forcing(_ptr(R), _ptr(f), _ptr(H0), _ptr(W))
+        pc = params.c()
+        fn = L.lib().se_subcycle_plain if plain else L.lib().se_subcycle
+        L.check(fn(self._h, ctypes.byref(pc), ctypes.byref(st), ctypes.byref(fo), int(nsub),
+                   float(dt), _ptr(workspace), _stream_ptr(stream)))
+        return eta, U, Uavg, volume
+
+    def check_faults(self, stream=None) -> int:
+        bits = ctypes.c_uint32()
+        L.check(L.lib().se_check_faults(self._h, 0, _stream_ptr(stream), ctypes.byref(bits)))
+        return bits.value
+
+
+def device_inputs(mesh: Mesh, case: dict, params: Params, device=None):
+    """Move a generated workload's fields to the device in the mesh's numbering.
+
+    Returns dict(eta, U, R, f, H0, W) of tensors with params.dtype; eta holds
+    eta - eta_ref in the FP32 mode.
+    """
+    torch = _torch()
+    dev = device or f"cuda:{mesh.device}"
+    dt_ = params.dtype
+    eta = mesh.v_in(case["eta0"])
+    if params.precision == "f32":
+        eta = eta - params.eta_ref
+    out = dict(
+        eta=torch.tensor(eta, dtype=dt_, device=dev),
+        U=torch.tensor(mesh.e_in(case["U0"]), dtype=dt_, device=dev).contiguous(),
+        R=torch.tensor(mesh.e_in(case["R"]), dtype=dt_, device=dev).contiguous(),
+        f=torch.tensor(mesh.e_in(case["f"]), dtype=dt_, device=dev),
+        H0=torch.tensor(mesh.v_in(case["H0"]), dtype=dt_, device=dev),
+        W=None if case.get("W") is None else torch.tensor(mesh.v_in(case["W"]), dtype=dt_,
+                                                          device=dev),
+    )
+    return out

@@ -1,0 +1,688 @@
+// C ABI of the barotropic subcycle library: argument validation, mesh and
+// plan management, and the launch sequences of the forward paths.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "kernels.h"
+#include "se_internal.h"
+
+namespace sesub {
+
+namespace {
+thread_local std::string g_err;
+}
+
+void set_error(const std::string &msg) { g_err = msg; }
+
+DevBuf::~DevBuf() {
+    if (p) (void)hipFree(p);
+}
+
+se_status DevBuf::alloc(size_t bytes) {
+    if (p) {
+        (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    if (bytes == 0) return SE_OK;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+        p = nullptr;
+        (void)hipGetLastError();
+        set_error("device allocation of " + std::to_string(bytes) + " bytes failed");
+        return SE_ERR_OOM;
+    }
+    n = bytes;
+    return SE_OK;
+}
+
+se_status DevBuf::upload(const void *src, size_t bytes) {
+    se_status s = alloc(bytes);
+    if (s != SE_OK || bytes == 0) return s;
+    if (hipMemcpy(p, src, bytes, hipMemcpyHostToDevice) != hipSuccess) {
+        set_error("host to device copy failed");
+        return SE_ERR_HIP;
+    }
+    return SE_OK;
+}
+
+namespace {
+
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = true;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+se_status hip_fail(hipError_t e, const char *where) {
+    set_error(std::string(where) + ": " + hipGetErrorString(e));
+    return SE_ERR_HIP;
+}
+
+#define SE_TRY(x)                         \
+    do {                                  \
+        se_status _s = (x);               \
+        if (_s != SE_OK) return _s;       \
+    } while (0)
+
+#define HIP_TRY(x, where)                         \
+    do {                                          \
+        hipError_t _e = (x);                      \
+        if (_e != hipSuccess) return hip_fail(_e, where); \
+    } while (0)
+
+constexpr size_t kAlign = 256;
+inline size_t al(size_t b) { return (b + kAlign - 1) & ~(kAlign - 1); }
+
+constexpr int kEpts[] = {1, 2, 3, 4, 6, 8};
+
+int pick_ept(int need) {
+    for (int e : kEpts)
+        if (e >= need) return e;
+    return -1;
+}
+
+// Geometry of a triangle set as 5 SoA arrays (gbx gby gcx gcy Ae).
+template <typename T>
+std::vector<T> pack_geom(const HostMesh &m, const std::vector<int32_t> *sel, int64_t off) {
+    const int64_t n = sel ? static_cast<int64_t>(sel->size()) : m.ne;
+    std::vector<T> g(5 * n);
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t e = sel ? (*sel)[i] - off : i;
+        const double *gn = &m.gN[6 * e];
+        g[i] = static_cast<T>(gn[2]);
+        g[n + i] = static_cast<T>(gn[3]);
+        g[2 * n + i] = static_cast<T>(gn[4]);
+        g[3 * n + i] = static_cast<T>(gn[5]);
+        g[4 * n + i] = static_cast<T>(m.Ae[e]);
+    }
+    return g;
+}
+
+// Register tiers that compile without scratch spills (triangles per thread).
+bool ept_ok(bool f32, int ept, int block) {
+    if (ept < 0) return false;
+    if (block == 256) return f32 ? ept <= 8 : ept <= 6;
+    return f32 ? ept <= 6 : ept <= 4;
+}
+
+// Host-side construction and statistics of a plan (no device memory).
+se_status plan_host(const std::vector<const HostMesh *> &members, const std::vector<int64_t> &voff,
+                    const std::vector<int64_t> &eoff, int32_t T, int32_t K, int32_t block,
+                    HostTiles &ht, se_plan_stats_t &st) {
+    if (T < 64 || T > 8192 || K < 1 || K > 8 || (block != 256 && block != 512)) {
+        set_error("se_set_plan: tile in [64, 8192], k_fused in [1, 8], block 256 or 512");
+        return SE_ERR_ARG;
+    }
+    SE_TRY(build_tiles(members, voff, eoff, T, K, ht));
+    st = se_plan_stats_t{};
+    const int ept = pick_ept((ht.max_ne + block - 1) / block);
+    st.ntiles = static_cast<int32_t>(ht.hdr.size());
+    st.max_tri = ht.max_ne;
+    st.max_vtx = ht.max_nv;
+    st.tri_per_thread = ept;
+    st.lds_f32 = tile_lds_bytes(true, block, K, ht.max_nv, ht.max_ne, ht.max_nvu, ht.max_cs);
+    st.lds_f64 = tile_lds_bytes(false, block, K, ht.max_nv, ht.max_ne, ht.max_nvu, ht.max_cs);
+    st.ok_f32 = ept_ok(true, ept, block) && st.lds_f32 <= 160 * 1024;
+    st.ok_f64 = ept_ok(false, ept, block) && st.lds_f64 <= 160 * 1024;
+    int64_t nv = 0, ne = 0;
+    for (const HostMesh *m : members) {
+        nv += m->nv;
+        ne += m->ne;
+    }
+    // compulsory bytes of one launch (all tiles), per precision s
+    int64_t sumV = 0, sumVu = 0, sumE = 0, sumC = 0;
+    for (size_t t = 0; t < ht.hdr.size(); ++t) {
+        sumV += ht.nV[t * (K + 1) + K];
+        sumVu += ht.nV[t * (K + 1) + K - 1];
+        sumE += ht.nE[t * (K + 1) + K];
+    }
+    sumC = static_cast<int64_t>(ht.cs_ent.size());
+    st.tri_overhead = static_cast<double>(sumE) / ne;
+    st.vtx_overhead = static_cast<double>(sumV) / nv;
+    for (int f = 0; f < 2; ++f) {
+        const double s = f == 0 ? 4.0 : 8.0;
+        const double bytes = sumV * (4 + 2 * s) + sumVu * (s + 2) + sumC * 2.0 +
+                             sumE * (4 + 8 + 5 * s + 2 * s + 2 * s + s) +
+                             ne * (32.0 + 2 * s) + nv * (s + 8.0);
+        (f == 0 ? st.bytes_per_vs_f32 : st.bytes_per_vs_f64) = bytes / (static_cast<double>(nv) * K);
+    }
+    return SE_OK;
+}
+
+// Build and upload a tile plan for a set of meshes forming a disjoint union.
+se_status make_plan(const std::vector<const HostMesh *> &members, const std::vector<int64_t> &voff,
+                    const std::vector<int64_t> &eoff, int32_t T, int32_t K, int32_t block,
+                    std::unique_ptr<DevTiles> &out) {
+    HostTiles ht;
+    se_plan_stats_t st;
+    SE_TRY(plan_host(members, voff, eoff, T, K, block, ht, st));
+    const int ept = st.tri_per_thread;
+    if (!st.ok_f32 && !st.ok_f64) {
+        set_error("se_set_plan: tile too large for the register or LDS budget (reduce tile or "
+                  "k_fused)");
+        return SE_ERR_ARG;
+    }
+    auto p = std::make_unique<DevTiles>();
+    p->T = T;
+    p->K = K;
+    p->block = block;
+    p->ept = ept;
+    p->ntiles = static_cast<int32_t>(ht.hdr.size());
+    p->max_nv = ht.max_nv;
+    p->max_ne = ht.max_ne;
+    p->max_nvu = ht.max_nvu;
+    p->max_cs = ht.max_cs;
+    p->lds_bytes64 = st.lds_f64;
+    p->lds_bytes32 = st.lds_f32;
+    p->ok32 = st.ok_f32;
+    p->ok64 = st.ok_f64;
+    p->hdr_host = ht.hdr;
+    static_assert(sizeof(TileHdr) == sizeof(TileHdrK), "tile header layouts differ");
+    SE_TRY(p->hdr.upload(ht.hdr.data(), ht.hdr.size() * sizeof(TileHdr)));
+    SE_TRY(p->nV.upload(ht.nV.data(), ht.nV.size() * 4));
+    SE_TRY(p->nE.upload(ht.nE.data(), ht.nE.size() * 4));
+    SE_TRY(p->lv_gid.upload(ht.lv_gid.data(), ht.lv_gid.size() * 4));
+    SE_TRY(p->le_gid.upload(ht.le_gid.data(), ht.le_gid.size() * 4));
+    SE_TRY(p->le_tri.upload(ht.le_tri.data(), ht.le_tri.size() * 4));
+    SE_TRY(p->cs_row.upload(ht.cs_row.data(), ht.cs_row.size() * 2));
+    SE_TRY(p->cs_ent.upload(ht.cs_ent.data(), std::max<size_t>(ht.cs_ent.size(), 1) * 2));
+    // local geometry per tile, gathered member by member
+    const int64_t nle = static_cast<int64_t>(ht.le_gid.size());
+    std::vector<double> g64(5 * nle);
+    std::vector<float> g32(5 * nle);
+    for (int64_t i = 0; i < nle; ++i) {
+        const int64_t ge = ht.le_gid[i];
+        size_t mi = std::upper_bound(eoff.begin(), eoff.end(), ge) - eoff.begin() - 1;
+        const HostMesh &m = *members[mi];
+        const int64_t e = ge - eoff[mi];
+        const double *gn = &m.gN[6 * e];
+        const double v[5] = {gn[2], gn[3], gn[4], gn[5], m.Ae[e]};
+        for (int q = 0; q < 5; ++q) {
+            g64[q * nle + i] = v[q];
+            g32[q * nle + i] = static_cast<float>(v[q]);
+        }
+    }
+    SE_TRY(p->geom64.upload(g64.data(), g64.size() * 8));
+    SE_TRY(p->geom32.upload(g32.data(), g32.size() * 4));
+    out = std::move(p);
+    return SE_OK;
+}
+
+struct Layout {
+    size_t eta_alt, U_alt, sum, U0c, phi, vol, total;
+};
+
+Layout fwd_layout(int64_t nv, int64_t ne, bool f32, int32_t nsub, int64_t width) {
+    const size_t s = f32 ? 4 : 8;
+    Layout L{};
+    size_t o = 0;
+    L.eta_alt = o;
+    o += al(nv * s);
+    L.U_alt = o;
+    o += al(2 * ne * s);
+    L.sum = o;
+    o += al(16 * ne);
+    L.U0c = o;
+    o += al(2 * ne * s);
+    L.phi = o;
+    o += al(3 * ne * s);
+    L.vol = o;
+    o += al(static_cast<size_t>(nsub + 1) * width * 8);
+    L.total = o;
+    return L;
+}
+
+int64_t vol_width(int64_t nv) { return std::max<int64_t>((nv + 63) / 64, (nv + 255) / 256); }
+
+se_status check_params(const se_mesh *m, const se_params *p, int32_t nsub, double dt) {
+    if (!m || !p) {
+        set_error("null mesh or params");
+        return SE_ERR_ARG;
+    }
+    if (p->precision != SE_F64 && p->precision != SE_F32_MIXED) {
+        set_error("unknown precision");
+        return SE_ERR_ARG;
+    }
+    if (nsub < 1 || !(dt > 0.0) || !std::isfinite(dt)) {
+        set_error("need nsub >= 1 and a finite dt > 0");
+        return SE_ERR_ARG;
+    }
+    if (!(p->g > 0.0) || !std::isfinite(p->g) || !(p->theta >= 0.0) || !std::isfinite(p->theta) ||
+        !std::isfinite(p->eta_ref)) {
+        set_error("need g > 0, theta >= 0 and a finite eta_ref");
+        return SE_ERR_ARG;
+    }
+    if (p->flags & SE_CHECK_CFL) {
+        if (!(p->h_max > 0.0)) {
+            set_error("SE_CHECK_CFL needs h_max > 0");
+            return SE_ERR_ARG;
+        }
+        const double dts = dt / nsub;
+        const double c = dts * std::sqrt(p->g * p->h_max * m->h.mu_max);
+        const double lim = 2.0 / std::sqrt(1.0 + 2.0 * p->theta);
+        if (c > lim) {
+            set_error("CFL: dt_s sqrt(g h_max mu_max) = " + std::to_string(c) +
+                      " exceeds the stability bound " + std::to_string(lim));
+            return SE_ERR_CFL;
+        }
+    }
+    return SE_OK;
+}
+
+StepC make_step(const se_params *p, int32_t nsub, double dt) {
+    StepC c{};
+    c.dts = dt / nsub;
+    c.g = p->g;
+    c.theta = p->theta;
+    c.opt = 1.0 + p->theta;
+    c.thM = p->theta / static_cast<double>(nsub);
+    c.Mdbl = static_cast<double>(nsub);
+    c.eta_ref = p->eta_ref;
+    c.dts_f = static_cast<float>(c.dts);
+    c.g_f = static_cast<float>(c.g);
+    c.theta_f = static_cast<float>(c.theta);
+    c.opt_f = static_cast<float>(c.opt);
+    c.eta_ref_f = static_cast<float>(c.eta_ref);
+    c.nsub = nsub;
+    c.flags = ((p->flags & SE_LINEAR_H) ? KF_LINEAR_H : 0) |
+              ((p->flags & SE_TRACK_VOLUME) ? KF_TRACK_VOLUME : 0);
+    return c;
+}
+
+se_status check_device(const se_mesh *m) {
+    if (m->device < 0) {
+        set_error("host-only mesh (created with device < 0) cannot run kernels");
+        return SE_ERR_ARG;
+    }
+    return SE_OK;
+}
+
+// Default plan when the caller set none: the first candidate that runs in
+// both precisions without spills.
+se_status ensure_plan(se_mesh *m) {
+    if (m->plan) return SE_OK;
+    std::vector<const HostMesh *> mem{&m->h};
+    static const int32_t cand[][3] = {{1024, 4, 512}, {512, 4, 512}, {512, 4, 256}, {512, 2, 256},
+                                      {256, 4, 256}, {256, 2, 256}, {128, 2, 256}, {64, 1, 256}};
+    for (const auto &c : cand) {
+        HostTiles ht;
+        se_plan_stats_t st;
+        if (plan_host(mem, {0, m->h.nv}, {0, m->h.ne}, c[0], c[1], c[2], ht, st) != SE_OK) continue;
+        if (!st.ok_f32 || !st.ok_f64) continue;
+        SE_TRY(make_plan(mem, {0, m->h.nv}, {0, m->h.ne}, c[0], c[1], c[2], m->plan));
+        m->plan_T = c[0];
+        m->plan_K = c[1];
+        m->plan_block = c[2];
+        return SE_OK;
+    }
+    set_error("no default plan fits this mesh");
+    return SE_ERR_ARG;
+}
+
+}  // namespace
+}  // namespace sesub
+
+using namespace sesub;
+
+extern "C" {
+
+const char *se_last_error(void) { return g_err.c_str(); }
+
+se_status se_mesh_create(const se_mesh_desc *desc, int device, se_mesh **out) {
+    if (!desc || !out) {
+        set_error("se_mesh_create: null argument");
+        return SE_ERR_ARG;
+    }
+    *out = nullptr;
+    auto m = std::make_unique<se_mesh>();
+    m->device = device;
+    SE_TRY(build_host_mesh(*desc, m->h));
+    if (device < 0) {   // host-only mesh: reordering and geometry, no device arrays
+        *out = m.release();
+        return SE_OK;
+    }
+    DeviceGuard dg(device);
+    if (!dg.ok) {
+        set_error("se_mesh_create: cannot select device " + std::to_string(device));
+        return SE_ERR_HIP;
+    }
+    const HostMesh &h = m->h;
+    DevMesh &d = m->d;
+    d.nv = h.nv;
+    d.ne = h.ne;
+    SE_TRY(d.tri.upload(h.tri.data(), h.tri.size() * 4));
+    SE_TRY(d.row_ptr.upload(h.row_ptr.data(), h.row_ptr.size() * 4));
+    std::vector<int32_t> pcol(h.col.size());
+    for (size_t j = 0; j < h.col.size(); ++j) pcol[j] = 3 * (h.col[j] >> 2) + (h.col[j] & 3);
+    SE_TRY(d.pcol.upload(pcol.data(), pcol.size() * 4));
+    auto g64 = pack_geom<double>(h, nullptr, 0);
+    auto g32 = pack_geom<float>(h, nullptr, 0);
+    SE_TRY(d.geom64.upload(g64.data(), g64.size() * 8));
+    SE_TRY(d.geom32.upload(g32.data(), g32.size() * 4));
+    SE_TRY(d.Av64.upload(h.Av.data(), h.Av.size() * 8));
+    std::vector<float> av32(h.Av.begin(), h.Av.end());
+    SE_TRY(d.Av32.upload(av32.data(), av32.size() * 4));
+    const uint32_t zero = 0;
+    SE_TRY(d.faults.upload(&zero, 4));
+    *out = m.release();
+    return SE_OK;
+}
+
+void se_mesh_destroy(se_mesh *mesh) {
+    if (!mesh) return;
+    if (mesh->device < 0) {
+        delete mesh;
+        return;
+    }
+    DeviceGuard dg(mesh->device);
+    delete mesh;
+}
+
+se_status se_mesh_info(const se_mesh *m, int64_t *nv, int64_t *ne, int64_t *nnz, double *mu_max) {
+    if (!m) {
+        set_error("se_mesh_info: null mesh");
+        return SE_ERR_ARG;
+    }
+    if (nv) *nv = m->h.nv;
+    if (ne) *ne = m->h.ne;
+    if (nnz) *nnz = 3 * m->h.ne;
+    if (mu_max) *mu_max = m->h.mu_max;
+    return SE_OK;
+}
+
+se_status se_mesh_perm(const se_mesh *m, int32_t *vperm, int32_t *eperm) {
+    if (!m) {
+        set_error("se_mesh_perm: null mesh");
+        return SE_ERR_ARG;
+    }
+    if (vperm) std::memcpy(vperm, m->h.vperm.data(), m->h.nv * 4);
+    if (eperm) std::memcpy(eperm, m->h.eperm.data(), m->h.ne * 4);
+    return SE_OK;
+}
+
+se_status se_mesh_csr(const se_mesh *m, int32_t *tri, int32_t *row_ptr, int32_t *col) {
+    if (!m) {
+        set_error("se_mesh_csr: null mesh");
+        return SE_ERR_ARG;
+    }
+    if (tri) std::memcpy(tri, m->h.tri.data(), m->h.tri.size() * 4);
+    if (row_ptr) std::memcpy(row_ptr, m->h.row_ptr.data(), m->h.row_ptr.size() * 4);
+    if (col) std::memcpy(col, m->h.col.data(), m->h.col.size() * 4);
+    return SE_OK;
+}
+
+se_status se_mesh_geometry(const se_mesh *m, double *Av, double *Ae, double *gN) {
+    if (!m) {
+        set_error("se_mesh_geometry: null mesh");
+        return SE_ERR_ARG;
+    }
+    if (Av) std::memcpy(Av, m->h.Av.data(), m->h.nv * 8);
+    if (Ae) std::memcpy(Ae, m->h.Ae.data(), m->h.ne * 8);
+    if (gN) std::memcpy(gN, m->h.gN.data(), m->h.ne * 48);
+    return SE_OK;
+}
+
+se_status se_set_plan(void *obj, int32_t kind, int32_t tile, int32_t k_fused, int32_t block) {
+    if (!obj || kind != 0) {
+        set_error("se_set_plan: null object or unsupported kind");
+        return obj ? SE_ERR_UNSUPPORTED : SE_ERR_ARG;
+    }
+    se_mesh *m = static_cast<se_mesh *>(obj);
+    if (m->device < 0) {   // host-only mesh: validate and remember the plan
+        HostTiles ht;
+        se_plan_stats_t st;
+        std::vector<const HostMesh *> mem{&m->h};
+        SE_TRY(plan_host(mem, {0, m->h.nv}, {0, m->h.ne}, tile, k_fused, block, ht, st));
+        m->plan_T = tile;
+        m->plan_K = k_fused;
+        m->plan_block = block;
+        return SE_OK;
+    }
+    DeviceGuard dg(m->device);
+    std::unique_ptr<DevTiles> p;
+    std::vector<const HostMesh *> mem{&m->h};
+    SE_TRY(make_plan(mem, {0, m->h.nv}, {0, m->h.ne}, tile, k_fused, block, p));
+    m->plan = std::move(p);
+    m->plan_T = tile;
+    m->plan_K = k_fused;
+    m->plan_block = block;
+    return SE_OK;
+}
+
+se_status se_get_plan(const void *obj, int32_t kind, int32_t *tile, int32_t *k_fused,
+                      int32_t *block) {
+    if (!obj || kind != 0) {
+        set_error("se_get_plan: null object or unsupported kind");
+        return SE_ERR_ARG;
+    }
+    const se_mesh *m = static_cast<const se_mesh *>(obj);
+    if (tile) *tile = m->plan_T;
+    if (k_fused) *k_fused = m->plan_K;
+    if (block) *block = m->plan_block;
+    return SE_OK;
+}
+
+se_status se_plan_stats(const void *obj, int32_t kind, int32_t tile, int32_t k_fused,
+                        int32_t block, se_plan_stats_t *stats) {
+    if (!obj || !stats || kind != 0) {
+        set_error("se_plan_stats: bad argument");
+        return SE_ERR_ARG;
+    }
+    const se_mesh *m = static_cast<const se_mesh *>(obj);
+    HostTiles ht;
+    std::vector<const HostMesh *> mem{&m->h};
+    return plan_host(mem, {0, m->h.nv}, {0, m->h.ne}, tile, k_fused, block, ht, *stats);
+}
+
+se_status se_workspace_bytes(const se_mesh *m, const se_params *p, int32_t nsub,
+                             int32_t ckpt_every, size_t *bytes) {
+    if (!m || !p || !bytes || nsub < 1) {
+        set_error("se_workspace_bytes: bad argument");
+        return SE_ERR_ARG;
+    }
+    (void)ckpt_every;
+    const bool f32 = p->precision == SE_F32_MIXED;
+    *bytes = fwd_layout(m->h.nv, m->h.ne, f32, nsub, vol_width(m->h.nv)).total;
+    return SE_OK;
+}
+
+static se_status check_state(const se_state *st, const se_forcing *fo, const void *ws) {
+    if (!st || !fo || !st->eta || !st->U || !fo->R || !fo->f || !fo->H0 || !ws) {
+        set_error("null state, forcing or workspace array");
+        return SE_ERR_ARG;
+    }
+    if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) {
+        set_error("workspace must be 256-byte aligned");
+        return SE_ERR_ARG;
+    }
+    return SE_OK;
+}
+
+se_status se_subcycle(se_mesh *m, const se_params *p, se_state *st, const se_forcing *fo,
+                      int32_t nsub, double dt, void *ws, void *stream) {
+    SE_TRY(check_params(m, p, nsub, dt));
+    SE_TRY(check_state(st, fo, ws));
+    SE_TRY(check_device(m));
+    DeviceGuard dg(m->device);
+    SE_TRY(ensure_plan(m));
+    const DevTiles &P = *m->plan;
+    const bool f32 = p->precision == SE_F32_MIXED;
+    if (!(f32 ? P.ok32 : P.ok64)) {
+        set_error("se_subcycle: the current plan does not fit the register/LDS budget of this "
+                  "precision (see se_plan_stats)");
+        return SE_ERR_ARG;
+    }
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t nv = m->h.nv, ne = m->h.ne;
+    const size_t es = f32 ? 4 : 8;
+    const Layout L = fwd_layout(nv, ne, f32, nsub, vol_width(nv));
+    char *w = static_cast<char *>(ws);
+    StepC c = make_step(p, nsub, dt);
+    c.ntiles = P.ntiles;
+    c.vol_off = 0;
+
+    TileArgs a{};
+    a.hdr = P.hdr.as<const TileHdrK>();
+    a.nV = P.nV.as<const int32_t>();
+    a.nE = P.nE.as<const int32_t>();
+    a.lv_gid = P.lv_gid.as<const int32_t>();
+    a.le_gid = P.le_gid.as<const int32_t>();
+    a.le_tri = P.le_tri.as<const uint32_t>();
+    a.cs_row = P.cs_row.as<const uint16_t>();
+    a.cs_ent = P.cs_ent.as<const uint16_t>();
+    a.lgeom = f32 ? P.geom32.p : P.geom64.p;
+    a.lgeom_stride = static_cast<int64_t>(P.geom64.n / 8 / 5);
+    a.mem = nullptr;
+    a.c0 = c;
+    a.R = fo->R;
+    a.f = fo->f;
+    a.H0 = fo->H0;
+    a.W = fo->W;
+    a.Av = f32 ? m->d.Av32.p : m->d.Av64.p;
+    a.Av64 = m->d.Av64.as<const double>();
+    a.sum = w + L.sum;
+    a.U0c = w + L.U0c;
+    a.Uavg = st->Uavg;
+    a.vol_part = reinterpret_cast<double *>(w + L.vol);
+    a.faults = m->d.faults.as<uint32_t>();
+    a.K = P.K;
+    a.ntiles = P.ntiles;
+    a.xcd = 1;
+    a.cap_nv = P.max_nv;
+    a.cap_ne = P.max_ne;
+    a.cap_nvu = P.max_nvu;
+    a.cap_cs = P.max_cs;
+    void *eta_u = st->eta, *U_u = st->U;
+    void *eta_w = w + L.eta_alt, *U_w = w + L.U_alt;
+    const int nlaunch = (nsub + P.K - 1) / P.K;
+    const size_t lds = f32 ? P.lds_bytes32 : P.lds_bytes64;
+    for (int ch = 0; ch < nlaunch; ++ch) {
+        const bool even = (ch % 2) == 0;
+        a.eta_in = even ? eta_u : eta_w;
+        a.eta_out = even ? eta_w : eta_u;
+        a.U_in = even ? U_u : U_w;
+        a.U_out = even ? U_w : U_u;
+        a.chunk = ch;
+        HIP_TRY(launch_tile(f32, P.ept, P.block, a, P.ntiles, lds, s), "se_subcycle launch");
+    }
+    if (nlaunch % 2 == 1) {
+        HIP_TRY(hipMemcpyAsync(eta_u, eta_w, nv * es, hipMemcpyDeviceToDevice, s), "copy eta");
+        HIP_TRY(hipMemcpyAsync(U_u, U_w, 2 * ne * es, hipMemcpyDeviceToDevice, s), "copy U");
+    }
+    if (st->volume) {
+        const int rows = (p->flags & SE_TRACK_VOLUME) ? nsub + 1 : 2;
+        double add = 0.0;
+        if (f32) {
+            double atot = 0.0;
+            for (double v : m->h.Av) atot += v;
+            add = p->eta_ref * atot;
+        }
+        HIP_TRY(launch_vol_reduce(a.vol_part, P.ntiles, rows, add, st->volume, s), "volume");
+    }
+    return SE_OK;
+}
+
+se_status se_subcycle_plain(se_mesh *m, const se_params *p, se_state *st, const se_forcing *fo,
+                            int32_t nsub, double dt, void *ws, void *stream) {
+    SE_TRY(check_params(m, p, nsub, dt));
+    SE_TRY(check_state(st, fo, ws));
+    SE_TRY(check_device(m));
+    DeviceGuard dg(m->device);
+    const bool f32 = p->precision == SE_F32_MIXED;
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t nv = m->h.nv, ne = m->h.ne;
+    const Layout L = fwd_layout(nv, ne, f32, nsub, vol_width(nv));
+    char *w = static_cast<char *>(ws);
+    PlainArgs a{};
+    a.nv = nv;
+    a.ne = ne;
+    a.tri = m->d.tri.as<const int32_t>();
+    a.row_ptr = m->d.row_ptr.as<const int32_t>();
+    a.pcol = m->d.pcol.as<const int32_t>();
+    a.geom = f32 ? m->d.geom32.p : m->d.geom64.p;
+    a.H0 = fo->H0;
+    a.R = fo->R;
+    a.f = fo->f;
+    a.W = fo->W;
+    a.Av = f32 ? m->d.Av32.p : m->d.Av64.p;
+    a.Av64 = m->d.Av64.as<const double>();
+    a.eta = st->eta;
+    a.U = st->U;
+    a.phi = w + L.phi;
+    a.sum = w + L.sum;
+    a.U0c = w + L.U0c;
+    a.Uavg = st->Uavg;
+    a.vol_part = reinterpret_cast<double *>(w + L.vol);
+    a.faults = m->d.faults.as<uint32_t>();
+    a.c = make_step(p, nsub, dt);
+    a.nblk_v = static_cast<int32_t>((nv + 255) / 256);
+    for (int mm = 0; mm < nsub; ++mm) {
+        a.m = mm;
+        HIP_TRY(launch_plain_step(f32, a, s), "se_subcycle_plain launch");
+    }
+    if (st->volume) {
+        const int rows = (p->flags & SE_TRACK_VOLUME) ? nsub + 1 : 2;
+        double add = 0.0;
+        if (f32) {
+            double atot = 0.0;
+            for (double v : m->h.Av) atot += v;
+            add = p->eta_ref * atot;
+        }
+        HIP_TRY(launch_vol_reduce(a.vol_part, a.nblk_v, rows, add, st->volume, s), "volume");
+    }
+    return SE_OK;
+}
+
+se_status se_check_faults(void *obj, int32_t kind, void *stream, uint32_t *bits) {
+    if (!obj || !bits || kind != 0) {
+        set_error("se_check_faults: bad argument");
+        return SE_ERR_ARG;
+    }
+    se_mesh *m = static_cast<se_mesh *>(obj);
+    SE_TRY(check_device(m));
+    DeviceGuard dg(m->device);
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    HIP_TRY(hipStreamSynchronize(s), "se_check_faults sync");
+    uint32_t v = 0;
+    HIP_TRY(hipMemcpy(&v, m->d.faults.p, 4, hipMemcpyDeviceToHost), "se_check_faults copy");
+    const uint32_t zero = 0;
+    HIP_TRY(hipMemcpy(m->d.faults.p, &zero, 4, hipMemcpyHostToDevice), "se_check_faults reset");
+    *bits = v;
+    return SE_OK;
+}
+
+se_status se_subcycle_adjoint(se_mesh *, const se_params *, const void *, const void *,
+                              const se_forcing *, int32_t, double, int32_t, const void *,
+                              const void *, const double *, void *, void *, void *, void *,
+                              void *, void *) {
+    set_error("se_subcycle_adjoint: not built yet");
+    return SE_ERR_UNSUPPORTED;
+}
+
+se_status se_batch_create(se_mesh *const *, int32_t, se_batch **out) {
+    if (out) *out = nullptr;
+    set_error("se_batch_create: not built yet");
+    return SE_ERR_UNSUPPORTED;
+}
+void se_batch_destroy(se_batch *) {}
+se_status se_batch_info(const se_batch *, int64_t *, int64_t *, int64_t *, int64_t *) {
+    return SE_ERR_UNSUPPORTED;
+}
+se_status se_batch_workspace_bytes(const se_batch *, const se_params *, const int32_t *, size_t *) {
+    return SE_ERR_UNSUPPORTED;
+}
+se_status se_subcycle_batched(se_batch *, const se_params *, se_state *, const se_forcing *,
+                              const int32_t *, const double *, int, void *, void *) {
+    return SE_ERR_UNSUPPORTED;
+}
+
+}  // extern "C"

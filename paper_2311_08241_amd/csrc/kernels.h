@@ -1,0 +1,70 @@
+// Kernel-side argument blocks shared by kernels.hip and the host launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace sesub {
+
+// Constants of one member's subcycle (one baroclinic step).
+struct StepC {
+    double dts, g, theta, opt, thM, Mdbl, eta_ref;   // opt = 1 + theta, thM = theta / M
+    float dts_f, g_f, theta_f, opt_f, eta_ref_f, pad_f;
+    int32_t nsub, flags, ntiles, pad_i;
+    int64_t vol_off;    // offset of this member's volume partials
+};
+
+enum : int32_t { KF_LINEAR_H = 1, KF_TRACK_VOLUME = 4 };
+
+struct TileHdrK {   // mirror of TileHdr (same layout)
+    int32_t vbase, nv0, ebase, nown, lv_off, le_off, cs_off, rw_off, member, mtile, p0, p1;
+};
+
+struct TileArgs {
+    const TileHdrK *hdr;
+    const int32_t *nV, *nE, *lv_gid, *le_gid;
+    const uint32_t *le_tri;
+    const uint16_t *cs_row, *cs_ent;
+    const void *lgeom;          // 5 SoA arrays, stride lgeom_stride elements
+    int64_t lgeom_stride;
+    const StepC *mem;           // per-member constants (batches); nullptr: use c0
+    StepC c0;
+    const void *eta_in;
+    void *eta_out;
+    const void *U_in;
+    void *U_out;
+    const void *R, *f, *H0, *W, *Av;
+    const double *Av64;
+    void *sum;                  // double2 (FP64) or float4 (FP32 hi/lo pairs) per triangle
+    void *U0c;                  // copy of U^0
+    double *Uavg;
+    double *vol_part;
+    uint32_t *faults;
+    int32_t K, chunk, ntiles, xcd;
+    int32_t cap_nv, cap_ne, cap_nvu, cap_cs;
+};
+
+struct PlainArgs {
+    int64_t nv, ne;
+    const int32_t *tri, *row_ptr, *pcol;
+    const void *geom;           // 5 SoA arrays [ne]
+    const void *H0, *R, *f, *W, *Av;
+    const double *Av64;
+    void *eta, *U, *phi, *sum, *U0c;
+    double *Uavg, *vol_part;
+    uint32_t *faults;
+    StepC c;
+    int32_t m;                  // substep index 0..nsub-1
+    int32_t nblk_v;             // blocks of the vertex launch (volume row width)
+};
+
+// Host launchers (kernels.hip)
+hipError_t launch_tile(bool f32, int ept, int block, const TileArgs &a, int grid, size_t lds,
+                       hipStream_t s);
+hipError_t launch_plain_step(bool f32, const PlainArgs &a, hipStream_t s);
+hipError_t launch_vol_reduce(const double *part, int64_t width, int32_t rows, double add,
+                             double *out, hipStream_t s);
+int tile_lds_bytes(bool f32, int block, int K, int cap_nv, int cap_ne, int cap_nvu, int cap_cs);
+
+}  // namespace sesub

@@ -1,0 +1,524 @@
+// HIP kernels (gfx950, wave64) of the split-explicit barotropic subcycle.
+//
+// One substep (Banerjee et al., arXiv 2311.08241, Sec. 2.2, eq. (eq4_10),
+// pressure sign of eq. (eq4_5)):
+//   triangle phase  grad eta (P1, difference form), H = mean(H0 + eta),
+//                   U' = (I + aJ)^-1 [(I - aJ) U + dt_s(-g H grad eta + R)],
+//                   a = f dt_s / 2, J = e_z x;  F = (1+theta) U' - theta U;
+//                   flux of F through each vertex's median-dual sub-cell
+//                   boundary inside the triangle: phi_k = F . (-A_e grad N_k)
+//   vertex phase    eta' = eta - dt_s (sum_k phi / A_v + W), summed over the
+//                   vertex's triangles in ascending triangle order
+// plus the running sum of U' for the averaged transport of eq. (eq4_12) and
+// the volume sum_v A_v eta_v.
+//
+// All floating-point code is compiled without FMA contraction so that every
+// path (plain, any tile plan) performs the same IEEE operations in the same
+// order: FP64 results do not depend on the plan.
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+
+namespace sesub {
+
+namespace {
+
+template <typename T> struct Vec2;
+template <> struct Vec2<double> { using type = double2; };
+template <> struct Vec2<float> { using type = float2; };
+
+template <typename T> __device__ __forceinline__ T cdts(const StepC &c);
+template <> __device__ __forceinline__ double cdts<double>(const StepC &c) { return c.dts; }
+template <> __device__ __forceinline__ float cdts<float>(const StepC &c) { return c.dts_f; }
+template <typename T> __device__ __forceinline__ T cg(const StepC &c);
+template <> __device__ __forceinline__ double cg<double>(const StepC &c) { return c.g; }
+template <> __device__ __forceinline__ float cg<float>(const StepC &c) { return c.g_f; }
+template <typename T> __device__ __forceinline__ T cth(const StepC &c);
+template <> __device__ __forceinline__ double cth<double>(const StepC &c) { return c.theta; }
+template <> __device__ __forceinline__ float cth<float>(const StepC &c) { return c.theta_f; }
+template <typename T> __device__ __forceinline__ T copt(const StepC &c);
+template <> __device__ __forceinline__ double copt<double>(const StepC &c) { return c.opt; }
+template <> __device__ __forceinline__ float copt<float>(const StepC &c) { return c.opt_f; }
+
+// Per-triangle update.  ea..ec: eta at the vertices (FP64: absolute; FP32:
+// deviation from eta_ref), ha..hc: H0.  Returns U' and the three sub-cell
+// fluxes; dry is set when the triangle's total depth is not positive.
+template <typename T, bool F32>
+__device__ __forceinline__ void tri_update(T ea, T eb, T ec, T ha, T hb, T hc, T gbx, T gby,
+                                           T gcx, T gcy, T Ae, T Ux, T Uy, T Rx, T Ry, T fc,
+                                           const StepC &c, bool linear_h, T &Unx, T &Uny,
+                                           T &pa, T &pb, T &pc, bool &dry) {
+    const T dts = cdts<T>(c), g = cg<T>(c), th = cth<T>(c), opt = copt<T>(c);
+    const T db = eb - ea, dc = ec - ea;
+    const T gx = db * gbx + dc * gcx;
+    const T gy = db * gby + dc * gcy;
+    T He;
+    if (linear_h) {
+        He = (ha + hb + hc) / T(3);
+    } else if (!F32) {
+        He = ((ha + ea) + (hb + eb) + (hc + ec)) / T(3);
+    } else {
+        He = ((ha + hb + hc) + (ea + eb + ec)) / T(3) + c.eta_ref_f;
+    }
+    dry = !(He > T(0));
+    const T al = T(0.5) * fc * dts;
+    const T rx = Ux + al * Uy + dts * (-g * He * gx + Rx);
+    const T ry = Uy - al * Ux + dts * (-g * He * gy + Ry);
+    const T den = T(1) + al * al;
+    Unx = (rx + al * ry) / den;
+    Uny = (ry - al * rx) / den;
+    const T Fx = opt * Unx - th * Ux;
+    const T Fy = opt * Uny - th * Uy;
+    const T gax = -(gbx + gcx), gay = -(gby + gcy);
+    pa = Fx * (-Ae * gax) + Fy * (-Ae * gay);
+    pb = Fx * (-Ae * gbx) + Fy * (-Ae * gby);
+    pc = Fx * (-Ae * gcx) + Fy * (-Ae * gcy);
+}
+
+// Error-free accumulation s + e += x (two-sum), for the FP32 running sum.
+__device__ __forceinline__ void two_sum_acc(float &s, float &e, float x) {
+    const float t = s + x;
+    const float bp = t - s;
+    e += (s - (t - bp)) + (x - bp);
+    s = t;
+}
+
+// Running-sum storage: FP64 keeps (sx, sy); FP32 keeps hi/lo pairs.
+template <bool F32> struct SumT;
+template <> struct SumT<false> {
+    double x, y;
+    __device__ __forceinline__ void init(double ux, double uy) { x = ux; y = uy; }
+    __device__ __forceinline__ void add(double ux, double uy) { x += ux; y += uy; }
+    __device__ __forceinline__ void load(const void *p, int64_t i) {
+        const double2 v = static_cast<const double2 *>(p)[i];
+        x = v.x;
+        y = v.y;
+    }
+    __device__ __forceinline__ void store(void *p, int64_t i) const {
+        static_cast<double2 *>(p)[i] = make_double2(x, y);
+    }
+    __device__ __forceinline__ double vx() const { return x; }
+    __device__ __forceinline__ double vy() const { return y; }
+};
+template <> struct SumT<true> {
+    float x, y, ex, ey;
+    __device__ __forceinline__ void init(float ux, float uy) { x = ux; y = uy; ex = 0.f; ey = 0.f; }
+    __device__ __forceinline__ void add(float ux, float uy) { two_sum_acc(x, ex, ux); two_sum_acc(y, ey, uy); }
+    __device__ __forceinline__ void load(const void *p, int64_t i) {
+        const float4 v = static_cast<const float4 *>(p)[i];
+        x = v.x;
+        y = v.y;
+        ex = v.z;
+        ey = v.w;
+    }
+    __device__ __forceinline__ void store(void *p, int64_t i) const {
+        static_cast<float4 *>(p)[i] = make_float4(x, y, ex, ey);
+    }
+    __device__ __forceinline__ double vx() const { return (double)x + (double)ex; }
+    __device__ __forceinline__ double vy() const { return (double)y + (double)ey; }
+};
+
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ void set_fault(uint32_t *faults, uint32_t bit) {
+    atomicOr(faults, bit);
+}
+
+template <typename T> __device__ __forceinline__ bool finite_val(T v) { return isfinite(v); }
+
+// ---------------------------------------------------------------------------
+// Plain two-kernel path
+// ---------------------------------------------------------------------------
+template <typename T, bool F32>
+__global__ void __launch_bounds__(256) k_plain_tri(PlainArgs a) {
+    using T2 = typename Vec2<T>::type;
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= a.ne) return;
+    const StepC &c = a.c;
+    const T *eta = static_cast<const T *>(a.eta);
+    const T *H0 = static_cast<const T *>(a.H0);
+    const T *geom = static_cast<const T *>(a.geom);
+    const int32_t va = a.tri[3 * e], vb = a.tri[3 * e + 1], vc = a.tri[3 * e + 2];
+    T2 *U = static_cast<T2 *>(a.U);
+    const T2 u = U[e];
+    const T2 r = static_cast<const T2 *>(a.R)[e];
+    const T fc = static_cast<const T *>(a.f)[e];
+    T Unx, Uny, pa, pb, pc;
+    bool dry;
+    tri_update<T, F32>(eta[va], eta[vb], eta[vc], H0[va], H0[vb], H0[vc], geom[e],
+                       geom[a.ne + e], geom[2 * a.ne + e], geom[3 * a.ne + e],
+                       geom[4 * a.ne + e], u.x, u.y, r.x, r.y, fc, c,
+                       (c.flags & KF_LINEAR_H) != 0, Unx, Uny, pa, pb, pc, dry);
+    if (dry) set_fault(a.faults, 1u);
+    T *phi = static_cast<T *>(a.phi);
+    phi[3 * e] = pa;
+    phi[3 * e + 1] = pb;
+    phi[3 * e + 2] = pc;
+    T2 un;
+    un.x = Unx;
+    un.y = Uny;
+    U[e] = un;
+    const bool first = a.m == 0, last = a.m == c.nsub - 1;
+    SumT<F32> s;
+    if (first) {
+        s.init(Unx, Uny);
+        static_cast<T2 *>(a.U0c)[e] = u;
+    } else {
+        s.load(a.sum, e);
+        s.add(Unx, Uny);
+    }
+    if (last) {
+        if (!a.Uavg) return;
+        const T2 u0 = first ? u : static_cast<const T2 *>(a.U0c)[e];
+        a.Uavg[2 * e] = s.vx() / c.Mdbl + c.thM * ((double)Unx - (double)u0.x);
+        a.Uavg[2 * e + 1] = s.vy() / c.Mdbl + c.thM * ((double)Uny - (double)u0.y);
+    } else {
+        s.store(a.sum, e);
+    }
+}
+
+template <typename T, bool F32>
+__global__ void __launch_bounds__(256) k_plain_vtx(PlainArgs a) {
+    __shared__ double red[2][4];
+    const int64_t v = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const StepC &c = a.c;
+    const bool first = a.m == 0, last = a.m == c.nsub - 1;
+    const bool track = (c.flags & KF_TRACK_VOLUME) != 0;
+    double v_new = 0.0, v_old = 0.0;
+    if (v < a.nv) {
+        T *eta = static_cast<T *>(a.eta);
+        const T *phi = static_cast<const T *>(a.phi);
+        T acc = T(0);
+        const int32_t j1 = a.row_ptr[v + 1];
+        for (int32_t j = a.row_ptr[v]; j < j1; ++j) acc += phi[a.pcol[j]];
+        const T eo = eta[v];
+        const T wv = a.W ? static_cast<const T *>(a.W)[v] : T(0);
+        const T en = eo - cdts<T>(c) * (acc / static_cast<const T *>(a.Av)[v] + wv);
+        eta[v] = en;
+        if (!finite_val(en)) set_fault(a.faults, 2u);
+        const double av = a.Av64[v];
+        v_new = av * (double)en;
+        v_old = av * (double)eo;
+    }
+    if (!(track || first || last)) return;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    v_new = wave_sum(v_new);
+    v_old = wave_sum(v_old);
+    if (lane == 0) {
+        red[0][w] = v_new;
+        red[1][w] = v_old;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double sn = ((red[0][0] + red[0][1]) + (red[0][2] + red[0][3]));
+        const int64_t row = track ? (a.m + 1) : 1;
+        if (track || last) a.vol_part[row * a.nblk_v + blockIdx.x] = sn;
+        if (first) a.vol_part[blockIdx.x] = ((red[1][0] + red[1][1]) + (red[1][2] + red[1][3]));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Temporally blocked tile kernel: up to K substeps of one tile per launch
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int align16(int b) { return (b + 15) & ~15; }
+
+template <typename T, bool F32, int EPT, int BLOCK>
+__global__ void __launch_bounds__(BLOCK) k_tile(TileArgs a) {
+    using T2 = typename Vec2<T>::type;
+    constexpr int NW = BLOCK / 64;
+    extern __shared__ __align__(16) unsigned char smem[];
+    int b = blockIdx.x;
+    if (a.xcd) {
+        // consecutive tiles on the same XCD (blocks are dealt round-robin to 8 XCDs)
+        const int G = gridDim.x, x = b & 7, q = b >> 3;
+        const int base = G >> 3, rem = G & 7;
+        b = x * base + (x < rem ? x : rem) + q;
+    }
+    if (b >= a.ntiles) return;
+    const TileHdrK h = a.hdr[b];
+    const StepC c = a.mem ? a.mem[h.member] : a.c0;
+    const int K = a.K;
+    const int m0 = a.chunk * K;
+    if (m0 >= c.nsub) return;
+    const int cnt = min(K, c.nsub - m0);
+    const bool first = m0 == 0, last = m0 + cnt == c.nsub;
+    const bool track = (c.flags & KF_TRACK_VOLUME) != 0;
+    const bool linear_h = (c.flags & KF_LINEAR_H) != 0;
+    const bool hasW = a.W != nullptr;
+    const int *nV = a.nV + b * (K + 1);
+    const int *nE = a.nE + b * (K + 1);
+    const int nv_load = nV[cnt], ne_load = nE[cnt], nvu = nV[cnt - 1];
+    const int tid = threadIdx.x;
+
+    // LDS carve-up
+    int off = 0;
+    double *red = reinterpret_cast<double *>(smem + off);
+    off = align16(off + 8 * NW * 9);
+    T *sEta = reinterpret_cast<T *>(smem + off);
+    off = align16(off + (int)sizeof(T) * a.cap_nv);
+    T *sH = reinterpret_cast<T *>(smem + off);
+    off = align16(off + (int)sizeof(T) * a.cap_nv);
+    T *sAv = reinterpret_cast<T *>(smem + off);
+    off = align16(off + (int)sizeof(T) * a.cap_nvu);
+    T *sW = reinterpret_cast<T *>(smem + off);
+    off = align16(off + (int)sizeof(T) * a.cap_nvu);
+    T *sPhi = reinterpret_cast<T *>(smem + off);
+    off = align16(off + (int)sizeof(T) * 3 * a.cap_ne);
+    uint16_t *sRow = reinterpret_cast<uint16_t *>(smem + off);
+    off = align16(off + 2 * (a.cap_nvu + 1));
+    uint16_t *sEnt = reinterpret_cast<uint16_t *>(smem + off);
+
+    const T *eta_in = static_cast<const T *>(a.eta_in);
+    const T *H0 = static_cast<const T *>(a.H0);
+    const T *Avt = static_cast<const T *>(a.Av);
+    const T *Wt = static_cast<const T *>(a.W);
+    const int32_t *lv = a.lv_gid + h.lv_off;
+    for (int i = tid; i < nv_load; i += BLOCK) {
+        const int g = lv[i];
+        sEta[i] = eta_in[g];
+        sH[i] = H0[g];
+        if (i < nvu) {
+            sAv[i] = Avt[g];
+            sW[i] = hasW ? Wt[g] : T(0);
+        }
+    }
+    const uint16_t *crow = a.cs_row + h.rw_off;
+    for (int i = tid; i <= nvu; i += BLOCK) sRow[i] = crow[i];
+    const int nent = crow[nvu];
+    const uint16_t *cent = a.cs_ent + h.cs_off;
+    for (int i = tid; i < nent; i += BLOCK) sEnt[i] = cent[i];
+
+    // triangle state in registers
+    const T *lg = static_cast<const T *>(a.lgeom) + h.le_off;
+    const int64_t ls = a.lgeom_stride;
+    const T2 *Uin = static_cast<const T2 *>(a.U_in);
+    const T2 *Rg = static_cast<const T2 *>(a.R);
+    const T *fg = static_cast<const T *>(a.f);
+    T rUx[EPT], rUy[EPT], rRx[EPT], rRy[EPT], rf[EPT], g0[EPT], g1[EPT], g2[EPT], g3[EPT], g4[EPT];
+    uint32_t t0[EPT], t1[EPT];
+    int gid[EPT];
+    SumT<F32> sm[EPT];
+#pragma unroll
+    for (int r = 0; r < EPT; ++r) {
+        const int le = tid + r * BLOCK;
+        if (le < ne_load) {
+            const int g = a.le_gid[h.le_off + le];
+            gid[r] = g;
+            t0[r] = a.le_tri[2 * (h.le_off + le)];
+            t1[r] = a.le_tri[2 * (h.le_off + le) + 1];
+            g0[r] = lg[le];
+            g1[r] = lg[ls + le];
+            g2[r] = lg[2 * ls + le];
+            g3[r] = lg[3 * ls + le];
+            g4[r] = lg[4 * ls + le];
+            const T2 u = Uin[g];
+            rUx[r] = u.x;
+            rUy[r] = u.y;
+            const T2 rr = Rg[g];
+            rRx[r] = rr.x;
+            rRy[r] = rr.y;
+            rf[r] = fg[g];
+            if (le < h.nown) {
+                if (first)
+                    static_cast<T2 *>(a.U0c)[g] = u;
+                else
+                    sm[r].load(a.sum, g);
+            }
+        }
+    }
+    __syncthreads();
+
+    double v0 = 0.0;
+    if (first) {
+        for (int i = tid; i < h.nv0; i += BLOCK) v0 += a.Av64[h.vbase + i] * (double)sEta[i];
+    }
+    bool dry_any = false, bad_any = false;
+    const T dts = cdts<T>(c);
+    for (int j = 0; j < cnt; ++j) {
+        const int lev = cnt - j;
+        const int ne_act = nE[lev], nv_act = nV[lev - 1];
+#pragma unroll
+        for (int r = 0; r < EPT; ++r) {
+            const int le = tid + r * BLOCK;
+            if (le < ne_act) {
+                const int ia = t0[r] & 0xffffu, ib = t0[r] >> 16, ic = t1[r];
+                T Unx, Uny, pa, pb, pc;
+                bool dry;
+                tri_update<T, F32>(sEta[ia], sEta[ib], sEta[ic], sH[ia], sH[ib], sH[ic], g0[r],
+                                   g1[r], g2[r], g3[r], g4[r], rUx[r], rUy[r], rRx[r], rRy[r],
+                                   rf[r], c, linear_h, Unx, Uny, pa, pb, pc, dry);
+                dry_any |= dry;
+                sPhi[3 * le] = pa;
+                sPhi[3 * le + 1] = pb;
+                sPhi[3 * le + 2] = pc;
+                rUx[r] = Unx;
+                rUy[r] = Uny;
+                if (le < h.nown) {
+                    if (first && j == 0)
+                        sm[r].init(Unx, Uny);
+                    else
+                        sm[r].add(Unx, Uny);
+                }
+            }
+        }
+        __syncthreads();
+        double vp = 0.0;
+        for (int i = tid; i < nv_act; i += BLOCK) {
+            T acc = T(0);
+            const int q1 = sRow[i + 1];
+            for (int q = sRow[i]; q < q1; ++q) acc += sPhi[sEnt[q]];
+            const T en = sEta[i] - dts * (acc / sAv[i] + sW[i]);
+            sEta[i] = en;
+            bad_any |= !finite_val(en);
+            if (i < h.nv0) vp += a.Av64[h.vbase + i] * (double)en;
+        }
+        if (track || (last && j == cnt - 1)) {
+            vp = wave_sum(vp);
+            if ((tid & 63) == 0) red[j * NW + (tid >> 6)] = vp;
+        }
+        __syncthreads();
+    }
+    if (dry_any) set_fault(a.faults, 1u);
+    if (bad_any) set_fault(a.faults, 2u);
+
+    // write back owned vertices and triangles
+    T *eta_out = static_cast<T *>(a.eta_out);
+    for (int i = tid; i < h.nv0; i += BLOCK) eta_out[h.vbase + i] = sEta[i];
+    T2 *Uout = static_cast<T2 *>(a.U_out);
+#pragma unroll
+    for (int r = 0; r < EPT; ++r) {
+        const int le = tid + r * BLOCK;
+        if (le < ne_load) {
+            const int g = gid[r];
+            if (le < h.nown) {
+                T2 u;
+                u.x = rUx[r];
+                u.y = rUy[r];
+                Uout[g] = u;
+                if (last) {
+                    if (!a.Uavg) continue;
+                    const T2 u0 = static_cast<const T2 *>(a.U0c)[g];
+                    a.Uavg[2 * g] = sm[r].vx() / c.Mdbl + c.thM * ((double)u.x - (double)u0.x);
+                    a.Uavg[2 * g + 1] = sm[r].vy() / c.Mdbl + c.thM * ((double)u.y - (double)u0.y);
+                } else {
+                    sm[r].store(a.sum, g);
+                }
+            }
+        }
+    }
+    // volume partials of this tile
+    if (first) {
+        v0 = wave_sum(v0);
+        if ((tid & 63) == 0) red[8 * NW + (tid >> 6)] = v0;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double *vp = a.vol_part + c.vol_off;
+        if (first) {
+            double s = 0.0;
+            for (int w = 0; w < NW; ++w) s += red[8 * NW + w];
+            vp[h.mtile] = s;
+        }
+        for (int j = 0; j < cnt; ++j) {
+            const bool keep = track || (last && j == cnt - 1);
+            if (!keep) continue;
+            double s = 0.0;
+            for (int w = 0; w < NW; ++w) s += red[j * NW + w];
+            const int64_t row = track ? (m0 + j + 1) : 1;
+            vp[row * c.ntiles + h.mtile] = s;
+        }
+    }
+}
+
+// Deterministic sum of each row of partials: out[r] = add + sum_i part[r*width + i].
+__global__ void __launch_bounds__(256) k_vol_reduce(const double *part, int64_t width,
+                                                    double add, double *out) {
+    __shared__ double red[4];
+    const int r = blockIdx.x;
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < width; i += 256) s += part[r * width + i];
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) out[r] = add + ((red[0] + red[1]) + (red[2] + red[3]));
+}
+
+template <typename T, bool F32, int EPT, int BLOCK>
+hipError_t launch_tile_t(const TileArgs &a, int grid, size_t lds, hipStream_t s) {
+    auto *kern = k_tile<T, F32, EPT, BLOCK>;
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(BLOCK), lds, s, a);
+    return hipGetLastError();
+}
+
+template <typename T, bool F32, int BLOCK>
+hipError_t launch_tile_ept(int ept, const TileArgs &a, int grid, size_t lds, hipStream_t s) {
+    switch (ept) {
+        case 1: return launch_tile_t<T, F32, 1, BLOCK>(a, grid, lds, s);
+        case 2: return launch_tile_t<T, F32, 2, BLOCK>(a, grid, lds, s);
+        case 3: return launch_tile_t<T, F32, 3, BLOCK>(a, grid, lds, s);
+        case 4: return launch_tile_t<T, F32, 4, BLOCK>(a, grid, lds, s);
+        case 6: return launch_tile_t<T, F32, 6, BLOCK>(a, grid, lds, s);
+        case 8: return launch_tile_t<T, F32, 8, BLOCK>(a, grid, lds, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+int tile_lds_bytes(bool f32, int block, int K, int cap_nv, int cap_ne, int cap_nvu, int cap_cs) {
+    (void)K;
+    const int ts = f32 ? 4 : 8;
+    int off = 0;
+    auto al = [](int b) { return (b + 15) & ~15; };
+    off = al(off + 8 * (block / 64) * 9);
+    off = al(off + ts * cap_nv);
+    off = al(off + ts * cap_nv);
+    off = al(off + ts * cap_nvu);
+    off = al(off + ts * cap_nvu);
+    off = al(off + ts * 3 * cap_ne);
+    off = al(off + 2 * (cap_nvu + 1));
+    off = al(off + 2 * cap_cs);
+    return off;
+}
+
+hipError_t launch_tile(bool f32, int ept, int block, const TileArgs &a, int grid, size_t lds,
+                       hipStream_t s) {
+    if (block == 256)
+        return f32 ? launch_tile_ept<float, true, 256>(ept, a, grid, lds, s)
+                   : launch_tile_ept<double, false, 256>(ept, a, grid, lds, s);
+    if (block == 512)
+        return f32 ? launch_tile_ept<float, true, 512>(ept, a, grid, lds, s)
+                   : launch_tile_ept<double, false, 512>(ept, a, grid, lds, s);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_plain_step(bool f32, const PlainArgs &a, hipStream_t s) {
+    const int ge = static_cast<int>((a.ne + 255) / 256), gv = static_cast<int>((a.nv + 255) / 256);
+    if (f32) {
+        hipLaunchKernelGGL((k_plain_tri<float, true>), dim3(ge), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((k_plain_vtx<float, true>), dim3(gv), dim3(256), 0, s, a);
+    } else {
+        hipLaunchKernelGGL((k_plain_tri<double, false>), dim3(ge), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((k_plain_vtx<double, false>), dim3(gv), dim3(256), 0, s, a);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_vol_reduce(const double *part, int64_t width, int32_t rows, double add,
+                             double *out, hipStream_t s) {
+    if (rows <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_vol_reduce, dim3(rows), dim3(256), 0, s, part, width, add, out);
+    return hipGetLastError();
+}
+
+}  // namespace sesub

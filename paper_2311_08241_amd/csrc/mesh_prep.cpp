@@ -1,0 +1,386 @@
+// Host-side mesh preparation: validation, space-filling-curve reordering,
+// vertex->triangle CSR, FP64 geometry, spectral bound, and the tile level
+// sets of the temporally blocked kernel.  Built with -ffp-contract=off so the
+// geometry is the plain IEEE evaluation of its formulas.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <tuple>
+
+#include "se_internal.h"
+
+namespace sesub {
+
+namespace {
+
+// Hilbert index of cell (x, y) on a side x side grid (side a power of two):
+// per bit level, quadrant code (3 rx) xor ry, then the sub-square is mapped
+// back to the canonical orientation (flip when rx and not ry, transpose when
+// not ry).
+uint64_t hilbert_index(uint32_t side, uint32_t x, uint32_t y) {
+    uint64_t d = 0;
+    uint32_t s = side >> 1;
+    while (s) {
+        const uint32_t rx = (x & s) != 0u, ry = (y & s) != 0u;
+        d += static_cast<uint64_t>(s) * s * ((3u * rx) ^ ry);
+        if (!ry) {
+            if (rx) {
+                x = side - 1u - x;
+                y = side - 1u - y;
+            }
+            std::swap(x, y);
+        }
+        s >>= 1;
+    }
+    return d;
+}
+
+inline uint32_t q16(double v, double lo, double scale) {
+    double q = std::floor((v - lo) * scale);
+    q = q < 0.0 ? 0.0 : (q > 65535.0 ? 65535.0 : q);
+    return static_cast<uint32_t>(q);
+}
+
+inline double wrap_period(double d, double per) {
+    if (d > 0.5 * per) return d - per;
+    if (d <= -0.5 * per) return d + per;
+    return d;
+}
+
+}  // namespace
+
+se_status build_host_mesh(const se_mesh_desc &d, HostMesh &m) {
+    if (!d.x || !d.y || !d.tri || d.nv <= 0 || d.ne <= 0) {
+        set_error("se_mesh_create: null array or empty mesh");
+        return SE_ERR_ARG;
+    }
+    if (d.nv >= (int64_t(1) << 31) || d.ne >= (int64_t(1) << 29)) {
+        set_error("se_mesh_create: mesh too large for 32-bit indices");
+        return SE_ERR_ARG;
+    }
+    if ((d.flags & SE_SPHERICAL) && !(d.radius > 0.0)) {
+        set_error("se_mesh_create: spherical mesh needs radius > 0");
+        return SE_ERR_ARG;
+    }
+    if ((d.flags & SE_PERIODIC_X) && !(d.flags & SE_SPHERICAL) && !(d.period_x > 0.0)) {
+        set_error("se_mesh_create: periodic x needs period_x > 0");
+        return SE_ERR_ARG;
+    }
+    if ((d.flags & SE_PERIODIC_Y) && !(d.period_y > 0.0)) {
+        set_error("se_mesh_create: periodic y needs period_y > 0");
+        return SE_ERR_ARG;
+    }
+    const int64_t nv = d.nv, ne = d.ne;
+    m.nv = nv;
+    m.ne = ne;
+    m.flags = d.flags;
+    m.period_x = d.period_x;
+    m.period_y = d.period_y;
+    m.radius = d.radius;
+    for (int64_t i = 0; i < 3 * ne; ++i) {
+        if (d.tri[i] < 0 || d.tri[i] >= nv) {
+            set_error("se_mesh_create: triangle vertex index out of range");
+            return SE_ERR_MESH;
+        }
+    }
+    for (int64_t i = 0; i < nv; ++i) {
+        if (!std::isfinite(d.x[i]) || !std::isfinite(d.y[i])) {
+            set_error("se_mesh_create: non-finite coordinate");
+            return SE_ERR_MESH;
+        }
+    }
+
+    // ---- vertices along the Hilbert curve (key, then input index) ----
+    double xlo = d.x[0], xhi = d.x[0], ylo = d.y[0], yhi = d.y[0];
+    for (int64_t i = 1; i < nv; ++i) {
+        xlo = std::min(xlo, d.x[i]);
+        xhi = std::max(xhi, d.x[i]);
+        ylo = std::min(ylo, d.y[i]);
+        yhi = std::max(yhi, d.y[i]);
+    }
+    const double sx = xhi > xlo ? 65535.0 / (xhi - xlo) : 0.0;
+    const double sy = yhi > ylo ? 65535.0 / (yhi - ylo) : 0.0;
+    std::vector<uint64_t> vkey(nv);
+    for (int64_t i = 0; i < nv; ++i) {
+        const uint64_t h = hilbert_index(65536u, q16(d.x[i], xlo, sx), q16(d.y[i], ylo, sy));
+        vkey[i] = (h << 32) | static_cast<uint64_t>(i);   // h < 2^32, i < 2^31
+    }
+    std::sort(vkey.begin(), vkey.end());
+    m.vperm.resize(nv);
+    std::vector<int32_t> vnew(nv);
+    for (int64_t k = 0; k < nv; ++k) {
+        const int32_t old = static_cast<int32_t>(vkey[k] & 0xffffffffu);
+        m.vperm[k] = old;
+        vnew[old] = static_cast<int32_t>(k);
+    }
+
+    // ---- triangles: smallest vertex first (cyclic), then lexicographic ----
+    struct TK {
+        int32_t a, b, c, src;
+    };
+    std::vector<TK> tk(ne);
+    for (int64_t e = 0; e < ne; ++e) {
+        int32_t v[3] = {vnew[d.tri[3 * e]], vnew[d.tri[3 * e + 1]], vnew[d.tri[3 * e + 2]]};
+        int r = 0;
+        if (v[1] < v[r]) r = 1;
+        if (v[2] < v[r]) r = 2;
+        tk[e] = {v[r], v[(r + 1) % 3], v[(r + 2) % 3], static_cast<int32_t>(e)};
+        if (v[0] == v[1] || v[1] == v[2] || v[0] == v[2]) {
+            set_error("se_mesh_create: triangle with a repeated vertex");
+            return SE_ERR_MESH;
+        }
+    }
+    std::sort(tk.begin(), tk.end(), [](const TK &p, const TK &q) {
+        return std::tie(p.a, p.b, p.c, p.src) < std::tie(q.a, q.b, q.c, q.src);
+    });
+    m.eperm.resize(ne);
+    m.tri.resize(3 * ne);
+    for (int64_t e = 0; e < ne; ++e) {
+        if (e && tk[e].a == tk[e - 1].a && tk[e].b == tk[e - 1].b && tk[e].c == tk[e - 1].c) {
+            set_error("se_mesh_create: duplicate triangle");
+            return SE_ERR_MESH;
+        }
+        m.eperm[e] = tk[e].src;
+        m.tri[3 * e] = tk[e].a;
+        m.tri[3 * e + 1] = tk[e].b;
+        m.tri[3 * e + 2] = tk[e].c;
+    }
+
+    // ---- CSR: counting sort, triangles ascending per vertex ----
+    m.row_ptr.assign(nv + 1, 0);
+    for (int64_t i = 0; i < 3 * ne; ++i) m.row_ptr[m.tri[i] + 1]++;
+    for (int64_t v = 0; v < nv; ++v) m.row_ptr[v + 1] += m.row_ptr[v];
+    m.col.resize(3 * ne);
+    {
+        std::vector<int32_t> cur(m.row_ptr.begin(), m.row_ptr.end() - 1);
+        for (int64_t e = 0; e < ne; ++e)
+            for (int k = 0; k < 3; ++k)
+                m.col[cur[m.tri[3 * e + k]]++] = static_cast<int32_t>((e << 2) | k);
+    }
+    for (int64_t v = 0; v < nv; ++v) {
+        if (m.row_ptr[v + 1] == m.row_ptr[v]) {
+            set_error("se_mesh_create: vertex not used by any triangle");
+            return SE_ERR_MESH;
+        }
+    }
+
+    // ---- FP64 geometry in the new numbering ----
+    m.x.resize(nv);
+    m.y.resize(nv);
+    for (int64_t k = 0; k < nv; ++k) {
+        m.x[k] = d.x[m.vperm[k]];
+        m.y[k] = d.y[m.vperm[k]];
+    }
+    m.Ae.resize(ne);
+    m.gN.resize(6 * ne);
+    m.Av.assign(nv, 0.0);
+    const double two_pi = 2.0 * M_PI;
+    for (int64_t e = 0; e < ne; ++e) {
+        const int32_t a = m.tri[3 * e], b = m.tri[3 * e + 1], c = m.tri[3 * e + 2];
+        double ux = m.x[b] - m.x[a], uy = m.y[b] - m.y[a];
+        double vx = m.x[c] - m.x[a], vy = m.y[c] - m.y[a];
+        if (d.flags & SE_SPHERICAL) {
+            ux = wrap_period(ux, two_pi);
+            vx = wrap_period(vx, two_pi);
+            const double lat = (m.y[a] + m.y[b] + m.y[c]) / 3.0;
+            const double cl = std::cos(lat);
+            ux = d.radius * cl * ux;
+            vx = d.radius * cl * vx;
+            uy = d.radius * uy;
+            vy = d.radius * vy;
+        } else {
+            if (d.flags & SE_PERIODIC_X) {
+                ux = wrap_period(ux, d.period_x);
+                vx = wrap_period(vx, d.period_x);
+            }
+            if (d.flags & SE_PERIODIC_Y) {
+                uy = wrap_period(uy, d.period_y);
+                vy = wrap_period(vy, d.period_y);
+            }
+        }
+        const double det = ux * vy - uy * vx;   // twice the signed area
+        if (!(det > 0.0)) {
+            set_error("se_mesh_create: triangle with non-positive area (orientation)");
+            return SE_ERR_MESH;
+        }
+        m.Ae[e] = 0.5 * det;
+        const double bx = vy / det, by = -vx / det;   // grad of the basis at vertex b
+        const double cx = -uy / det, cy = ux / det;   // ... at vertex c
+        double *g = &m.gN[6 * e];
+        g[0] = -(bx + cx);
+        g[1] = -(by + cy);
+        g[2] = bx;
+        g[3] = by;
+        g[4] = cx;
+        g[5] = cy;
+    }
+    // median-dual areas: each triangle gives a third of its area to each vertex,
+    // accumulated per vertex in ascending triangle order
+    for (int64_t v = 0; v < nv; ++v) {
+        double s = 0.0;
+        for (int32_t j = m.row_ptr[v]; j < m.row_ptr[v + 1]; ++j) s += m.Ae[m.col[j] >> 2] / 3.0;
+        m.Av[v] = s;
+    }
+
+    // ---- Gershgorin bound of K = -D G:  K_vu = (1/A_v) sum_e A_e gN_v . gN_u ----
+    double mu = 0.0;
+    std::vector<std::pair<int32_t, double>> row;
+    for (int64_t v = 0; v < nv; ++v) {
+        row.clear();
+        for (int32_t j = m.row_ptr[v]; j < m.row_ptr[v + 1]; ++j) {
+            const int64_t e = m.col[j] >> 2;
+            const int k = m.col[j] & 3;
+            const double *g = &m.gN[6 * e];
+            for (int l = 0; l < 3; ++l) {
+                const double w = m.Ae[e] * (g[2 * k] * g[2 * l] + g[2 * k + 1] * g[2 * l + 1]);
+                const int32_t u = m.tri[3 * e + l];
+                bool found = false;
+                for (auto &pr : row)
+                    if (pr.first == u) {
+                        pr.second += w;
+                        found = true;
+                        break;
+                    }
+                if (!found) row.emplace_back(u, w);
+            }
+        }
+        double r = 0.0;
+        for (auto &pr : row) r += std::fabs(pr.second);
+        mu = std::max(mu, r / m.Av[v]);
+    }
+    m.mu_max = mu;
+    return SE_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Tiles and their K-ring level sets
+// ---------------------------------------------------------------------------
+se_status build_tiles(const std::vector<const HostMesh *> &members,
+                      const std::vector<int64_t> &voff, const std::vector<int64_t> &eoff,
+                      int32_t T, int32_t K, HostTiles &out) {
+    out = HostTiles();
+    out.T = T;
+    out.K = K;
+    for (size_t mi = 0; mi < members.size(); ++mi) {
+        const HostMesh &m = *members[mi];
+        const int64_t nv = m.nv, ne = m.ne;
+        // first triangle whose smallest vertex is >= v
+        std::vector<int32_t> efirst(nv + 1, static_cast<int32_t>(ne));
+        for (int64_t e = ne - 1; e >= 0; --e) efirst[m.tri[3 * e]] = static_cast<int32_t>(e);
+        for (int64_t v = nv - 1; v >= 0; --v) efirst[v] = std::min(efirst[v], efirst[v + 1]);
+        std::vector<int32_t> vloc(nv, -1), eloc(ne, -1);
+        std::vector<int32_t> lv, le, fresh;
+        const int64_t ntile_m = (nv + T - 1) / T;
+        for (int64_t t = 0; t < ntile_m; ++t) {
+            const int32_t vb = static_cast<int32_t>(t * T);
+            const int32_t nv0 = static_cast<int32_t>(std::min<int64_t>(T, nv - vb));
+            const int32_t eb = efirst[vb], ee = efirst[vb + nv0];
+            lv.clear();
+            le.clear();
+            std::vector<int32_t> nVl(K + 1), nEl(K + 1);
+            for (int32_t v = vb; v < vb + nv0; ++v) {
+                vloc[v] = static_cast<int32_t>(lv.size());
+                lv.push_back(v);
+            }
+            for (int32_t e = eb; e < ee; ++e) {
+                eloc[e] = static_cast<int32_t>(le.size());
+                le.push_back(e);
+            }
+            nVl[0] = nv0;
+            nEl[0] = ee - eb;
+            for (int32_t i = 1; i <= K; ++i) {
+                fresh.clear();
+                for (int32_t q = 0; q < nVl[i - 1]; ++q) {
+                    const int32_t v = lv[q];
+                    for (int32_t j = m.row_ptr[v]; j < m.row_ptr[v + 1]; ++j) {
+                        const int32_t e = m.col[j] >> 2;
+                        if (eloc[e] == -1) {
+                            eloc[e] = -2;   // queued at this level
+                            fresh.push_back(e);
+                        }
+                    }
+                }
+                std::sort(fresh.begin(), fresh.end());
+                const size_t e_from = (i == 1) ? 0 : le.size();
+                for (int32_t e : fresh) {
+                    eloc[e] = static_cast<int32_t>(le.size());
+                    le.push_back(e);
+                }
+                nEl[i] = static_cast<int32_t>(le.size());
+                // new vertices: those of triangles added at this level (all of E_1 at level 1)
+                fresh.clear();
+                for (size_t q = e_from; q < le.size(); ++q)
+                    for (int k = 0; k < 3; ++k) {
+                        const int32_t v = m.tri[3 * le[q] + k];
+                        if (vloc[v] == -1) {
+                            vloc[v] = -2;   // queued at this level
+                            fresh.push_back(v);
+                        }
+                    }
+                std::sort(fresh.begin(), fresh.end());
+                for (int32_t v : fresh) {
+                    vloc[v] = static_cast<int32_t>(lv.size());
+                    lv.push_back(v);
+                }
+                nVl[i] = static_cast<int32_t>(lv.size());
+            }
+            if (nVl[K] > 65535 || 3 * static_cast<int64_t>(nEl[K]) > 65535) {
+                for (int32_t v : lv) vloc[v] = -1;
+                for (int32_t e : le) eloc[e] = -1;
+                set_error("se_set_plan: tile halo too large for 16-bit local indices");
+                return SE_ERR_ARG;
+            }
+            TileHdr h{};
+            h.vbase = static_cast<int32_t>(voff[mi] + vb);
+            h.nv0 = nv0;
+            h.ebase = static_cast<int32_t>(eoff[mi] + eb);
+            h.nown = ee - eb;
+            h.lv_off = static_cast<int32_t>(out.lv_gid.size());
+            h.le_off = static_cast<int32_t>(out.le_gid.size());
+            h.cs_off = static_cast<int32_t>(out.cs_ent.size());
+            h.rw_off = static_cast<int32_t>(out.cs_row.size());
+            h.member = static_cast<int32_t>(mi);
+            h.mtile = static_cast<int32_t>(t);
+            out.hdr.push_back(h);
+            for (int32_t i = 0; i <= K; ++i) {
+                out.nV.push_back(nVl[i]);
+                out.nE.push_back(nEl[i]);
+            }
+            for (int32_t v : lv) out.lv_gid.push_back(static_cast<int32_t>(voff[mi] + v));
+            for (int32_t e : le) {
+                out.le_gid.push_back(static_cast<int32_t>(eoff[mi] + e));
+                const uint32_t a = vloc[m.tri[3 * e]], b = vloc[m.tri[3 * e + 1]],
+                               c = vloc[m.tri[3 * e + 2]];
+                out.le_tri.push_back(a | (b << 16));
+                out.le_tri.push_back(c);
+            }
+            // local CSR of the vertices updated at some inner substep: V_{K-1}
+            const int32_t nvu = nVl[K - 1];
+            const size_t ent0 = out.cs_ent.size();
+            for (int32_t q = 0; q < nvu; ++q) {
+                out.cs_row.push_back(static_cast<uint16_t>(out.cs_ent.size() - ent0));
+                const int32_t v = lv[q];
+                for (int32_t j = m.row_ptr[v]; j < m.row_ptr[v + 1]; ++j) {
+                    const int32_t e = m.col[j] >> 2;
+                    out.cs_ent.push_back(static_cast<uint16_t>(3 * eloc[e] + (m.col[j] & 3)));
+                }
+            }
+            const size_t nent = out.cs_ent.size() - ent0;
+            if (nent > 65535) {
+                set_error("se_set_plan: tile CSR too large for 16-bit offsets");
+                return SE_ERR_ARG;
+            }
+            out.cs_row.push_back(static_cast<uint16_t>(nent));
+            out.max_nv = std::max(out.max_nv, nVl[K]);
+            out.max_ne = std::max(out.max_ne, nEl[K]);
+            out.max_nvu = std::max(out.max_nvu, nvu);
+            out.max_cs = std::max(out.max_cs, static_cast<int32_t>(nent));
+            for (int32_t v : lv) vloc[v] = -1;
+            for (int32_t e : le) eloc[e] = -1;
+        }
+    }
+    return SE_OK;
+}
+
+}  // namespace sesub

@@ -1,0 +1,109 @@
+// Internal structures of the barotropic subcycle library (host side).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/sesub.h"
+
+namespace sesub {
+
+void set_error(const std::string &msg);
+
+// ---------------------------------------------------------------------------
+// Host mesh after reordering: integer connectivity plus FP64 geometry.
+// ---------------------------------------------------------------------------
+struct HostMesh {
+    int64_t nv = 0, ne = 0;
+    uint32_t flags = 0;
+    double period_x = 0, period_y = 0, radius = 0;
+    std::vector<int32_t> vperm, eperm;   // new -> input
+    std::vector<int32_t> tri;            // [ne*3], smallest vertex first
+    std::vector<int32_t> row_ptr, col;   // vertex -> (tri << 2 | slot)
+    std::vector<double> x, y;            // reordered coordinates
+    std::vector<double> Ae, gN, Av;      // gN [ne][3][2]
+    double mu_max = 0;                   // Gershgorin bound of -div grad
+};
+
+// Build the reordered mesh; returns SE_OK or an error with set_error().
+se_status build_host_mesh(const se_mesh_desc &d, HostMesh &m);
+
+// ---------------------------------------------------------------------------
+// Tile plan of the temporally blocked kernel (one mesh or a disjoint union).
+// Tile t owns vertices [vbase, vbase + nv0) and the triangles whose smallest
+// vertex it owns.  Level sets: V_0 = owned vertices, E_i = triangles touching
+// V_{i-1}, V_i = vertices of E_i, i = 1..K.  Local vertex order: V_0, then
+// V_1 \ V_0, ...; local triangle order: owned, E_1 \ owned, E_2 \ E_1, ...
+// ---------------------------------------------------------------------------
+struct TileHdr {
+    int32_t vbase, nv0;     // owned vertex range (global, union numbering)
+    int32_t ebase, nown;    // owned triangle range
+    int32_t lv_off, le_off; // offsets into local vertex / triangle arrays
+    int32_t cs_off, rw_off; // offsets into local CSR entries / rows
+    int32_t member;         // batch member (0 for a single mesh)
+    int32_t mtile;          // tile index within its member
+    int32_t pad0, pad1;
+};
+
+struct HostTiles {
+    int32_t T = 0, K = 0;
+    std::vector<TileHdr> hdr;
+    std::vector<int32_t> nV;      // [ntiles][K+1] cumulative |V_i|
+    std::vector<int32_t> nE;      // [ntiles][K+1] cumulative |E_i| (entry 0 = owned)
+    std::vector<int32_t> lv_gid;  // local vertex -> global vertex
+    std::vector<int32_t> le_gid;  // local triangle -> global triangle
+    std::vector<uint32_t> le_tri; // [2 per local triangle]: a | b << 16, c
+    std::vector<uint16_t> cs_row; // per tile: nV[K-1] + 1 row offsets (local)
+    std::vector<uint16_t> cs_ent; // local triangle * 3 + slot
+    int32_t max_nv = 0, max_ne = 0, max_nvu = 0, max_cs = 0;
+};
+
+se_status build_tiles(const std::vector<const HostMesh *> &members,
+                      const std::vector<int64_t> &voff, const std::vector<int64_t> &eoff,
+                      int32_t T, int32_t K, HostTiles &out);
+
+// ---------------------------------------------------------------------------
+// Device-side arrays
+// ---------------------------------------------------------------------------
+struct DevBuf {
+    void *p = nullptr;
+    size_t n = 0;
+    ~DevBuf();
+    se_status alloc(size_t bytes);
+    se_status upload(const void *src, size_t bytes);
+    template <class T> T *as() const { return static_cast<T *>(p); }
+};
+
+struct DevTiles {
+    int32_t T = 0, K = 0, block = 256, ept = 0, ntiles = 0;
+    int32_t max_nv = 0, max_ne = 0, max_nvu = 0, max_cs = 0;
+    size_t lds_bytes64 = 0, lds_bytes32 = 0;
+    bool ok32 = false, ok64 = false;
+    std::vector<TileHdr> hdr_host;
+    DevBuf hdr, nV, nE, lv_gid, le_gid, le_tri, cs_row, cs_ent;
+    DevBuf geom64, geom32;        // per local triangle, 5 SoA arrays
+};
+
+// Mesh geometry and connectivity on the device (global numbering).
+struct DevMesh {
+    int64_t nv = 0, ne = 0;
+    DevBuf tri, row_ptr, pcol;    // pcol = 3 * tri + slot, CSR order
+    DevBuf geom64, geom32;        // 5 SoA arrays [ne]: gbx gby gcx gcy Ae
+    DevBuf Av64, Av32;
+    DevBuf faults;                // uint32 fault word
+};
+
+}  // namespace sesub
+
+struct se_mesh {
+    int device = 0;
+    sesub::HostMesh h;
+    sesub::DevMesh d;
+    std::unique_ptr<sesub::DevTiles> plan;
+    int32_t plan_T = 1024, plan_K = 4, plan_block = 256;
+};

@@ -1,0 +1,143 @@
+"""Host-side checks of the GPU library that need no GPU.
+
+The library is loaded and its exported symbols checked against the header;
+meshes are created host-only (device -1), which runs the library's own
+reordering and FP64 geometry, and compared integer for integer with the
+oracle's independent implementation.  Argument and CFL errors are forced from
+the host.
+"""
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle
+import sesynth
+from oracle import brute
+from paper_2311_08241_amd import _lib as L
+from paper_2311_08241_amd import Mesh, Params
+
+
+def test_library_exports_every_header_function():
+    lib = L.lib()
+    names = L.header_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def _cases():
+    yield "jitter76", sesynth.tiny_mesh("jitter76")
+    yield "chan54", sesynth.tiny_mesh("chan54")
+    yield "sphere86", sesynth.tiny_mesh("sphere86")
+    yield "torus43", sesynth.tiny_mesh("torus43")
+    yield "C1", sesynth.basin_c1()
+    yield "C2small", sesynth.channel_c2(nx=96, ny=40, nsteps=1)
+    yield "C3small", sesynth.latlon_c3(nlon=128, nlat=96, nsteps=1)
+    yield "C5small", sesynth.adjoint_c5(n=48)
+
+
+@pytest.mark.parametrize("name,mesh", list(_cases()))
+def test_reorder_and_geometry_match_oracle_exactly(name, mesh):
+    m = Mesh.from_dict(mesh, device=-1)
+    vperm, eperm, tri, row, col = oracle.reorder(mesh)
+    assert np.array_equal(m.vperm, vperm) and np.array_equal(m.eperm, eperm)
+    t2, r2, c2 = m.csr()
+    assert np.array_equal(t2, tri) and np.array_equal(r2, row) and np.array_equal(c2, col)
+    Av, Ae, gN = m.geometry()
+    om = oracle.Mesh(mesh, reordered=True)
+    assert np.array_equal(Av, om.Av) and np.array_equal(Ae, om.Ae) and np.array_equal(gN, om.gN)
+
+
+@pytest.mark.parametrize("kind", ["jitter65", "chan54", "torus43", "grid3"])
+def test_mu_max_bounds_the_spectrum(kind):
+    mesh = sesynth.tiny_mesh(kind)
+    m = Mesh.from_dict(mesh, device=-1)
+    ops = brute.dense_operators(mesh)
+    mu = np.linalg.eigvals(-ops["D"] @ ops["G"]).real.max()
+    assert m.mu_max >= mu * (1 - 1e-12)
+    assert m.mu_max <= 3.0 * mu
+
+
+def test_mu_max_is_tight_on_a_split_torus():
+    t = sesynth.torus(8, 6, 1000.0, 1300.0)
+    m = Mesh.from_dict(t, device=-1)
+    expect = 4 / 1000.0 ** 2 + 4 / 1300.0 ** 2     # 5-point Laplacian at the Nyquist mode
+    assert abs(m.mu_max - expect) <= 1e-12 * expect
+
+
+def _desc(x, y, tri, flags=0, px=0.0, py=0.0, radius=0.0):
+    x = np.ascontiguousarray(x, np.float64)
+    y = np.ascontiguousarray(y, np.float64)
+    tri = np.ascontiguousarray(tri, np.int32)
+    d = L.MeshDesc(x.size, tri.shape[0], x.ctypes.data_as(ctypes.c_void_p),
+                   y.ctypes.data_as(ctypes.c_void_p), tri.ctypes.data_as(ctypes.c_void_p),
+                   flags, px, py, radius)
+    return d, (x, y, tri)
+
+
+def _create(d):
+    h = ctypes.c_void_p()
+    st = L.lib().se_mesh_create(ctypes.byref(d), -1, ctypes.byref(h))
+    if st == 0:
+        L.lib().se_mesh_destroy(h)
+    return st
+
+
+def test_mesh_errors():
+    x = [0.0, 1.0, 1.0, 0.0]
+    y = [0.0, 0.0, 1.0, 1.0]
+    assert _create(_desc(x, y, [[0, 1, 2], [0, 2, 3]])[0]) == L.SE_OK
+    assert _create(_desc(x, y, [[0, 1, 2], [0, 2, 4]])[0]) == L.SE_ERR_MESH      # index range
+    assert _create(_desc(x, y, [[0, 2, 1], [0, 2, 3]])[0]) == L.SE_ERR_MESH      # clockwise
+    assert _create(_desc(x, y, [[0, 1, 2], [1, 2, 0]])[0]) == L.SE_ERR_MESH      # duplicate
+    assert _create(_desc(x, y, [[0, 1, 1], [0, 2, 3]])[0]) == L.SE_ERR_MESH      # repeated vertex
+    assert _create(_desc(x + [5.0], y + [5.0], [[0, 1, 2], [0, 2, 3]])[0]) == L.SE_ERR_MESH  # orphan
+    assert _create(_desc(x, y, np.zeros((0, 3)))[0]) == L.SE_ERR_ARG
+    assert _create(_desc(x, y, [[0, 1, 2], [0, 2, 3]], flags=L.SE_SPHERICAL)[0]) == L.SE_ERR_ARG
+    assert _create(_desc([0.0, 1.0, np.nan, 0.0], y, [[0, 1, 2], [0, 2, 3]])[0]) == L.SE_ERR_MESH
+
+
+def _call_subcycle(mesh, params, nsub=10, dt=100.0, null_eta=False):
+    dummy = ctypes.c_void_p(256)
+    st = L.State(None if null_eta else dummy, dummy, None, None)
+    fo = L.Forcing(dummy, dummy, dummy, None)
+    pc = params.c()
+    return L.lib().se_subcycle(mesh.handle, ctypes.byref(pc), ctypes.byref(st), ctypes.byref(fo),
+                               nsub, dt, dummy, None)
+
+
+def test_subcycle_argument_and_cfl_errors():
+    mesh = sesynth.tiny_mesh("jitter65")
+    m = Mesh.from_dict(mesh, device=-1)
+    ok = Params(h_max=100.0, check_cfl=True)
+    # within the bound: fails only because the mesh is host-only
+    assert _call_subcycle(m, ok, nsub=10, dt=10.0) == L.SE_ERR_ARG
+    lim = 2 / np.sqrt(1 + 2 * 0.14)
+    dts_lim = lim / np.sqrt(9.81 * 5000.0 * m.mu_max)
+    hot = Params(h_max=5000.0, check_cfl=True)
+    assert _call_subcycle(m, hot, nsub=10, dt=10 * dts_lim * 1.01) == L.SE_ERR_CFL
+    assert _call_subcycle(m, hot, nsub=10, dt=10 * dts_lim * 0.99) == L.SE_ERR_ARG
+    assert _call_subcycle(m, Params(h_max=0.0, check_cfl=True)) == L.SE_ERR_ARG
+    assert _call_subcycle(m, Params(), nsub=0) == L.SE_ERR_ARG
+    assert _call_subcycle(m, Params(), dt=-1.0) == L.SE_ERR_ARG
+    assert _call_subcycle(m, Params(), dt=float("nan")) == L.SE_ERR_ARG
+    assert _call_subcycle(m, Params(g=0.0)) == L.SE_ERR_ARG
+    assert _call_subcycle(m, Params(), null_eta=True) == L.SE_ERR_ARG
+    bad = Params()
+    pc = bad.c()
+    pc.precision = 7
+    dummy = ctypes.c_void_p(256)
+    st = L.State(dummy, dummy, None, None)
+    fo = L.Forcing(dummy, dummy, dummy, None)
+    assert L.lib().se_subcycle(m.handle, ctypes.byref(pc), ctypes.byref(st), ctypes.byref(fo),
+                               5, 1.0, dummy, None) == L.SE_ERR_ARG
+    assert b"precision" in L.lib().se_last_error()
+
+
+def test_workspace_size_grows_with_substeps():
+    m = Mesh.from_dict(sesynth.tiny_mesh("jitter76"), device=-1)
+    a = m.workspace_bytes(Params(), 10)
+    b = m.workspace_bytes(Params(), 100)
+    c = m.workspace_bytes(Params(precision="f32"), 10)
+    assert b > a > c > 0 and a % 256 == 0
