@@ -121,7 +121,11 @@ def main():
     else:
         from paper_2311_08241_amd.autotune import autotune
         scratch = {k: (v.clone() if v is not None else None) for k, v in d.items()}
-        tune = autotune(mesh, lambda: step(scratch), prec, nsub, log=log)
+
+        def reset():
+            scratch["eta"].copy_(d["eta"])
+            scratch["U"].copy_(d["U"])
+        tune = autotune(mesh, lambda: step(scratch), prec, nsub, log=log, reset=reset)
         del scratch
         log(f"[bench] autotuned plan {tune['plan']} ({tune['ms']:.3f} ms/step, "
             f"cached={tune['cached']})")
@@ -174,7 +178,14 @@ def main():
         ws64 = mesh.workspace(p64, nsub)
         if prec != "f64":
             from paper_2311_08241_amd.autotune import autotune
-            t64 = autotune(mesh, lambda: step(d64, p64, ws64), "f64", nsub, log=log)
+            e64, u64 = d64["eta"].clone(), d64["U"].clone()
+
+            def reset64():
+                d64["eta"].copy_(e64)
+                d64["U"].copy_(u64)
+            t64 = autotune(mesh, lambda: step(d64, p64, ws64), "f64", nsub, log=log,
+                           reset=reset64)
+            reset64()
             extra["fp64_plan"] = t64["plan"]
         for label, plain in (("fp64_plain", True), ("fp64_fused", False)):
             def s64():

@@ -6,3 +6,9 @@ package does not load the library; the first call does, and fails with
 ImportError if it has not been built.
 """
 from .api import Mesh, Params, device_inputs  # noqa: F401
+
+
+def subcycle_autograd(*args, **kw):
+    """Differentiable subcycle (see autograd.subcycle)."""
+    from .autograd import subcycle
+    return subcycle(*args, **kw)

@@ -206,6 +206,43 @@ class Mesh:
                    float(dt), _ptr(workspace), _stream_ptr(stream)))
         return eta, U, Uavg, volume
 
+    def adjoint(self, eta0, U0, *, R, f, H0, W=None, nsub: int, dt: float, params: Params,
+                ckpt_every: int = 5, lam_eta=None, lam_U=None, lam_Uavg=None, g_eta0=None,
+                g_U0=None, g_R=None, g_H0=None, workspace=None, stream=None):
+        """se_subcycle_adjoint: gradients of <lam_eta, eta^M> + <lam_U, U^M> + <lam_Uavg, <<U>>>.
+
+        Outputs that are None are allocated; returns (g_eta0, g_U0, g_R, g_H0).
+        """
+        torch = _torch()
+        dt_ = params.dtype
+        dev = f"cuda:{self.device}"
+        for t, n, name, cols in ((eta0, self.nv, "eta0", None), (U0, self.ne, "U0", 2),
+                                 (R, self.ne, "R", 2), (f, self.ne, "f", None),
+                                 (H0, self.nv, "H0", None)):
+            self._check_tensor(t, n, name, dt_, cols)
+        self._check_tensor(W, self.nv, "W", dt_, allow_none=True)
+        self._check_tensor(lam_eta, self.nv, "lam_eta", dt_, allow_none=True)
+        self._check_tensor(lam_U, self.ne, "lam_U", dt_, 2, allow_none=True)
+        self._check_tensor(lam_Uavg, self.ne, "lam_Uavg", torch.float64, 2, allow_none=True)
+        g_eta0 = torch.empty(self.nv, dtype=dt_, device=dev) if g_eta0 is None else g_eta0
+        g_U0 = torch.empty((self.ne, 2), dtype=dt_, device=dev) if g_U0 is None else g_U0
+        g_R = torch.empty((self.ne, 2), dtype=dt_, device=dev) if g_R is None else g_R
+        g_H0 = torch.empty(self.nv, dtype=dt_, device=dev) if g_H0 is None else g_H0
+        self._check_tensor(g_eta0, self.nv, "g_eta0", dt_)
+        self._check_tensor(g_U0, self.ne, "g_U0", dt_, 2)
+        self._check_tensor(g_R, self.ne, "g_R", dt_, 2)
+        self._check_tensor(g_H0, self.nv, "g_H0", dt_)
+        if workspace is None:
+            workspace = self.workspace(params, nsub, ckpt_every)
+        fo = L.Forcing(_ptr(R), _ptr(f), _ptr(H0), _ptr(W))
+        pc = params.c()
+        L.check(L.lib().se_subcycle_adjoint(
+            self._h, ctypes.byref(pc), _ptr(eta0), _ptr(U0), ctypes.byref(fo), int(nsub),
+            float(dt), int(ckpt_every), _ptr(lam_eta), _ptr(lam_U), _ptr(lam_Uavg),
+            _ptr(g_eta0), _ptr(g_U0), _ptr(g_R), _ptr(g_H0), _ptr(workspace),
+            _stream_ptr(stream)))
+        return g_eta0, g_U0, g_R, g_H0
+
     def check_faults(self, stream=None) -> int:
         bits = ctypes.c_uint32()
         L.check(L.lib().se_check_faults(self._h, 0, _stream_ptr(stream), ctypes.byref(bits)))

@@ -74,15 +74,17 @@ def _save_cache(c):
 
 
 def autotune(mesh, run_step, precision: str, nsub: int, *, top: int = 8, reps: int = 3,
-             use_cache: bool = True, log=None):
+             use_cache: bool = True, log=None, reset=None):
     """Pick and install the fastest plan.
 
     run_step() must perform one se_subcycle call with the mesh's current plan
-    on the caller's stream (state may evolve; only time is measured).
+    on the caller's stream; reset(), if given, restores the state before each
+    candidate (outside the timed region) so long tuning runs stay physical.
     Returns dict(plan=(T, K, B), ms=..., table=[...]).
     """
     import torch
-    dev = torch.cuda.get_device_name(mesh.device)
+    props = torch.cuda.get_device_properties(mesh.device)
+    dev = f"{getattr(props, 'gcnArchName', '?')}x{props.multi_processor_count}"
     key = f"{dev}|{precision}|{mesh_signature(mesh)}|{nsub}"
     cache = _load_cache() if use_cache else {}
     if key in cache:
@@ -95,6 +97,8 @@ def autotune(mesh, run_step, precision: str, nsub: int, *, top: int = 8, reps: i
     for model, T, K, B, st in candidates(mesh, precision, nsub, top):
         t0 = time.time()
         mesh.set_plan(T, K, B)
+        if reset is not None:
+            reset()
         run_step()
         torch.cuda.synchronize()
         e0.record()

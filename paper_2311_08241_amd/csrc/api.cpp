@@ -111,7 +111,7 @@ std::vector<T> pack_geom(const HostMesh &m, const std::vector<int32_t> *sel, int
 bool ept_ok(bool f32, int ept, int block) {
     if (ept < 0) return false;
     if (block == 256) return f32 ? ept <= 8 : ept <= 6;
-    return f32 ? ept <= 6 : ept <= 4;
+    return f32 ? ept <= 8 : ept <= 4;
 }
 
 // Host-side construction and statistics of a plan (no device memory).
@@ -237,6 +237,36 @@ Layout fwd_layout(int64_t nv, int64_t ne, bool f32, int32_t nsub, int64_t width)
     o += al(3 * ne * s);
     L.vol = o;
     o += al(static_cast<size_t>(nsub + 1) * width * 8);
+    L.total = o;
+    return L;
+}
+
+struct AdjLayout {
+    size_t ckpt, traj, lam_eta, lam_U, psi, gR, gH0, total;
+    int32_t nseg, k;
+};
+
+AdjLayout adj_layout(int64_t nv, int64_t ne, bool f32, int32_t nsub, int32_t k, size_t base) {
+    const size_t s = f32 ? 4 : 8;
+    const size_t st = al((nv + 2 * ne) * s);   // one state (eta then U)
+    AdjLayout L{};
+    L.k = k;
+    L.nseg = (nsub + k - 1) / k;
+    size_t o = base;
+    L.ckpt = o;
+    o += st * L.nseg;
+    L.traj = o;
+    o += st * k;
+    L.lam_eta = o;
+    o += al(nv * s);
+    L.lam_U = o;
+    o += al(2 * ne * s);
+    L.psi = o;
+    o += al(4 * ne * s);
+    L.gR = o;
+    o += al(2 * ne * s);
+    L.gH0 = o;
+    o += al(nv * s);
     L.total = o;
     return L;
 }
@@ -489,9 +519,13 @@ se_status se_workspace_bytes(const se_mesh *m, const se_params *p, int32_t nsub,
         set_error("se_workspace_bytes: bad argument");
         return SE_ERR_ARG;
     }
-    (void)ckpt_every;
     const bool f32 = p->precision == SE_F32_MIXED;
-    *bytes = fwd_layout(m->h.nv, m->h.ne, f32, nsub, vol_width(m->h.nv)).total;
+    const Layout L = fwd_layout(m->h.nv, m->h.ne, f32, nsub, vol_width(m->h.nv));
+    *bytes = L.total;
+    if (ckpt_every > 0) {
+        const int32_t k = std::min(ckpt_every, nsub);
+        *bytes = adj_layout(m->h.nv, m->h.ne, f32, nsub, k, L.total).total;
+    }
     return SE_OK;
 }
 
@@ -660,12 +694,120 @@ se_status se_check_faults(void *obj, int32_t kind, void *stream, uint32_t *bits)
     return SE_OK;
 }
 
-se_status se_subcycle_adjoint(se_mesh *, const se_params *, const void *, const void *,
-                              const se_forcing *, int32_t, double, int32_t, const void *,
-                              const void *, const double *, void *, void *, void *, void *,
-                              void *, void *) {
-    set_error("se_subcycle_adjoint: not built yet");
-    return SE_ERR_UNSUPPORTED;
+
+se_status se_subcycle_adjoint(se_mesh *m, const se_params *p, const void *eta0, const void *U0,
+                              const se_forcing *fo, int32_t nsub, double dt, int32_t ckpt_every,
+                              const void *lam_eta, const void *lam_U, const double *lam_Uavg,
+                              void *g_eta0, void *g_U0, void *g_R, void *g_H0, void *ws,
+                              void *stream) {
+    SE_TRY(check_params(m, p, nsub, dt));
+    if (!eta0 || !U0 || !fo || !fo->R || !fo->f || !fo->H0 || !ws) {
+        set_error("se_subcycle_adjoint: null input, forcing or workspace");
+        return SE_ERR_ARG;
+    }
+    if (ckpt_every < 1 || ckpt_every > nsub) {
+        set_error("se_subcycle_adjoint: need 1 <= ckpt_every <= nsub");
+        return SE_ERR_ARG;
+    }
+    if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) {
+        set_error("workspace must be 256-byte aligned");
+        return SE_ERR_ARG;
+    }
+    SE_TRY(check_device(m));
+    DeviceGuard dg(m->device);
+    const bool f32 = p->precision == SE_F32_MIXED;
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t nv = m->h.nv, ne = m->h.ne;
+    const size_t es = f32 ? 4 : 8;
+    const Layout L = fwd_layout(nv, ne, f32, nsub, vol_width(nv));
+    const AdjLayout A = adj_layout(nv, ne, f32, nsub, ckpt_every, L.total);
+    char *w = static_cast<char *>(ws);
+    const size_t st_bytes = al((nv + 2 * ne) * es);
+    auto st_eta = [&](size_t off) { return w + off; };
+    auto st_U = [&](size_t off) { return w + off + nv * es; };
+
+    // forward substep (state update only) on the plain path
+    PlainArgs fa{};
+    fa.nv = nv;
+    fa.ne = ne;
+    fa.tri = m->d.tri.as<const int32_t>();
+    fa.row_ptr = m->d.row_ptr.as<const int32_t>();
+    fa.pcol = m->d.pcol.as<const int32_t>();
+    fa.geom = f32 ? m->d.geom32.p : m->d.geom64.p;
+    fa.H0 = fo->H0;
+    fa.R = fo->R;
+    fa.f = fo->f;
+    fa.W = fo->W;
+    fa.Av = f32 ? m->d.Av32.p : m->d.Av64.p;
+    fa.Av64 = m->d.Av64.as<const double>();
+    fa.phi = w + L.phi;
+    fa.sum = w + L.sum;
+    fa.U0c = w + L.U0c;
+    fa.faults = m->d.faults.as<uint32_t>();
+    fa.c = make_step(p, nsub, dt);
+    fa.nblk_v = static_cast<int32_t>((nv + 255) / 256);
+    fa.fwd_only = 1;
+    auto fstep = [&](size_t off) -> se_status {
+        fa.eta = st_eta(off);
+        fa.U = st_U(off);
+        HIP_TRY(launch_plain_step(f32, fa, s), "adjoint: forward substep");
+        return SE_OK;
+    };
+    auto copy_state = [&](size_t dst, size_t src) -> se_status {
+        HIP_TRY(hipMemcpyAsync(w + dst, w + src, (nv + 2 * ne) * es, hipMemcpyDeviceToDevice, s),
+                "adjoint: state copy");
+        return SE_OK;
+    };
+
+    // 1. forward sweep storing a checkpoint every k substeps
+    const int32_t k = A.k;
+    HIP_TRY(hipMemcpyAsync(st_eta(A.ckpt), eta0, nv * es, hipMemcpyDeviceToDevice, s), "copy eta0");
+    HIP_TRY(hipMemcpyAsync(st_U(A.ckpt), U0, 2 * ne * es, hipMemcpyDeviceToDevice, s), "copy U0");
+    SE_TRY(copy_state(A.traj, A.ckpt));
+    for (int32_t mm = 0; mm + 1 < nsub; ++mm) {
+        SE_TRY(fstep(A.traj));
+        if ((mm + 1) % k == 0) SE_TRY(copy_state(A.ckpt + st_bytes * ((mm + 1) / k), A.traj));
+    }
+
+    // 2. reverse sweep, segment by segment, recomputing each segment's states
+    AdjArgs aa{};
+    aa.nv = nv;
+    aa.ne = ne;
+    aa.tri = fa.tri;
+    aa.row_ptr = fa.row_ptr;
+    aa.pcol = fa.pcol;
+    aa.geom = fa.geom;
+    aa.H0 = fo->H0;
+    aa.Av = fa.Av;
+    aa.f = fo->f;
+    aa.lam_eta = w + A.lam_eta;
+    aa.lam_U = w + A.lam_U;
+    aa.lam_Uavg = lam_Uavg;
+    aa.gR = g_R ? g_R : static_cast<void *>(w + A.gR);
+    aa.gH0 = g_H0 ? g_H0 : static_cast<void *>(w + A.gH0);
+    aa.psi = w + A.psi;
+    aa.c = fa.c;
+    aa.rM = 1.0 / static_cast<double>(nsub);
+    aa.thrM = p->theta * aa.rM;
+    HIP_TRY(launch_adj_init(f32, aa, lam_eta, lam_U, s), "adjoint: init");
+    for (int32_t sg = A.nseg - 1; sg >= 0; --sg) {
+        const int32_t m0 = sg * k, m1 = std::min(nsub, m0 + k);
+        SE_TRY(copy_state(A.traj, A.ckpt + st_bytes * sg));
+        for (int32_t j = 1; j < m1 - m0; ++j) {
+            SE_TRY(copy_state(A.traj + st_bytes * j, A.traj + st_bytes * (j - 1)));
+            SE_TRY(fstep(A.traj + st_bytes * j));
+        }
+        for (int32_t mm = m1 - 1; mm >= m0; --mm) {
+            aa.eta_m = st_eta(A.traj + st_bytes * (mm - m0));
+            HIP_TRY(launch_adj_step(f32, aa, s), "adjoint: reverse substep");
+        }
+    }
+    HIP_TRY(launch_adj_final(f32, aa, s), "adjoint: final");
+    if (g_eta0)
+        HIP_TRY(hipMemcpyAsync(g_eta0, aa.lam_eta, nv * es, hipMemcpyDeviceToDevice, s), "g_eta0");
+    if (g_U0)
+        HIP_TRY(hipMemcpyAsync(g_U0, aa.lam_U, 2 * ne * es, hipMemcpyDeviceToDevice, s), "g_U0");
+    return SE_OK;
 }
 
 se_status se_batch_create(se_mesh *const *, int32_t, se_batch **out) {

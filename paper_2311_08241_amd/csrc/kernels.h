@@ -57,6 +57,24 @@ struct PlainArgs {
     StepC c;
     int32_t m;                  // substep index 0..nsub-1
     int32_t nblk_v;             // blocks of the vertex launch (volume row width)
+    int32_t fwd_only;           // 1: state update only (no running sum, average, volume)
+};
+
+// Reverse (adjoint) substep: triangle gather then vertex CSR sum.
+struct AdjArgs {
+    int64_t nv, ne;
+    const int32_t *tri, *row_ptr, *pcol;
+    const void *geom;           // 5 SoA arrays [ne]
+    const void *H0, *Av;
+    const void *f;
+    const void *eta_m;          // forward state eta^m
+    void *lam_eta;              // in: lambda_eta^{m+1}; out: lambda_eta^m
+    void *lam_U;                // in: lambda_U^{m+1};   out: lambda_U^m
+    const double *lam_Uavg;     // seed of <<U>> or nullptr
+    void *gR, *gH0;             // accumulated gradients (R: [ne][2], H0: [nv])
+    void *psi;                  // [ne][4] scratch: three slot terms and lambda_H / 3
+    StepC c;
+    double rM, thrM;            // 1/M and theta/M
 };
 
 // Host launchers (kernels.hip)
@@ -65,6 +83,12 @@ hipError_t launch_tile(bool f32, int ept, int block, const TileArgs &a, int grid
 hipError_t launch_plain_step(bool f32, const PlainArgs &a, hipStream_t s);
 hipError_t launch_vol_reduce(const double *part, int64_t width, int32_t rows, double add,
                              double *out, hipStream_t s);
+hipError_t launch_adj_step(bool f32, const AdjArgs &a, hipStream_t s);
+// lam_eta = seed or 0; lam_U = seed + thrM * lam_Uavg; gR = gH0 = 0
+hipError_t launch_adj_init(bool f32, const AdjArgs &a, const void *seed_eta, const void *seed_U,
+                           hipStream_t s);
+// lam_U -= thrM * lam_Uavg
+hipError_t launch_adj_final(bool f32, const AdjArgs &a, hipStream_t s);
 int tile_lds_bytes(bool f32, int block, int K, int cap_nv, int cap_ne, int cap_nvu, int cap_cs);
 
 }  // namespace sesub

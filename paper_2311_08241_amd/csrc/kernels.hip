@@ -17,6 +17,8 @@
 // order: FP64 results do not depend on the plan.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "kernels.h"
 
 namespace sesub {
@@ -161,6 +163,7 @@ __global__ void __launch_bounds__(256) k_plain_tri(PlainArgs a) {
     un.x = Unx;
     un.y = Uny;
     U[e] = un;
+    if (a.fwd_only) return;
     const bool first = a.m == 0, last = a.m == c.nsub - 1;
     SumT<F32> s;
     if (first) {
@@ -203,7 +206,7 @@ __global__ void __launch_bounds__(256) k_plain_vtx(PlainArgs a) {
         v_new = av * (double)en;
         v_old = av * (double)eo;
     }
-    if (!(track || first || last)) return;
+    if (a.fwd_only || !(track || first || last)) return;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     v_new = wave_sum(v_new);
     v_old = wave_sum(v_old);
@@ -261,43 +264,75 @@ __global__ void __launch_bounds__(BLOCK) k_tile(TileArgs a) {
     off = align16(off + (int)sizeof(T) * a.cap_nv);
     T *sH = reinterpret_cast<T *>(smem + off);
     off = align16(off + (int)sizeof(T) * a.cap_nv);
-    T *sAv = reinterpret_cast<T *>(smem + off);
+    T *sAv = reinterpret_cast<T *>(smem + off);   // FP64: A_v; FP32: 1 / A_v
     off = align16(off + (int)sizeof(T) * a.cap_nvu);
     T *sW = reinterpret_cast<T *>(smem + off);
     off = align16(off + (int)sizeof(T) * a.cap_nvu);
     T *sPhi = reinterpret_cast<T *>(smem + off);
     off = align16(off + (int)sizeof(T) * 3 * a.cap_ne);
     uint16_t *sRow = reinterpret_cast<uint16_t *>(smem + off);
-    off = align16(off + 2 * (a.cap_nvu + 1));
+    off = align16(off + 2 * (a.cap_nvu + 4));
     uint16_t *sEnt = reinterpret_cast<uint16_t *>(smem + off);
 
+    // ---- stage vertex data (batches of 4 per thread: loads first, then LDS stores)
     const T *eta_in = static_cast<const T *>(a.eta_in);
     const T *H0 = static_cast<const T *>(a.H0);
     const T *Avt = static_cast<const T *>(a.Av);
     const T *Wt = static_cast<const T *>(a.W);
     const int32_t *lv = a.lv_gid + h.lv_off;
-    for (int i = tid; i < nv_load; i += BLOCK) {
-        const int g = lv[i];
-        sEta[i] = eta_in[g];
-        sH[i] = H0[g];
-        if (i < nvu) {
-            sAv[i] = Avt[g];
-            sW[i] = hasW ? Wt[g] : T(0);
+    for (int i0 = tid; i0 < nv_load; i0 += 4 * BLOCK) {
+        int g[4];
+        T ve[4], vh[4], va[4], vw[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int i = i0 + u * BLOCK;
+            g[u] = i < nv_load ? lv[i] : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int i = i0 + u * BLOCK;
+            if (g[u] >= 0) {
+                ve[u] = eta_in[g[u]];
+                vh[u] = H0[g[u]];
+                va[u] = i < nvu ? Avt[g[u]] : T(1);
+                vw[u] = (i < nvu && hasW) ? Wt[g[u]] : T(0);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int i = i0 + u * BLOCK;
+            if (g[u] >= 0) {
+                sEta[i] = ve[u];
+                sH[i] = vh[u];
+                if (i < nvu) {
+                    sAv[i] = F32 ? T(1) / va[u] : va[u];
+                    sW[i] = vw[u];
+                }
+            }
         }
     }
-    const uint16_t *crow = a.cs_row + h.rw_off;
-    for (int i = tid; i <= nvu; i += BLOCK) sRow[i] = crow[i];
-    const int nent = crow[nvu];
-    const uint16_t *cent = a.cs_ent + h.cs_off;
-    for (int i = tid; i < nent; i += BLOCK) sEnt[i] = cent[i];
+    // ---- stage the local CSR (chunks are padded to multiples of 4 entries)
+    {
+        const uint2 *crow = reinterpret_cast<const uint2 *>(a.cs_row + h.rw_off);
+        uint2 *srow2 = reinterpret_cast<uint2 *>(sRow);
+        const int nrow4 = (nvu + 1 + 3) >> 2;
+        for (int i = tid; i < nrow4; i += BLOCK) srow2[i] = crow[i];
+        const uint2 *cent = reinterpret_cast<const uint2 *>(a.cs_ent + h.cs_off);
+        uint2 *sent2 = reinterpret_cast<uint2 *>(sEnt);
+        const int nent = a.cs_row[h.rw_off + nvu];
+        const int nent4 = (nent + 3) >> 2;
+        for (int i = tid; i < nent4; i += BLOCK) sent2[i] = cent[i];
+    }
 
-    // triangle state in registers
+    // ---- triangle state in registers
     const T *lg = static_cast<const T *>(a.lgeom) + h.le_off;
     const int64_t ls = a.lgeom_stride;
     const T2 *Uin = static_cast<const T2 *>(a.U_in);
     const T2 *Rg = static_cast<const T2 *>(a.R);
     const T *fg = static_cast<const T *>(a.f);
-    T rUx[EPT], rUy[EPT], rRx[EPT], rRy[EPT], rf[EPT], g0[EPT], g1[EPT], g2[EPT], g3[EPT], g4[EPT];
+    const T dts = cdts<T>(c);
+    T rUx[EPT], rUy[EPT], rRx[EPT], rRy[EPT], rf[EPT], rk[EPT], g0[EPT], g1[EPT], g2[EPT],
+        g3[EPT], g4[EPT];
     uint32_t t0[EPT], t1[EPT];
     int gid[EPT];
     SumT<F32> sm[EPT];
@@ -307,8 +342,9 @@ __global__ void __launch_bounds__(BLOCK) k_tile(TileArgs a) {
         if (le < ne_load) {
             const int g = a.le_gid[h.le_off + le];
             gid[r] = g;
-            t0[r] = a.le_tri[2 * (h.le_off + le)];
-            t1[r] = a.le_tri[2 * (h.le_off + le) + 1];
+            const uint2 tt = reinterpret_cast<const uint2 *>(a.le_tri)[h.le_off + le];
+            t0[r] = tt.x;
+            t1[r] = tt.y;
             g0[r] = lg[le];
             g1[r] = lg[ls + le];
             g2[r] = lg[2 * ls + le];
@@ -330,13 +366,41 @@ __global__ void __launch_bounds__(BLOCK) k_tile(TileArgs a) {
         }
     }
     __syncthreads();
+    if constexpr (F32) {
+        // FP32: per-triangle constants of the launch replace divisions in the loop:
+        // a = f dt/2 (rf), 1/(1 + a^2) (rk), dt R (rRx, rRy), -A_e (g4); below, the
+        // triangle mean of H0 (+ eta_ref unless H is linear) (rH)
+#pragma unroll
+        for (int r = 0; r < EPT; ++r) {
+            const int le = tid + r * BLOCK;
+            if (le < ne_load) {
+                const T al = T(0.5) * rf[r] * dts;
+                rk[r] = T(1) / (T(1) + al * al);
+                rf[r] = al;
+                rRx[r] = dts * rRx[r];
+                rRy[r] = dts * rRy[r];
+                g4[r] = -g4[r];
+            }
+        }
+    }
+    T rH[F32 ? EPT : 1];
+    if constexpr (F32) {
+#pragma unroll
+        for (int r = 0; r < EPT; ++r) {
+            const int le = tid + r * BLOCK;
+            if (le < ne_load) {
+                const int ia = t0[r] & 0xffffu, ib = t0[r] >> 16, ic = t1[r];
+                rH[r] = (sH[ia] + sH[ib] + sH[ic]) * T(1.0f / 3.0f) + (linear_h ? T(0) : c.eta_ref_f);
+            }
+        }
+    }
 
     double v0 = 0.0;
     if (first) {
         for (int i = tid; i < h.nv0; i += BLOCK) v0 += a.Av64[h.vbase + i] * (double)sEta[i];
     }
     bool dry_any = false, bad_any = false;
-    const T dts = cdts<T>(c);
+    const T gd = cg<T>(c) * dts, th = cth<T>(c), opt = copt<T>(c);
     for (int j = 0; j < cnt; ++j) {
         const int lev = cnt - j;
         const int ne_act = nE[lev], nv_act = nV[lev - 1];
@@ -346,11 +410,32 @@ __global__ void __launch_bounds__(BLOCK) k_tile(TileArgs a) {
             if (le < ne_act) {
                 const int ia = t0[r] & 0xffffu, ib = t0[r] >> 16, ic = t1[r];
                 T Unx, Uny, pa, pb, pc;
-                bool dry;
-                tri_update<T, F32>(sEta[ia], sEta[ib], sEta[ic], sH[ia], sH[ib], sH[ic], g0[r],
-                                   g1[r], g2[r], g3[r], g4[r], rUx[r], rUy[r], rRx[r], rRy[r],
-                                   rf[r], c, linear_h, Unx, Uny, pa, pb, pc, dry);
-                dry_any |= dry;
+                if constexpr (F32) {
+                    const T ea = sEta[ia], eb = sEta[ib], ec = sEta[ic];
+                    const T db = eb - ea, dc = ec - ea;
+                    const T gx = db * g0[r] + dc * g2[r];
+                    const T gy = db * g1[r] + dc * g3[r];
+                    const T He = linear_h ? rH[r] : rH[r] + (ea + eb + ec) * T(1.0f / 3.0f);
+                    dry_any |= !(He > T(0));
+                    const T gHe = gd * He, al = rf[r];
+                    const T ux = rUx[r], uy = rUy[r];
+                    const T rx = ux + al * uy + (rRx[r] - gHe * gx);
+                    const T ry = uy - al * ux + (rRy[r] - gHe * gy);
+                    Unx = (rx + al * ry) * rk[r];
+                    Uny = (ry - al * rx) * rk[r];
+                    const T Fx = opt * Unx - th * ux;
+                    const T Fy = opt * Uny - th * uy;
+                    pb = g4[r] * (Fx * g0[r] + Fy * g1[r]);
+                    pc = g4[r] * (Fx * g2[r] + Fy * g3[r]);
+                    pa = -(pb + pc);
+                } else {
+                    bool dry;
+                    tri_update<T, F32>(sEta[ia], sEta[ib], sEta[ic], sH[ia], sH[ib], sH[ic],
+                                       g0[r], g1[r], g2[r], g3[r], g4[r], rUx[r], rUy[r],
+                                       rRx[r], rRy[r], rf[r], c, linear_h, Unx, Uny, pa, pb,
+                                       pc, dry);
+                    dry_any |= dry;
+                }
                 sPhi[3 * le] = pa;
                 sPhi[3 * le + 1] = pb;
                 sPhi[3 * le + 2] = pc;
@@ -370,7 +455,11 @@ __global__ void __launch_bounds__(BLOCK) k_tile(TileArgs a) {
             T acc = T(0);
             const int q1 = sRow[i + 1];
             for (int q = sRow[i]; q < q1; ++q) acc += sPhi[sEnt[q]];
-            const T en = sEta[i] - dts * (acc / sAv[i] + sW[i]);
+            T en;
+            if constexpr (F32)
+                en = sEta[i] - dts * (acc * sAv[i] + sW[i]);
+            else
+                en = sEta[i] - dts * (acc / sAv[i] + sW[i]);
             sEta[i] = en;
             bad_any |= !finite_val(en);
             if (i < h.nv0) vp += a.Av64[h.vbase + i] * (double)en;
@@ -433,6 +522,132 @@ __global__ void __launch_bounds__(BLOCK) k_tile(TileArgs a) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Adjoint of one substep (reverse of the triangle and vertex phases)
+// ---------------------------------------------------------------------------
+template <typename T, bool F32>
+__global__ void __launch_bounds__(256) k_adj_tri(AdjArgs a) {
+    using T2 = typename Vec2<T>::type;
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= a.ne) return;
+    const StepC &c = a.c;
+    const T dts = cdts<T>(c), g = cg<T>(c), th = cth<T>(c), opt = copt<T>(c);
+    const T *geom = static_cast<const T *>(a.geom);
+    const T gbx = geom[e], gby = geom[a.ne + e], gcx = geom[2 * a.ne + e],
+            gcy = geom[3 * a.ne + e], Ae = geom[4 * a.ne + e];
+    const T gax = -(gbx + gcx), gay = -(gby + gcy);
+    const int32_t v0 = a.tri[3 * e], v1 = a.tri[3 * e + 1], v2 = a.tri[3 * e + 2];
+    const T *le = static_cast<const T *>(a.lam_eta);
+    const T *Av = static_cast<const T *>(a.Av);
+    // lambda_F = -dt_s sum_k (lambda_eta_k / A_k) S_k,  S_k = -A_e grad N_k
+    T lFx = T(0), lFy = T(0);
+    {
+        const T w0 = -dts * le[v0] / Av[v0];
+        lFx += w0 * (-Ae * gax);
+        lFy += w0 * (-Ae * gay);
+        const T w1 = -dts * le[v1] / Av[v1];
+        lFx += w1 * (-Ae * gbx);
+        lFy += w1 * (-Ae * gby);
+        const T w2 = -dts * le[v2] / Av[v2];
+        lFx += w2 * (-Ae * gcx);
+        lFy += w2 * (-Ae * gcy);
+    }
+    T2 *lU = static_cast<T2 *>(a.lam_U);
+    T2 lu = lU[e];
+    if (a.lam_Uavg) {   // U^{m+1} enters the running sum with weight 1/M
+        lu.x = lu.x + (T)(a.rM * a.lam_Uavg[2 * e]);
+        lu.y = lu.y + (T)(a.rM * a.lam_Uavg[2 * e + 1]);
+    }
+    const T lUnx = lu.x + opt * lFx, lUny = lu.y + opt * lFy;
+    T lUox = -th * lFx, lUoy = -th * lFy;
+    // triangle quantities of the forward substep
+    const T *eta = static_cast<const T *>(a.eta_m);
+    const T *H0 = static_cast<const T *>(a.H0);
+    const T ea = eta[v0], eb = eta[v1], ec = eta[v2];
+    const T db = eb - ea, dc = ec - ea;
+    const T gx = db * gbx + dc * gcx;
+    const T gy = db * gby + dc * gcy;
+    T He;
+    if (c.flags & KF_LINEAR_H) {
+        He = (H0[v0] + H0[v1] + H0[v2]) / T(3);
+    } else if (!F32) {
+        He = ((H0[v0] + ea) + (H0[v1] + eb) + (H0[v2] + ec)) / T(3);
+    } else {
+        He = ((H0[v0] + H0[v1] + H0[v2]) + (ea + eb + ec)) / T(3) + c.eta_ref_f;
+    }
+    const T al = T(0.5) * static_cast<const T *>(a.f)[e] * dts;
+    const T den = T(1) + al * al;
+    // U' = C r with C = (I + aJ)^-1:  lambda_r = C^T lambda_U'
+    const T lrx = (lUnx - al * lUny) / den;
+    const T lry = (lUny + al * lUnx) / den;
+    // r = (I - aJ) U + dt_s(-g H grad eta + R)
+    lUox += lrx - al * lry;
+    lUoy += lry + al * lrx;
+    T2 *gR = static_cast<T2 *>(a.gR);
+    T2 gr = gR[e];
+    gr.x += dts * lrx;
+    gr.y += dts * lry;
+    gR[e] = gr;
+    const T lgx = -dts * g * He * lrx, lgy = -dts * g * He * lry;
+    const T lHe = -dts * g * (gx * lrx + gy * lry);
+    T *psi = static_cast<T *>(a.psi) + 4 * e;
+    psi[0] = gax * lgx + gay * lgy;
+    psi[1] = gbx * lgx + gby * lgy;
+    psi[2] = gcx * lgx + gcy * lgy;
+    psi[3] = lHe / T(3);
+    T2 lo;
+    lo.x = lUox;
+    lo.y = lUoy;
+    lU[e] = lo;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_adj_vtx(AdjArgs a) {
+    const int64_t v = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (v >= a.nv) return;
+    const bool nonlin = !(a.c.flags & KF_LINEAR_H);
+    T *le = static_cast<T *>(a.lam_eta);
+    T *gH0 = static_cast<T *>(a.gH0);
+    const T *psi = static_cast<const T *>(a.psi);
+    T acc = le[v];
+    T gh = gH0[v];
+    const int32_t j1 = a.row_ptr[v + 1];
+    for (int32_t j = a.row_ptr[v]; j < j1; ++j) {
+        const int32_t q = a.pcol[j];
+        const int32_t e = q / 3, k = q - 3 * e;
+        acc += psi[4 * e + k];
+        const T chi = psi[4 * e + 3];
+        if (nonlin) acc += chi;
+        gh += chi;
+    }
+    le[v] = acc;
+    gH0[v] = gh;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_adj_init(AdjArgs a, const T *seed_eta, const T *seed_U) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < a.nv) {
+        static_cast<T *>(a.lam_eta)[i] = seed_eta ? seed_eta[i] : T(0);
+        static_cast<T *>(a.gH0)[i] = T(0);
+    }
+    if (i < 2 * a.ne) {
+        T u = seed_U ? seed_U[i] : T(0);
+        if (a.lam_Uavg) u = u + (T)(a.thrM * a.lam_Uavg[i]);
+        static_cast<T *>(a.lam_U)[i] = u;
+        static_cast<T *>(a.gR)[i] = T(0);
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_adj_final(AdjArgs a) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < 2 * a.ne && a.lam_Uavg) {
+        T *lU = static_cast<T *>(a.lam_U);
+        lU[i] = lU[i] - (T)(a.thrM * a.lam_Uavg[i]);
+    }
+}
+
 // Deterministic sum of each row of partials: out[r] = add + sum_i part[r*width + i].
 __global__ void __launch_bounds__(256) k_vol_reduce(const double *part, int64_t width,
                                                     double add, double *out) {
@@ -486,8 +701,8 @@ int tile_lds_bytes(bool f32, int block, int K, int cap_nv, int cap_ne, int cap_n
     off = al(off + ts * cap_nvu);
     off = al(off + ts * cap_nvu);
     off = al(off + ts * 3 * cap_ne);
-    off = al(off + 2 * (cap_nvu + 1));
-    off = al(off + 2 * cap_cs);
+    off = al(off + 2 * (cap_nvu + 4));
+    off = al(off + 2 * (cap_cs + 4));
     return off;
 }
 
@@ -511,6 +726,41 @@ hipError_t launch_plain_step(bool f32, const PlainArgs &a, hipStream_t s) {
         hipLaunchKernelGGL((k_plain_tri<double, false>), dim3(ge), dim3(256), 0, s, a);
         hipLaunchKernelGGL((k_plain_vtx<double, false>), dim3(gv), dim3(256), 0, s, a);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_step(bool f32, const AdjArgs &a, hipStream_t s) {
+    const int ge = static_cast<int>((a.ne + 255) / 256), gv = static_cast<int>((a.nv + 255) / 256);
+    if (f32) {
+        hipLaunchKernelGGL((k_adj_tri<float, true>), dim3(ge), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((k_adj_vtx<float>), dim3(gv), dim3(256), 0, s, a);
+    } else {
+        hipLaunchKernelGGL((k_adj_tri<double, false>), dim3(ge), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((k_adj_vtx<double>), dim3(gv), dim3(256), 0, s, a);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_init(bool f32, const AdjArgs &a, const void *seed_eta, const void *seed_U,
+                           hipStream_t s) {
+    const int64_t n = std::max<int64_t>(a.nv, 2 * a.ne);
+    const int g = static_cast<int>((n + 255) / 256);
+    if (f32)
+        hipLaunchKernelGGL((k_adj_init<float>), dim3(g), dim3(256), 0, s, a,
+                           static_cast<const float *>(seed_eta), static_cast<const float *>(seed_U));
+    else
+        hipLaunchKernelGGL((k_adj_init<double>), dim3(g), dim3(256), 0, s, a,
+                           static_cast<const double *>(seed_eta),
+                           static_cast<const double *>(seed_U));
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_final(bool f32, const AdjArgs &a, hipStream_t s) {
+    const int g = static_cast<int>((2 * a.ne + 255) / 256);
+    if (f32)
+        hipLaunchKernelGGL((k_adj_final<float>), dim3(g), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_adj_final<double>), dim3(g), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

@@ -372,6 +372,9 @@ se_status build_tiles(const std::vector<const HostMesh *> &members,
                 return SE_ERR_ARG;
             }
             out.cs_row.push_back(static_cast<uint16_t>(nent));
+            // pad both chunks to multiples of 4 entries (8-byte vector loads)
+            while (out.cs_row.size() % 4) out.cs_row.push_back(0);
+            while (out.cs_ent.size() % 4) out.cs_ent.push_back(0);
             out.max_nv = std::max(out.max_nv, nVl[K]);
             out.max_ne = std::max(out.max_ne, nEl[K]);
             out.max_nvu = std::max(out.max_nvu, nvu);

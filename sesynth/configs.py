@@ -70,9 +70,18 @@ def _rms_scale(v, target):
 
 
 def _smooth_noise(r, shape, sigma, wrap_x=True):
+    """Gaussian-filtered white noise, unit variance, statistically uniform up to the edges.
+
+    The noise is drawn on a grid padded by 3 sigma on every non-periodic side and
+    cropped after filtering, so edge rows are no rougher or larger than the interior.
+    """
     from scipy.ndimage import gaussian_filter
-    z = r.standard_normal(shape)
+    pad = int(np.ceil(3 * sigma))
+    ny, nx = shape
+    px = 0 if wrap_x else pad
+    z = r.standard_normal((ny + 2 * pad, nx + 2 * px))
     z = gaussian_filter(z, sigma=sigma, mode=("nearest", "wrap" if wrap_x else "nearest"))
+    z = z[pad:pad + ny, px:px + nx]
     z = z - z.mean()
     return z / max(z.std(), 1e-300)
 
