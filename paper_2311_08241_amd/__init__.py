@@ -5,7 +5,7 @@ include/sesub.h; this package marshals arguments to it.  Importing the
 package does not load the library; the first call does, and fails with
 ImportError if it has not been built.
 """
-from .api import Mesh, Params, device_inputs  # noqa: F401
+from .api import Batch, Mesh, Params, batch_inputs, device_inputs  # noqa: F401
 
 
 def subcycle_autograd(*args, **kw):

@@ -249,6 +249,118 @@ class Mesh:
         return bits.value
 
 
+class Batch:
+    """Ensemble of independent meshes advanced together (se_batch_create).
+
+    Field tensors are the members' internal-numbering arrays concatenated in
+    member order (vertex arrays at vert_offset, triangle arrays at elem_offset).
+    """
+
+    def __init__(self, meshes):
+        self.meshes = list(meshes)
+        arr = (ctypes.c_void_p * len(self.meshes))(*[m.handle.value for m in self.meshes])
+        h = ctypes.c_void_p()
+        L.check(L.lib().se_batch_create(arr, len(self.meshes), ctypes.byref(h)))
+        self._h = h
+        self.device = self.meshes[0].device
+        n = len(self.meshes)
+        nv, ne = ctypes.c_int64(), ctypes.c_int64()
+        vo = (ctypes.c_int64 * (n + 1))()
+        eo = (ctypes.c_int64 * (n + 1))()
+        L.check(L.lib().se_batch_info(h, ctypes.byref(nv), ctypes.byref(ne), vo, eo))
+        self.nv, self.ne = nv.value, ne.value
+        self.vert_offset = np.array(vo[:], np.int64)
+        self.elem_offset = np.array(eo[:], np.int64)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            L.lib().se_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def signature(self) -> str:
+        from .autotune import mesh_signature
+        return "+".join(mesh_signature(m) for m in self.meshes)
+
+    def set_plan(self, tile: int, k_fused: int, block: int = 256):
+        L.check(L.lib().se_set_plan(self._h, 1, int(tile), int(k_fused), int(block)))
+
+    def get_plan(self):
+        t, k, b = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        L.check(L.lib().se_get_plan(self._h, 1, ctypes.byref(t), ctypes.byref(k), ctypes.byref(b)))
+        return t.value, k.value, b.value
+
+    def plan_stats(self, tile: int, k_fused: int, block: int = 256) -> dict:
+        st = L.PlanStats()
+        L.check(L.lib().se_plan_stats(self._h, 1, int(tile), int(k_fused), int(block),
+                                      ctypes.byref(st)))
+        return st.as_dict()
+
+    def volume_size(self, params: Params, nsub) -> int:
+        return int(sum((k + 1) if params.track_volume else 2 for k in nsub))
+
+    def workspace(self, params: Params, nsub):
+        torch = _torch()
+        ns = (ctypes.c_int32 * len(nsub))(*[int(k) for k in nsub])
+        n = ctypes.c_size_t()
+        pc = params.c()
+        L.check(L.lib().se_batch_workspace_bytes(self._h, ctypes.byref(pc), ns, ctypes.byref(n)))
+        return torch.empty(max(n.value, 256), dtype=torch.uint8, device=f"cuda:{self.device}")
+
+    def subcycle(self, eta, U, *, R, f, H0, W=None, nsub, dt, params: Params, Uavg=None,
+                 volume=None, workspace=None, use_graph=False, stream=None):
+        """se_subcycle_batched: one baroclinic step of every member."""
+        torch = _torch()
+        dt_ = params.dtype
+        chk = Mesh._check_tensor
+        chk(self, eta, self.nv, "eta", dt_)
+        chk(self, U, self.ne, "U", dt_, 2)
+        chk(self, R, self.ne, "R", dt_, 2)
+        chk(self, f, self.ne, "f", dt_)
+        chk(self, H0, self.nv, "H0", dt_)
+        chk(self, W, self.nv, "W", dt_, allow_none=True)
+        chk(self, Uavg, self.ne, "Uavg", torch.float64, 2, allow_none=True)
+        chk(self, volume, self.volume_size(params, nsub), "volume", torch.float64, allow_none=True)
+        if len(nsub) != len(self.meshes) or len(dt) != len(self.meshes):
+            raise ValueError("nsub and dt need one entry per member")
+        if workspace is None:
+            workspace = self.workspace(params, nsub)
+        ns = (ctypes.c_int32 * len(nsub))(*[int(k) for k in nsub])
+        dts = (ctypes.c_double * len(dt))(*[float(v) for v in dt])
+        st = L.State(_ptr(eta), _ptr(U), _ptr(Uavg), _ptr(volume))
+        fo = L.Forcing(_ptr(R), _ptr(f), _ptr(H0), _ptr(W))
+        pc = params.c()
+        L.check(L.lib().se_subcycle_batched(self._h, ctypes.byref(pc), ctypes.byref(st),
+                                            ctypes.byref(fo), ns, dts, int(bool(use_graph)),
+                                            _ptr(workspace), _stream_ptr(stream)))
+        return eta, U, Uavg, volume
+
+    def check_faults(self, stream=None) -> int:
+        bits = ctypes.c_uint32()
+        L.check(L.lib().se_check_faults(self._h, 1, _stream_ptr(stream), ctypes.byref(bits)))
+        return bits.value
+
+
+def batch_inputs(batch: Batch, cases, params: Params):
+    """Concatenate generated member workloads into device tensors (internal numbering)."""
+    parts = [device_inputs(m, c, params) for m, c in zip(batch.meshes, cases)]
+    torch = _torch()
+    out = {}
+    for k in ("eta", "U", "R", "f", "H0"):
+        out[k] = torch.cat([p[k] for p in parts]).contiguous()
+    out["W"] = None
+    return out
+
+
 def device_inputs(mesh: Mesh, case: dict, params: Params, device=None):
     """Move a generated workload's fields to the device in the mesh's numbering.
 

@@ -24,6 +24,8 @@ CACHE = os.environ.get("SESUB_TUNE_CACHE",
 
 
 def mesh_signature(mesh) -> str:
+    if hasattr(mesh, "signature"):
+        return hashlib.sha256(mesh.signature().encode()).hexdigest()[:20]
     h = hashlib.sha256()
     tri, row, col = mesh.csr()
     h.update(np.int64([mesh.nv, mesh.ne]).tobytes())

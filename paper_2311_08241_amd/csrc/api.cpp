@@ -461,10 +461,17 @@ se_status se_mesh_geometry(const se_mesh *m, double *Av, double *Ae, double *gN)
     return SE_OK;
 }
 
+se_status se_batch_set_plan_impl(se_batch *b, int32_t tile, int32_t k_fused, int32_t block);
+se_status se_batch_get_plan_impl(const se_batch *b, int32_t *tile, int32_t *k_fused, int32_t *block);
+se_status se_batch_plan_stats_impl(const se_batch *b, int32_t tile, int32_t k_fused, int32_t block,
+                                   se_plan_stats_t *stats);
+se_status se_batch_faults_impl(se_batch *b, void *stream, uint32_t *bits);
+
 se_status se_set_plan(void *obj, int32_t kind, int32_t tile, int32_t k_fused, int32_t block) {
+    if (obj && kind == 1) return se_batch_set_plan_impl(static_cast<se_batch *>(obj), tile, k_fused, block);
     if (!obj || kind != 0) {
-        set_error("se_set_plan: null object or unsupported kind");
-        return obj ? SE_ERR_UNSUPPORTED : SE_ERR_ARG;
+        set_error("se_set_plan: null object or unknown kind (0 mesh, 1 batch)");
+        return SE_ERR_ARG;
     }
     se_mesh *m = static_cast<se_mesh *>(obj);
     if (m->device < 0) {   // host-only mesh: validate and remember the plan
@@ -490,6 +497,8 @@ se_status se_set_plan(void *obj, int32_t kind, int32_t tile, int32_t k_fused, in
 
 se_status se_get_plan(const void *obj, int32_t kind, int32_t *tile, int32_t *k_fused,
                       int32_t *block) {
+    if (obj && kind == 1)
+        return se_batch_get_plan_impl(static_cast<const se_batch *>(obj), tile, k_fused, block);
     if (!obj || kind != 0) {
         set_error("se_get_plan: null object or unsupported kind");
         return SE_ERR_ARG;
@@ -503,6 +512,9 @@ se_status se_get_plan(const void *obj, int32_t kind, int32_t *tile, int32_t *k_f
 
 se_status se_plan_stats(const void *obj, int32_t kind, int32_t tile, int32_t k_fused,
                         int32_t block, se_plan_stats_t *stats) {
+    if (obj && stats && kind == 1)
+        return se_batch_plan_stats_impl(static_cast<const se_batch *>(obj), tile, k_fused, block,
+                                        stats);
     if (!obj || !stats || kind != 0) {
         set_error("se_plan_stats: bad argument");
         return SE_ERR_ARG;
@@ -599,12 +611,12 @@ se_status se_subcycle(se_mesh *m, const se_params *p, se_state *st, const se_for
     void *eta_w = w + L.eta_alt, *U_w = w + L.U_alt;
     const int nlaunch = (nsub + P.K - 1) / P.K;
     const size_t lds = f32 ? P.lds_bytes32 : P.lds_bytes64;
+    HIP_TRY(prepare_tile(f32, P.ept, P.block), "se_subcycle prepare");
+    a.eta_u = eta_u;
+    a.eta_w = eta_w;
+    a.U_u = U_u;
+    a.U_w = U_w;
     for (int ch = 0; ch < nlaunch; ++ch) {
-        const bool even = (ch % 2) == 0;
-        a.eta_in = even ? eta_u : eta_w;
-        a.eta_out = even ? eta_w : eta_u;
-        a.U_in = even ? U_u : U_w;
-        a.U_out = even ? U_w : U_u;
         a.chunk = ch;
         HIP_TRY(launch_tile(f32, P.ept, P.block, a, P.ntiles, lds, s), "se_subcycle launch");
     }
@@ -677,6 +689,7 @@ se_status se_subcycle_plain(se_mesh *m, const se_params *p, se_state *st, const 
 }
 
 se_status se_check_faults(void *obj, int32_t kind, void *stream, uint32_t *bits) {
+    if (obj && bits && kind == 1) return se_batch_faults_impl(static_cast<se_batch *>(obj), stream, bits);
     if (!obj || !bits || kind != 0) {
         set_error("se_check_faults: bad argument");
         return SE_ERR_ARG;
@@ -810,21 +823,436 @@ se_status se_subcycle_adjoint(se_mesh *m, const se_params *p, const void *eta0, 
     return SE_OK;
 }
 
-se_status se_batch_create(se_mesh *const *, int32_t, se_batch **out) {
-    if (out) *out = nullptr;
-    set_error("se_batch_create: not built yet");
-    return SE_ERR_UNSUPPORTED;
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batched ensemble: a disjoint union of member meshes sharing one tile table
+// ---------------------------------------------------------------------------
+struct se_batch {
+    int device = 0;
+    std::vector<sesub::HostMesh> h;
+    std::vector<int64_t> voff, eoff;
+    int64_t nv = 0, ne = 0;
+    std::vector<double> atot;            // per member total area
+    sesub::DevBuf Av64, Av32, faults, table, lists;
+    std::vector<sesub::StepC> table_host;
+    std::vector<int32_t> list_off;       // per launch offset into lists (size nlaunch + 1)
+    std::unique_ptr<sesub::DevTiles> plan;
+    int32_t plan_T = 768, plan_K = 4, plan_block = 512;
+    std::vector<int32_t> mtiles, mtile_first;
+    struct Graph {
+        std::vector<uint64_t> key;
+        hipGraph_t g = nullptr;
+        hipGraphExec_t x = nullptr;
+    };
+    std::vector<Graph> graphs;
+    void drop_graphs() {
+        for (auto &gr : graphs) {
+            if (gr.x) (void)hipGraphExecDestroy(gr.x);
+            if (gr.g) (void)hipGraphDestroy(gr.g);
+        }
+        graphs.clear();
+    }
+    ~se_batch() { drop_graphs(); }
+};
+
+namespace sesub {
+namespace {
+
+std::vector<const HostMesh *> batch_members(const se_batch *b) {
+    std::vector<const HostMesh *> v;
+    for (const auto &m : b->h) v.push_back(&m);
+    return v;
 }
-void se_batch_destroy(se_batch *) {}
-se_status se_batch_info(const se_batch *, int64_t *, int64_t *, int64_t *, int64_t *) {
-    return SE_ERR_UNSUPPORTED;
+
+se_status batch_install_plan(se_batch *b, int32_t T, int32_t K, int32_t block) {
+    std::unique_ptr<DevTiles> p;
+    SE_TRY(make_plan(batch_members(b), b->voff, b->eoff, T, K, block, p));
+    const size_t n = b->h.size();
+    b->mtiles.assign(n, 0);
+    b->mtile_first.assign(n, -1);
+    for (size_t t = 0; t < p->hdr_host.size(); ++t) {
+        const int mb = p->hdr_host[t].member;
+        if (b->mtile_first[mb] < 0) b->mtile_first[mb] = static_cast<int32_t>(t);
+        b->mtiles[mb]++;
+    }
+    b->plan = std::move(p);
+    b->plan_T = T;
+    b->plan_K = K;
+    b->plan_block = block;
+    b->table_host.clear();   // forces a new schedule
+    b->drop_graphs();
+    return SE_OK;
 }
-se_status se_batch_workspace_bytes(const se_batch *, const se_params *, const int32_t *, size_t *) {
-    return SE_ERR_UNSUPPORTED;
+
+se_status batch_ensure_plan(se_batch *b) {
+    if (b->plan) return SE_OK;
+    static const int32_t cand[][3] = {{768, 4, 512}, {512, 4, 512}, {512, 2, 512}, {256, 4, 512},
+                                      {256, 2, 256}, {128, 2, 256}, {64, 1, 256}};
+    for (const auto &c : cand) {
+        HostTiles ht;
+        se_plan_stats_t st;
+        if (plan_host(batch_members(b), b->voff, b->eoff, c[0], c[1], c[2], ht, st) != SE_OK)
+            continue;
+        if (!st.ok_f32 || !st.ok_f64) continue;
+        return batch_install_plan(b, c[0], c[1], c[2]);
+    }
+    set_error("no default plan fits this batch");
+    return SE_ERR_ARG;
 }
-se_status se_subcycle_batched(se_batch *, const se_params *, se_state *, const se_forcing *,
-                              const int32_t *, const double *, int, void *, void *) {
-    return SE_ERR_UNSUPPORTED;
+
+int64_t batch_vol_rows(const se_params *p, const int32_t *nsub, size_t i) {
+    return (p->flags & SE_TRACK_VOLUME) ? nsub[i] + 1 : 2;
+}
+
+struct BatchLayout {
+    size_t eta_alt, U_alt, sum, U0c, vol, total;
+    std::vector<int64_t> vol_off;   // per member offset (elements) into vol partials
+};
+
+BatchLayout batch_layout(const se_batch *b, bool f32, const se_params *p, const int32_t *nsub) {
+    const size_t s = f32 ? 4 : 8;
+    BatchLayout L{};
+    size_t o = 0;
+    L.eta_alt = o;
+    o += al(b->nv * s);
+    L.U_alt = o;
+    o += al(2 * b->ne * s);
+    L.sum = o;
+    o += al(16 * b->ne);
+    L.U0c = o;
+    o += al(2 * b->ne * s);
+    L.vol = o;
+    int64_t acc = 0;
+    for (size_t i = 0; i < b->h.size(); ++i) {
+        L.vol_off.push_back(acc);
+        acc += batch_vol_rows(p, nsub, i) * ((b->h[i].nv + 63) / 64);
+    }
+    o += al(acc * 8);
+    L.total = o;
+    return L;
+}
+
+}  // namespace
+}  // namespace sesub
+
+extern "C" {
+
+se_status se_batch_create(se_mesh *const *members, int32_t n, se_batch **out) {
+    if (!members || n < 1 || !out) {
+        set_error("se_batch_create: need n >= 1 members and an output pointer");
+        return SE_ERR_ARG;
+    }
+    *out = nullptr;
+    auto b = std::make_unique<se_batch>();
+    b->device = members[0] ? members[0]->device : -1;
+    b->voff.push_back(0);
+    b->eoff.push_back(0);
+    for (int32_t i = 0; i < n; ++i) {
+        if (!members[i] || members[i]->device != b->device) {
+            set_error("se_batch_create: null member or members on different devices");
+            return SE_ERR_ARG;
+        }
+        b->h.push_back(members[i]->h);
+        b->voff.push_back(b->voff.back() + members[i]->h.nv);
+        b->eoff.push_back(b->eoff.back() + members[i]->h.ne);
+    }
+    b->nv = b->voff.back();
+    b->ne = b->eoff.back();
+    if (b->nv >= (int64_t(1) << 31) || b->ne >= (int64_t(1) << 30)) {
+        set_error("se_batch_create: batch too large for 32-bit indices");
+        return SE_ERR_ARG;
+    }
+    std::vector<double> av;
+    av.reserve(b->nv);
+    for (const auto &m : b->h) {
+        double s = 0.0;
+        for (double v : m.Av) s += v;
+        b->atot.push_back(s);
+        av.insert(av.end(), m.Av.begin(), m.Av.end());
+    }
+    if (b->device >= 0) {
+        DeviceGuard dg(b->device);
+        SE_TRY(b->Av64.upload(av.data(), av.size() * 8));
+        std::vector<float> av32(av.begin(), av.end());
+        SE_TRY(b->Av32.upload(av32.data(), av32.size() * 4));
+        const uint32_t zero = 0;
+        SE_TRY(b->faults.upload(&zero, 4));
+    }
+    *out = b.release();
+    return SE_OK;
+}
+
+void se_batch_destroy(se_batch *b) {
+    if (!b) return;
+    if (b->device < 0) {
+        delete b;
+        return;
+    }
+    DeviceGuard dg(b->device);
+    delete b;
+}
+
+se_status se_batch_info(const se_batch *b, int64_t *nv_total, int64_t *ne_total,
+                        int64_t *vert_offset, int64_t *elem_offset) {
+    if (!b) {
+        set_error("se_batch_info: null batch");
+        return SE_ERR_ARG;
+    }
+    if (nv_total) *nv_total = b->nv;
+    if (ne_total) *ne_total = b->ne;
+    if (vert_offset) std::memcpy(vert_offset, b->voff.data(), b->voff.size() * 8);
+    if (elem_offset) std::memcpy(elem_offset, b->eoff.data(), b->eoff.size() * 8);
+    return SE_OK;
+}
+
+se_status se_batch_workspace_bytes(const se_batch *b, const se_params *p, const int32_t *nsub,
+                                   size_t *bytes) {
+    if (!b || !p || !nsub || !bytes) {
+        set_error("se_batch_workspace_bytes: bad argument");
+        return SE_ERR_ARG;
+    }
+    for (size_t i = 0; i < b->h.size(); ++i)
+        if (nsub[i] < 1) {
+            set_error("se_batch_workspace_bytes: nsub must be >= 1");
+            return SE_ERR_ARG;
+        }
+    *bytes = batch_layout(b, p->precision == SE_F32_MIXED, p, nsub).total;
+    return SE_OK;
+}
+
+se_status se_subcycle_batched(se_batch *b, const se_params *p, se_state *st, const se_forcing *fo,
+                              const int32_t *nsub, const double *dt, int use_graph, void *ws,
+                              void *stream) {
+    if (!b || !p || !nsub || !dt) {
+        set_error("se_subcycle_batched: null argument");
+        return SE_ERR_ARG;
+    }
+    SE_TRY(check_state(st, fo, ws));
+    if (b->device < 0) {
+        set_error("host-only batch cannot run kernels");
+        return SE_ERR_ARG;
+    }
+    const size_t n = b->h.size();
+    // per-member validation (CFL uses each member's own spectral bound)
+    for (size_t i = 0; i < n; ++i) {
+        se_mesh probe;
+        probe.h.mu_max = b->h[i].mu_max;
+        SE_TRY(check_params(&probe, p, nsub[i], dt[i]));
+    }
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    if (use_graph && s == nullptr) {
+        set_error("se_subcycle_batched: graph capture needs a non-default stream");
+        return SE_ERR_ARG;
+    }
+    DeviceGuard dg(b->device);
+    SE_TRY(batch_ensure_plan(b));
+    const DevTiles &P = *b->plan;
+    const bool f32 = p->precision == SE_F32_MIXED;
+    if (!(f32 ? P.ok32 : P.ok64)) {
+        set_error("se_subcycle_batched: plan does not fit this precision");
+        return SE_ERR_ARG;
+    }
+    const BatchLayout L = batch_layout(b, f32, p, nsub);
+    const int32_t K = P.K;
+
+    // member constants and launch offsets (balance the active tiles per launch)
+    std::vector<StepC> tab(n);
+    std::vector<int32_t> Lm(n), order(n);
+    int32_t Lmax = 0;
+    for (size_t i = 0; i < n; ++i) {
+        Lm[i] = (nsub[i] + K - 1) / K;
+        Lmax = std::max(Lmax, Lm[i]);
+        order[i] = static_cast<int32_t>(i);
+    }
+    std::sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+        return Lm[x] != Lm[y] ? Lm[x] > Lm[y] : b->mtiles[x] > b->mtiles[y];
+    });
+    std::vector<int64_t> load(Lmax, 0);
+    std::vector<int32_t> off(n, 0);
+    for (int32_t i : order) {
+        int32_t best = 0;
+        int64_t best_peak = -1;
+        for (int32_t o = 0; o + Lm[i] <= Lmax; ++o) {
+            int64_t peak = 0;
+            for (int32_t c = o; c < o + Lm[i]; ++c) peak = std::max(peak, load[c]);
+            if (best_peak < 0 || peak < best_peak) {
+                best_peak = peak;
+                best = o;
+            }
+        }
+        off[i] = best;
+        for (int32_t c = best; c < best + Lm[i]; ++c) load[c] += b->mtiles[i];
+    }
+    for (size_t i = 0; i < n; ++i) {
+        tab[i] = make_step(p, nsub[i], dt[i]);
+        tab[i].ntiles = b->mtiles[i];
+        tab[i].vol_off = L.vol_off[i];
+        tab[i].chunk0 = off[i];
+    }
+    const bool same = b->table_host.size() == n &&
+                      std::memcmp(b->table_host.data(), tab.data(), n * sizeof(StepC)) == 0;
+    if (!same) {
+        // new configuration: upload constants and per-launch tile lists
+        HIP_TRY(hipStreamSynchronize(s), "batched: sync before table update");
+        std::vector<int32_t> lists;
+        std::vector<int32_t> loff{0};
+        for (int32_t c = 0; c < Lmax; ++c) {
+            for (size_t i = 0; i < n; ++i)
+                if (c >= off[i] && c < off[i] + Lm[i])
+                    for (int32_t t = 0; t < b->mtiles[i]; ++t) lists.push_back(b->mtile_first[i] + t);
+            loff.push_back(static_cast<int32_t>(lists.size()));
+        }
+        SE_TRY(b->table.upload(tab.data(), n * sizeof(StepC)));
+        SE_TRY(b->lists.upload(lists.data(), std::max<size_t>(lists.size(), 1) * 4));
+        b->list_off = loff;
+        b->table_host = tab;
+        b->drop_graphs();
+    }
+    char *w = static_cast<char *>(ws);
+    TileArgs a{};
+    a.hdr = P.hdr.as<const TileHdrK>();
+    a.nV = P.nV.as<const int32_t>();
+    a.nE = P.nE.as<const int32_t>();
+    a.lv_gid = P.lv_gid.as<const int32_t>();
+    a.le_gid = P.le_gid.as<const int32_t>();
+    a.le_tri = P.le_tri.as<const uint32_t>();
+    a.cs_row = P.cs_row.as<const uint16_t>();
+    a.cs_ent = P.cs_ent.as<const uint16_t>();
+    a.lgeom = f32 ? P.geom32.p : P.geom64.p;
+    a.lgeom_stride = static_cast<int64_t>(P.geom64.n / 8 / 5);
+    a.mem = b->table.as<const StepC>();
+    a.R = fo->R;
+    a.f = fo->f;
+    a.H0 = fo->H0;
+    a.W = fo->W;
+    a.Av = f32 ? b->Av32.p : b->Av64.p;
+    a.Av64 = b->Av64.as<const double>();
+    a.sum = w + L.sum;
+    a.U0c = w + L.U0c;
+    a.Uavg = st->Uavg;
+    a.vol_part = reinterpret_cast<double *>(w + L.vol);
+    a.faults = b->faults.as<uint32_t>();
+    a.K = K;
+    a.xcd = 1;
+    a.cap_nv = P.max_nv;
+    a.cap_ne = P.max_ne;
+    a.cap_nvu = P.max_nvu;
+    a.cap_cs = P.max_cs;
+    a.eta_u = st->eta;
+    a.eta_w = w + L.eta_alt;
+    a.U_u = st->U;
+    a.U_w = w + L.U_alt;
+    const size_t es = f32 ? 4 : 8;
+    const size_t lds = f32 ? P.lds_bytes32 : P.lds_bytes64;
+    HIP_TRY(prepare_tile(f32, P.ept, P.block), "batched prepare");
+
+    auto enqueue = [&]() -> se_status {
+        for (int32_t c = 0; c < Lmax; ++c) {
+            const int32_t cnt = b->list_off[c + 1] - b->list_off[c];
+            if (cnt == 0) continue;
+            a.chunk = c;
+            a.tile_list = b->lists.as<const int32_t>() + b->list_off[c];
+            a.ntiles = cnt;
+            HIP_TRY(launch_tile(f32, P.ept, P.block, a, cnt, lds, s), "batched launch");
+        }
+        int64_t vout = 0;
+        for (size_t i = 0; i < n; ++i) {
+            if (Lm[i] % 2 == 1) {   // this member's final state sits in the ping-pong buffers
+                HIP_TRY(hipMemcpyAsync(static_cast<char *>(st->eta) + b->voff[i] * es,
+                                       w + L.eta_alt + b->voff[i] * es, b->h[i].nv * es,
+                                       hipMemcpyDeviceToDevice, s), "batched copy eta");
+                HIP_TRY(hipMemcpyAsync(static_cast<char *>(st->U) + 2 * b->eoff[i] * es,
+                                       w + L.U_alt + 2 * b->eoff[i] * es, 2 * b->h[i].ne * es,
+                                       hipMemcpyDeviceToDevice, s), "batched copy U");
+            }
+            const int64_t rows = batch_vol_rows(p, nsub, i);
+            if (st->volume) {
+                const double add = f32 ? p->eta_ref * b->atot[i] : 0.0;
+                HIP_TRY(launch_vol_reduce(a.vol_part + L.vol_off[i], b->mtiles[i],
+                                          static_cast<int32_t>(rows), add, st->volume + vout, s),
+                        "batched volume");
+            }
+            vout += rows;
+        }
+        return SE_OK;
+    };
+
+    if (!use_graph) return enqueue();
+    std::vector<uint64_t> key = {
+        reinterpret_cast<uint64_t>(st->eta), reinterpret_cast<uint64_t>(st->U),
+        reinterpret_cast<uint64_t>(st->Uavg), reinterpret_cast<uint64_t>(st->volume),
+        reinterpret_cast<uint64_t>(fo->R), reinterpret_cast<uint64_t>(fo->f),
+        reinterpret_cast<uint64_t>(fo->H0), reinterpret_cast<uint64_t>(fo->W),
+        reinterpret_cast<uint64_t>(ws), reinterpret_cast<uint64_t>(s),
+        static_cast<uint64_t>(p->precision), static_cast<uint64_t>(p->flags)};
+    for (auto &gr : b->graphs) {
+        if (gr.key == key) {
+            HIP_TRY(hipGraphLaunch(gr.x, s), "batched graph launch");
+            return SE_OK;
+        }
+    }
+    se_batch::Graph gr;
+    gr.key = key;
+    HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "begin capture");
+    const se_status es_ = enqueue();
+    hipGraph_t g = nullptr;
+    const hipError_t ee = hipStreamEndCapture(s, &g);
+    if (es_ != SE_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return es_;
+    }
+    if (ee != hipSuccess) return hip_fail(ee, "end capture");
+    gr.g = g;
+    HIP_TRY(hipGraphInstantiate(&gr.x, g, nullptr, nullptr, 0), "graph instantiate");
+    b->graphs.push_back(gr);
+    HIP_TRY(hipGraphLaunch(gr.x, s), "batched graph launch");
+    return SE_OK;
+}
+
+
+se_status se_batch_set_plan_impl(se_batch *b, int32_t tile, int32_t k_fused, int32_t block) {
+    if (b->device < 0) {
+        HostTiles ht;
+        se_plan_stats_t st;
+        SE_TRY(plan_host(batch_members(b), b->voff, b->eoff, tile, k_fused, block, ht, st));
+        b->plan_T = tile;
+        b->plan_K = k_fused;
+        b->plan_block = block;
+        return SE_OK;
+    }
+    DeviceGuard dg(b->device);
+    return batch_install_plan(b, tile, k_fused, block);
+}
+
+se_status se_batch_get_plan_impl(const se_batch *b, int32_t *tile, int32_t *k_fused,
+                                 int32_t *block) {
+    if (tile) *tile = b->plan_T;
+    if (k_fused) *k_fused = b->plan_K;
+    if (block) *block = b->plan_block;
+    return SE_OK;
+}
+
+se_status se_batch_plan_stats_impl(const se_batch *b, int32_t tile, int32_t k_fused,
+                                   int32_t block, se_plan_stats_t *stats) {
+    HostTiles ht;
+    return plan_host(batch_members(b), b->voff, b->eoff, tile, k_fused, block, ht, *stats);
+}
+
+se_status se_batch_faults_impl(se_batch *b, void *stream, uint32_t *bits) {
+    if (b->device < 0) {
+        set_error("host-only batch has no fault word");
+        return SE_ERR_ARG;
+    }
+    DeviceGuard dg(b->device);
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    HIP_TRY(hipStreamSynchronize(s), "se_check_faults sync");
+    uint32_t v = 0;
+    HIP_TRY(hipMemcpy(&v, b->faults.p, 4, hipMemcpyDeviceToHost), "se_check_faults copy");
+    const uint32_t zero = 0;
+    HIP_TRY(hipMemcpy(b->faults.p, &zero, 4, hipMemcpyHostToDevice), "se_check_faults reset");
+    *bits = v;
+    return SE_OK;
 }
 
 }  // extern "C"

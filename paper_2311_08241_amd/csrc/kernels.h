@@ -11,7 +11,7 @@ namespace sesub {
 struct StepC {
     double dts, g, theta, opt, thM, Mdbl, eta_ref;   // opt = 1 + theta, thM = theta / M
     float dts_f, g_f, theta_f, opt_f, eta_ref_f, pad_f;
-    int32_t nsub, flags, ntiles, pad_i;
+    int32_t nsub, flags, ntiles, chunk0;   // chunk0: first launch index of this member
     int64_t vol_off;    // offset of this member's volume partials
 };
 
@@ -30,10 +30,8 @@ struct TileArgs {
     int64_t lgeom_stride;
     const StepC *mem;           // per-member constants (batches); nullptr: use c0
     StepC c0;
-    const void *eta_in;
-    void *eta_out;
-    const void *U_in;
-    void *U_out;
+    void *eta_u, *eta_w;        // ping-pong pair: member chunk ch reads (ch even ? u : w)
+    void *U_u, *U_w;
     const void *R, *f, *H0, *W, *Av;
     const double *Av64;
     void *sum;                  // double2 (FP64) or float4 (FP32 hi/lo pairs) per triangle
@@ -41,6 +39,7 @@ struct TileArgs {
     double *Uavg;
     double *vol_part;
     uint32_t *faults;
+    const int32_t *tile_list;   // tiles of this launch (nullptr: all ntiles)
     int32_t K, chunk, ntiles, xcd;
     int32_t cap_nv, cap_ne, cap_nvu, cap_cs;
 };
@@ -89,6 +88,9 @@ hipError_t launch_adj_init(bool f32, const AdjArgs &a, const void *seed_eta, con
                            hipStream_t s);
 // lam_U -= thrM * lam_Uavg
 hipError_t launch_adj_final(bool f32, const AdjArgs &a, hipStream_t s);
+// Raise the dynamic-LDS limit of a tile kernel instantiation (call before any
+// stream capture that launches it).
+hipError_t prepare_tile(bool f32, int ept, int block);
 int tile_lds_bytes(bool f32, int block, int K, int cap_nv, int cap_ne, int cap_nvu, int cap_cs);
 
 }  // namespace sesub

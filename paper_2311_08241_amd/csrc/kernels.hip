@@ -241,11 +241,15 @@ __global__ void __launch_bounds__(BLOCK) k_tile(TileArgs a) {
         b = x * base + (x < rem ? x : rem) + q;
     }
     if (b >= a.ntiles) return;
+    if (a.tile_list) b = a.tile_list[b];
     const TileHdrK h = a.hdr[b];
     const StepC c = a.mem ? a.mem[h.member] : a.c0;
     const int K = a.K;
-    const int m0 = a.chunk * K;
+    const int ch = a.chunk - c.chunk0;   // this member's chunk index
+    if (ch < 0) return;
+    const int m0 = ch * K;
     if (m0 >= c.nsub) return;
+    const bool even = (ch & 1) == 0;
     const int cnt = min(K, c.nsub - m0);
     const bool first = m0 == 0, last = m0 + cnt == c.nsub;
     const bool track = (c.flags & KF_TRACK_VOLUME) != 0;
@@ -275,7 +279,7 @@ __global__ void __launch_bounds__(BLOCK) k_tile(TileArgs a) {
     uint16_t *sEnt = reinterpret_cast<uint16_t *>(smem + off);
 
     // ---- stage vertex data (batches of 4 per thread: loads first, then LDS stores)
-    const T *eta_in = static_cast<const T *>(a.eta_in);
+    const T *eta_in = static_cast<const T *>(even ? a.eta_u : a.eta_w);
     const T *H0 = static_cast<const T *>(a.H0);
     const T *Avt = static_cast<const T *>(a.Av);
     const T *Wt = static_cast<const T *>(a.W);
@@ -327,7 +331,7 @@ __global__ void __launch_bounds__(BLOCK) k_tile(TileArgs a) {
     // ---- triangle state in registers
     const T *lg = static_cast<const T *>(a.lgeom) + h.le_off;
     const int64_t ls = a.lgeom_stride;
-    const T2 *Uin = static_cast<const T2 *>(a.U_in);
+    const T2 *Uin = static_cast<const T2 *>(even ? a.U_u : a.U_w);
     const T2 *Rg = static_cast<const T2 *>(a.R);
     const T *fg = static_cast<const T *>(a.f);
     const T dts = cdts<T>(c);
@@ -474,9 +478,9 @@ __global__ void __launch_bounds__(BLOCK) k_tile(TileArgs a) {
     if (bad_any) set_fault(a.faults, 2u);
 
     // write back owned vertices and triangles
-    T *eta_out = static_cast<T *>(a.eta_out);
+    T *eta_out = static_cast<T *>(even ? a.eta_w : a.eta_u);
     for (int i = tid; i < h.nv0; i += BLOCK) eta_out[h.vbase + i] = sEta[i];
-    T2 *Uout = static_cast<T2 *>(a.U_out);
+    T2 *Uout = static_cast<T2 *>(even ? a.U_w : a.U_u);
 #pragma unroll
     for (int r = 0; r < EPT; ++r) {
         const int le = tid + r * BLOCK;
@@ -662,21 +666,17 @@ __global__ void __launch_bounds__(256) k_vol_reduce(const double *part, int64_t 
 }
 
 template <typename T, bool F32, int EPT, int BLOCK>
-hipError_t launch_tile_t(const TileArgs &a, int grid, size_t lds, hipStream_t s) {
+hipError_t launch_tile_t(const TileArgs *a, int grid, size_t lds, hipStream_t s) {
     auto *kern = k_tile<T, F32, EPT, BLOCK>;
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        if (e != hipSuccess) return e;
-        attr_set = true;
-    }
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(BLOCK), lds, s, a);
+    if (!a)   // prepare only
+        return hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(BLOCK), lds, s, *a);
     return hipGetLastError();
 }
 
 template <typename T, bool F32, int BLOCK>
-hipError_t launch_tile_ept(int ept, const TileArgs &a, int grid, size_t lds, hipStream_t s) {
+hipError_t launch_tile_ept(int ept, const TileArgs *a, int grid, size_t lds, hipStream_t s) {
     switch (ept) {
         case 1: return launch_tile_t<T, F32, 1, BLOCK>(a, grid, lds, s);
         case 2: return launch_tile_t<T, F32, 2, BLOCK>(a, grid, lds, s);
@@ -686,6 +686,17 @@ hipError_t launch_tile_ept(int ept, const TileArgs &a, int grid, size_t lds, hip
         case 8: return launch_tile_t<T, F32, 8, BLOCK>(a, grid, lds, s);
         default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_tile_any(bool f32, int ept, int block, const TileArgs *a, int grid, size_t lds,
+                           hipStream_t s) {
+    if (block == 256)
+        return f32 ? launch_tile_ept<float, true, 256>(ept, a, grid, lds, s)
+                   : launch_tile_ept<double, false, 256>(ept, a, grid, lds, s);
+    if (block == 512)
+        return f32 ? launch_tile_ept<float, true, 512>(ept, a, grid, lds, s)
+                   : launch_tile_ept<double, false, 512>(ept, a, grid, lds, s);
+    return hipErrorInvalidValue;
 }
 
 }  // namespace
@@ -706,15 +717,13 @@ int tile_lds_bytes(bool f32, int block, int K, int cap_nv, int cap_ne, int cap_n
     return off;
 }
 
+hipError_t prepare_tile(bool f32, int ept, int block) {
+    return launch_tile_any(f32, ept, block, nullptr, 0, 0, nullptr);
+}
+
 hipError_t launch_tile(bool f32, int ept, int block, const TileArgs &a, int grid, size_t lds,
                        hipStream_t s) {
-    if (block == 256)
-        return f32 ? launch_tile_ept<float, true, 256>(ept, a, grid, lds, s)
-                   : launch_tile_ept<double, false, 256>(ept, a, grid, lds, s);
-    if (block == 512)
-        return f32 ? launch_tile_ept<float, true, 512>(ept, a, grid, lds, s)
-                   : launch_tile_ept<double, false, 512>(ept, a, grid, lds, s);
-    return hipErrorInvalidValue;
+    return launch_tile_any(f32, ept, block, &a, grid, lds, s);
 }
 
 hipError_t launch_plain_step(bool f32, const PlainArgs &a, hipStream_t s) {
