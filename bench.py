@@ -65,6 +65,139 @@ def read_traffic(workload_tag):
         return None
 
 
+def _time(fn, n, stream=None):
+    import torch
+    s = stream or torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(n):
+        fn()
+    e1.record(s)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / n
+
+
+def bench_batched(args, log):
+    """Ensemble of 64 jittered basins (10k-200k vertices, 20-120 substeps): one graph-captured
+    FP32 batched launch sequence vs a per-member loop of the plain FP64 path."""
+    import torch
+
+    import sesynth
+    from paper_2311_08241_amd import Batch, Mesh, Params, batch_inputs, device_inputs
+    from paper_2311_08241_amd.autotune import autotune
+    t0 = time.time()
+    cases = sesynth.batch_c4() if not args.small else sesynth.batch_c4(nmembers=8, nv_hi=30000)
+    meshes = [Mesh.from_dict(c, device=0) for c in cases]
+    batch = Batch(meshes)
+    nsub = [c["nsub"] for c in cases]
+    dts = [c["tau"] for c in cases]
+    work = float(sum(m.nv * k for m, k in zip(meshes, nsub)))
+    log(f"[bench] ensemble: {len(cases)} members, {batch.nv} vertices, "
+        f"{work:.3e} vertex-substeps per step ({time.time() - t0:.1f}s setup)")
+    eta_ref = float(np.mean(np.concatenate([c["eta0"] for c in cases])))
+    p32 = Params(precision="f32", eta_ref=eta_ref, track_volume=True)
+    p64 = Params(precision="f64", track_volume=True)
+    d32 = batch_inputs(batch, cases, p32)
+    stream = torch.cuda.Stream()
+    ws = batch.workspace(p32, nsub)
+    Uavg = torch.empty((batch.ne, 2), dtype=torch.float64, device="cuda:0")
+    vol = torch.empty(batch.volume_size(p32, nsub), dtype=torch.float64, device="cuda:0")
+    e_init, u_init = d32["eta"].clone(), d32["U"].clone()
+
+    def reset():
+        d32["eta"].copy_(e_init)
+        d32["U"].copy_(u_init)
+
+    def step(graph=True):
+        batch.subcycle(d32["eta"], d32["U"], R=d32["R"], f=d32["f"], H0=d32["H0"], nsub=nsub,
+                       dt=dts, params=p32, Uavg=Uavg, volume=vol, workspace=ws,
+                       use_graph=graph, stream=stream)
+    with torch.cuda.stream(stream):
+        tune = autotune(batch, lambda: step(False), "f32", max(nsub), log=log, reset=reset)
+        reset()
+        step(True)          # capture
+        stream.synchronize()
+        reset()
+        step(True)
+        stream.synchronize()
+        eta32 = d32["eta"].double().cpu().numpy() + eta_ref
+        ua32 = Uavg.cpu().numpy()
+        ms = _time(lambda: step(True), 5, stream)
+    faults = batch.check_faults(stream=stream)
+    log(f"[bench] ensemble FP32 batched (graph): {ms:.2f} ms/step, {work / ms * 1e3:.3e} "
+        f"vertex-substeps/s, plan {tune['plan']}")
+    # FP64 reference and baseline: per-member loop of the plain path
+    members64 = []
+    for m, c in zip(meshes, cases):
+        d = device_inputs(m, c, p64)
+        members64.append((m, c, d, torch.empty((m.ne, 2), dtype=torch.float64, device="cuda:0"),
+                          m.workspace(p64, c["nsub"]), d["eta"].clone(), d["U"].clone()))
+
+    def loop64():
+        for m, c, d, ua, w, _, _ in members64:
+            m.subcycle(d["eta"], d["U"], R=d["R"], f=d["f"], H0=d["H0"], nsub=c["nsub"],
+                       dt=c["tau"], params=p64, Uavg=ua, workspace=w, plain=True)
+    loop64()
+    torch.cuda.synchronize()
+    e_max = 0.0
+    u_max = 0.0
+    vo, eo = batch.vert_offset, batch.elem_offset
+    for i, (m, c, d, ua, w, e0_, u0_) in enumerate(members64):
+        e64 = d["eta"].cpu().numpy()
+        den = np.abs(e64 - eta_ref).max()
+        e_max = max(e_max, float(np.abs(eta32[vo[i]:vo[i + 1]] - e64).max() / den))
+        ua64 = ua.cpu().numpy()
+        u_max = max(u_max, float(np.abs(ua32[eo[i]:eo[i + 1]] - ua64).max() / np.abs(ua64).max()))
+        d["eta"].copy_(e0_)
+        d["U"].copy_(u0_)
+    ms64 = _time(loop64, 2)
+    log(f"[bench] ensemble FP64 per-member plain loop: {ms64:.2f} ms/step")
+    return {"workload": f"{len(cases)} jittered basins, {batch.nv} vertices, substeps "
+                        f"{min(nsub)}-{max(nsub)}",
+            "value": work / ms * 1e3, "unit": "vertex-substeps/s", "ms_per_step": ms,
+            "plan": tune["plan"], "graph": True, "faults": faults,
+            "fp64_member_loop": {"value": work / ms64 * 1e3, "ms_per_step": ms64},
+            "speedup_vs_fp64_member_loop": ms64 / ms,
+            "eta_max_err_vs_fp64": e_max, "Uavg_max_err_vs_fp64": u_max}
+
+
+def bench_adjoint(args, log):
+    """Adjoint workload: 256x256 jittered basin, 30 substeps, checkpoints every 5."""
+    import torch
+
+    import sesynth
+    from paper_2311_08241_amd import Mesh, Params, device_inputs
+    case = sesynth.adjoint_c5()
+    mesh = Mesh.from_dict(case, device=0)
+    out = {"workload": f"{mesh.nv} vertices, {case['nsub']} substeps, checkpoint every "
+                       f"{case['ckpt_every']}"}
+    for prec in ("f64", "f32"):
+        p = Params(precision=prec, eta_ref=case["eta_ref"] if prec == "f32" else 0.0)
+        d = device_inputs(mesh, case, p)
+        lam = torch.ones(mesh.nv, dtype=p.dtype, device="cuda:0")
+        ws = mesh.workspace(p, case["nsub"], case["ckpt_every"])
+        g = [torch.empty_like(d["eta"]), torch.empty_like(d["U"]), torch.empty_like(d["R"]),
+             torch.empty_like(d["H0"])]
+
+        def adj():
+            mesh.adjoint(d["eta"], d["U"], R=d["R"], f=d["f"], H0=d["H0"], nsub=case["nsub"],
+                         dt=case["tau"], params=p, ckpt_every=case["ckpt_every"], lam_eta=lam,
+                         g_eta0=g[0], g_U0=g[1], g_R=g[2], g_H0=g[3], workspace=ws)
+        adj()
+        torch.cuda.synchronize()
+        ms = _time(adj, 5)
+        e, U = d["eta"].clone(), d["U"].clone()
+
+        def fwd():
+            mesh.subcycle(e, U, R=d["R"], f=d["f"], H0=d["H0"], nsub=case["nsub"],
+                          dt=case["tau"], params=p, workspace=ws)
+        fwd()
+        msf = _time(fwd, 5)
+        out[prec] = {"ms_adjoint": ms, "ms_forward": msf, "adjoint_over_forward": ms / msf}
+        log(f"[bench] adjoint {prec}: {ms:.3f} ms (forward {msf:.3f} ms)")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -243,6 +376,10 @@ def main():
                                       np.sum(Ae[:, None] * ua_r ** 2))),
         }
         log(f"[bench] errors vs oracle: {errors}")
+
+    if not args.no_extra:
+        extra["batched"] = bench_batched(args, log)
+        extra["adjoint"] = bench_adjoint(args, log)
 
     out = {
         "metric": METRIC, "value": value, "unit": "vertex-substeps/s", "n_gpus": 1,

@@ -38,11 +38,14 @@ def candidates(mesh, precision: str, nsub: int, top: int = 8):
     key = "ok_f32" if precision == "f32" else "ok_f64"
     bkey = "bytes_per_vs_f32" if precision == "f32" else "bytes_per_vs_f64"
     out = []
-    for T in TILES:
-        for K in KS:
-            if K > nsub:
-                continue
-            for B in BLOCKS:
+    # at fixed (K, B) a larger tile has less halo and less modelled traffic, so only
+    # the largest feasible tile and the next smaller one are kept
+    for K in KS:
+        if K > nsub:
+            continue
+        for B in BLOCKS:
+            kept = 0
+            for T in sorted(TILES, reverse=True):
                 try:
                     st = mesh.plan_stats(T, K, B)
                 except Exception:
@@ -52,6 +55,9 @@ def candidates(mesh, precision: str, nsub: int, top: int = 8):
                 # a launch sequence with a short last chunk wastes part of a launch
                 waste = (-(-nsub // K) * K) / nsub
                 out.append((st[bkey] * waste, T, K, B, st))
+                kept += 1
+                if kept == 2:
+                    break
     out.sort(key=lambda r: r[0])
     return out[:top]
 

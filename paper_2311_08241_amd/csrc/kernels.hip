@@ -77,6 +77,44 @@ __device__ __forceinline__ void tri_update(T ea, T eb, T ec, T ha, T hb, T hc, T
     pc = Fx * (-Ae * gcx) + Fy * (-Ae * gcy);
 }
 
+// FP32 triangle update with per-triangle constants of the call: a = f dt/2 (al),
+// 1/(1 + a^2) (rk), dt R (dRx, dRy), -A_e (mAe), mean H0 (+ eta_ref unless H is
+// linear) (rH); gd = g dt.  The Crank-Nicolson step is evaluated as the increment
+//   U' = U + C (q - 2 a J U),  C = (I + aJ)^-1,  q = dt (R - g H grad eta),
+// algebraically equal to C [(I - aJ) U + q]; in FP32 the rounded rotation
+// coefficients then perturb only the small increment instead of scaling U by
+// 1 + O(eps) every substep, which would bias its amplitude over many substeps.
+__device__ __forceinline__ void tri_update_f32(float ea, float eb, float ec, float rH, float gbx,
+                                               float gby, float gcx, float gcy, float mAe,
+                                               float ux, float uy, float dRx, float dRy,
+                                               float al, float rk, float gd, float th,
+                                               bool linear_h, float &Unx, float &Uny, float &pa,
+                                               float &pb, float &pc, bool &dry) {
+    const float db = eb - ea, dc = ec - ea;
+    const float gx = db * gbx + dc * gcx;
+    const float gy = db * gby + dc * gcy;
+    const float He = linear_h ? rH : rH + (ea + eb + ec) * (1.0f / 3.0f);
+    dry = !(He > 0.0f);
+    const float gHe = gd * He;
+    const float px = (dRx - gHe * gx) + 2.0f * al * uy;
+    const float py = (dRy - gHe * gy) - 2.0f * al * ux;
+    const float dx = (px + al * py) * rk;
+    const float dy = (py - al * px) * rk;
+    Unx = ux + dx;
+    Uny = uy + dy;
+    const float Fx = Unx + th * dx;   // (1 + theta) U' - theta U
+    const float Fy = Uny + th * dy;
+    pb = mAe * (Fx * gbx + Fy * gby);
+    pc = mAe * (Fx * gcx + Fy * gcy);
+    pa = -(pb + pc);
+}
+
+// Per-triangle constants of the FP32 update (identical in every path).
+__device__ __forceinline__ void tri_consts_f32(float f, float dts, float &al, float &rk) {
+    al = 0.5f * f * dts;
+    rk = 1.0f / (1.0f + al * al);
+}
+
 // Error-free accumulation s + e += x (two-sum), for the FP32 running sum.
 __device__ __forceinline__ void two_sum_acc(float &s, float &e, float x) {
     const float t = s + x;
@@ -150,10 +188,21 @@ __global__ void __launch_bounds__(256) k_plain_tri(PlainArgs a) {
     const T fc = static_cast<const T *>(a.f)[e];
     T Unx, Uny, pa, pb, pc;
     bool dry;
-    tri_update<T, F32>(eta[va], eta[vb], eta[vc], H0[va], H0[vb], H0[vc], geom[e],
-                       geom[a.ne + e], geom[2 * a.ne + e], geom[3 * a.ne + e],
-                       geom[4 * a.ne + e], u.x, u.y, r.x, r.y, fc, c,
-                       (c.flags & KF_LINEAR_H) != 0, Unx, Uny, pa, pb, pc, dry);
+    const bool linear_h = (c.flags & KF_LINEAR_H) != 0;
+    if constexpr (F32) {
+        float al, rk;
+        tri_consts_f32(fc, c.dts_f, al, rk);
+        const float rH = (H0[va] + H0[vb] + H0[vc]) * (1.0f / 3.0f) + (linear_h ? 0.0f : c.eta_ref_f);
+        tri_update_f32(eta[va], eta[vb], eta[vc], rH, geom[e], geom[a.ne + e],
+                       geom[2 * a.ne + e], geom[3 * a.ne + e], -geom[4 * a.ne + e], u.x, u.y,
+                       c.dts_f * r.x, c.dts_f * r.y, al, rk, c.g_f * c.dts_f, c.theta_f,
+                       linear_h, Unx, Uny, pa, pb, pc, dry);
+    } else {
+        tri_update<T, F32>(eta[va], eta[vb], eta[vc], H0[va], H0[vb], H0[vc], geom[e],
+                           geom[a.ne + e], geom[2 * a.ne + e], geom[3 * a.ne + e],
+                           geom[4 * a.ne + e], u.x, u.y, r.x, r.y, fc, c, linear_h, Unx, Uny,
+                           pa, pb, pc, dry);
+    }
     if (dry) set_fault(a.faults, 1u);
     T *phi = static_cast<T *>(a.phi);
     phi[3 * e] = pa;
@@ -199,12 +248,14 @@ __global__ void __launch_bounds__(256) k_plain_vtx(PlainArgs a) {
         for (int32_t j = a.row_ptr[v]; j < j1; ++j) acc += phi[a.pcol[j]];
         const T eo = eta[v];
         const T wv = a.W ? static_cast<const T *>(a.W)[v] : T(0);
-        const T en = eo - cdts<T>(c) * (acc / static_cast<const T *>(a.Av)[v] + wv);
+        const T av = static_cast<const T *>(a.Av)[v];
+        const T en = F32 ? eo - cdts<T>(c) * (acc * (T(1) / av) + wv)
+                         : eo - cdts<T>(c) * (acc / av + wv);
         eta[v] = en;
         if (!finite_val(en)) set_fault(a.faults, 2u);
-        const double av = a.Av64[v];
-        v_new = av * (double)en;
-        v_old = av * (double)eo;
+        const double av64 = a.Av64[v];
+        v_new = av64 * (double)en;
+        v_old = av64 * (double)eo;
     }
     if (a.fwd_only || !(track || first || last)) return;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -371,15 +422,14 @@ __global__ void __launch_bounds__(BLOCK) k_tile(TileArgs a) {
     }
     __syncthreads();
     if constexpr (F32) {
-        // FP32: per-triangle constants of the launch replace divisions in the loop:
-        // a = f dt/2 (rf), 1/(1 + a^2) (rk), dt R (rRx, rRy), -A_e (g4); below, the
-        // triangle mean of H0 (+ eta_ref unless H is linear) (rH)
+        // FP32: per-triangle constants of the launch (see tri_update_f32)
 #pragma unroll
         for (int r = 0; r < EPT; ++r) {
             const int le = tid + r * BLOCK;
             if (le < ne_load) {
-                const T al = T(0.5) * rf[r] * dts;
-                rk[r] = T(1) / (T(1) + al * al);
+                float al, kk;
+                tri_consts_f32(rf[r], dts, al, kk);
+                rk[r] = kk;
                 rf[r] = al;
                 rRx[r] = dts * rRx[r];
                 rRy[r] = dts * rRy[r];
@@ -394,7 +444,7 @@ __global__ void __launch_bounds__(BLOCK) k_tile(TileArgs a) {
             const int le = tid + r * BLOCK;
             if (le < ne_load) {
                 const int ia = t0[r] & 0xffffu, ib = t0[r] >> 16, ic = t1[r];
-                rH[r] = (sH[ia] + sH[ib] + sH[ic]) * T(1.0f / 3.0f) + (linear_h ? T(0) : c.eta_ref_f);
+                rH[r] = (sH[ia] + sH[ib] + sH[ic]) * (1.0f / 3.0f) + (linear_h ? 0.0f : c.eta_ref_f);
             }
         }
     }
@@ -404,7 +454,7 @@ __global__ void __launch_bounds__(BLOCK) k_tile(TileArgs a) {
         for (int i = tid; i < h.nv0; i += BLOCK) v0 += a.Av64[h.vbase + i] * (double)sEta[i];
     }
     bool dry_any = false, bad_any = false;
-    const T gd = cg<T>(c) * dts, th = cth<T>(c), opt = copt<T>(c);
+    const T gd = cg<T>(c) * dts, th = cth<T>(c);
     for (int j = 0; j < cnt; ++j) {
         const int lev = cnt - j;
         const int ne_act = nE[lev], nv_act = nV[lev - 1];
@@ -415,23 +465,11 @@ __global__ void __launch_bounds__(BLOCK) k_tile(TileArgs a) {
                 const int ia = t0[r] & 0xffffu, ib = t0[r] >> 16, ic = t1[r];
                 T Unx, Uny, pa, pb, pc;
                 if constexpr (F32) {
-                    const T ea = sEta[ia], eb = sEta[ib], ec = sEta[ic];
-                    const T db = eb - ea, dc = ec - ea;
-                    const T gx = db * g0[r] + dc * g2[r];
-                    const T gy = db * g1[r] + dc * g3[r];
-                    const T He = linear_h ? rH[r] : rH[r] + (ea + eb + ec) * T(1.0f / 3.0f);
-                    dry_any |= !(He > T(0));
-                    const T gHe = gd * He, al = rf[r];
-                    const T ux = rUx[r], uy = rUy[r];
-                    const T rx = ux + al * uy + (rRx[r] - gHe * gx);
-                    const T ry = uy - al * ux + (rRy[r] - gHe * gy);
-                    Unx = (rx + al * ry) * rk[r];
-                    Uny = (ry - al * rx) * rk[r];
-                    const T Fx = opt * Unx - th * ux;
-                    const T Fy = opt * Uny - th * uy;
-                    pb = g4[r] * (Fx * g0[r] + Fy * g1[r]);
-                    pc = g4[r] * (Fx * g2[r] + Fy * g3[r]);
-                    pa = -(pb + pc);
+                    bool dry;
+                    tri_update_f32(sEta[ia], sEta[ib], sEta[ic], rH[r], g0[r], g1[r], g2[r],
+                                   g3[r], g4[r], rUx[r], rUy[r], rRx[r], rRy[r], rf[r], rk[r],
+                                   gd, th, linear_h, Unx, Uny, pa, pb, pc, dry);
+                    dry_any |= dry;
                 } else {
                     bool dry;
                     tri_update<T, F32>(sEta[ia], sEta[ib], sEta[ic], sH[ia], sH[ib], sH[ic],

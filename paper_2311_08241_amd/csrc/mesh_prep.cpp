@@ -3,6 +3,8 @@
 // sets of the temporally blocked kernel.  Built with -ffp-contract=off so the
 // geometry is the plain IEEE evaluation of its formulas.
 #include <algorithm>
+#include <atomic>
+#include <thread>
 #include <cmath>
 #include <cstring>
 #include <numeric>
@@ -256,132 +258,219 @@ se_status build_host_mesh(const se_mesh_desc &d, HostMesh &m) {
 // ---------------------------------------------------------------------------
 // Tiles and their K-ring level sets
 // ---------------------------------------------------------------------------
+namespace {
+
+// Tiles [t0, t1) of member mi appended to `out` (offsets local to `out`).
+se_status build_tile_range(const HostMesh &m, size_t mi, int64_t voff, int64_t eoff,
+                           const std::vector<int32_t> &efirst, int64_t t0, int64_t t1, int32_t T,
+                           int32_t K, std::vector<int32_t> &vloc, std::vector<int32_t> &eloc,
+                           HostTiles &out) {
+    const int64_t nv = m.nv;
+    std::vector<int32_t> lv, le, fresh;
+    for (int64_t t = t0; t < t1; ++t) {
+        const int32_t vb = static_cast<int32_t>(t * T);
+        const int32_t nv0 = static_cast<int32_t>(std::min<int64_t>(T, nv - vb));
+        const int32_t eb = efirst[vb], ee = efirst[vb + nv0];
+        lv.clear();
+        le.clear();
+        std::vector<int32_t> nVl(K + 1), nEl(K + 1);
+        for (int32_t v = vb; v < vb + nv0; ++v) {
+            vloc[v] = static_cast<int32_t>(lv.size());
+            lv.push_back(v);
+        }
+        for (int32_t e = eb; e < ee; ++e) {
+            eloc[e] = static_cast<int32_t>(le.size());
+            le.push_back(e);
+        }
+        nVl[0] = nv0;
+        nEl[0] = ee - eb;
+        for (int32_t i = 1; i <= K; ++i) {
+            fresh.clear();
+            // triangles touching V_{i-1}: only vertices new at level i-1 can add any
+            const int32_t q0 = (i == 1) ? 0 : nVl[i - 2];
+            for (int32_t q = q0; q < nVl[i - 1]; ++q) {
+                const int32_t v = lv[q];
+                for (int32_t j = m.row_ptr[v]; j < m.row_ptr[v + 1]; ++j) {
+                    const int32_t e = m.col[j] >> 2;
+                    if (eloc[e] == -1) {
+                        eloc[e] = -2;   // queued at this level
+                        fresh.push_back(e);
+                    }
+                }
+            }
+            std::sort(fresh.begin(), fresh.end());
+            const size_t e_from = (i == 1) ? 0 : le.size();
+            for (int32_t e : fresh) {
+                eloc[e] = static_cast<int32_t>(le.size());
+                le.push_back(e);
+            }
+            nEl[i] = static_cast<int32_t>(le.size());
+            // new vertices: those of triangles added at this level (all of E_1 at level 1)
+            fresh.clear();
+            for (size_t q = e_from; q < le.size(); ++q)
+                for (int k = 0; k < 3; ++k) {
+                    const int32_t v = m.tri[3 * le[q] + k];
+                    if (vloc[v] == -1) {
+                        vloc[v] = -2;   // queued at this level
+                        fresh.push_back(v);
+                    }
+                }
+            std::sort(fresh.begin(), fresh.end());
+            for (int32_t v : fresh) {
+                vloc[v] = static_cast<int32_t>(lv.size());
+                lv.push_back(v);
+            }
+            nVl[i] = static_cast<int32_t>(lv.size());
+        }
+        if (nVl[K] > 65535 || 3 * static_cast<int64_t>(nEl[K]) > 65535) {
+            for (int32_t v : lv) vloc[v] = -1;
+            for (int32_t e : le) eloc[e] = -1;
+            set_error("se_set_plan: tile halo too large for 16-bit local indices");
+            return SE_ERR_ARG;
+        }
+        TileHdr h{};
+        h.vbase = static_cast<int32_t>(voff + vb);
+        h.nv0 = nv0;
+        h.ebase = static_cast<int32_t>(eoff + eb);
+        h.nown = ee - eb;
+        h.lv_off = static_cast<int32_t>(out.lv_gid.size());
+        h.le_off = static_cast<int32_t>(out.le_gid.size());
+        h.cs_off = static_cast<int32_t>(out.cs_ent.size());
+        h.rw_off = static_cast<int32_t>(out.cs_row.size());
+        h.member = static_cast<int32_t>(mi);
+        h.mtile = static_cast<int32_t>(t);
+        out.hdr.push_back(h);
+        for (int32_t i = 0; i <= K; ++i) {
+            out.nV.push_back(nVl[i]);
+            out.nE.push_back(nEl[i]);
+        }
+        for (int32_t v : lv) out.lv_gid.push_back(static_cast<int32_t>(voff + v));
+        for (int32_t e : le) {
+            out.le_gid.push_back(static_cast<int32_t>(eoff + e));
+            const uint32_t a = vloc[m.tri[3 * e]], b = vloc[m.tri[3 * e + 1]],
+                           c = vloc[m.tri[3 * e + 2]];
+            out.le_tri.push_back(a | (b << 16));
+            out.le_tri.push_back(c);
+        }
+        // local CSR of the vertices updated at some inner substep: V_{K-1}
+        const int32_t nvu = nVl[K - 1];
+        const size_t ent0 = out.cs_ent.size();
+        for (int32_t q = 0; q < nvu; ++q) {
+            out.cs_row.push_back(static_cast<uint16_t>(out.cs_ent.size() - ent0));
+            const int32_t v = lv[q];
+            for (int32_t j = m.row_ptr[v]; j < m.row_ptr[v + 1]; ++j) {
+                const int32_t e = m.col[j] >> 2;
+                out.cs_ent.push_back(static_cast<uint16_t>(3 * eloc[e] + (m.col[j] & 3)));
+            }
+        }
+        const size_t nent = out.cs_ent.size() - ent0;
+        if (nent > 65535) {
+            set_error("se_set_plan: tile CSR too large for 16-bit offsets");
+            return SE_ERR_ARG;
+        }
+        out.cs_row.push_back(static_cast<uint16_t>(nent));
+        // pad both chunks to multiples of 4 entries (8-byte vector loads)
+        while (out.cs_row.size() % 4) out.cs_row.push_back(0);
+        while (out.cs_ent.size() % 4) out.cs_ent.push_back(0);
+        out.max_nv = std::max(out.max_nv, nVl[K]);
+        out.max_ne = std::max(out.max_ne, nEl[K]);
+        out.max_nvu = std::max(out.max_nvu, nvu);
+        out.max_cs = std::max(out.max_cs, static_cast<int32_t>(nent));
+        for (int32_t v : lv) vloc[v] = -1;
+        for (int32_t e : le) eloc[e] = -1;
+    }
+    return SE_OK;
+}
+
+}  // namespace
+
 se_status build_tiles(const std::vector<const HostMesh *> &members,
                       const std::vector<int64_t> &voff, const std::vector<int64_t> &eoff,
                       int32_t T, int32_t K, HostTiles &out) {
     out = HostTiles();
     out.T = T;
     out.K = K;
+    // first triangle whose smallest vertex is >= v, per member
+    std::vector<std::vector<int32_t>> efirst(members.size());
+    struct Unit {
+        size_t mi;
+        int64_t t0, t1;
+    };
+    std::vector<Unit> units;
+    unsigned nthreads = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    int64_t total_tiles = 0;
+    for (size_t mi = 0; mi < members.size(); ++mi)
+        total_tiles += (members[mi]->nv + T - 1) / T;
+    const int64_t chunk = std::max<int64_t>(1, total_tiles / (8 * nthreads));
     for (size_t mi = 0; mi < members.size(); ++mi) {
         const HostMesh &m = *members[mi];
-        const int64_t nv = m.nv, ne = m.ne;
-        // first triangle whose smallest vertex is >= v
-        std::vector<int32_t> efirst(nv + 1, static_cast<int32_t>(ne));
-        for (int64_t e = ne - 1; e >= 0; --e) efirst[m.tri[3 * e]] = static_cast<int32_t>(e);
-        for (int64_t v = nv - 1; v >= 0; --v) efirst[v] = std::min(efirst[v], efirst[v + 1]);
-        std::vector<int32_t> vloc(nv, -1), eloc(ne, -1);
-        std::vector<int32_t> lv, le, fresh;
-        const int64_t ntile_m = (nv + T - 1) / T;
-        for (int64_t t = 0; t < ntile_m; ++t) {
-            const int32_t vb = static_cast<int32_t>(t * T);
-            const int32_t nv0 = static_cast<int32_t>(std::min<int64_t>(T, nv - vb));
-            const int32_t eb = efirst[vb], ee = efirst[vb + nv0];
-            lv.clear();
-            le.clear();
-            std::vector<int32_t> nVl(K + 1), nEl(K + 1);
-            for (int32_t v = vb; v < vb + nv0; ++v) {
-                vloc[v] = static_cast<int32_t>(lv.size());
-                lv.push_back(v);
+        std::vector<int32_t> &ef = efirst[mi];
+        ef.assign(m.nv + 1, static_cast<int32_t>(m.ne));
+        for (int64_t e = m.ne - 1; e >= 0; --e) ef[m.tri[3 * e]] = static_cast<int32_t>(e);
+        for (int64_t v = m.nv - 1; v >= 0; --v) ef[v] = std::min(ef[v], ef[v + 1]);
+        const int64_t nt = (m.nv + T - 1) / T;
+        for (int64_t t = 0; t < nt; t += chunk) units.push_back({mi, t, std::min(nt, t + chunk)});
+    }
+    std::vector<HostTiles> parts(units.size());
+    std::vector<se_status> st(units.size(), SE_OK);
+    std::atomic<size_t> next{0};
+    auto worker = [&]() {
+        std::vector<int32_t> vloc, eloc;
+        size_t cur_member = static_cast<size_t>(-1);
+        for (;;) {
+            const size_t u = next.fetch_add(1);
+            if (u >= units.size()) break;
+            const Unit &U = units[u];
+            const HostMesh &m = *members[U.mi];
+            if (U.mi != cur_member) {
+                vloc.assign(m.nv, -1);
+                eloc.assign(m.ne, -1);
+                cur_member = U.mi;
             }
-            for (int32_t e = eb; e < ee; ++e) {
-                eloc[e] = static_cast<int32_t>(le.size());
-                le.push_back(e);
+            parts[u].K = K;
+            st[u] = build_tile_range(m, U.mi, voff[U.mi], eoff[U.mi], efirst[U.mi], U.t0, U.t1, T,
+                                     K, vloc, eloc, parts[u]);
+            if (st[u] != SE_OK) {   // stamps may be dirty after an early return
+                cur_member = static_cast<size_t>(-1);
             }
-            nVl[0] = nv0;
-            nEl[0] = ee - eb;
-            for (int32_t i = 1; i <= K; ++i) {
-                fresh.clear();
-                for (int32_t q = 0; q < nVl[i - 1]; ++q) {
-                    const int32_t v = lv[q];
-                    for (int32_t j = m.row_ptr[v]; j < m.row_ptr[v + 1]; ++j) {
-                        const int32_t e = m.col[j] >> 2;
-                        if (eloc[e] == -1) {
-                            eloc[e] = -2;   // queued at this level
-                            fresh.push_back(e);
-                        }
-                    }
-                }
-                std::sort(fresh.begin(), fresh.end());
-                const size_t e_from = (i == 1) ? 0 : le.size();
-                for (int32_t e : fresh) {
-                    eloc[e] = static_cast<int32_t>(le.size());
-                    le.push_back(e);
-                }
-                nEl[i] = static_cast<int32_t>(le.size());
-                // new vertices: those of triangles added at this level (all of E_1 at level 1)
-                fresh.clear();
-                for (size_t q = e_from; q < le.size(); ++q)
-                    for (int k = 0; k < 3; ++k) {
-                        const int32_t v = m.tri[3 * le[q] + k];
-                        if (vloc[v] == -1) {
-                            vloc[v] = -2;   // queued at this level
-                            fresh.push_back(v);
-                        }
-                    }
-                std::sort(fresh.begin(), fresh.end());
-                for (int32_t v : fresh) {
-                    vloc[v] = static_cast<int32_t>(lv.size());
-                    lv.push_back(v);
-                }
-                nVl[i] = static_cast<int32_t>(lv.size());
-            }
-            if (nVl[K] > 65535 || 3 * static_cast<int64_t>(nEl[K]) > 65535) {
-                for (int32_t v : lv) vloc[v] = -1;
-                for (int32_t e : le) eloc[e] = -1;
-                set_error("se_set_plan: tile halo too large for 16-bit local indices");
-                return SE_ERR_ARG;
-            }
-            TileHdr h{};
-            h.vbase = static_cast<int32_t>(voff[mi] + vb);
-            h.nv0 = nv0;
-            h.ebase = static_cast<int32_t>(eoff[mi] + eb);
-            h.nown = ee - eb;
-            h.lv_off = static_cast<int32_t>(out.lv_gid.size());
-            h.le_off = static_cast<int32_t>(out.le_gid.size());
-            h.cs_off = static_cast<int32_t>(out.cs_ent.size());
-            h.rw_off = static_cast<int32_t>(out.cs_row.size());
-            h.member = static_cast<int32_t>(mi);
-            h.mtile = static_cast<int32_t>(t);
-            out.hdr.push_back(h);
-            for (int32_t i = 0; i <= K; ++i) {
-                out.nV.push_back(nVl[i]);
-                out.nE.push_back(nEl[i]);
-            }
-            for (int32_t v : lv) out.lv_gid.push_back(static_cast<int32_t>(voff[mi] + v));
-            for (int32_t e : le) {
-                out.le_gid.push_back(static_cast<int32_t>(eoff[mi] + e));
-                const uint32_t a = vloc[m.tri[3 * e]], b = vloc[m.tri[3 * e + 1]],
-                               c = vloc[m.tri[3 * e + 2]];
-                out.le_tri.push_back(a | (b << 16));
-                out.le_tri.push_back(c);
-            }
-            // local CSR of the vertices updated at some inner substep: V_{K-1}
-            const int32_t nvu = nVl[K - 1];
-            const size_t ent0 = out.cs_ent.size();
-            for (int32_t q = 0; q < nvu; ++q) {
-                out.cs_row.push_back(static_cast<uint16_t>(out.cs_ent.size() - ent0));
-                const int32_t v = lv[q];
-                for (int32_t j = m.row_ptr[v]; j < m.row_ptr[v + 1]; ++j) {
-                    const int32_t e = m.col[j] >> 2;
-                    out.cs_ent.push_back(static_cast<uint16_t>(3 * eloc[e] + (m.col[j] & 3)));
-                }
-            }
-            const size_t nent = out.cs_ent.size() - ent0;
-            if (nent > 65535) {
-                set_error("se_set_plan: tile CSR too large for 16-bit offsets");
-                return SE_ERR_ARG;
-            }
-            out.cs_row.push_back(static_cast<uint16_t>(nent));
-            // pad both chunks to multiples of 4 entries (8-byte vector loads)
-            while (out.cs_row.size() % 4) out.cs_row.push_back(0);
-            while (out.cs_ent.size() % 4) out.cs_ent.push_back(0);
-            out.max_nv = std::max(out.max_nv, nVl[K]);
-            out.max_ne = std::max(out.max_ne, nEl[K]);
-            out.max_nvu = std::max(out.max_nvu, nvu);
-            out.max_cs = std::max(out.max_cs, static_cast<int32_t>(nent));
-            for (int32_t v : lv) vloc[v] = -1;
-            for (int32_t e : le) eloc[e] = -1;
         }
+    };
+    nthreads = static_cast<unsigned>(std::min<size_t>(nthreads, units.size()));
+    std::vector<std::thread> pool;
+    for (unsigned k = 1; k < nthreads; ++k) pool.emplace_back(worker);
+    worker();
+    for (auto &th : pool) th.join();
+    for (size_t u = 0; u < units.size(); ++u)
+        if (st[u] != SE_OK) {
+            set_error("se_set_plan: tile halo or local CSR too large for 16-bit local indices "
+                      "(reduce tile or k_fused)");
+            return st[u];
+        }
+    // concatenate in unit order (deterministic), shifting local offsets
+    for (size_t u = 0; u < units.size(); ++u) {
+        HostTiles &p = parts[u];
+        const int32_t dlv = static_cast<int32_t>(out.lv_gid.size());
+        const int32_t dle = static_cast<int32_t>(out.le_gid.size());
+        const int32_t dcs = static_cast<int32_t>(out.cs_ent.size());
+        const int32_t drw = static_cast<int32_t>(out.cs_row.size());
+        for (TileHdr h : p.hdr) {
+            h.lv_off += dlv;
+            h.le_off += dle;
+            h.cs_off += dcs;
+            h.rw_off += drw;
+            out.hdr.push_back(h);
+        }
+        out.nV.insert(out.nV.end(), p.nV.begin(), p.nV.end());
+        out.nE.insert(out.nE.end(), p.nE.begin(), p.nE.end());
+        out.lv_gid.insert(out.lv_gid.end(), p.lv_gid.begin(), p.lv_gid.end());
+        out.le_gid.insert(out.le_gid.end(), p.le_gid.begin(), p.le_gid.end());
+        out.le_tri.insert(out.le_tri.end(), p.le_tri.begin(), p.le_tri.end());
+        out.cs_row.insert(out.cs_row.end(), p.cs_row.begin(), p.cs_row.end());
+        out.cs_ent.insert(out.cs_ent.end(), p.cs_ent.begin(), p.cs_ent.end());
+        out.max_nv = std::max(out.max_nv, p.max_nv);
+        out.max_ne = std::max(out.max_ne, p.max_ne);
+        out.max_nvu = std::max(out.max_nvu, p.max_nvu);
+        out.max_cs = std::max(out.max_cs, p.max_cs);
     }
     return SE_OK;
 }

@@ -137,6 +137,17 @@ def test_fp64_bitwise_identical_across_plans_and_paths():
             assert np.array_equal(a, b)
 
 
+def test_fp32_bitwise_identical_across_plans_and_paths():
+    case = _case("C2s")
+    mesh = _lib_mesh(case)
+    p = _params(case, "f32")
+    outs = [_run_gpu(case, mesh, p, 2, plan=pl) for pl in PLANS]
+    outs.append(_run_gpu(case, mesh, p, 2, plain=True))
+    for o in outs[1:]:
+        for a, b in zip(o[:3], outs[0][:3]):
+            assert np.array_equal(a, b)
+
+
 def test_fp64_is_run_to_run_deterministic():
     case = _case("C2s")
     mesh = _lib_mesh(case)
