@@ -202,7 +202,7 @@ se_status se_subcycle_batched(se_batch *batch, const se_params *params, se_state
 
 /* Execution plan of the temporally blocked kernel: tile = vertices per
  * tile (64..8192), k_fused = substeps per launch (1..8), block = threads per
- * workgroup (256 or 512).  Applies to a mesh (kind 0) or a batch (kind 1).
+ * workgroup (256, 512 or 1024).  Applies to a mesh (kind 0) or a batch (kind 1).
  * Returns SE_ERR_ARG if the plan does not fit the kernel's register or LDS
  * budget for this mesh. */
 se_status se_set_plan(void *mesh_or_batch, int32_t kind, int32_t tile, int32_t k_fused,

@@ -16,11 +16,22 @@ import time
 
 import numpy as np
 
-TILES = (128, 256, 384, 512, 768, 1024)
-KS = (1, 2, 3, 4, 5, 6, 8)
-BLOCKS = (256, 512)
+TILES = (256, 384, 512, 768, 1024)
+KS = (2, 3, 4, 5, 6, 8)
+BLOCKS = (256, 512, 1024)
+EPT_TIERS = (1, 2, 3, 4, 6, 8)
+LDS_MAX = 160 * 1024
 CACHE = os.environ.get("SESUB_TUNE_CACHE",
                        os.path.join(os.path.expanduser("~"), ".cache", "sesub_plans.json"))
+
+
+def _tier_ok(precision: str, ept: int, block: int) -> bool:
+    """Register tiers the library runs without spills (mirror of its plan check)."""
+    if block == 256:
+        return ept <= (8 if precision == "f32" else 6)
+    if block == 512:
+        return ept <= (8 if precision == "f32" else 4)
+    return ept <= (4 if precision == "f32" else 1)
 
 
 def mesh_signature(mesh) -> str:
@@ -33,33 +44,44 @@ def mesh_signature(mesh) -> str:
     return h.hexdigest()[:20]
 
 
-def candidates(mesh, precision: str, nsub: int, top: int = 8):
-    """Feasible plans ranked by modelled bytes per vertex-substep."""
-    key = "ok_f32" if precision == "f32" else "ok_f64"
+def candidates(mesh, precision: str, nsub: int, top: int = 18):
+    """Feasible plans: a diverse shortlist ranked by modelled traffic and halo work.
+
+    One se_plan_stats call per (tile, k) gives the largest triangle count of a tile;
+    the register tier of each workgroup size follows from it.  From every
+    (workgroup size, tier) group the three best-scoring plans are kept, so that
+    plans of different occupancy are all timed.
+    """
+    lkey = "lds_f32" if precision == "f32" else "lds_f64"
     bkey = "bytes_per_vs_f32" if precision == "f32" else "bytes_per_vs_f64"
-    out = []
-    # at fixed (K, B) a larger tile has less halo and less modelled traffic, so only
-    # the largest feasible tile and the next smaller one are kept
+    b_stream = 236.0 if precision == "f32" else 356.0   # one streaming pass per substep
+    groups = {}
     for K in KS:
         if K > nsub:
             continue
-        for B in BLOCKS:
-            kept = 0
-            for T in sorted(TILES, reverse=True):
-                try:
-                    st = mesh.plan_stats(T, K, B)
-                except Exception:
+        for T in TILES:
+            try:
+                st = mesh.plan_stats(T, K, 256)
+            except Exception:
+                continue
+            if st[lkey] > LDS_MAX:
+                continue
+            waste = (-(-nsub // K) * K) / nsub     # short last chunk of the launch sequence
+            for B in BLOCKS:
+                need = -(-st["max_tri"] // B)
+                ept = next((e for e in EPT_TIERS if e >= need), None)
+                if ept is None or not _tier_ok(precision, ept, B):
                     continue
-                if not st[key]:
-                    continue
-                # a launch sequence with a short last chunk wastes part of a launch
-                waste = (-(-nsub // K) * K) / nsub
-                out.append((st[bkey] * waste, T, K, B, st))
-                kept += 1
-                if kept == 2:
-                    break
-    out.sort(key=lambda r: r[0])
-    return out[:top]
+                # relative device traffic plus relative triangle work (the halo rings
+                # are recomputed; on average half of the outermost ring's overhead)
+                score = (st[bkey] / b_stream + 0.5 * (1.0 + st["tri_overhead"])) * waste
+                groups.setdefault((B, ept), []).append((score, T, K, B, st))
+    short = []
+    for g in groups.values():
+        g.sort(key=lambda r: r[0])
+        short.extend(g[:4])
+    short.sort(key=lambda r: r[0])
+    return short[:top]
 
 
 def _load_cache():
@@ -81,7 +103,7 @@ def _save_cache(c):
         pass
 
 
-def autotune(mesh, run_step, precision: str, nsub: int, *, top: int = 8, reps: int = 3,
+def autotune(mesh, run_step, precision: str, nsub: int, *, top: int = 18, reps: int = 3,
              use_cache: bool = True, log=None, reset=None):
     """Pick and install the fastest plan.
 
@@ -115,10 +137,10 @@ def autotune(mesh, run_step, precision: str, nsub: int, *, top: int = 8, reps: i
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / reps
-        table.append({"plan": [T, K, B], "ms": ms, "model_bytes_per_vs": model,
+        table.append({"plan": [T, K, B], "ms": ms, "score": model,
                       "tri_overhead": st["tri_overhead"]})
         if log:
-            log(f"[tune] T={T} K={K} B={B}: {ms:.3f} ms/step (model {model:.1f} B/vs, "
+            log(f"[tune] T={T} K={K} B={B}: {ms:.3f} ms/step (score {model:.2f}, "
                 f"setup {time.time() - t0:.1f}s)")
         if best is None or ms < best[0]:
             best = (ms, T, K, B)

@@ -111,15 +111,16 @@ std::vector<T> pack_geom(const HostMesh &m, const std::vector<int32_t> *sel, int
 bool ept_ok(bool f32, int ept, int block) {
     if (ept < 0) return false;
     if (block == 256) return f32 ? ept <= 8 : ept <= 6;
-    return f32 ? ept <= 8 : ept <= 4;
+    if (block == 512) return f32 ? ept <= 8 : ept <= 4;
+    return f32 ? ept <= 4 : ept <= 1;   // 1024 threads: at most 128 VGPRs
 }
 
 // Host-side construction and statistics of a plan (no device memory).
 se_status plan_host(const std::vector<const HostMesh *> &members, const std::vector<int64_t> &voff,
                     const std::vector<int64_t> &eoff, int32_t T, int32_t K, int32_t block,
                     HostTiles &ht, se_plan_stats_t &st) {
-    if (T < 64 || T > 8192 || K < 1 || K > 8 || (block != 256 && block != 512)) {
-        set_error("se_set_plan: tile in [64, 8192], k_fused in [1, 8], block 256 or 512");
+    if (T < 64 || T > 8192 || K < 1 || K > 8 || (block != 256 && block != 512 && block != 1024)) {
+        set_error("se_set_plan: tile in [64, 8192], k_fused in [1, 8], block 256, 512 or 1024");
         return SE_ERR_ARG;
     }
     SE_TRY(build_tiles(members, voff, eoff, T, K, ht));
@@ -145,13 +146,13 @@ se_status plan_host(const std::vector<const HostMesh *> &members, const std::vec
         sumVu += ht.nV[t * (K + 1) + K - 1];
         sumE += ht.nE[t * (K + 1) + K];
     }
-    sumC = static_cast<int64_t>(ht.cs_ent.size());
+    sumC = ht.n_ent;
     st.tri_overhead = static_cast<double>(sumE) / ne;
     st.vtx_overhead = static_cast<double>(sumV) / nv;
     for (int f = 0; f < 2; ++f) {
         const double s = f == 0 ? 4.0 : 8.0;
-        const double bytes = sumV * (4 + 2 * s) + sumVu * (s + 2) + sumC * 2.0 +
-                             sumE * (4 + 8 + 5 * s + 2 * s + 2 * s + s) +
+        const double bytes = sumV * (4 + 2 * s) + sumVu * (s + 2) + sumC * 0.0 +
+                             sumE * (4 + 12 + 5 * s + 2 * s + 2 * s + s) +
                              ne * (32.0 + 2 * s) + nv * (s + 8.0);
         (f == 0 ? st.bytes_per_vs_f32 : st.bytes_per_vs_f64) = bytes / (static_cast<double>(nv) * K);
     }
@@ -194,7 +195,6 @@ se_status make_plan(const std::vector<const HostMesh *> &members, const std::vec
     SE_TRY(p->le_gid.upload(ht.le_gid.data(), ht.le_gid.size() * 4));
     SE_TRY(p->le_tri.upload(ht.le_tri.data(), ht.le_tri.size() * 4));
     SE_TRY(p->cs_row.upload(ht.cs_row.data(), ht.cs_row.size() * 2));
-    SE_TRY(p->cs_ent.upload(ht.cs_ent.data(), std::max<size_t>(ht.cs_ent.size(), 1) * 2));
     // local geometry per tile, gathered member by member
     const int64_t nle = static_cast<int64_t>(ht.le_gid.size());
     std::vector<double> g64(5 * nle);
@@ -584,7 +584,6 @@ se_status se_subcycle(se_mesh *m, const se_params *p, se_state *st, const se_for
     a.le_gid = P.le_gid.as<const int32_t>();
     a.le_tri = P.le_tri.as<const uint32_t>();
     a.cs_row = P.cs_row.as<const uint16_t>();
-    a.cs_ent = P.cs_ent.as<const uint16_t>();
     a.lgeom = f32 ? P.geom32.p : P.geom64.p;
     a.lgeom_stride = static_cast<int64_t>(P.geom64.n / 8 / 5);
     a.mem = nullptr;
@@ -1118,7 +1117,6 @@ se_status se_subcycle_batched(se_batch *b, const se_params *p, se_state *st, con
     a.le_gid = P.le_gid.as<const int32_t>();
     a.le_tri = P.le_tri.as<const uint32_t>();
     a.cs_row = P.cs_row.as<const uint16_t>();
-    a.cs_ent = P.cs_ent.as<const uint16_t>();
     a.lgeom = f32 ? P.geom32.p : P.geom64.p;
     a.lgeom_stride = static_cast<int64_t>(P.geom64.n / 8 / 5);
     a.mem = b->table.as<const StepC>();

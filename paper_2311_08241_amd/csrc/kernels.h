@@ -25,7 +25,7 @@ struct TileArgs {
     const TileHdrK *hdr;
     const int32_t *nV, *nE, *lv_gid, *le_gid;
     const uint32_t *le_tri;
-    const uint16_t *cs_row, *cs_ent;
+    const uint16_t *cs_row;
     const void *lgeom;          // 5 SoA arrays, stride lgeom_stride elements
     int64_t lgeom_stride;
     const StepC *mem;           // per-member constants (batches); nullptr: use c0

@@ -323,11 +323,9 @@ __global__ void __launch_bounds__(BLOCK) k_tile(TileArgs a) {
     off = align16(off + (int)sizeof(T) * a.cap_nvu);
     T *sW = reinterpret_cast<T *>(smem + off);
     off = align16(off + (int)sizeof(T) * a.cap_nvu);
-    T *sPhi = reinterpret_cast<T *>(smem + off);
-    off = align16(off + (int)sizeof(T) * 3 * a.cap_ne);
+    T *sAcc = reinterpret_cast<T *>(smem + off);   // sub-cell fluxes in local CSR order
+    off = align16(off + (int)sizeof(T) * a.cap_cs);
     uint16_t *sRow = reinterpret_cast<uint16_t *>(smem + off);
-    off = align16(off + 2 * (a.cap_nvu + 4));
-    uint16_t *sEnt = reinterpret_cast<uint16_t *>(smem + off);
 
     // ---- stage vertex data (batches of 4 per thread: loads first, then LDS stores)
     const T *eta_in = static_cast<const T *>(even ? a.eta_u : a.eta_w);
@@ -366,17 +364,12 @@ __global__ void __launch_bounds__(BLOCK) k_tile(TileArgs a) {
             }
         }
     }
-    // ---- stage the local CSR (chunks are padded to multiples of 4 entries)
+    // ---- stage the local CSR row offsets (chunks padded to multiples of 4 entries)
     {
         const uint2 *crow = reinterpret_cast<const uint2 *>(a.cs_row + h.rw_off);
         uint2 *srow2 = reinterpret_cast<uint2 *>(sRow);
         const int nrow4 = (nvu + 1 + 3) >> 2;
         for (int i = tid; i < nrow4; i += BLOCK) srow2[i] = crow[i];
-        const uint2 *cent = reinterpret_cast<const uint2 *>(a.cs_ent + h.cs_off);
-        uint2 *sent2 = reinterpret_cast<uint2 *>(sEnt);
-        const int nent = a.cs_row[h.rw_off + nvu];
-        const int nent4 = (nent + 3) >> 2;
-        for (int i = tid; i < nent4; i += BLOCK) sent2[i] = cent[i];
     }
 
     // ---- triangle state in registers
@@ -388,18 +381,18 @@ __global__ void __launch_bounds__(BLOCK) k_tile(TileArgs a) {
     const T dts = cdts<T>(c);
     T rUx[EPT], rUy[EPT], rRx[EPT], rRy[EPT], rf[EPT], rk[EPT], g0[EPT], g1[EPT], g2[EPT],
         g3[EPT], g4[EPT];
-    uint32_t t0[EPT], t1[EPT];
-    int gid[EPT];
+    uint32_t t0[EPT], t1[EPT], t2[EPT];   // local vertices and flux positions, 16 bits each
     SumT<F32> sm[EPT];
 #pragma unroll
     for (int r = 0; r < EPT; ++r) {
         const int le = tid + r * BLOCK;
         if (le < ne_load) {
-            const int g = a.le_gid[h.le_off + le];
-            gid[r] = g;
-            const uint2 tt = reinterpret_cast<const uint2 *>(a.le_tri)[h.le_off + le];
-            t0[r] = tt.x;
-            t1[r] = tt.y;
+            // owned triangles are the tile's contiguous global range
+            const int g = le < h.nown ? h.ebase + le : a.le_gid[h.le_off + le];
+            const uint32_t *tt = a.le_tri + 3 * (h.le_off + le);
+            t0[r] = tt[0];
+            t1[r] = tt[1];
+            t2[r] = tt[2];
             g0[r] = lg[le];
             g1[r] = lg[ls + le];
             g2[r] = lg[2 * ls + le];
@@ -443,7 +436,7 @@ __global__ void __launch_bounds__(BLOCK) k_tile(TileArgs a) {
         for (int r = 0; r < EPT; ++r) {
             const int le = tid + r * BLOCK;
             if (le < ne_load) {
-                const int ia = t0[r] & 0xffffu, ib = t0[r] >> 16, ic = t1[r];
+                const int ia = t0[r] & 0xffffu, ib = t0[r] >> 16, ic = t1[r] & 0xffffu;
                 rH[r] = (sH[ia] + sH[ib] + sH[ic]) * (1.0f / 3.0f) + (linear_h ? 0.0f : c.eta_ref_f);
             }
         }
@@ -462,7 +455,7 @@ __global__ void __launch_bounds__(BLOCK) k_tile(TileArgs a) {
         for (int r = 0; r < EPT; ++r) {
             const int le = tid + r * BLOCK;
             if (le < ne_act) {
-                const int ia = t0[r] & 0xffffu, ib = t0[r] >> 16, ic = t1[r];
+                const int ia = t0[r] & 0xffffu, ib = t0[r] >> 16, ic = t1[r] & 0xffffu;
                 T Unx, Uny, pa, pb, pc;
                 if constexpr (F32) {
                     bool dry;
@@ -478,9 +471,9 @@ __global__ void __launch_bounds__(BLOCK) k_tile(TileArgs a) {
                                        pc, dry);
                     dry_any |= dry;
                 }
-                sPhi[3 * le] = pa;
-                sPhi[3 * le + 1] = pb;
-                sPhi[3 * le + 2] = pc;
+                sAcc[t1[r] >> 16] = pa;
+                sAcc[t2[r] & 0xffffu] = pb;
+                sAcc[t2[r] >> 16] = pc;
                 rUx[r] = Unx;
                 rUy[r] = Uny;
                 if (le < h.nown) {
@@ -496,7 +489,7 @@ __global__ void __launch_bounds__(BLOCK) k_tile(TileArgs a) {
         for (int i = tid; i < nv_act; i += BLOCK) {
             T acc = T(0);
             const int q1 = sRow[i + 1];
-            for (int q = sRow[i]; q < q1; ++q) acc += sPhi[sEnt[q]];
+            for (int q = sRow[i]; q < q1; ++q) acc += sAcc[q];
             T en;
             if constexpr (F32)
                 en = sEta[i] - dts * (acc * sAv[i] + sW[i]);
@@ -523,7 +516,7 @@ __global__ void __launch_bounds__(BLOCK) k_tile(TileArgs a) {
     for (int r = 0; r < EPT; ++r) {
         const int le = tid + r * BLOCK;
         if (le < ne_load) {
-            const int g = gid[r];
+            const int g = h.ebase + le;
             if (le < h.nown) {
                 T2 u;
                 u.x = rUx[r];
@@ -726,8 +719,28 @@ hipError_t launch_tile_ept(int ept, const TileArgs *a, int grid, size_t lds, hip
     }
 }
 
+// 1024-thread workgroups must fit 128 VGPRs: FP32 up to 4 triangles per thread,
+// FP64 one.
+template <typename T, bool F32>
+hipError_t launch_tile_1024(int ept, const TileArgs *a, int grid, size_t lds, hipStream_t s) {
+    if constexpr (F32) {
+        switch (ept) {
+            case 1: return launch_tile_t<T, F32, 1, 1024>(a, grid, lds, s);
+            case 2: return launch_tile_t<T, F32, 2, 1024>(a, grid, lds, s);
+            case 3: return launch_tile_t<T, F32, 3, 1024>(a, grid, lds, s);
+            case 4: return launch_tile_t<T, F32, 4, 1024>(a, grid, lds, s);
+            default: return hipErrorInvalidValue;
+        }
+    } else {
+        return ept == 1 ? launch_tile_t<T, F32, 1, 1024>(a, grid, lds, s) : hipErrorInvalidValue;
+    }
+}
+
 hipError_t launch_tile_any(bool f32, int ept, int block, const TileArgs *a, int grid, size_t lds,
                            hipStream_t s) {
+    if (block == 1024)
+        return f32 ? launch_tile_1024<float, true>(ept, a, grid, lds, s)
+                   : launch_tile_1024<double, false>(ept, a, grid, lds, s);
     if (block == 256)
         return f32 ? launch_tile_ept<float, true, 256>(ept, a, grid, lds, s)
                    : launch_tile_ept<double, false, 256>(ept, a, grid, lds, s);
@@ -749,9 +762,8 @@ int tile_lds_bytes(bool f32, int block, int K, int cap_nv, int cap_ne, int cap_n
     off = al(off + ts * cap_nv);
     off = al(off + ts * cap_nvu);
     off = al(off + ts * cap_nvu);
-    off = al(off + ts * 3 * cap_ne);
+    off = al(off + ts * cap_cs);
     off = al(off + 2 * (cap_nvu + 4));
-    off = al(off + 2 * (cap_cs + 4));
     return off;
 }
 

@@ -266,7 +266,7 @@ se_status build_tile_range(const HostMesh &m, size_t mi, int64_t voff, int64_t e
                            int32_t K, std::vector<int32_t> &vloc, std::vector<int32_t> &eloc,
                            HostTiles &out) {
     const int64_t nv = m.nv;
-    std::vector<int32_t> lv, le, fresh;
+    std::vector<int32_t> lv, le, fresh, pos;
     for (int64_t t = t0; t < t1; ++t) {
         const int32_t vb = static_cast<int32_t>(t * T);
         const int32_t nv0 = static_cast<int32_t>(std::min<int64_t>(T, nv - vb));
@@ -335,47 +335,58 @@ se_status build_tile_range(const HostMesh &m, size_t mi, int64_t voff, int64_t e
         h.nown = ee - eb;
         h.lv_off = static_cast<int32_t>(out.lv_gid.size());
         h.le_off = static_cast<int32_t>(out.le_gid.size());
-        h.cs_off = static_cast<int32_t>(out.cs_ent.size());
+        h.cs_off = 0;
         h.rw_off = static_cast<int32_t>(out.cs_row.size());
         h.member = static_cast<int32_t>(mi);
         h.mtile = static_cast<int32_t>(t);
+        // local CSR of the vertices updated at some inner substep (V_{K-1}); each
+        // incidence (triangle, slot) gets the position of its entry, where the
+        // triangle phase deposits its sub-cell flux.  Incidences of vertices that
+        // are never updated go to one of 64 scratch slots past the entries.
+        const int32_t nvu = nVl[K - 1];
+        pos.assign(3 * le.size(), -1);
+        int32_t nent = 0;
+        for (int32_t q = 0; q < nvu; ++q) {
+            out.cs_row.push_back(static_cast<uint16_t>(nent));
+            const int32_t v = lv[q];
+            for (int32_t j = m.row_ptr[v]; j < m.row_ptr[v + 1]; ++j) {
+                const int32_t e = m.col[j] >> 2;
+                pos[3 * eloc[e] + (m.col[j] & 3)] = nent++;
+            }
+        }
+        if (nent + 64 > 65535) {
+            for (int32_t v : lv) vloc[v] = -1;
+            for (int32_t e : le) eloc[e] = -1;
+            set_error("se_set_plan: tile CSR too large for 16-bit offsets");
+            return SE_ERR_ARG;
+        }
+        out.cs_row.push_back(static_cast<uint16_t>(nent));
+        while (out.cs_row.size() % 4) out.cs_row.push_back(0);   // 8-byte vector loads
+        out.n_ent += nent;
         out.hdr.push_back(h);
         for (int32_t i = 0; i <= K; ++i) {
             out.nV.push_back(nVl[i]);
             out.nE.push_back(nEl[i]);
         }
         for (int32_t v : lv) out.lv_gid.push_back(static_cast<int32_t>(voff + v));
-        for (int32_t e : le) {
+        for (size_t q = 0; q < le.size(); ++q) {
+            const int32_t e = le[q];
             out.le_gid.push_back(static_cast<int32_t>(eoff + e));
             const uint32_t a = vloc[m.tri[3 * e]], b = vloc[m.tri[3 * e + 1]],
                            c = vloc[m.tri[3 * e + 2]];
+            uint32_t p3[3];
+            for (int k = 0; k < 3; ++k)
+                p3[k] = pos[3 * q + k] >= 0 ? static_cast<uint32_t>(pos[3 * q + k])
+                                            : static_cast<uint32_t>(nent + (q & 63));
+            // three local vertices and three flux positions, 16 bits each
             out.le_tri.push_back(a | (b << 16));
-            out.le_tri.push_back(c);
+            out.le_tri.push_back(c | (p3[0] << 16));
+            out.le_tri.push_back(p3[1] | (p3[2] << 16));
         }
-        // local CSR of the vertices updated at some inner substep: V_{K-1}
-        const int32_t nvu = nVl[K - 1];
-        const size_t ent0 = out.cs_ent.size();
-        for (int32_t q = 0; q < nvu; ++q) {
-            out.cs_row.push_back(static_cast<uint16_t>(out.cs_ent.size() - ent0));
-            const int32_t v = lv[q];
-            for (int32_t j = m.row_ptr[v]; j < m.row_ptr[v + 1]; ++j) {
-                const int32_t e = m.col[j] >> 2;
-                out.cs_ent.push_back(static_cast<uint16_t>(3 * eloc[e] + (m.col[j] & 3)));
-            }
-        }
-        const size_t nent = out.cs_ent.size() - ent0;
-        if (nent > 65535) {
-            set_error("se_set_plan: tile CSR too large for 16-bit offsets");
-            return SE_ERR_ARG;
-        }
-        out.cs_row.push_back(static_cast<uint16_t>(nent));
-        // pad both chunks to multiples of 4 entries (8-byte vector loads)
-        while (out.cs_row.size() % 4) out.cs_row.push_back(0);
-        while (out.cs_ent.size() % 4) out.cs_ent.push_back(0);
         out.max_nv = std::max(out.max_nv, nVl[K]);
         out.max_ne = std::max(out.max_ne, nEl[K]);
         out.max_nvu = std::max(out.max_nvu, nvu);
-        out.max_cs = std::max(out.max_cs, static_cast<int32_t>(nent));
+        out.max_cs = std::max(out.max_cs, nent + 64);
         for (int32_t v : lv) vloc[v] = -1;
         for (int32_t e : le) eloc[e] = -1;
     }
@@ -451,12 +462,10 @@ se_status build_tiles(const std::vector<const HostMesh *> &members,
         HostTiles &p = parts[u];
         const int32_t dlv = static_cast<int32_t>(out.lv_gid.size());
         const int32_t dle = static_cast<int32_t>(out.le_gid.size());
-        const int32_t dcs = static_cast<int32_t>(out.cs_ent.size());
         const int32_t drw = static_cast<int32_t>(out.cs_row.size());
         for (TileHdr h : p.hdr) {
             h.lv_off += dlv;
             h.le_off += dle;
-            h.cs_off += dcs;
             h.rw_off += drw;
             out.hdr.push_back(h);
         }
@@ -466,7 +475,7 @@ se_status build_tiles(const std::vector<const HostMesh *> &members,
         out.le_gid.insert(out.le_gid.end(), p.le_gid.begin(), p.le_gid.end());
         out.le_tri.insert(out.le_tri.end(), p.le_tri.begin(), p.le_tri.end());
         out.cs_row.insert(out.cs_row.end(), p.cs_row.begin(), p.cs_row.end());
-        out.cs_ent.insert(out.cs_ent.end(), p.cs_ent.begin(), p.cs_ent.end());
+        out.n_ent += p.n_ent;
         out.max_nv = std::max(out.max_nv, p.max_nv);
         out.max_ne = std::max(out.max_ne, p.max_ne);
         out.max_nvu = std::max(out.max_nvu, p.max_nvu);

@@ -44,7 +44,7 @@ struct TileHdr {
     int32_t vbase, nv0;     // owned vertex range (global, union numbering)
     int32_t ebase, nown;    // owned triangle range
     int32_t lv_off, le_off; // offsets into local vertex / triangle arrays
-    int32_t cs_off, rw_off; // offsets into local CSR entries / rows
+    int32_t cs_off, rw_off; // (unused) / offset into local CSR rows
     int32_t member;         // batch member (0 for a single mesh)
     int32_t mtile;          // tile index within its member
     int32_t pad0, pad1;
@@ -57,10 +57,12 @@ struct HostTiles {
     std::vector<int32_t> nE;      // [ntiles][K+1] cumulative |E_i| (entry 0 = owned)
     std::vector<int32_t> lv_gid;  // local vertex -> global vertex
     std::vector<int32_t> le_gid;  // local triangle -> global triangle
-    std::vector<uint32_t> le_tri; // [2 per local triangle]: a | b << 16, c
-    std::vector<uint16_t> cs_row; // per tile: nV[K-1] + 1 row offsets (local)
-    std::vector<uint16_t> cs_ent; // local triangle * 3 + slot
-    int32_t max_nv = 0, max_ne = 0, max_nvu = 0, max_cs = 0;
+    // [3 per local triangle]: a | b << 16, c | p0 << 16, p1 | p2 << 16 with local
+    // vertex indices a, b, c and the CSR positions p0..p2 of the three incidences
+    std::vector<uint32_t> le_tri;
+    std::vector<uint16_t> cs_row; // per tile: nV[K-1] + 1 row offsets (local), padded to 4
+    int64_t n_ent = 0;            // local CSR entries over all tiles
+    int32_t max_nv = 0, max_ne = 0, max_nvu = 0, max_cs = 0;   // max_cs: entries + 64 scratch
 };
 
 se_status build_tiles(const std::vector<const HostMesh *> &members,
@@ -85,7 +87,7 @@ struct DevTiles {
     size_t lds_bytes64 = 0, lds_bytes32 = 0;
     bool ok32 = false, ok64 = false;
     std::vector<TileHdr> hdr_host;
-    DevBuf hdr, nV, nE, lv_gid, le_gid, le_tri, cs_row, cs_ent;
+    DevBuf hdr, nV, nE, lv_gid, le_gid, le_tri, cs_row;
     DevBuf geom64, geom32;        // per local triangle, 5 SoA arrays
 };
 
