@@ -47,8 +47,9 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def read_traffic(workload_tag):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if current."""
+def read_traffic(workload_tag, plan):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was
+    taken with the same kernel source and plan."""
     path = os.path.join(ROOT, "profiles", f"pmc_k_tile_{workload_tag}.txt")
     if not os.path.exists(path):
         return None
@@ -58,6 +59,8 @@ def read_traffic(workload_tag):
             k, v = line.split("=", 1)
             kv[k.strip()] = v.strip()
     if kv.get("kernels_hip_sha256_16") != kernel_source_hash():
+        return None
+    if kv.get("plan") != ",".join(str(v) for v in plan):
         return None
     try:
         return float(kv["hbm_bytes_per_launch"])
@@ -296,10 +299,13 @@ def main():
     avg_launch_s = ms * 1e-3 / nlaunch
     units_per_launch = float(mesh.nv) * nsub / -(-nsub // plan[1])
     achieved = B_ALG[prec] * units_per_launch / avg_launch_s / 1e9
-    traffic = read_traffic(f"{tag}_{prec}")
+    traffic = read_traffic(f"{tag}_{prec}", plan)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic, "kernel": "k_tile",
+                "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                "hbm_frac_measured": (None if traffic is None else
+                                      round(traffic / avg_launch_s / 1e9 / HBM_PEAK_GBS, 4)),
                 "avg_launch_us": round(avg_launch_s * 1e6, 2),
                 "bytes_per_unit": B_ALG[prec], "units_per_launch": units_per_launch}
 
