@@ -213,6 +213,20 @@ se_status make_plan(const std::vector<const HostMesh *> &members, const std::vec
     }
     SE_TRY(p->geom64.upload(g64.data(), g64.size() * 8));
     SE_TRY(p->geom32.upload(g32.data(), g32.size() * 4));
+    // dual-cell areas per local vertex (contiguous per tile: no index round trip);
+    // FP32 holds the reciprocal of the FP32-rounded area, rounded once
+    const int64_t nlv = static_cast<int64_t>(ht.lv_gid.size());
+    std::vector<double> a64(nlv);
+    std::vector<float> a32(nlv);
+    for (int64_t i = 0; i < nlv; ++i) {
+        const int64_t gv = ht.lv_gid[i];
+        size_t mi = std::upper_bound(voff.begin(), voff.end(), gv) - voff.begin() - 1;
+        const double av = members[mi]->Av[gv - voff[mi]];
+        a64[i] = av;
+        a32[i] = 1.0f / static_cast<float>(av);
+    }
+    SE_TRY(p->lav64.upload(a64.data(), nlv * 8));
+    SE_TRY(p->lav32.upload(a32.data(), nlv * 4));
     out = std::move(p);
     return SE_OK;
 }
@@ -586,6 +600,7 @@ se_status se_subcycle(se_mesh *m, const se_params *p, se_state *st, const se_for
     a.cs_row = P.cs_row.as<const uint16_t>();
     a.lgeom = f32 ? P.geom32.p : P.geom64.p;
     a.lgeom_stride = static_cast<int64_t>(P.geom64.n / 8 / 5);
+    a.lv_av = f32 ? P.lav32.p : P.lav64.p;
     a.mem = nullptr;
     a.c0 = c;
     a.R = fo->R;
@@ -1119,6 +1134,7 @@ se_status se_subcycle_batched(se_batch *b, const se_params *p, se_state *st, con
     a.cs_row = P.cs_row.as<const uint16_t>();
     a.lgeom = f32 ? P.geom32.p : P.geom64.p;
     a.lgeom_stride = static_cast<int64_t>(P.geom64.n / 8 / 5);
+    a.lv_av = f32 ? P.lav32.p : P.lav64.p;
     a.mem = b->table.as<const StepC>();
     a.R = fo->R;
     a.f = fo->f;

@@ -28,6 +28,7 @@ struct TileArgs {
     const uint16_t *cs_row;
     const void *lgeom;          // 5 SoA arrays, stride lgeom_stride elements
     int64_t lgeom_stride;
+    const void *lv_av;          // per local vertex: A_v (FP64) or 1 / A_v (FP32)
     const StepC *mem;           // per-member constants (batches); nullptr: use c0
     StepC c0;
     void *eta_u, *eta_w;        // ping-pong pair: member chunk ch reads (ch even ? u : w)

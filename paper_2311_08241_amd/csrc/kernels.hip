@@ -294,7 +294,24 @@ __global__ void __launch_bounds__(BLOCK) k_tile(TileArgs a) {
     if (b >= a.ntiles) return;
     if (a.tile_list) b = a.tile_list[b];
     const TileHdrK h = a.hdr[b];
-    const StepC c = a.mem ? a.mem[h.member] : a.c0;
+    // step constants: the member's table row (batches) or the launch's own copy,
+    // moved word by word so that both sources stay in scalar registers
+    StepC c;
+    {
+        constexpr int NWD = sizeof(StepC) / 4;
+        static_assert(sizeof(StepC) % 4 == 0, "StepC size");
+        uint32_t wd[NWD];
+        const uint32_t *kw = reinterpret_cast<const uint32_t *>(&a.c0);
+        if (a.mem) {
+            const uint32_t *gw = reinterpret_cast<const uint32_t *>(a.mem + h.member);
+#pragma unroll
+            for (int q = 0; q < NWD; ++q) wd[q] = gw[q];
+        } else {
+#pragma unroll
+            for (int q = 0; q < NWD; ++q) wd[q] = kw[q];
+        }
+        __builtin_memcpy(&c, wd, sizeof(StepC));
+    }
     const int K = a.K;
     const int ch = a.chunk - c.chunk0;   // this member's chunk index
     if (ch < 0) return;
@@ -306,15 +323,13 @@ __global__ void __launch_bounds__(BLOCK) k_tile(TileArgs a) {
     const bool track = (c.flags & KF_TRACK_VOLUME) != 0;
     const bool linear_h = (c.flags & KF_LINEAR_H) != 0;
     const bool hasW = a.W != nullptr;
-    const int *nV = a.nV + b * (K + 1);
+    const int *nV = a.nV + b * (K + 1);   // level counts of the tile (uniform loads)
     const int *nE = a.nE + b * (K + 1);
     const int nv_load = nV[cnt], ne_load = nE[cnt], nvu = nV[cnt - 1];
     const int tid = threadIdx.x;
 
-    // LDS carve-up
+    // LDS carve-up: the vertex arrays filled by direct-to-LDS loads come first
     int off = 0;
-    double *red = reinterpret_cast<double *>(smem + off);
-    off = align16(off + 8 * NW * 9);
     T *sEta = reinterpret_cast<T *>(smem + off);
     off = align16(off + (int)sizeof(T) * a.cap_nv);
     T *sH = reinterpret_cast<T *>(smem + off);
@@ -323,56 +338,32 @@ __global__ void __launch_bounds__(BLOCK) k_tile(TileArgs a) {
     off = align16(off + (int)sizeof(T) * a.cap_nvu);
     T *sW = reinterpret_cast<T *>(smem + off);
     off = align16(off + (int)sizeof(T) * a.cap_nvu);
+    double *red = reinterpret_cast<double *>(smem + off);
+    off = align16(off + 8 * NW * 9);
     T *sAcc = reinterpret_cast<T *>(smem + off);   // sub-cell fluxes in local CSR order
     off = align16(off + (int)sizeof(T) * a.cap_cs);
     uint16_t *sRow = reinterpret_cast<uint16_t *>(smem + off);
 
-    // ---- stage vertex data (batches of 4 per thread: loads first, then LDS stores)
+    // ---- load phase in two rounds of independent loads: (A) index and static data
+    // (local vertex ids, triangle ids, packed local connectivity, geometry, row
+    // offsets, running sums), one wait, then (B) the gathers through those indices,
+    // one wait before the barrier.  FP32 vertex gathers go straight to LDS
+    // (global_load_lds: LDS address from M0, used while the vertex arrays end within
+    // the first 64 KiB of LDS), the rest through registers.
+    const bool dma =
+        F32 && (uint32_t)(size_t)(__attribute__((address_space(3))) T *)(sW + a.cap_nvu) <= 65536u;
     const T *eta_in = static_cast<const T *>(even ? a.eta_u : a.eta_w);
     const T *H0 = static_cast<const T *>(a.H0);
-    const T *Avt = static_cast<const T *>(a.Av);
     const T *Wt = static_cast<const T *>(a.W);
+    const T *lav = static_cast<const T *>(a.lv_av) + h.lv_off;   // FP64: A_v; FP32: 1/A_v
     const int32_t *lv = a.lv_gid + h.lv_off;
-    for (int i0 = tid; i0 < nv_load; i0 += 4 * BLOCK) {
-        int g[4];
-        T ve[4], vh[4], va[4], vw[4];
+    // vertex slots per thread staged in the rounds (the rest, for large tiles on
+    // small workgroups, in a loop afterwards)
+    constexpr int VS = F32 ? (BLOCK >= 512 ? 3072 / BLOCK : 8) : 2;
+    int gv[VS];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int i = i0 + u * BLOCK;
-            g[u] = i < nv_load ? lv[i] : -1;
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int i = i0 + u * BLOCK;
-            if (g[u] >= 0) {
-                ve[u] = eta_in[g[u]];
-                vh[u] = H0[g[u]];
-                va[u] = i < nvu ? Avt[g[u]] : T(1);
-                vw[u] = (i < nvu && hasW) ? Wt[g[u]] : T(0);
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int i = i0 + u * BLOCK;
-            if (g[u] >= 0) {
-                sEta[i] = ve[u];
-                sH[i] = vh[u];
-                if (i < nvu) {
-                    sAv[i] = F32 ? T(1) / va[u] : va[u];
-                    sW[i] = vw[u];
-                }
-            }
-        }
-    }
-    // ---- stage the local CSR row offsets (chunks padded to multiples of 4 entries)
-    {
-        const uint2 *crow = reinterpret_cast<const uint2 *>(a.cs_row + h.rw_off);
-        uint2 *srow2 = reinterpret_cast<uint2 *>(sRow);
-        const int nrow4 = (nvu + 1 + 3) >> 2;
-        for (int i = tid; i < nrow4; i += BLOCK) srow2[i] = crow[i];
-    }
+    for (int u = 0; u < VS; ++u) gv[u] = lv[min(tid + u * BLOCK, nv_load - 1)];
 
-    // ---- triangle state in registers
     const T *lg = static_cast<const T *>(a.lgeom) + h.le_off;
     const int64_t ls = a.lgeom_stride;
     const T2 *Uin = static_cast<const T2 *>(even ? a.U_u : a.U_w);
@@ -382,22 +373,76 @@ __global__ void __launch_bounds__(BLOCK) k_tile(TileArgs a) {
     T rUx[EPT], rUy[EPT], rRx[EPT], rRy[EPT], rf[EPT], rk[EPT], g0[EPT], g1[EPT], g2[EPT],
         g3[EPT], g4[EPT];
     uint32_t t0[EPT], t1[EPT], t2[EPT];   // local vertices and flux positions, 16 bits each
+    int gt[EPT];
     SumT<F32> sm[EPT];
+    if (ne_load > 0) {
 #pragma unroll
-    for (int r = 0; r < EPT; ++r) {
-        const int le = tid + r * BLOCK;
-        if (le < ne_load) {
-            // owned triangles are the tile's contiguous global range
-            const int g = le < h.nown ? h.ebase + le : a.le_gid[h.le_off + le];
-            const uint32_t *tt = a.le_tri + 3 * (h.le_off + le);
+        for (int r = 0; r < EPT; ++r) {
+            const int lc = min(tid + r * BLOCK, ne_load - 1);
+            gt[r] = a.le_gid[h.le_off + lc];
+            const uint32_t *tt = a.le_tri + 3 * (h.le_off + lc);
             t0[r] = tt[0];
             t1[r] = tt[1];
             t2[r] = tt[2];
-            g0[r] = lg[le];
-            g1[r] = lg[ls + le];
-            g2[r] = lg[2 * ls + le];
-            g3[r] = lg[3 * ls + le];
-            g4[r] = lg[4 * ls + le];
+            g0[r] = lg[lc];
+            g1[r] = lg[ls + lc];
+            g2[r] = lg[2 * ls + lc];
+            g3[r] = lg[3 * ls + lc];
+            g4[r] = lg[4 * ls + lc];
+        }
+        if (!first && h.nown > 0) {
+            // running sums of owned triangles (the tile's contiguous global range)
+#pragma unroll
+            for (int r = 0; r < EPT; ++r) sm[r].load(a.sum, h.ebase + min(tid + r * BLOCK, h.nown - 1));
+        }
+    }
+    // local CSR row offsets (chunks padded to multiples of 4 entries)
+    const uint2 *crow = reinterpret_cast<const uint2 *>(a.cs_row + h.rw_off);
+    const int nrow4 = (nvu + 1 + 3) >> 2;
+    const uint2 row0 = crow[min(tid, nrow4 - 1)];
+    __builtin_amdgcn_s_waitcnt(0);   // round A complete
+
+    auto stage_vertex = [&](int i, int g) {   // register path
+        const T ve = eta_in[g], vh = H0[g];
+        const T va = i < nvu ? lav[i] : T(0);
+        const T vw = (i < nvu && hasW) ? Wt[g] : T(0);
+        sEta[i] = ve;
+        sH[i] = vh;
+        if (i < nvu) {
+            sAv[i] = va;
+            sW[i] = vw;
+        }
+    };
+    auto dma_vertex = [&](int i, int g) {   // lane l of the wave writes LDS element i0 + l
+        const int i0 = i - (tid & 63);
+        __builtin_amdgcn_global_load_lds((__attribute__((address_space(1))) void *)(eta_in + g),
+                                         (__attribute__((address_space(3))) void *)(sEta + i0), 4, 0, 0);
+        __builtin_amdgcn_global_load_lds((__attribute__((address_space(1))) void *)(H0 + g),
+                                         (__attribute__((address_space(3))) void *)(sH + i0), 4, 0, 0);
+        if (i < nvu) {
+            __builtin_amdgcn_global_load_lds((__attribute__((address_space(1))) void *)(lav + i),
+                                             (__attribute__((address_space(3))) void *)(sAv + i0), 4, 0, 0);
+            if (hasW)
+                __builtin_amdgcn_global_load_lds((__attribute__((address_space(1))) void *)(Wt + g),
+                                                 (__attribute__((address_space(3))) void *)(sW + i0), 4, 0, 0);
+            else
+                sW[i] = T(0);
+        }
+    };
+    // round B
+    if constexpr (F32) {
+        if (dma) {
+#pragma unroll
+            for (int u = 0; u < VS; ++u) {
+                const int i = tid + u * BLOCK;
+                if (i < nv_load) dma_vertex(i, gv[u]);
+            }
+        }
+    }
+    if (ne_load > 0) {
+#pragma unroll
+        for (int r = 0; r < EPT; ++r) {
+            const int g = gt[r];
             const T2 u = Uin[g];
             rUx[r] = u.x;
             rUy[r] = u.y;
@@ -405,14 +450,43 @@ __global__ void __launch_bounds__(BLOCK) k_tile(TileArgs a) {
             rRx[r] = rr.x;
             rRy[r] = rr.y;
             rf[r] = fg[g];
+        }
+    }
+    {
+        uint2 *srow2 = reinterpret_cast<uint2 *>(sRow);
+        if (tid < nrow4) srow2[tid] = row0;
+    }
+    if (!dma) {
+#pragma unroll
+        for (int u = 0; u < VS; ++u) {
+            const int i = tid + u * BLOCK;
+            if (i < nv_load) stage_vertex(i, gv[u]);
+        }
+    }
+    // remainders: vertices beyond the staged slots, rows beyond the first chunk
+    for (int i = tid + VS * BLOCK; i < nv_load; i += BLOCK) {
+        if constexpr (F32) {
+            if (dma) {
+                dma_vertex(i, lv[i]);
+                continue;
+            }
+        }
+        stage_vertex(i, lv[i]);
+    }
+    for (int i = tid + BLOCK; i < nrow4; i += BLOCK) reinterpret_cast<uint2 *>(sRow)[i] = crow[i];
+    if (first) {
+#pragma unroll
+        for (int r = 0; r < EPT; ++r) {
+            const int le = tid + r * BLOCK;
             if (le < h.nown) {
-                if (first)
-                    static_cast<T2 *>(a.U0c)[g] = u;
-                else
-                    sm[r].load(a.sum, g);
+                T2 u;
+                u.x = rUx[r];
+                u.y = rUy[r];
+                static_cast<T2 *>(a.U0c)[h.ebase + le] = u;
             }
         }
     }
+    __builtin_amdgcn_s_waitcnt(0);   // round B complete (direct-to-LDS loads included)
     __syncthreads();
     if constexpr (F32) {
         // FP32: per-triangle constants of the launch (see tri_update_f32)
@@ -757,11 +831,11 @@ int tile_lds_bytes(bool f32, int block, int K, int cap_nv, int cap_ne, int cap_n
     const int ts = f32 ? 4 : 8;
     int off = 0;
     auto al = [](int b) { return (b + 15) & ~15; };
+    off = al(off + ts * cap_nv);
+    off = al(off + ts * cap_nv);
+    off = al(off + ts * cap_nvu);
+    off = al(off + ts * cap_nvu);
     off = al(off + 8 * (block / 64) * 9);
-    off = al(off + ts * cap_nv);
-    off = al(off + ts * cap_nv);
-    off = al(off + ts * cap_nvu);
-    off = al(off + ts * cap_nvu);
     off = al(off + ts * cap_cs);
     off = al(off + 2 * (cap_nvu + 4));
     return off;

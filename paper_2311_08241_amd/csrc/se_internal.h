@@ -89,6 +89,7 @@ struct DevTiles {
     std::vector<TileHdr> hdr_host;
     DevBuf hdr, nV, nE, lv_gid, le_gid, le_tri, cs_row;
     DevBuf geom64, geom32;        // per local triangle, 5 SoA arrays
+    DevBuf lav64, lav32;          // per local vertex: A_v (FP64), 1 / A_v (FP32)
 };
 
 // Mesh geometry and connectivity on the device (global numbering).
