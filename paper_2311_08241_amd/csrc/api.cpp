@@ -192,27 +192,36 @@ se_status make_plan(const std::vector<const HostMesh *> &members, const std::vec
     SE_TRY(p->nV.upload(ht.nV.data(), ht.nV.size() * 4));
     SE_TRY(p->nE.upload(ht.nE.data(), ht.nE.size() * 4));
     SE_TRY(p->lv_gid.upload(ht.lv_gid.data(), ht.lv_gid.size() * 4));
-    SE_TRY(p->le_gid.upload(ht.le_gid.data(), ht.le_gid.size() * 4));
-    SE_TRY(p->le_tri.upload(ht.le_tri.data(), ht.le_tri.size() * 4));
+    const int64_t nle = static_cast<int64_t>(ht.le_gid.size());
+    {
+        std::vector<uint32_t> rec(4 * nle);
+        for (int64_t i = 0; i < nle; ++i) {
+            rec[4 * i] = static_cast<uint32_t>(ht.le_gid[i]);
+            for (int k = 0; k < 3; ++k) rec[4 * i + 1 + k] = ht.le_tri[3 * i + k];
+        }
+        SE_TRY(p->le_rec.upload(rec.data(), rec.size() * 4));
+    }
     SE_TRY(p->cs_row.upload(ht.cs_row.data(), ht.cs_row.size() * 2));
     // local geometry per tile, gathered member by member
-    const int64_t nle = static_cast<int64_t>(ht.le_gid.size());
-    std::vector<double> g64(5 * nle);
-    std::vector<float> g32(5 * nle);
+    std::vector<double> g64(4 * nle), a64e(nle);
+    std::vector<float> g32(4 * nle), a32e(nle);
     for (int64_t i = 0; i < nle; ++i) {
         const int64_t ge = ht.le_gid[i];
         size_t mi = std::upper_bound(eoff.begin(), eoff.end(), ge) - eoff.begin() - 1;
         const HostMesh &m = *members[mi];
         const int64_t e = ge - eoff[mi];
         const double *gn = &m.gN[6 * e];
-        const double v[5] = {gn[2], gn[3], gn[4], gn[5], m.Ae[e]};
-        for (int q = 0; q < 5; ++q) {
-            g64[q * nle + i] = v[q];
-            g32[q * nle + i] = static_cast<float>(v[q]);
+        for (int q = 0; q < 4; ++q) {
+            g64[4 * i + q] = gn[2 + q];
+            g32[4 * i + q] = static_cast<float>(gn[2 + q]);
         }
+        a64e[i] = m.Ae[e];
+        a32e[i] = static_cast<float>(m.Ae[e]);
     }
-    SE_TRY(p->geom64.upload(g64.data(), g64.size() * 8));
-    SE_TRY(p->geom32.upload(g32.data(), g32.size() * 4));
+    SE_TRY(p->geo64.upload(g64.data(), g64.size() * 8));
+    SE_TRY(p->geo32.upload(g32.data(), g32.size() * 4));
+    SE_TRY(p->ae64.upload(a64e.data(), a64e.size() * 8));
+    SE_TRY(p->ae32.upload(a32e.data(), a32e.size() * 4));
     // dual-cell areas per local vertex (contiguous per tile: no index round trip);
     // FP32 holds the reciprocal of the FP32-rounded area, rounded once
     const int64_t nlv = static_cast<int64_t>(ht.lv_gid.size());
@@ -595,11 +604,10 @@ se_status se_subcycle(se_mesh *m, const se_params *p, se_state *st, const se_for
     a.nV = P.nV.as<const int32_t>();
     a.nE = P.nE.as<const int32_t>();
     a.lv_gid = P.lv_gid.as<const int32_t>();
-    a.le_gid = P.le_gid.as<const int32_t>();
-    a.le_tri = P.le_tri.as<const uint32_t>();
+    a.le_rec = P.le_rec.as<const uint32_t>();
     a.cs_row = P.cs_row.as<const uint16_t>();
-    a.lgeom = f32 ? P.geom32.p : P.geom64.p;
-    a.lgeom_stride = static_cast<int64_t>(P.geom64.n / 8 / 5);
+    a.lgeo = f32 ? P.geo32.p : P.geo64.p;
+    a.lae = f32 ? P.ae32.p : P.ae64.p;
     a.lv_av = f32 ? P.lav32.p : P.lav64.p;
     a.mem = nullptr;
     a.c0 = c;
@@ -1129,11 +1137,10 @@ se_status se_subcycle_batched(se_batch *b, const se_params *p, se_state *st, con
     a.nV = P.nV.as<const int32_t>();
     a.nE = P.nE.as<const int32_t>();
     a.lv_gid = P.lv_gid.as<const int32_t>();
-    a.le_gid = P.le_gid.as<const int32_t>();
-    a.le_tri = P.le_tri.as<const uint32_t>();
+    a.le_rec = P.le_rec.as<const uint32_t>();
     a.cs_row = P.cs_row.as<const uint16_t>();
-    a.lgeom = f32 ? P.geom32.p : P.geom64.p;
-    a.lgeom_stride = static_cast<int64_t>(P.geom64.n / 8 / 5);
+    a.lgeo = f32 ? P.geo32.p : P.geo64.p;
+    a.lae = f32 ? P.ae32.p : P.ae64.p;
     a.lv_av = f32 ? P.lav32.p : P.lav64.p;
     a.mem = b->table.as<const StepC>();
     a.R = fo->R;

@@ -23,11 +23,12 @@ struct TileHdrK {   // mirror of TileHdr (same layout)
 
 struct TileArgs {
     const TileHdrK *hdr;
-    const int32_t *nV, *nE, *lv_gid, *le_gid;
-    const uint32_t *le_tri;
+    const int32_t *nV, *nE, *lv_gid;
+    const uint32_t *le_rec;     // per local triangle, 4 words: global id, packed local
+                                // vertices and flux positions (3 words)
     const uint16_t *cs_row;
-    const void *lgeom;          // 5 SoA arrays, stride lgeom_stride elements
-    int64_t lgeom_stride;
+    const void *lgeo;           // per local triangle: gbx, gby, gcx, gcy (4 values)
+    const void *lae;            // per local triangle: A_e
     const void *lv_av;          // per local vertex: A_v (FP64) or 1 / A_v (FP32)
     const StepC *mem;           // per-member constants (batches); nullptr: use c0
     StepC c0;
@@ -35,7 +36,7 @@ struct TileArgs {
     void *U_u, *U_w;
     const void *R, *f, *H0, *W, *Av;
     const double *Av64;
-    void *sum;                  // double2 (FP64) or float4 (FP32 hi/lo pairs) per triangle
+    void *sum;                  // double2 running sum per triangle (both precisions)
     void *U0c;                  // copy of U^0
     double *Uavg;
     double *vol_part;

@@ -115,20 +115,19 @@ __device__ __forceinline__ void tri_consts_f32(float f, float dts, float &al, fl
     rk = 1.0f / (1.0f + al * al);
 }
 
-// Error-free accumulation s + e += x (two-sum), for the FP32 running sum.
-__device__ __forceinline__ void two_sum_acc(float &s, float &e, float x) {
-    const float t = s + x;
-    const float bp = t - s;
-    e += (s - (t - bp)) + (x - bp);
-    s = t;
-}
-
-// Running-sum storage: FP64 keeps (sx, sy); FP32 keeps hi/lo pairs.
-template <bool F32> struct SumT;
-template <> struct SumT<false> {
+// Running sum of the substep transports, always accumulated in FP64 (the FP32 path
+// converts each FP32 transport exactly and adds it in FP64: on this hardware an FP64
+// add issues at the FP32 rate, and the sum carries no FP32 rounding).
+template <bool F32> struct SumT {
     double x, y;
-    __device__ __forceinline__ void init(double ux, double uy) { x = ux; y = uy; }
-    __device__ __forceinline__ void add(double ux, double uy) { x += ux; y += uy; }
+    template <typename V> __device__ __forceinline__ void init(V ux, V uy) {
+        x = (double)ux;
+        y = (double)uy;
+    }
+    template <typename V> __device__ __forceinline__ void add(V ux, V uy) {
+        x += (double)ux;
+        y += (double)uy;
+    }
     __device__ __forceinline__ void load(const void *p, int64_t i) {
         const double2 v = static_cast<const double2 *>(p)[i];
         x = v.x;
@@ -139,23 +138,6 @@ template <> struct SumT<false> {
     }
     __device__ __forceinline__ double vx() const { return x; }
     __device__ __forceinline__ double vy() const { return y; }
-};
-template <> struct SumT<true> {
-    float x, y, ex, ey;
-    __device__ __forceinline__ void init(float ux, float uy) { x = ux; y = uy; ex = 0.f; ey = 0.f; }
-    __device__ __forceinline__ void add(float ux, float uy) { two_sum_acc(x, ex, ux); two_sum_acc(y, ey, uy); }
-    __device__ __forceinline__ void load(const void *p, int64_t i) {
-        const float4 v = static_cast<const float4 *>(p)[i];
-        x = v.x;
-        y = v.y;
-        ex = v.z;
-        ey = v.w;
-    }
-    __device__ __forceinline__ void store(void *p, int64_t i) const {
-        static_cast<float4 *>(p)[i] = make_float4(x, y, ex, ey);
-    }
-    __device__ __forceinline__ double vx() const { return (double)x + (double)ex; }
-    __device__ __forceinline__ double vy() const { return (double)y + (double)ey; }
 };
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -340,6 +322,8 @@ __global__ void __launch_bounds__(BLOCK) k_tile(TileArgs a) {
     off = align16(off + (int)sizeof(T) * a.cap_nvu);
     double *red = reinterpret_cast<double *>(smem + off);
     off = align16(off + 8 * NW * 9);
+    int *sLev = reinterpret_cast<int *>(smem + off);   // level counts: V_0..V_8, E_0..E_8
+    off = align16(off + 4 * 18);
     T *sAcc = reinterpret_cast<T *>(smem + off);   // sub-cell fluxes in local CSR order
     off = align16(off + (int)sizeof(T) * a.cap_cs);
     uint16_t *sRow = reinterpret_cast<uint16_t *>(smem + off);
@@ -364,8 +348,9 @@ __global__ void __launch_bounds__(BLOCK) k_tile(TileArgs a) {
 #pragma unroll
     for (int u = 0; u < VS; ++u) gv[u] = lv[min(tid + u * BLOCK, nv_load - 1)];
 
-    const T *lg = static_cast<const T *>(a.lgeom) + h.le_off;
-    const int64_t ls = a.lgeom_stride;
+    const uint4 *lrec = reinterpret_cast<const uint4 *>(a.le_rec) + h.le_off;
+    const T *lgeo = static_cast<const T *>(a.lgeo) + 4 * (int64_t)h.le_off;
+    const T *lae = static_cast<const T *>(a.lae) + h.le_off;
     const T2 *Uin = static_cast<const T2 *>(even ? a.U_u : a.U_w);
     const T2 *Rg = static_cast<const T2 *>(a.R);
     const T *fg = static_cast<const T *>(a.f);
@@ -379,16 +364,26 @@ __global__ void __launch_bounds__(BLOCK) k_tile(TileArgs a) {
 #pragma unroll
         for (int r = 0; r < EPT; ++r) {
             const int lc = min(tid + r * BLOCK, ne_load - 1);
-            gt[r] = a.le_gid[h.le_off + lc];
-            const uint32_t *tt = a.le_tri + 3 * (h.le_off + lc);
-            t0[r] = tt[0];
-            t1[r] = tt[1];
-            t2[r] = tt[2];
-            g0[r] = lg[lc];
-            g1[r] = lg[ls + lc];
-            g2[r] = lg[2 * ls + lc];
-            g3[r] = lg[3 * ls + lc];
-            g4[r] = lg[4 * ls + lc];
+            const uint4 rec = lrec[lc];
+            gt[r] = (int)rec.x;
+            t0[r] = rec.y;
+            t1[r] = rec.z;
+            t2[r] = rec.w;
+            if constexpr (F32) {
+                const float4 gg = reinterpret_cast<const float4 *>(lgeo)[lc];
+                g0[r] = gg.x;
+                g1[r] = gg.y;
+                g2[r] = gg.z;
+                g3[r] = gg.w;
+            } else {
+                const double2 ga = reinterpret_cast<const double2 *>(lgeo)[2 * lc];
+                const double2 gb = reinterpret_cast<const double2 *>(lgeo)[2 * lc + 1];
+                g0[r] = ga.x;
+                g1[r] = ga.y;
+                g2[r] = gb.x;
+                g3[r] = gb.y;
+            }
+            g4[r] = lae[lc];
         }
         if (!first && h.nown > 0) {
             // running sums of owned triangles (the tile's contiguous global range)
@@ -396,6 +391,17 @@ __global__ void __launch_bounds__(BLOCK) k_tile(TileArgs a) {
             for (int r = 0; r < EPT; ++r) sm[r].load(a.sum, h.ebase + min(tid + r * BLOCK, h.nown - 1));
         }
     }
+    // FP64 dual-cell areas of owned vertices, for the volume sums of this launch
+    constexpr int VO = 2;   // owned-vertex slots held in registers
+    const bool need_vol = first || track || last;
+    double rAv64[VO];
+    if (need_vol) {
+#pragma unroll
+        for (int k = 0; k < VO; ++k) rAv64[k] = a.Av64[h.vbase + min(tid + k * BLOCK, h.nv0 - 1)];
+    }
+    // level counts for the substep loop
+    const int lev_cnt = tid <= K ? nV[tid] : 0;
+    const int lev_cnt_e = tid <= K ? nE[tid] : 0;
     // local CSR row offsets (chunks padded to multiples of 4 entries)
     const uint2 *crow = reinterpret_cast<const uint2 *>(a.cs_row + h.rw_off);
     const int nrow4 = (nvu + 1 + 3) >> 2;
@@ -455,6 +461,10 @@ __global__ void __launch_bounds__(BLOCK) k_tile(TileArgs a) {
     {
         uint2 *srow2 = reinterpret_cast<uint2 *>(sRow);
         if (tid < nrow4) srow2[tid] = row0;
+        if (tid <= K) {
+            sLev[tid] = lev_cnt;
+            sLev[9 + tid] = lev_cnt_e;
+        }
     }
     if (!dma) {
 #pragma unroll
@@ -518,13 +528,18 @@ __global__ void __launch_bounds__(BLOCK) k_tile(TileArgs a) {
 
     double v0 = 0.0;
     if (first) {
-        for (int i = tid; i < h.nv0; i += BLOCK) v0 += a.Av64[h.vbase + i] * (double)sEta[i];
+#pragma unroll
+        for (int k = 0; k < VO; ++k) {
+            const int i = tid + k * BLOCK;
+            if (i < h.nv0) v0 += rAv64[k] * (double)sEta[i];
+        }
+        for (int i = tid + VO * BLOCK; i < h.nv0; i += BLOCK) v0 += a.Av64[h.vbase + i] * (double)sEta[i];
     }
     bool dry_any = false, bad_any = false;
     const T gd = cg<T>(c) * dts, th = cth<T>(c);
     for (int j = 0; j < cnt; ++j) {
         const int lev = cnt - j;
-        const int ne_act = nE[lev], nv_act = nV[lev - 1];
+        const int ne_act = sLev[9 + lev], nv_act = sLev[lev - 1];
 #pragma unroll
         for (int r = 0; r < EPT; ++r) {
             const int le = tid + r * BLOCK;
@@ -559,11 +574,25 @@ __global__ void __launch_bounds__(BLOCK) k_tile(TileArgs a) {
             }
         }
         __syncthreads();
-        double vp = 0.0;
-        for (int i = tid; i < nv_act; i += BLOCK) {
+        // vertex phase: row sums in entry order, loads issued four (or the last up to
+        // three) at a time; reads past a row end stay inside the flux array (its 64
+        // scratch slots) and are not summed
+        auto vertex = [&](int i) -> T {
             T acc = T(0);
+            int q = sRow[i];
             const int q1 = sRow[i + 1];
-            for (int q = sRow[i]; q < q1; ++q) acc += sAcc[q];
+            for (; q + 4 <= q1; q += 4) {
+                const T b0 = sAcc[q], b1 = sAcc[q + 1], b2 = sAcc[q + 2], b3 = sAcc[q + 3];
+                acc += b0;
+                acc += b1;
+                acc += b2;
+                acc += b3;
+            }
+            const int rem = q1 - q;
+            const T b0 = sAcc[q], b1 = sAcc[q + 1], b2 = sAcc[q + 2];
+            if (rem > 0) acc += b0;
+            if (rem > 1) acc += b1;
+            if (rem > 2) acc += b2;
             T en;
             if constexpr (F32)
                 en = sEta[i] - dts * (acc * sAv[i] + sW[i]);
@@ -571,9 +600,23 @@ __global__ void __launch_bounds__(BLOCK) k_tile(TileArgs a) {
                 en = sEta[i] - dts * (acc / sAv[i] + sW[i]);
             sEta[i] = en;
             bad_any |= !finite_val(en);
-            if (i < h.nv0) vp += a.Av64[h.vbase + i] * (double)en;
+            return en;
+        };
+        const bool vol_j = track || (last && j == cnt - 1);
+        double vp = 0.0;
+#pragma unroll
+        for (int k = 0; k < VO; ++k) {
+            const int i = tid + k * BLOCK;
+            if (i < nv_act) {
+                const T en = vertex(i);
+                if (vol_j && i < h.nv0) vp += rAv64[k] * (double)en;
+            }
         }
-        if (track || (last && j == cnt - 1)) {
+        for (int i = tid + VO * BLOCK; i < nv_act; i += BLOCK) {
+            const T en = vertex(i);
+            if (vol_j && i < h.nv0) vp += a.Av64[h.vbase + i] * (double)en;
+        }
+        if (vol_j) {
             vp = wave_sum(vp);
             if ((tid & 63) == 0) red[j * NW + (tid >> 6)] = vp;
         }
@@ -836,6 +879,7 @@ int tile_lds_bytes(bool f32, int block, int K, int cap_nv, int cap_ne, int cap_n
     off = al(off + ts * cap_nvu);
     off = al(off + ts * cap_nvu);
     off = al(off + 8 * (block / 64) * 9);
+    off = al(off + 4 * 18);
     off = al(off + ts * cap_cs);
     off = al(off + 2 * (cap_nvu + 4));
     return off;

@@ -87,8 +87,8 @@ struct DevTiles {
     size_t lds_bytes64 = 0, lds_bytes32 = 0;
     bool ok32 = false, ok64 = false;
     std::vector<TileHdr> hdr_host;
-    DevBuf hdr, nV, nE, lv_gid, le_gid, le_tri, cs_row;
-    DevBuf geom64, geom32;        // per local triangle, 5 SoA arrays
+    DevBuf hdr, nV, nE, lv_gid, le_rec, cs_row;
+    DevBuf geo64, geo32, ae64, ae32;   // per local triangle: 4 gradient values; A_e
     DevBuf lav64, lav32;          // per local vertex: A_v (FP64), 1 / A_v (FP32)
 };
 
