@@ -116,7 +116,8 @@ def bench_batched(args, log):
                        dt=dts, params=p32, Uavg=Uavg, volume=vol, workspace=ws,
                        use_graph=graph, stream=stream)
     with torch.cuda.stream(stream):
-        tune = autotune(batch, lambda: step(False), "f32", max(nsub), log=log, reset=reset)
+        tune = autotune(batch, lambda: step(False), "f32", max(nsub), top=24, log=log,
+                        reset=reset)
         reset()
         step(True)          # capture
         stream.synchronize()
@@ -322,7 +323,7 @@ def main():
             def reset64():
                 d64["eta"].copy_(e64)
                 d64["U"].copy_(u64)
-            t64 = autotune(mesh, lambda: step(d64, p64, ws64), "f64", nsub, log=log,
+            t64 = autotune(mesh, lambda: step(d64, p64, ws64), "f64", nsub, top=24, log=log,
                            reset=reset64)
             reset64()
             extra["fp64_plan"] = t64["plan"]

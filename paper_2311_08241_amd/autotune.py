@@ -2,9 +2,9 @@
 
 Candidates (vertices per tile, substeps per launch, workgroup size) are
 filtered on the host by se_plan_stats (register and LDS budget of the
-requested precision) and ranked by the modelled device-memory bytes per
-vertex-substep; the best-ranked few are timed on the GPU with the caller's
-state and the fastest is installed with se_set_plan.  Results are cached per
+requested precision) and ranked by a latency/occupancy model of one tile; the
+best-ranked are timed on the GPU with the caller's state, the fastest few timed
+again, and the winner is installed with se_set_plan.  Results are cached per
 (device name, precision, mesh signature, substep count) in a JSON file.
 """
 from __future__ import annotations
@@ -16,8 +16,8 @@ import time
 
 import numpy as np
 
-TILES = (256, 384, 512, 768, 1024)
-KS = (2, 3, 4, 5, 6, 8)
+TILES = (256, 320, 384, 448, 512, 576, 640, 768, 1024)
+KS = (2, 3, 4, 5, 6)
 BLOCKS = (256, 512, 1024)
 EPT_TIERS = (1, 2, 3, 4, 6, 8)
 LDS_MAX = 160 * 1024
@@ -44,21 +44,30 @@ def mesh_signature(mesh) -> str:
     return h.hexdigest()[:20]
 
 
-def candidates(mesh, precision: str, nsub: int, top: int = 18):
-    """Feasible plans: a diverse shortlist ranked by modelled traffic and halo work.
+def _vgprs(precision: str, ept: int) -> int:
+    """Approximate VGPRs of the tile kernel per register tier (measured from the
+    compiler's resource report: about 24 per triangle slot in FP32, 45 in FP64)."""
+    v = 32 + 24 * ept if precision == "f32" else 44 + 45 * ept
+    return -(-v // 8) * 8
 
-    One se_plan_stats call per (tile, k) gives the largest triangle count of a tile;
-    the register tier of each workgroup size follows from it.  From every
-    (workgroup size, tier) group the three best-scoring plans are kept, so that
-    plans of different occupancy are all timed.
+
+def candidates(mesh, precision: str, nsub: int, top: int = 30):
+    """Feasible plans, ranked by a latency/occupancy model of one tile.
+
+    A tile costs a fixed load/write-back latency plus, per substep, time
+    proportional to its triangles per thread; tiles resident per CU follow from
+    the register tier (VGPRs per wave) and the LDS size.  The estimate
+    (tile time) / (vertex-substeps per tile x resident tiles) orders the plans;
+    the shortlist is then timed.  One se_plan_stats call per (tile, k) gives the
+    largest triangle count and the LDS size.
     """
     lkey = "lds_f32" if precision == "f32" else "lds_f64"
-    bkey = "bytes_per_vs_f32" if precision == "f32" else "bytes_per_vs_f64"
-    b_stream = 236.0 if precision == "f32" else 356.0   # one streaming pass per substep
-    groups = {}
+    lat_us, sub_us = 5.8, 0.45      # load + write-back; per substep and triangle/thread
+    rows = []
     for K in KS:
         if K > nsub:
             continue
+        waste = (-(-nsub // K) * K) / nsub     # short last chunk of the launch sequence
         for T in TILES:
             try:
                 st = mesh.plan_stats(T, K, 256)
@@ -66,22 +75,20 @@ def candidates(mesh, precision: str, nsub: int, top: int = 18):
                 continue
             if st[lkey] > LDS_MAX:
                 continue
-            waste = (-(-nsub // K) * K) / nsub     # short last chunk of the launch sequence
             for B in BLOCKS:
                 need = -(-st["max_tri"] // B)
                 ept = next((e for e in EPT_TIERS if e >= need), None)
                 if ept is None or not _tier_ok(precision, ept, B):
                     continue
-                # relative device traffic plus relative triangle work (the halo rings
-                # are recomputed; on average half of the outermost ring's overhead)
-                score = (st[bkey] / b_stream + 0.5 * (1.0 + st["tri_overhead"])) * waste
-                groups.setdefault((B, ept), []).append((score, T, K, B, st))
-    short = []
-    for g in groups.values():
-        g.sort(key=lambda r: r[0])
-        short.extend(g[:4])
-    short.sort(key=lambda r: r[0])
-    return short[:top]
+                waves = min(8, 512 // _vgprs(precision, ept))
+                resident = min((4 * waves) // (B // 64), LDS_MAX // max(1, st[lkey]))
+                if resident < 1:
+                    continue
+                tile_us = lat_us + K * sub_us * st["max_tri"] / B
+                score = tile_us / (T * K * resident) * waste * 1e3
+                rows.append((score, T, K, B, st))
+    rows.sort(key=lambda r: r[0])
+    return rows[:top]
 
 
 def _load_cache():
@@ -103,10 +110,13 @@ def _save_cache(c):
         pass
 
 
-def autotune(mesh, run_step, precision: str, nsub: int, *, top: int = 18, reps: int = 3,
-             use_cache: bool = True, log=None, reset=None):
+def autotune(mesh, run_step, precision: str, nsub: int, *, top: int = 30, reps: int = 3,
+             final: int = 3, final_reps: int = 10, use_cache: bool = True, log=None,
+             reset=None):
     """Pick and install the fastest plan.
 
+    Every candidate is timed over `reps` steps; the `final` fastest are timed again
+    over `final_reps` steps and the fastest of those is installed.
     run_step() must perform one se_subcycle call with the mesh's current plan
     on the caller's stream; reset(), if given, restores the state before each
     candidate (outside the timed region) so long tuning runs stay physical.
@@ -122,30 +132,40 @@ def autotune(mesh, run_step, precision: str, nsub: int, *, top: int = 18, reps: 
         mesh.set_plan(T, K, B)
         return dict(cache[key], cached=True)
     table = []
-    best = None
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    for model, T, K, B, st in candidates(mesh, precision, nsub, top):
-        t0 = time.time()
+
+    def timed(T, K, B, n):
         mesh.set_plan(T, K, B)
         if reset is not None:
             reset()
         run_step()
         torch.cuda.synchronize()
         e0.record()
-        for _ in range(reps):
+        for _ in range(n):
             run_step()
         e1.record()
         torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / reps
+        return e0.elapsed_time(e1) / n
+
+    for model, T, K, B, st in candidates(mesh, precision, nsub, top):
+        t0 = time.time()
+        ms = timed(T, K, B, reps)
         table.append({"plan": [T, K, B], "ms": ms, "score": model,
                       "tri_overhead": st["tri_overhead"]})
         if log:
             log(f"[tune] T={T} K={K} B={B}: {ms:.3f} ms/step (score {model:.2f}, "
                 f"setup {time.time() - t0:.1f}s)")
-        if best is None or ms < best[0]:
-            best = (ms, T, K, B)
-    if best is None:
+    if not table:
         raise RuntimeError("autotune: no feasible plan")
+    best = None
+    for row in sorted(table, key=lambda r: r["ms"])[:final]:
+        ms = timed(*row["plan"], final_reps)
+        row["ms_final"] = ms
+        if log:
+            log(f"[tune] final T={row['plan'][0]} K={row['plan'][1]} B={row['plan'][2]}: "
+                f"{ms:.3f} ms/step")
+        if best is None or ms < best[0]:
+            best = (ms, *row["plan"])
     mesh.set_plan(*best[1:])
     res = {"plan": list(best[1:]), "ms": best[0], "table": table}
     if use_cache:

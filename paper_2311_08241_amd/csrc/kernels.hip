@@ -90,23 +90,32 @@ __device__ __forceinline__ void tri_update_f32(float ea, float eb, float ec, flo
                                                float al, float rk, float gd, float th,
                                                bool linear_h, float &Unx, float &Uny, float &pa,
                                                float &pb, float &pc, bool &dry) {
+    // fused multiply-adds (one rounding each) where a product feeds a sum
     const float db = eb - ea, dc = ec - ea;
-    const float gx = db * gbx + dc * gcx;
-    const float gy = db * gby + dc * gcy;
-    const float He = linear_h ? rH : rH + (ea + eb + ec) * (1.0f / 3.0f);
+    const float gx = __builtin_fmaf(db, gbx, dc * gcx);
+    const float gy = __builtin_fmaf(db, gby, dc * gcy);
+    const float He = linear_h ? rH : __builtin_fmaf(ea + eb + ec, 1.0f / 3.0f, rH);
     dry = !(He > 0.0f);
     const float gHe = gd * He;
-    const float px = (dRx - gHe * gx) + 2.0f * al * uy;
-    const float py = (dRy - gHe * gy) - 2.0f * al * ux;
-    const float dx = (px + al * py) * rk;
-    const float dy = (py - al * px) * rk;
+    const float al2 = 2.0f * al;
+    const float px = __builtin_fmaf(al2, uy, __builtin_fmaf(-gHe, gx, dRx));
+    const float py = __builtin_fmaf(-al2, ux, __builtin_fmaf(-gHe, gy, dRy));
+    const float dx = __builtin_fmaf(al, py, px) * rk;
+    const float dy = __builtin_fmaf(-al, px, py) * rk;
     Unx = ux + dx;
     Uny = uy + dy;
-    const float Fx = Unx + th * dx;   // (1 + theta) U' - theta U
-    const float Fy = Uny + th * dy;
-    pb = mAe * (Fx * gbx + Fy * gby);
-    pc = mAe * (Fx * gcx + Fy * gcy);
+    const float Fx = __builtin_fmaf(th, dx, Unx);   // (1 + theta) U' - theta U
+    const float Fy = __builtin_fmaf(th, dy, Uny);
+    pb = mAe * __builtin_fmaf(Fx, gbx, Fy * gby);
+    pc = mAe * __builtin_fmaf(Fx, gcx, Fy * gcy);
     pa = -(pb + pc);
+}
+
+// FP32 vertex update eta - dt (sum / A_v + W) with the reciprocal area 1 / A_v
+// (identical in every path).
+template <typename T>
+__device__ __forceinline__ T vtx_update_f32(T eta, T acc, T rav, T w, T dts) {
+    return __builtin_fmaf(-dts, __builtin_fmaf(acc, rav, w), eta);
 }
 
 // Per-triangle constants of the FP32 update (identical in every path).
@@ -231,7 +240,7 @@ __global__ void __launch_bounds__(256) k_plain_vtx(PlainArgs a) {
         const T eo = eta[v];
         const T wv = a.W ? static_cast<const T *>(a.W)[v] : T(0);
         const T av = static_cast<const T *>(a.Av)[v];
-        const T en = F32 ? eo - cdts<T>(c) * (acc * (T(1) / av) + wv)
+        const T en = F32 ? vtx_update_f32(eo, acc, T(1) / av, wv, cdts<T>(c))
                          : eo - cdts<T>(c) * (acc / av + wv);
         eta[v] = en;
         if (!finite_val(en)) set_fault(a.faults, 2u);
@@ -329,13 +338,11 @@ __global__ void __launch_bounds__(BLOCK) k_tile(TileArgs a) {
     uint16_t *sRow = reinterpret_cast<uint16_t *>(smem + off);
 
     // ---- load phase in two rounds of independent loads: (A) index and static data
-    // (local vertex ids, triangle ids, packed local connectivity, geometry, row
-    // offsets, running sums), one wait, then (B) the gathers through those indices,
-    // one wait before the barrier.  FP32 vertex gathers go straight to LDS
-    // (global_load_lds: LDS address from M0, used while the vertex arrays end within
-    // the first 64 KiB of LDS), the rest through registers.
-    const bool dma =
-        F32 && (uint32_t)(size_t)(__attribute__((address_space(3))) T *)(sW + a.cap_nvu) <= 65536u;
+    // (local vertex ids, triangle records, geometry, row offsets, running sums), one
+    // wait, then (B) the gathers through those indices, one wait before the barrier.
+    // FP32 vertex gathers go straight to LDS (global_load_lds, the LDS address from
+    // M0), FP64 ones through registers.
+    constexpr bool dma = F32;
     const T *eta_in = static_cast<const T *>(even ? a.eta_u : a.eta_w);
     const T *H0 = static_cast<const T *>(a.H0);
     const T *Wt = static_cast<const T *>(a.W);
@@ -595,7 +602,7 @@ __global__ void __launch_bounds__(BLOCK) k_tile(TileArgs a) {
             if (rem > 2) acc += b2;
             T en;
             if constexpr (F32)
-                en = sEta[i] - dts * (acc * sAv[i] + sW[i]);
+                en = vtx_update_f32(sEta[i], acc, sAv[i], sW[i], dts);
             else
                 en = sEta[i] - dts * (acc / sAv[i] + sW[i]);
             sEta[i] = en;
