@@ -117,7 +117,7 @@ def bench_batched(args, log):
                        use_graph=graph, stream=stream)
     with torch.cuda.stream(stream):
         tune = autotune(batch, lambda: step(False), "f32", max(nsub), top=24, log=log,
-                        reset=reset)
+                        reset=reset, use_cache=not args.retune)
         reset()
         step(True)          # capture
         stream.synchronize()
@@ -212,6 +212,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
     ap.add_argument("--no-extra", action="store_true", help="skip the FP64 comparison runs")
     ap.add_argument("--small", action="store_true", help="reduced mesh (testing the script)")
+    ap.add_argument("--retune", action="store_true",
+                    help="time the plan candidates even if a tuned plan is cached or shipped")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only; multi-GPU sharding is designed "
@@ -262,7 +264,8 @@ def main():
         def reset():
             scratch["eta"].copy_(d["eta"])
             scratch["U"].copy_(d["U"])
-        tune = autotune(mesh, lambda: step(scratch), prec, nsub, log=log, reset=reset)
+        tune = autotune(mesh, lambda: step(scratch), prec, nsub, log=log, reset=reset,
+                        use_cache=not args.retune)
         del scratch
         log(f"[bench] autotuned plan {tune['plan']} ({tune['ms']:.3f} ms/step, "
             f"cached={tune['cached']})")
@@ -324,7 +327,7 @@ def main():
                 d64["eta"].copy_(e64)
                 d64["U"].copy_(u64)
             t64 = autotune(mesh, lambda: step(d64, p64, ws64), "f64", nsub, top=24, log=log,
-                           reset=reset64)
+                           reset=reset64, use_cache=not args.retune)
             reset64()
             extra["fp64_plan"] = t64["plan"]
         for label, plain in (("fp64_plain", True), ("fp64_fused", False)):

@@ -23,6 +23,9 @@ EPT_TIERS = (1, 2, 3, 4, 6, 8)
 LDS_MAX = 160 * 1024
 CACHE = os.environ.get("SESUB_TUNE_CACHE",
                        os.path.join(os.path.expanduser("~"), ".cache", "sesub_plans.json"))
+# plans tuned on MI355X for the synthetic workloads, consulted when CACHE has no
+# entry (read-only; keys as in CACHE)
+SHIPPED = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_plans.json")
 
 
 def _tier_ok(precision: str, ept: int, block: int) -> bool:
@@ -91,12 +94,16 @@ def candidates(mesh, precision: str, nsub: int, top: int = 30):
     return rows[:top]
 
 
-def _load_cache():
+def _load_json(path):
     try:
-        with open(CACHE) as f:
+        with open(path) as f:
             return json.load(f)
     except Exception:
         return {}
+
+
+def _load_cache():
+    return _load_json(CACHE)
 
 
 def _save_cache(c):
@@ -126,11 +133,12 @@ def autotune(mesh, run_step, precision: str, nsub: int, *, top: int = 30, reps: 
     props = torch.cuda.get_device_properties(mesh.device)
     dev = f"{getattr(props, 'gcnArchName', '?')}x{props.multi_processor_count}"
     key = f"{dev}|{precision}|{mesh_signature(mesh)}|{nsub}"
-    cache = _load_cache() if use_cache else {}
-    if key in cache:
-        T, K, B = cache[key]["plan"]
-        mesh.set_plan(T, K, B)
-        return dict(cache[key], cached=True)
+    if use_cache:
+        for src in (_load_cache(), _load_json(SHIPPED)):
+            if key in src:
+                T, K, B = src[key]["plan"]
+                mesh.set_plan(T, K, B)
+                return dict(src[key], cached=True)
     table = []
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
