@@ -5,7 +5,8 @@ leg of the benchmark may import this package; the GPU library never does, and
 this package imports nothing from it.
 
 Contents
-  oracle.c     plain C definition (reorder, geometry, forward, TLM, adjoint)
+  oracle.c     plain C definition (reorder, geometry, forward SE and SESM, TLM,
+               adjoint)
   brute.py     dense operators from an independent median-dual construction
   analytic.py  closed forms of the paper's Sec. 3 (amplification matrix,
                characteristic polynomial, small-c expansions)
@@ -154,6 +155,24 @@ class Mesh:
         _check(L.orc_subcycle(*self._common(g, theta, linear_h, H0, f, R, W),
                               ctypes.c_int32(nsub), ctypes.c_double(tau), _p(eta), _p(U),
                               _p(Uavg), _p(vol)))
+        return eta, U, Uavg, vol
+
+    def subcycle_sesm(self, eta, U, *, H0, f, R, W=None, g, beta, delta, gamma, zeta, nsub,
+                      tau, linear_h=False, volume=True):
+        """One baroclinic step of the AB3-AM4 (SESM) scheme, eqs. (eq4_7)-(eq4_8).
+        Returns (eta, U, Uavg, volume); Uavg is the mean AB3 transport."""
+        L = _load()
+        eta = _f64(eta).copy()
+        U = _f64(U, (self.ne, 2)).copy()
+        Uavg = np.empty((self.ne, 2))
+        vol = np.empty(nsub + 1) if volume else None
+        args = (ctypes.c_int64(self.nv), ctypes.c_int64(self.ne), _p(self.tri), _p(self.Ae),
+                _p(self.gN), _p(self.Av), ctypes.c_double(g), ctypes.c_double(beta),
+                ctypes.c_double(delta), ctypes.c_double(gamma), ctypes.c_double(zeta),
+                ctypes.c_int(1 if linear_h else 0), _p(_f64(H0)), _p(_f64(f)),
+                _p(_f64(R, (self.ne, 2))), _p(None if W is None else _f64(W)),
+                ctypes.c_int32(nsub), ctypes.c_double(tau), _p(eta), _p(U), _p(Uavg), _p(vol))
+        _check(L.orc_subcycle_sesm(*args))
         return eta, U, Uavg, vol
 
     def tlm(self, eta0, U0, d_eta0, d_U0, d_R, d_H0, *, H0, f, R, W=None, g, theta, nsub,

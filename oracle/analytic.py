@@ -96,6 +96,51 @@ def sesm_char_poly_coeffs(c, b, d, g, z):
         1.0])
 
 
+def sesm_params(theta, beta=0.281105):
+    """(beta, delta, gamma, zeta) of the SESM scheme at the dissipation of SE(theta).
+
+    2 chi = theta (eq. (eqdp_4), SE line); beta of the largest stability limit
+    (Sec. 3.2); zeta and gamma from eq. (eqdp_6), second line (no O(c^3) phase
+    constraint; the setting of Fig. 2); delta from 2 chi = delta - gamma - 2 zeta - 1/2
+    (eq. (eqdp_4), SESM line).
+    """
+    chi = 0.5 * theta
+    zeta = 0.010 - 0.135 * chi
+    gamma = 0.083 - 0.514 * chi
+    delta = 2.0 * chi + gamma + 2.0 * zeta + 0.5
+    return beta, delta, gamma, zeta
+
+
+def sesm_stability_limit(beta, delta, gamma, zeta, c_max=3.0, n=3000):
+    """Largest c on a grid below which every eigenvalue of eq. (eq3_5) has |lambda| <= 1."""
+    last = 0.0
+    for c in np.linspace(c_max / n, c_max, n):
+        if np.max(np.abs(np.linalg.eigvals(sesm_matrix(c, beta, delta, gamma, zeta)))) > 1 + 1e-12:
+            return last
+        last = c
+    return last
+
+
+def sesm_torus_mode_amplitudes(c2, params, nsub, restart_every=None):
+    """a_m: eta^m = a_m cos(k.x) from eta^0 = cos(k.x), U^0 = 0 under eq. (eq3_5).
+
+    The history levels start equal to the initial state; with restart_every = n
+    they are reset to the current state every n substeps (a new subcycle).
+    """
+    c = np.sqrt(c2)
+    Mc = sesm_matrix(c, *params)
+    v = np.array([1, 1, 1, 0, 0, 0], dtype=complex)
+    out = [1.0]
+    for m in range(1, nsub + 1):
+        v = Mc @ v
+        out.append(v[0])
+        if restart_every and m % restart_every == 0:
+            v = np.array([v[0], v[0], v[0], v[3], v[3], v[3]])
+    out = np.array(out)
+    assert np.max(np.abs(out.imag)) < 1e-12 * max(1.0, np.max(np.abs(out.real)))
+    return out.real
+
+
 # ---- mesh symbol on a consistently split rectangular torus --------------------
 def torus_symbol(kx, ky, dx, dy):
     """Eigenvalue of -D G for exp(i k.x): the 5-point Laplacian symbol."""

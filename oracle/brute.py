@@ -13,7 +13,8 @@ used by ``oracle.c``:
 
 The substep then follows eq. (eq4_10) of the paper with dense matrices and
 numpy.linalg.solve for the Crank-Nicolson Coriolis system (pressure sign of
-eq. (eq4_5), see oracle.c).
+eq. (eq4_5), see oracle.c); the AB3-AM4 substep of eqs. (eq4_7)-(eq4_8) is
+written the same way, with the histories kept as lists of states.
 """
 from __future__ import annotations
 
@@ -132,3 +133,29 @@ def linear_step_matrix(ops, *, H, theta, dts):
         Mx[:nv, j] = en
         Mx[nv:, j] = Un.reshape(-1)
     return Mx
+
+
+def subcycle_sesm(ops, eta, U, *, H0, f, R, W=None, g, beta, delta, gamma, zeta, nsub, tau,
+                  linear_h=False):
+    """AB3-AM4 subcycle with the dense operators; histories start from the initial
+    state.  Returns (eta^M, U^M, mean of the AB3 transports)."""
+    dts = tau / nsub
+    ne = ops["ne"]
+    Us = [np.asarray(U, float).reshape(ne, 2).copy()] * 3      # U^m, U^{m-1}, U^{m-2}
+    etas = [np.asarray(eta, float).copy()] * 3
+    ab = np.array([1.5 + beta, -(0.5 + 2.0 * beta), beta])
+    am = np.array([delta, 1.0 - delta - gamma - zeta, gamma, zeta])
+    fz = np.asarray(f, float)[:, None]
+    acc = np.zeros((ne, 2))
+    for _ in range(nsub):
+        Uab = ab[0] * Us[0] + ab[1] * Us[1] + ab[2] * Us[2]
+        eta_n = etas[0] - dts * (ops["D"] @ Uab.reshape(-1) + (0.0 if W is None else W))
+        eam = am[0] * eta_n + am[1] * etas[0] + am[2] * etas[1] + am[3] * etas[2]
+        grad = (ops["G"] @ eam).reshape(ne, 2)
+        He = ops["P"] @ (H0 if linear_h else H0 + eam)
+        cor = np.column_stack([fz[:, 0] * Uab[:, 1], -fz[:, 0] * Uab[:, 0]])   # -f e_z x U
+        Un = Us[0] + dts * (cor - g * He[:, None] * grad + np.asarray(R, float).reshape(ne, 2))
+        Us = [Un, Us[0], Us[1]]
+        etas = [eta_n, etas[0], etas[1]]
+        acc += Uab
+    return etas[0], Us[0], acc / nsub

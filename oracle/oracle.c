@@ -349,6 +349,87 @@ int orc_subcycle(int64_t nv, int64_t ne, const int32_t *tri, const double *Ae,
 }
 
 /* ------------------------------------------------------------------------ */
+/* SESM: the AB3-AM4 substep with dissipative coefficients (Sec. 2.2,        */
+/* eqs. (eq4_7), (eq4_8)).  Per substep m, in the order of eq. (eq4_8):      */
+/*   U_ab = (3/2 + beta) U^m - (1/2 + 2 beta) U^{m-1} + beta U^{m-2}         */
+/*   eta^{m+1} = eta^m - dt_s (div U_ab + W)                                 */
+/*   eta_am = delta eta^{m+1} + (1 - delta - gamma - zeta) eta^m             */
+/*            + gamma eta^{m-1} + zeta eta^{m-2}                             */
+/*   U^{m+1} = U^m + dt_s (-f e_z x U_ab - g H_am grad eta_am + R)           */
+/* with H_am the triangle mean of H0 + eta_am (the depth of eq. (eq4_5) at   */
+/* the AM4 level; mean H0 with linear_h).  Readings where the paper is       */
+/* silent: the histories start from the initial state (U^{-1} = U^{-2} =    */
+/* U^0, likewise eta), and the averaged transport is the mean of U_ab over   */
+/* m = 0..M-1, the transport whose divergence the elevation sums over the    */
+/* subcycle (the counterpart of eq. (eq4_11)).                               */
+/* ------------------------------------------------------------------------ */
+int orc_subcycle_sesm(int64_t nv, int64_t ne, const int32_t *tri, const double *Ae,
+                      const double *gN, const double *Av, double g, double beta,
+                      double delta, double gamma, double zeta, int linear_h,
+                      const double *H0, const double *f, const double *R, const double *W,
+                      int32_t nsub, double tau, double *eta, double *U, double *Uavg,
+                      double *volume)
+{
+    if (nsub <= 0 || nv <= 0 || ne <= 0) return ORC_ERR_ARG;
+    orc_mesh m = {nv, ne, tri, Ae, gN, Av};
+    double dts = tau / (double)nsub;
+    size_t nb2 = sizeof(double) * 2 * ne, nbv = sizeof(double) * nv;
+    double *U1 = (double *)malloc(nb2), *U2 = (double *)malloc(nb2), *Uab = (double *)malloc(nb2);
+    double *e1 = (double *)malloc(nbv), *e2 = (double *)malloc(nbv), *enew = (double *)malloc(nbv);
+    double *eam = (double *)malloc(nbv), *div = (double *)malloc(nbv);
+    double *sum = (double *)calloc((size_t)(2 * ne), sizeof(double));
+    if (!U1 || !U2 || !Uab || !e1 || !e2 || !enew || !eam || !div || !sum) {
+        free(U1); free(U2); free(Uab); free(e1); free(e2); free(enew); free(eam); free(div);
+        free(sum);
+        return ORC_ERR_OOM;
+    }
+    memcpy(U1, U, nb2);
+    memcpy(U2, U, nb2);
+    memcpy(e1, eta, nbv);
+    memcpy(e2, eta, nbv);
+    if (volume) volume[0] = volume_of(&m, eta);
+    for (int32_t s = 0; s < nsub; ++s) {
+        /* AB3 transport */
+        for (int64_t i = 0; i < 2 * ne; ++i)
+            Uab[i] = (1.5 + beta) * U[i] - (0.5 + 2.0 * beta) * U1[i] + beta * U2[i];
+        /* elevation from the divergence of the AB3 transport */
+        for (int64_t v = 0; v < nv; ++v) div[v] = 0.0;
+        for (int64_t e = 0; e < ne; ++e)
+            for (int k = 0; k < 3; ++k) div[tri[3 * e + k]] += slot_flux(&m, e, k, Uab + 2 * e);
+        for (int64_t v = 0; v < nv; ++v)
+            enew[v] = eta[v] - dts * (div[v] / Av[v] + (W ? W[v] : 0.0));
+        /* AM4 elevation */
+        for (int64_t v = 0; v < nv; ++v)
+            eam[v] = delta * enew[v] + (1.0 - delta - gamma - zeta) * eta[v] + gamma * e1[v] +
+                     zeta * e2[v];
+        /* transport: explicit Coriolis on U_ab, pressure of eta_am */
+        for (int64_t e = 0; e < ne; ++e) {
+            orc_elem q;
+            elem_quantities(&m, e, eam, H0, f[e], dts, linear_h, &q);
+            const double *ua = Uab + 2 * e;
+            double Unx = U[2 * e] + dts * (f[e] * ua[1] - g * q.He * q.gx + R[2 * e]);
+            double Uny = U[2 * e + 1] + dts * (-f[e] * ua[0] - g * q.He * q.gy + R[2 * e + 1]);
+            U2[2 * e] = U1[2 * e];
+            U2[2 * e + 1] = U1[2 * e + 1];
+            U1[2 * e] = U[2 * e];
+            U1[2 * e + 1] = U[2 * e + 1];
+            U[2 * e] = Unx;
+            U[2 * e + 1] = Uny;
+        }
+        for (int64_t v = 0; v < nv; ++v) {
+            e2[v] = e1[v];
+            e1[v] = eta[v];
+            eta[v] = enew[v];
+        }
+        for (int64_t i = 0; i < 2 * ne; ++i) sum[i] += Uab[i];
+        if (volume) volume[s + 1] = volume_of(&m, eta);
+    }
+    for (int64_t i = 0; i < 2 * ne; ++i) Uavg[i] = sum[i] / (double)nsub;
+    free(U1); free(U2); free(Uab); free(e1); free(e2); free(enew); free(eam); free(div); free(sum);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Tangent-linear model: derivative of the subcycle map along                */
 /* (d_eta0, d_U0, d_R, d_H0); the state is advanced alongside.               */
 /* ------------------------------------------------------------------------ */
