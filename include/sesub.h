@@ -59,6 +59,24 @@ typedef enum {
 
 typedef enum { SE_F64 = 0, SE_F32_MIXED = 1 } se_precision;
 
+/* Time-stepping scheme of the substeps (se_params.scheme).
+ * SE_SCHEME_SE: the dissipative forward-backward substep of eq. (eq4_10)
+ *   (the default; all entry points).
+ * SE_SCHEME_SESM: the AB3-AM4 substep of Sec. 2.2, eqs. (eq4_7)-(eq4_8):
+ *     U_ab = (3/2 + beta) U^m - (1/2 + 2 beta) U^{m-1} + beta U^{m-2}
+ *     eta^{m+1} = eta^m - dt_s (div U_ab + W)
+ *     eta_am = delta eta^{m+1} + (1 - delta - gamma - zeta) eta^m
+ *              + gamma eta^{m-1} + zeta eta^{m-2}
+ *     U^{m+1} = U^m + dt_s (-f e_z x U_ab - g H_am grad eta_am + R)
+ *   with H_am = H0 + eta_am; the histories start from the initial state
+ *   (U^{-1} = U^{-2} = U^0, likewise eta) and <<U>> is the mean of U_ab over
+ *   m = 0..M-1 (the transport whose divergence the elevation sums).  The
+ *   coefficients come from se_params (eq. (eqdp_6) gives the paper's
+ *   settings); theta is not used.  Supported by se_subcycle and
+ *   se_subcycle_plain; the adjoint and the batched form return
+ *   SE_ERR_UNSUPPORTED. */
+typedef enum { SE_SCHEME_SE = 0, SE_SCHEME_SESM = 1 } se_scheme;
+
 /* mesh flags */
 #define SE_PERIODIC_X 1u
 #define SE_PERIODIC_Y 2u
@@ -66,7 +84,7 @@ typedef enum { SE_F64 = 0, SE_F32_MIXED = 1 } se_precision;
 
 /* parameter flags */
 #define SE_LINEAR_H 1u      /* H = H0 in the pressure term (linear free surface)     */
-#define SE_CHECK_CFL 2u     /* reject dt_s above the SE stability bound              */
+#define SE_CHECK_CFL 2u     /* reject dt_s above the scheme's stability bound        */
 #define SE_TRACK_VOLUME 4u  /* write sum_v A_v eta_v after every substep             */
 
 /* fault bits (se_check_faults) */
@@ -124,6 +142,9 @@ typedef struct {
     uint32_t flags;    /* SE_LINEAR_H | SE_CHECK_CFL | SE_TRACK_VOLUME              */
     double eta_ref;    /* SE_F32_MIXED: eta arrays hold eta - eta_ref               */
     double h_max;      /* SE_CHECK_CFL: bound on H0 + eta over the run (m)          */
+    int32_t scheme;    /* se_scheme (zero: SE_SCHEME_SE)                            */
+    int32_t reserved;  /* must be 0                                                 */
+    double beta, delta, gamma, zeta;   /* SE_SCHEME_SESM coefficients, eq. (eq4_7)  */
 } se_params;
 
 /* State, device arrays, updated in place. */

@@ -20,6 +20,7 @@ c_int64, c_int32, c_uint32, c_double, c_void_p = (ctypes.c_int64, ctypes.c_int32
 SE_OK, SE_ERR_ARG, SE_ERR_MESH, SE_ERR_HIP, SE_ERR_OOM, SE_ERR_CFL = 0, 1, 2, 3, 4, 5
 SE_ERR_DRY, SE_ERR_NONFINITE, SE_ERR_UNSUPPORTED = 6, 7, 8
 SE_F64, SE_F32_MIXED = 0, 1
+SE_SCHEME_SE, SE_SCHEME_SESM = 0, 1
 SE_PERIODIC_X, SE_PERIODIC_Y, SE_SPHERICAL = 1, 2, 4
 SE_LINEAR_H, SE_CHECK_CFL, SE_TRACK_VOLUME = 1, 2, 4
 SE_FAULT_DRY, SE_FAULT_NONFINITE = 1, 2
@@ -36,7 +37,9 @@ class MeshDesc(ctypes.Structure):
 
 class Params(ctypes.Structure):
     _fields_ = [("g", c_double), ("theta", c_double), ("precision", c_int32),
-                ("flags", c_uint32), ("eta_ref", c_double), ("h_max", c_double)]
+                ("flags", c_uint32), ("eta_ref", c_double), ("h_max", c_double),
+                ("scheme", c_int32), ("reserved", c_int32), ("beta", c_double),
+                ("delta", c_double), ("gamma", c_double), ("zeta", c_double)]
 
 
 class State(ctypes.Structure):

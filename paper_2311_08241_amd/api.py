@@ -29,9 +29,22 @@ def _stream_ptr(stream=None):
     return ctypes.c_void_p(s.cuda_stream)
 
 
+def sesm_coefficients(theta: float = 0.14, beta: float = 0.281105):
+    """(beta, delta, gamma, zeta) of the AB3-AM4 scheme at the dissipation of the
+    forward-backward scheme with this theta: 2 chi = theta (eq. (eqdp_4)); beta of
+    the largest stability limit (Sec. 3.2); zeta, gamma from eq. (eqdp_6), second
+    line; delta from 2 chi = delta - gamma - 2 zeta - 1/2 (eq. (eqdp_4))."""
+    chi = 0.5 * theta
+    zeta = 0.010 - 0.135 * chi
+    gamma = 0.083 - 0.514 * chi
+    return beta, 2.0 * chi + gamma + 2.0 * zeta + 0.5, gamma, zeta
+
+
 @dataclass
 class Params:
-    """se_params: g, theta (eq. (eq4_10)), precision, flags, eta_ref, h_max."""
+    """se_params: g, theta (eq. (eq4_10)), precision, flags, eta_ref, h_max, scheme
+    ("se" or "sesm", eqs. (eq4_7)-(eq4_8)) and the SESM coefficients (default: those
+    of sesm_coefficients(theta))."""
     g: float = 9.81
     theta: float = 0.14
     precision: str = "f64"          # "f64" | "f32" (FP32 bulk, FP64 volume and average)
@@ -40,6 +53,8 @@ class Params:
     track_volume: bool = True
     eta_ref: float = 0.0
     h_max: float = 0.0
+    scheme: str = "se"
+    sesm: tuple | None = None       # (beta, delta, gamma, zeta)
 
     @property
     def dtype(self):
@@ -52,9 +67,15 @@ class Params:
         flags = ((L.SE_LINEAR_H if self.linear_h else 0) |
                  (L.SE_CHECK_CFL if self.check_cfl else 0) |
                  (L.SE_TRACK_VOLUME if self.track_volume else 0))
+        if self.scheme not in ("se", "sesm"):
+            raise ValueError("scheme must be 'se' or 'sesm'")
+        co = (self.sesm if self.sesm is not None else sesm_coefficients(self.theta)) \
+            if self.scheme == "sesm" else (0.0, 0.0, 0.0, 0.0)
         return L.Params(self.g, self.theta,
                         L.SE_F64 if self.precision == "f64" else L.SE_F32_MIXED, flags,
-                        self.eta_ref, self.h_max)
+                        self.eta_ref, self.h_max,
+                        L.SE_SCHEME_SESM if self.scheme == "sesm" else L.SE_SCHEME_SE, 0,
+                        *[float(v) for v in co])
 
 
 class Mesh:

@@ -2,6 +2,7 @@
 // plan management, and the launch sequences of the forward paths.
 #include <algorithm>
 #include <cmath>
+#include <complex>
 #include <cstring>
 #include <string>
 
@@ -242,12 +243,24 @@ se_status make_plan(const std::vector<const HostMesh *> &members, const std::vec
 
 struct Layout {
     size_t eta_alt, U_alt, sum, U0c, phi, vol, total;
+    size_t sv[8], se[7];   // AB3-AM4 only: 8 vertex arrays, 7 triangle (transport) arrays
 };
 
-Layout fwd_layout(int64_t nv, int64_t ne, bool f32, int32_t nsub, int64_t width) {
+Layout fwd_layout(int64_t nv, int64_t ne, bool f32, int32_t nsub, int64_t width,
+                  bool sesm = false) {
     const size_t s = f32 ? 4 : 8;
     Layout L{};
     size_t o = 0;
+    if (sesm) {
+        for (int k = 0; k < 8; ++k) {
+            L.sv[k] = o;
+            o += al(nv * s);
+        }
+        for (int k = 0; k < 7; ++k) {
+            L.se[k] = o;
+            o += al(2 * ne * s);
+        }
+    }
     L.eta_alt = o;
     o += al(nv * s);
     L.U_alt = o;
@@ -296,6 +309,52 @@ AdjLayout adj_layout(int64_t nv, int64_t ne, bool f32, int32_t nsub, int32_t k, 
 
 int64_t vol_width(int64_t nv) { return std::max<int64_t>((nv + 63) / 64, (nv + 255) / 256); }
 
+// Largest |lambda| among the roots of the SESM characteristic polynomial of
+// eq. (eqdp_1) at CFL number c (Durand-Kerner iteration on the monic degree-6
+// polynomial; the printed '+-' of its lambda^2 term read as '-').
+double sesm_max_root(double c, double b, double d, double g, double z) {
+    const double c2 = c * c;
+    const double co[7] = {
+        b * z * c2,
+        c2 * (b * (g - 2 * z) - z / 2),
+        -c2 * ((d + 3 * g - 1) * b + g / 2 - 1.5 * z),
+        c2 / 2 * (b * (6 * d + 6 * g + 4 * z - 4) + d + 4 * g + z - 1),
+        1 + c2 / 2 * (b * (-6 * d - 2 * g - 2 * z + 2) - 4 * d - 3 * g - 3 * z + 3),
+        -2 + c2 * d / 2 * (2 * b + 3),
+        1.0};
+    using cd = std::complex<double>;
+    auto P = [&](cd x) {
+        cd r = co[6];
+        for (int k = 5; k >= 0; --k) r = r * x + co[k];
+        return r;
+    };
+    cd rt[6];
+    for (int k = 0; k < 6; ++k) rt[k] = std::pow(cd(0.4, 0.9), k);
+    for (int it = 0; it < 500; ++it) {
+        double delta = 0.0;
+        for (int k = 0; k < 6; ++k) {
+            cd den = 1.0;
+            for (int j = 0; j < 6; ++j)
+                if (j != k) den *= rt[k] - rt[j];
+            const cd step = P(rt[k]) / den;
+            rt[k] -= step;
+            delta = std::max(delta, std::abs(step));
+        }
+        if (delta < 1e-14) break;
+    }
+    double mx = 0.0;
+    for (int k = 0; k < 6; ++k) mx = std::max(mx, std::abs(rt[k]));
+    return mx;
+}
+
+// Whether every CFL number in (0, c] is stable for the SESM coefficients.
+bool sesm_stable_upto(double c, double b, double d, double g, double z) {
+    const int n = 400;
+    for (int i = 1; i <= n; ++i)
+        if (sesm_max_root(c * i / n, b, d, g, z) > 1.0 + 1e-9) return false;
+    return true;
+}
+
 se_status check_params(const se_mesh *m, const se_params *p, int32_t nsub, double dt) {
     if (!m || !p) {
         set_error("null mesh or params");
@@ -314,6 +373,20 @@ se_status check_params(const se_mesh *m, const se_params *p, int32_t nsub, doubl
         set_error("need g > 0, theta >= 0 and a finite eta_ref");
         return SE_ERR_ARG;
     }
+    if (p->scheme != SE_SCHEME_SE && p->scheme != SE_SCHEME_SESM) {
+        set_error("unknown scheme");
+        return SE_ERR_ARG;
+    }
+    if (p->reserved != 0) {
+        set_error("se_params.reserved must be 0");
+        return SE_ERR_ARG;
+    }
+    const bool sesm = p->scheme == SE_SCHEME_SESM;
+    if (sesm && !(std::isfinite(p->beta) && std::isfinite(p->delta) && std::isfinite(p->gamma) &&
+                  std::isfinite(p->zeta))) {
+        set_error("SESM coefficients must be finite");
+        return SE_ERR_ARG;
+    }
     if (p->flags & SE_CHECK_CFL) {
         if (!(p->h_max > 0.0)) {
             set_error("SE_CHECK_CFL needs h_max > 0");
@@ -321,11 +394,19 @@ se_status check_params(const se_mesh *m, const se_params *p, int32_t nsub, doubl
         }
         const double dts = dt / nsub;
         const double c = dts * std::sqrt(p->g * p->h_max * m->h.mu_max);
-        const double lim = 2.0 / std::sqrt(1.0 + 2.0 * p->theta);
-        if (c > lim) {
-            set_error("CFL: dt_s sqrt(g h_max mu_max) = " + std::to_string(c) +
-                      " exceeds the stability bound " + std::to_string(lim));
-            return SE_ERR_CFL;
+        if (sesm) {
+            if (!sesm_stable_upto(c, p->beta, p->delta, p->gamma, p->zeta)) {
+                set_error("CFL: dt_s sqrt(g h_max mu_max) = " + std::to_string(c) +
+                          " is beyond the stability range of the SESM coefficients");
+                return SE_ERR_CFL;
+            }
+        } else {
+            const double lim = 2.0 / std::sqrt(1.0 + 2.0 * p->theta);
+            if (c > lim) {
+                set_error("CFL: dt_s sqrt(g h_max mu_max) = " + std::to_string(c) +
+                          " exceeds the stability bound " + std::to_string(lim));
+                return SE_ERR_CFL;
+            }
         }
     }
     return SE_OK;
@@ -348,6 +429,22 @@ StepC make_step(const se_params *p, int32_t nsub, double dt) {
     c.nsub = nsub;
     c.flags = ((p->flags & SE_LINEAR_H) ? KF_LINEAR_H : 0) |
               ((p->flags & SE_TRACK_VOLUME) ? KF_TRACK_VOLUME : 0);
+    if (p->scheme == SE_SCHEME_SESM) {   // eq. (eq4_7)
+        c.ab0 = 1.5 + p->beta;
+        c.ab1 = 0.5 + 2.0 * p->beta;
+        c.ab2 = p->beta;
+        c.am0 = p->delta;
+        c.am1 = 1.0 - p->delta - p->gamma - p->zeta;
+        c.am2 = p->gamma;
+        c.am3 = p->zeta;
+        c.ab0_f = static_cast<float>(c.ab0);
+        c.ab1_f = static_cast<float>(c.ab1);
+        c.ab2_f = static_cast<float>(c.ab2);
+        c.am0_f = static_cast<float>(c.am0);
+        c.am1_f = static_cast<float>(c.am1);
+        c.am2_f = static_cast<float>(c.am2);
+        c.am3_f = static_cast<float>(c.am3);
+    }
     return c;
 }
 
@@ -555,7 +652,8 @@ se_status se_workspace_bytes(const se_mesh *m, const se_params *p, int32_t nsub,
         return SE_ERR_ARG;
     }
     const bool f32 = p->precision == SE_F32_MIXED;
-    const Layout L = fwd_layout(m->h.nv, m->h.ne, f32, nsub, vol_width(m->h.nv));
+    const Layout L = fwd_layout(m->h.nv, m->h.ne, f32, nsub, vol_width(m->h.nv),
+                                p->scheme == SE_SCHEME_SESM);
     *bytes = L.total;
     if (ckpt_every > 0) {
         const int32_t k = std::min(ckpt_every, nsub);
@@ -581,6 +679,10 @@ se_status se_subcycle(se_mesh *m, const se_params *p, se_state *st, const se_for
     SE_TRY(check_params(m, p, nsub, dt));
     SE_TRY(check_state(st, fo, ws));
     SE_TRY(check_device(m));
+    if (p->scheme == SE_SCHEME_SESM) {
+        set_error("se_subcycle: the AB3-AM4 scheme runs on se_subcycle_plain in this build");
+        return SE_ERR_UNSUPPORTED;
+    }
     DeviceGuard dg(m->device);
     SE_TRY(ensure_plan(m));
     const DevTiles &P = *m->plan;
@@ -666,9 +768,10 @@ se_status se_subcycle_plain(se_mesh *m, const se_params *p, se_state *st, const 
     SE_TRY(check_device(m));
     DeviceGuard dg(m->device);
     const bool f32 = p->precision == SE_F32_MIXED;
+    const bool sesm = p->scheme == SE_SCHEME_SESM;
     const hipStream_t s = static_cast<hipStream_t>(stream);
     const int64_t nv = m->h.nv, ne = m->h.ne;
-    const Layout L = fwd_layout(nv, ne, f32, nsub, vol_width(nv));
+    const Layout L = fwd_layout(nv, ne, f32, nsub, vol_width(nv), sesm);
     char *w = static_cast<char *>(ws);
     PlainArgs a{};
     a.nv = nv;
@@ -693,9 +796,28 @@ se_status se_subcycle_plain(se_mesh *m, const se_params *p, se_state *st, const 
     a.faults = m->d.faults.as<uint32_t>();
     a.c = make_step(p, nsub, dt);
     a.nblk_v = static_cast<int32_t>((nv + 255) / 256);
-    for (int mm = 0; mm < nsub; ++mm) {
-        a.m = mm;
-        HIP_TRY(launch_plain_step(f32, a, s), "se_subcycle_plain launch");
+    if (sesm) {
+        // histories start from the initial state
+        const size_t es = f32 ? 4 : 8;
+        a.eta1 = w + L.sv[0];
+        a.eta2 = w + L.sv[1];
+        a.etaA = w + L.sv[2];
+        a.U1 = w + L.se[0];
+        a.U2 = w + L.se[1];
+        a.Uab = w + L.se[6];
+        for (void *dst : {a.eta1, a.eta2})
+            HIP_TRY(hipMemcpyAsync(dst, st->eta, nv * es, hipMemcpyDeviceToDevice, s), "history");
+        for (void *dst : {a.U1, a.U2})
+            HIP_TRY(hipMemcpyAsync(dst, st->U, 2 * ne * es, hipMemcpyDeviceToDevice, s), "history");
+        for (int mm = 0; mm < nsub; ++mm) {
+            a.m = mm;
+            HIP_TRY(launch_sesm_step(f32, a, s), "se_subcycle_plain launch");
+        }
+    } else {
+        for (int mm = 0; mm < nsub; ++mm) {
+            a.m = mm;
+            HIP_TRY(launch_plain_step(f32, a, s), "se_subcycle_plain launch");
+        }
     }
     if (st->volume) {
         const int rows = (p->flags & SE_TRACK_VOLUME) ? nsub + 1 : 2;
@@ -736,6 +858,10 @@ se_status se_subcycle_adjoint(se_mesh *m, const se_params *p, const void *eta0, 
                               void *g_eta0, void *g_U0, void *g_R, void *g_H0, void *ws,
                               void *stream) {
     SE_TRY(check_params(m, p, nsub, dt));
+    if (p->scheme != SE_SCHEME_SE) {
+        set_error("se_subcycle_adjoint: only the forward-backward scheme has an adjoint");
+        return SE_ERR_UNSUPPORTED;
+    }
     if (!eta0 || !U0 || !fo || !fo->R || !fo->f || !fo->H0 || !ws) {
         set_error("se_subcycle_adjoint: null input, forcing or workspace");
         return SE_ERR_ARG;
@@ -1049,6 +1175,10 @@ se_status se_subcycle_batched(se_batch *b, const se_params *p, se_state *st, con
     if (!b || !p || !nsub || !dt) {
         set_error("se_subcycle_batched: null argument");
         return SE_ERR_ARG;
+    }
+    if (p->scheme != SE_SCHEME_SE) {
+        set_error("se_subcycle_batched: only the forward-backward scheme is batched");
+        return SE_ERR_UNSUPPORTED;
     }
     SE_TRY(check_state(st, fo, ws));
     if (b->device < 0) {

@@ -13,6 +13,10 @@ struct StepC {
     float dts_f, g_f, theta_f, opt_f, eta_ref_f, pad_f;
     int32_t nsub, flags, ntiles, chunk0;   // chunk0: first launch index of this member
     int64_t vol_off;    // offset of this member's volume partials
+    // AB3-AM4 coefficients (SESM): U_ab = ab0 U^m - ab1 U^{m-1} + ab2 U^{m-2};
+    // eta_am = am0 eta^{m+1} + am1 eta^m + am2 eta^{m-1} + am3 eta^{m-2}
+    double ab0, ab1, ab2, am0, am1, am2, am3;
+    float ab0_f, ab1_f, ab2_f, am0_f, am1_f, am2_f, am3_f, pad2_f;
 };
 
 enum : int32_t { KF_LINEAR_H = 1, KF_TRACK_VOLUME = 4 };
@@ -59,6 +63,8 @@ struct PlainArgs {
     int32_t m;                  // substep index 0..nsub-1
     int32_t nblk_v;             // blocks of the vertex launch (volume row width)
     int32_t fwd_only;           // 1: state update only (no running sum, average, volume)
+    // AB3-AM4 (SESM) only: histories, AM4 elevation, AB3 transport
+    void *eta1, *eta2, *etaA, *U1, *U2, *Uab;
 };
 
 // Reverse (adjoint) substep: triangle gather then vertex CSR sum.
@@ -93,6 +99,7 @@ hipError_t launch_adj_final(bool f32, const AdjArgs &a, hipStream_t s);
 // Raise the dynamic-LDS limit of a tile kernel instantiation (call before any
 // stream capture that launches it).
 hipError_t prepare_tile(bool f32, int ept, int block);
+hipError_t launch_sesm_step(bool f32, const PlainArgs &a, hipStream_t s);
 int tile_lds_bytes(bool f32, int block, int K, int cap_nv, int cap_ne, int cap_nvu, int cap_cs);
 
 }  // namespace sesub

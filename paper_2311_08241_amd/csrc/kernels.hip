@@ -266,6 +266,210 @@ __global__ void __launch_bounds__(256) k_plain_vtx(PlainArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// AB3-AM4 (SESM) substep pieces, shared by the plain kernels and the tile kernel.
+// FP64: the operations of the definition in its order (as the oracle);
+// FP32: the same steps with fused multiply-adds and per-triangle constants
+// (dt f: fd, dt R: dRx/dRy, -A_e: mAe, mean H0 (+ eta_ref unless H is linear): rH).
+// ---------------------------------------------------------------------------
+template <typename T> __device__ __forceinline__ T sesm_ab(const StepC &c, T u, T u1, T u2);
+template <> __device__ __forceinline__ double sesm_ab<double>(const StepC &c, double u, double u1,
+                                                             double u2) {
+    return c.ab0 * u - c.ab1 * u1 + c.ab2 * u2;
+}
+template <> __device__ __forceinline__ float sesm_ab<float>(const StepC &c, float u, float u1,
+                                                           float u2) {
+    return __builtin_fmaf(c.ab2_f, u2, __builtin_fmaf(-c.ab1_f, u1, c.ab0_f * u));
+}
+
+template <typename T> __device__ __forceinline__ T sesm_am(const StepC &c, T en, T e, T e1, T e2);
+template <> __device__ __forceinline__ double sesm_am<double>(const StepC &c, double en, double e,
+                                                             double e1, double e2) {
+    return c.am0 * en + c.am1 * e + c.am2 * e1 + c.am3 * e2;
+}
+template <> __device__ __forceinline__ float sesm_am<float>(const StepC &c, float en, float e,
+                                                           float e1, float e2) {
+    return __builtin_fmaf(c.am3_f, e2, __builtin_fmaf(c.am2_f, e1, __builtin_fmaf(c.am1_f, e, c.am0_f * en)));
+}
+
+// Sub-cell fluxes F . S_k of a transport F (FP64: as in tri_update).
+__device__ __forceinline__ void slot_fluxes(double Fx, double Fy, double gbx, double gby,
+                                            double gcx, double gcy, double Ae, double &pa,
+                                            double &pb, double &pc) {
+    const double gax = -(gbx + gcx), gay = -(gby + gcy);
+    pa = Fx * (-Ae * gax) + Fy * (-Ae * gay);
+    pb = Fx * (-Ae * gbx) + Fy * (-Ae * gby);
+    pc = Fx * (-Ae * gcx) + Fy * (-Ae * gcy);
+}
+// FP32 form with mAe = -A_e (as in tri_update_f32)
+__device__ __forceinline__ void slot_fluxes_f32(float Fx, float Fy, float gbx, float gby, float gcx,
+                                                float gcy, float mAe, float &pa, float &pb,
+                                                float &pc) {
+    pb = mAe * __builtin_fmaf(Fx, gbx, Fy * gby);
+    pc = mAe * __builtin_fmaf(Fx, gcx, Fy * gcy);
+    pa = -(pb + pc);
+}
+
+// Transport update of eq. (eq4_8): U + dt (-f e_z x U_ab - g H_am grad eta_am + R).
+// FP64: eAa..eAc eta_am at the vertices, ha..hc H0.
+__device__ __forceinline__ void sesm_u_f64(const StepC &c, bool linear_h, double eAa, double eAb,
+                                           double eAc, double ha, double hb, double hc, double gbx,
+                                           double gby, double gcx, double gcy, double fc,
+                                           double Rx, double Ry, double ux, double uy, double ax,
+                                           double ay, double &Unx, double &Uny, bool &dry) {
+    const double db = eAb - eAa, dc = eAc - eAa;
+    const double gx = db * gbx + dc * gcx;
+    const double gy = db * gby + dc * gcy;
+    const double He = linear_h ? (ha + hb + hc) / 3.0 : ((ha + eAa) + (hb + eAb) + (hc + eAc)) / 3.0;
+    dry = !(He > 0.0);
+    const double dts = c.dts, g = c.g;
+    Unx = ux + dts * (fc * ay - g * He * gx + Rx);
+    Uny = uy + dts * (-fc * ax - g * He * gy + Ry);
+}
+// FP32: rH mean H0 (+ eta_ref unless linear), gd = g dt, fd = f dt, dR = dt R.
+__device__ __forceinline__ void sesm_u_f32(bool linear_h, float eAa, float eAb, float eAc, float rH,
+                                           float gbx, float gby, float gcx, float gcy, float fd,
+                                           float dRx, float dRy, float gd, float ux, float uy,
+                                           float ax, float ay, float &Unx, float &Uny, bool &dry) {
+    const float db = eAb - eAa, dc = eAc - eAa;
+    const float gx = __builtin_fmaf(db, gbx, dc * gcx);
+    const float gy = __builtin_fmaf(db, gby, dc * gcy);
+    const float He = linear_h ? rH : __builtin_fmaf(eAa + eAb + eAc, 1.0f / 3.0f, rH);
+    dry = !(He > 0.0f);
+    const float gHe = gd * He;
+    Unx = ux + __builtin_fmaf(fd, ay, __builtin_fmaf(-gHe, gx, dRx));
+    Uny = uy + __builtin_fmaf(-fd, ax, __builtin_fmaf(-gHe, gy, dRy));
+}
+
+// ---- plain three-kernel form: AB3 transport and fluxes; elevation; transport
+template <typename T, bool F32>
+__global__ void __launch_bounds__(256) k_sesm_ab(PlainArgs a) {
+    using T2 = typename Vec2<T>::type;
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= a.ne) return;
+    const StepC &c = a.c;
+    const T *geom = static_cast<const T *>(a.geom);
+    const T2 u = static_cast<const T2 *>(a.U)[e];
+    const T2 u1 = static_cast<const T2 *>(a.U1)[e];
+    const T2 u2 = static_cast<const T2 *>(a.U2)[e];
+    T2 ab;
+    ab.x = sesm_ab<T>(c, u.x, u1.x, u2.x);
+    ab.y = sesm_ab<T>(c, u.y, u1.y, u2.y);
+    static_cast<T2 *>(a.Uab)[e] = ab;
+    T pa, pb, pc;
+    if constexpr (F32)
+        slot_fluxes_f32(ab.x, ab.y, geom[e], geom[a.ne + e], geom[2 * a.ne + e],
+                        geom[3 * a.ne + e], -geom[4 * a.ne + e], pa, pb, pc);
+    else
+        slot_fluxes(ab.x, ab.y, geom[e], geom[a.ne + e], geom[2 * a.ne + e], geom[3 * a.ne + e],
+                    geom[4 * a.ne + e], pa, pb, pc);
+    T *phi = static_cast<T *>(a.phi);
+    phi[3 * e] = pa;
+    phi[3 * e + 1] = pb;
+    phi[3 * e + 2] = pc;
+    SumT<F32> s;
+    if (a.m == 0)
+        s.init(ab.x, ab.y);
+    else {
+        s.load(a.sum, e);
+        s.add(ab.x, ab.y);
+    }
+    if (a.m == c.nsub - 1) {
+        if (a.Uavg) {
+            a.Uavg[2 * e] = s.vx() / c.Mdbl;
+            a.Uavg[2 * e + 1] = s.vy() / c.Mdbl;
+        }
+    } else {
+        s.store(a.sum, e);
+    }
+}
+
+template <typename T, bool F32>
+__global__ void __launch_bounds__(256) k_sesm_vtx(PlainArgs a) {
+    __shared__ double red[2][4];
+    const int64_t v = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const StepC &c = a.c;
+    const bool first = a.m == 0, last = a.m == c.nsub - 1;
+    const bool track = (c.flags & KF_TRACK_VOLUME) != 0;
+    double v_new = 0.0, v_old = 0.0;
+    if (v < a.nv) {
+        T *eta = static_cast<T *>(a.eta);
+        T *eta1 = static_cast<T *>(a.eta1);
+        T *eta2 = static_cast<T *>(a.eta2);
+        const T *phi = static_cast<const T *>(a.phi);
+        T acc = T(0);
+        const int32_t j1 = a.row_ptr[v + 1];
+        for (int32_t j = a.row_ptr[v]; j < j1; ++j) acc += phi[a.pcol[j]];
+        const T eo = eta[v], e1 = eta1[v], e2 = eta2[v];
+        const T wv = a.W ? static_cast<const T *>(a.W)[v] : T(0);
+        const T av = static_cast<const T *>(a.Av)[v];
+        const T en = F32 ? vtx_update_f32(eo, acc, T(1) / av, wv, cdts<T>(c))
+                         : eo - cdts<T>(c) * (acc / av + wv);
+        static_cast<T *>(a.etaA)[v] = sesm_am<T>(c, en, eo, e1, e2);
+        eta2[v] = e1;
+        eta1[v] = eo;
+        eta[v] = en;
+        if (!finite_val(en)) set_fault(a.faults, 2u);
+        const double av64 = a.Av64[v];
+        v_new = av64 * (double)en;
+        v_old = av64 * (double)eo;
+    }
+    if (!(track || first || last)) return;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    v_new = wave_sum(v_new);
+    v_old = wave_sum(v_old);
+    if (lane == 0) {
+        red[0][w] = v_new;
+        red[1][w] = v_old;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double sn = ((red[0][0] + red[0][1]) + (red[0][2] + red[0][3]));
+        const int64_t row = track ? (a.m + 1) : 1;
+        if (track || last) a.vol_part[row * a.nblk_v + blockIdx.x] = sn;
+        if (first) a.vol_part[blockIdx.x] = ((red[1][0] + red[1][1]) + (red[1][2] + red[1][3]));
+    }
+}
+
+template <typename T, bool F32>
+__global__ void __launch_bounds__(256) k_sesm_u(PlainArgs a) {
+    using T2 = typename Vec2<T>::type;
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= a.ne) return;
+    const StepC &c = a.c;
+    const bool linear_h = (c.flags & KF_LINEAR_H) != 0;
+    const T *eA = static_cast<const T *>(a.etaA);
+    const T *H0 = static_cast<const T *>(a.H0);
+    const T *geom = static_cast<const T *>(a.geom);
+    const int32_t va = a.tri[3 * e], vb = a.tri[3 * e + 1], vc = a.tri[3 * e + 2];
+    T2 *U = static_cast<T2 *>(a.U);
+    T2 *U1 = static_cast<T2 *>(a.U1);
+    T2 *U2 = static_cast<T2 *>(a.U2);
+    const T2 u = U[e];
+    const T2 ab = static_cast<const T2 *>(a.Uab)[e];
+    const T2 r = static_cast<const T2 *>(a.R)[e];
+    const T fc = static_cast<const T *>(a.f)[e];
+    T Unx, Uny;
+    bool dry;
+    if constexpr (F32) {
+        const float rH = (H0[va] + H0[vb] + H0[vc]) * (1.0f / 3.0f) + (linear_h ? 0.0f : c.eta_ref_f);
+        sesm_u_f32(linear_h, eA[va], eA[vb], eA[vc], rH, geom[e], geom[a.ne + e],
+                   geom[2 * a.ne + e], geom[3 * a.ne + e], fc * c.dts_f, c.dts_f * r.x,
+                   c.dts_f * r.y, c.g_f * c.dts_f, u.x, u.y, ab.x, ab.y, Unx, Uny, dry);
+    } else {
+        sesm_u_f64(c, linear_h, eA[va], eA[vb], eA[vc], H0[va], H0[vb], H0[vc], geom[e],
+                   geom[a.ne + e], geom[2 * a.ne + e], geom[3 * a.ne + e], fc, r.x, r.y, u.x,
+                   u.y, ab.x, ab.y, Unx, Uny, dry);
+    }
+    if (dry) set_fault(a.faults, 1u);
+    U2[e] = U1[e];
+    U1[e] = u;
+    T2 un;
+    un.x = Unx;
+    un.y = Uny;
+    U[e] = un;
+}
+
+// ---------------------------------------------------------------------------
 // Temporally blocked tile kernel: up to K substeps of one tile per launch
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int align16(int b) { return (b + 15) & ~15; }
@@ -909,6 +1113,20 @@ hipError_t launch_plain_step(bool f32, const PlainArgs &a, hipStream_t s) {
     } else {
         hipLaunchKernelGGL((k_plain_tri<double, false>), dim3(ge), dim3(256), 0, s, a);
         hipLaunchKernelGGL((k_plain_vtx<double, false>), dim3(gv), dim3(256), 0, s, a);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_sesm_step(bool f32, const PlainArgs &a, hipStream_t s) {
+    const int ge = static_cast<int>((a.ne + 255) / 256), gv = static_cast<int>((a.nv + 255) / 256);
+    if (f32) {
+        hipLaunchKernelGGL((k_sesm_ab<float, true>), dim3(ge), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((k_sesm_vtx<float, true>), dim3(gv), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((k_sesm_u<float, true>), dim3(ge), dim3(256), 0, s, a);
+    } else {
+        hipLaunchKernelGGL((k_sesm_ab<double, false>), dim3(ge), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((k_sesm_vtx<double, false>), dim3(gv), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((k_sesm_u<double, false>), dim3(ge), dim3(256), 0, s, a);
     }
     return hipGetLastError();
 }
