@@ -72,8 +72,10 @@ typedef enum { SE_F64 = 0, SE_F32_MIXED = 1 } se_precision;
  *   (U^{-1} = U^{-2} = U^0, likewise eta) and <<U>> is the mean of U_ab over
  *   m = 0..M-1 (the transport whose divergence the elevation sums).  The
  *   coefficients come from se_params (eq. (eqdp_6) gives the paper's
- *   settings); theta is not used.  Supported by se_subcycle and
- *   se_subcycle_plain; the adjoint and the batched form return
+ *   settings); theta is not used.  Supported by se_subcycle (the tile kernel
+ *   hands (eta, eta^{m-1}, eta^{m-2}, eta_am) and (U, U^{m-1}, U_ab) from launch
+ *   to launch with the last transport update pending; a final kernel applies
+ *   it) and se_subcycle_plain; the adjoint and the batched form return
  *   SE_ERR_UNSUPPORTED. */
 typedef enum { SE_SCHEME_SE = 0, SE_SCHEME_SESM = 1 } se_scheme;
 
@@ -244,6 +246,9 @@ typedef struct {
     int32_t ntiles, max_tri, max_vtx, tri_per_thread;
     int32_t lds_f32, lds_f64, ok_f32, ok_f64;
     double tri_overhead, vtx_overhead, bytes_per_vs_f32, bytes_per_vs_f64;
+    /* the same budget for the AB3-AM4 scheme (three more vertex arrays in LDS,
+     * two more transports per triangle in registers) */
+    int32_t lds_sesm_f32, lds_sesm_f64, ok_sesm_f32, ok_sesm_f64;
 } se_plan_stats_t;
 se_status se_plan_stats(const void *mesh_or_batch, int32_t kind, int32_t tile, int32_t k_fused,
                         int32_t block, se_plan_stats_t *stats);

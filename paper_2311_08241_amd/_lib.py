@@ -55,7 +55,8 @@ class PlanStats(ctypes.Structure):
                 ("tri_per_thread", c_int32), ("lds_f32", c_int32), ("lds_f64", c_int32),
                 ("ok_f32", c_int32), ("ok_f64", c_int32), ("tri_overhead", c_double),
                 ("vtx_overhead", c_double), ("bytes_per_vs_f32", c_double),
-                ("bytes_per_vs_f64", c_double)]
+                ("bytes_per_vs_f64", c_double), ("lds_sesm_f32", c_int32),
+                ("lds_sesm_f64", c_int32), ("ok_sesm_f32", c_int32), ("ok_sesm_f64", c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -109,11 +109,12 @@ std::vector<T> pack_geom(const HostMesh &m, const std::vector<int32_t> *sel, int
 }
 
 // Register tiers that compile without scratch spills (triangles per thread).
-bool ept_ok(bool f32, int ept, int block) {
+bool ept_ok(bool f32, int ept, int block, bool sm = false) {
     if (ept < 0) return false;
     if (block == 256) return f32 ? ept <= 8 : ept <= 6;
     if (block == 512) return f32 ? ept <= 8 : ept <= 4;
-    return f32 ? ept <= 4 : ept <= 1;   // 1024 threads: at most 128 VGPRs
+    // 1024 threads: at most 128 VGPRs (the AB3-AM4 form holds two more transports)
+    return f32 ? ept <= (sm ? 3 : 4) : ept <= 1;
 }
 
 // Host-side construction and statistics of a plan (no device memory).
@@ -131,10 +132,16 @@ se_status plan_host(const std::vector<const HostMesh *> &members, const std::vec
     st.max_tri = ht.max_ne;
     st.max_vtx = ht.max_nv;
     st.tri_per_thread = ept;
-    st.lds_f32 = tile_lds_bytes(true, block, K, ht.max_nv, ht.max_ne, ht.max_nvu, ht.max_cs);
-    st.lds_f64 = tile_lds_bytes(false, block, K, ht.max_nv, ht.max_ne, ht.max_nvu, ht.max_cs);
+    st.lds_f32 = tile_lds_bytes(true, false, block, K, ht.max_nv, ht.max_ne, ht.max_nvu, ht.max_cs);
+    st.lds_f64 = tile_lds_bytes(false, false, block, K, ht.max_nv, ht.max_ne, ht.max_nvu, ht.max_cs);
     st.ok_f32 = ept_ok(true, ept, block) && st.lds_f32 <= 160 * 1024;
     st.ok_f64 = ept_ok(false, ept, block) && st.lds_f64 <= 160 * 1024;
+    st.lds_sesm_f32 = tile_lds_bytes(true, true, block, K, ht.max_nv, ht.max_ne, ht.max_nvu,
+                                     ht.max_cs);
+    st.lds_sesm_f64 = tile_lds_bytes(false, true, block, K, ht.max_nv, ht.max_ne, ht.max_nvu,
+                                     ht.max_cs);
+    st.ok_sesm_f32 = ept_ok(true, ept, block, true) && st.lds_sesm_f32 <= 160 * 1024;
+    st.ok_sesm_f64 = ept_ok(false, ept, block, true) && st.lds_sesm_f64 <= 160 * 1024;
     int64_t nv = 0, ne = 0;
     for (const HostMesh *m : members) {
         nv += m->nv;
@@ -187,6 +194,10 @@ se_status make_plan(const std::vector<const HostMesh *> &members, const std::vec
     p->lds_bytes32 = st.lds_f32;
     p->ok32 = st.ok_f32;
     p->ok64 = st.ok_f64;
+    p->lds_sm32 = st.lds_sesm_f32;
+    p->lds_sm64 = st.lds_sesm_f64;
+    p->ok_sm32 = st.ok_sesm_f32;
+    p->ok_sm64 = st.ok_sesm_f64;
     p->hdr_host = ht.hdr;
     static_assert(sizeof(TileHdr) == sizeof(TileHdrK), "tile header layouts differ");
     SE_TRY(p->hdr.upload(ht.hdr.data(), ht.hdr.size() * sizeof(TileHdr)));
@@ -467,7 +478,7 @@ se_status ensure_plan(se_mesh *m) {
         HostTiles ht;
         se_plan_stats_t st;
         if (plan_host(mem, {0, m->h.nv}, {0, m->h.ne}, c[0], c[1], c[2], ht, st) != SE_OK) continue;
-        if (!st.ok_f32 || !st.ok_f64) continue;
+        if (!st.ok_f32 || !st.ok_f64 || !st.ok_sesm_f32 || !st.ok_sesm_f64) continue;
         SE_TRY(make_plan(mem, {0, m->h.nv}, {0, m->h.ne}, c[0], c[1], c[2], m->plan));
         m->plan_T = c[0];
         m->plan_K = c[1];
@@ -679,23 +690,20 @@ se_status se_subcycle(se_mesh *m, const se_params *p, se_state *st, const se_for
     SE_TRY(check_params(m, p, nsub, dt));
     SE_TRY(check_state(st, fo, ws));
     SE_TRY(check_device(m));
-    if (p->scheme == SE_SCHEME_SESM) {
-        set_error("se_subcycle: the AB3-AM4 scheme runs on se_subcycle_plain in this build");
-        return SE_ERR_UNSUPPORTED;
-    }
     DeviceGuard dg(m->device);
     SE_TRY(ensure_plan(m));
     const DevTiles &P = *m->plan;
     const bool f32 = p->precision == SE_F32_MIXED;
-    if (!(f32 ? P.ok32 : P.ok64)) {
+    const bool sm = p->scheme == SE_SCHEME_SESM;
+    if (!P.ok(f32, sm)) {
         set_error("se_subcycle: the current plan does not fit the register/LDS budget of this "
-                  "precision (see se_plan_stats)");
+                  "precision and scheme (see se_plan_stats)");
         return SE_ERR_ARG;
     }
     const hipStream_t s = static_cast<hipStream_t>(stream);
     const int64_t nv = m->h.nv, ne = m->h.ne;
     const size_t es = f32 ? 4 : 8;
-    const Layout L = fwd_layout(nv, ne, f32, nsub, vol_width(nv));
+    const Layout L = fwd_layout(nv, ne, f32, nsub, vol_width(nv), sm);
     char *w = static_cast<char *>(ws);
     StepC c = make_step(p, nsub, dt);
     c.ntiles = P.ntiles;
@@ -734,17 +742,42 @@ se_status se_subcycle(se_mesh *m, const se_params *p, se_state *st, const se_for
     void *eta_u = st->eta, *U_u = st->U;
     void *eta_w = w + L.eta_alt, *U_w = w + L.U_alt;
     const int nlaunch = (nsub + P.K - 1) / P.K;
-    const size_t lds = f32 ? P.lds_bytes32 : P.lds_bytes64;
-    HIP_TRY(prepare_tile(f32, P.ept, P.block), "se_subcycle prepare");
+    const size_t lds = P.lds(f32, sm);
+    HIP_TRY(prepare_tile(f32, sm, P.ept, P.block), "se_subcycle prepare");
     a.eta_u = eta_u;
     a.eta_w = eta_w;
     a.U_u = U_u;
     a.U_w = U_w;
+    if (sm)
+        for (int k = 0; k < 2; ++k) {
+            for (int q = 0; q < 4; ++q) a.sm_v[k][q] = w + L.sv[4 * k + q];
+            for (int q = 0; q < 3; ++q) a.sm_e[k][q] = w + L.se[3 * k + q];
+        }
     for (int ch = 0; ch < nlaunch; ++ch) {
         a.chunk = ch;
-        HIP_TRY(launch_tile(f32, P.ept, P.block, a, P.ntiles, lds, s), "se_subcycle launch");
+        HIP_TRY(launch_tile(f32, sm, P.ept, P.block, a, P.ntiles, lds, s), "se_subcycle launch");
     }
-    if (nlaunch % 2 == 1) {
+    if (sm) {
+        // the last substep's transport update (pending) and the final elevation
+        const int lw = (nlaunch - 1) & 1;
+        PlainArgs fa{};
+        fa.nv = nv;
+        fa.ne = ne;
+        fa.tri = m->d.tri.as<const int32_t>();
+        fa.geom = f32 ? m->d.geom32.p : m->d.geom64.p;
+        fa.H0 = fo->H0;
+        fa.R = fo->R;
+        fa.f = fo->f;
+        fa.eta = st->eta;
+        fa.U = st->U;
+        fa.eta1 = a.sm_v[lw][0];
+        fa.etaA = a.sm_v[lw][3];
+        fa.U1 = a.sm_e[lw][0];
+        fa.Uab = a.sm_e[lw][2];
+        fa.faults = m->d.faults.as<uint32_t>();
+        fa.c = c;
+        HIP_TRY(launch_sesm_fin(f32, fa, s), "se_subcycle final update");
+    } else if (nlaunch % 2 == 1) {
         HIP_TRY(hipMemcpyAsync(eta_u, eta_w, nv * es, hipMemcpyDeviceToDevice, s), "copy eta");
         HIP_TRY(hipMemcpyAsync(U_u, U_w, 2 * ne * es, hipMemcpyDeviceToDevice, s), "copy U");
     }
@@ -1042,7 +1075,7 @@ se_status batch_ensure_plan(se_batch *b) {
         se_plan_stats_t st;
         if (plan_host(batch_members(b), b->voff, b->eoff, c[0], c[1], c[2], ht, st) != SE_OK)
             continue;
-        if (!st.ok_f32 || !st.ok_f64) continue;
+        if (!st.ok_f32 || !st.ok_f64 || !st.ok_sesm_f32 || !st.ok_sesm_f64) continue;
         return batch_install_plan(b, c[0], c[1], c[2]);
     }
     set_error("no default plan fits this batch");
@@ -1296,7 +1329,7 @@ se_status se_subcycle_batched(se_batch *b, const se_params *p, se_state *st, con
     a.U_w = w + L.U_alt;
     const size_t es = f32 ? 4 : 8;
     const size_t lds = f32 ? P.lds_bytes32 : P.lds_bytes64;
-    HIP_TRY(prepare_tile(f32, P.ept, P.block), "batched prepare");
+    HIP_TRY(prepare_tile(f32, false, P.ept, P.block), "batched prepare");
 
     auto enqueue = [&]() -> se_status {
         for (int32_t c = 0; c < Lmax; ++c) {
@@ -1305,7 +1338,7 @@ se_status se_subcycle_batched(se_batch *b, const se_params *p, se_state *st, con
             a.chunk = c;
             a.tile_list = b->lists.as<const int32_t>() + b->list_off[c];
             a.ntiles = cnt;
-            HIP_TRY(launch_tile(f32, P.ept, P.block, a, cnt, lds, s), "batched launch");
+            HIP_TRY(launch_tile(f32, false, P.ept, P.block, a, cnt, lds, s), "batched launch");
         }
         int64_t vout = 0;
         for (size_t i = 0; i < n; ++i) {

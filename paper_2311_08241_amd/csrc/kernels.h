@@ -48,6 +48,11 @@ struct TileArgs {
     const int32_t *tile_list;   // tiles of this launch (nullptr: all ntiles)
     int32_t K, chunk, ntiles, xcd;
     int32_t cap_nv, cap_ne, cap_nvu, cap_cs;
+    // AB3-AM4 only: two sets of (eta, eta^{-1}, eta^{-2}, eta_am) and of
+    // (U, U^{-1}, U_ab), global numbering; chunk ch writes set ch & 1 and reads
+    // set (ch - 1) & 1 (the caller's eta_u / U_u at the member's first chunk)
+    void *sm_v[2][4];
+    void *sm_e[2][3];
 };
 
 struct PlainArgs {
@@ -85,8 +90,8 @@ struct AdjArgs {
 };
 
 // Host launchers (kernels.hip)
-hipError_t launch_tile(bool f32, int ept, int block, const TileArgs &a, int grid, size_t lds,
-                       hipStream_t s);
+hipError_t launch_tile(bool f32, bool sm, int ept, int block, const TileArgs &a, int grid,
+                       size_t lds, hipStream_t s);
 hipError_t launch_plain_step(bool f32, const PlainArgs &a, hipStream_t s);
 hipError_t launch_vol_reduce(const double *part, int64_t width, int32_t rows, double add,
                              double *out, hipStream_t s);
@@ -98,8 +103,10 @@ hipError_t launch_adj_init(bool f32, const AdjArgs &a, const void *seed_eta, con
 hipError_t launch_adj_final(bool f32, const AdjArgs &a, hipStream_t s);
 // Raise the dynamic-LDS limit of a tile kernel instantiation (call before any
 // stream capture that launches it).
-hipError_t prepare_tile(bool f32, int ept, int block);
+hipError_t prepare_tile(bool f32, bool sm, int ept, int block);
 hipError_t launch_sesm_step(bool f32, const PlainArgs &a, hipStream_t s);
-int tile_lds_bytes(bool f32, int block, int K, int cap_nv, int cap_ne, int cap_nvu, int cap_cs);
+int tile_lds_bytes(bool f32, bool sm, int block, int K, int cap_nv, int cap_ne, int cap_nvu,
+                   int cap_cs);
+hipError_t launch_sesm_fin(bool f32, const PlainArgs &a, hipStream_t s);
 
 }  // namespace sesub

@@ -469,12 +469,57 @@ __global__ void __launch_bounds__(256) k_sesm_u(PlainArgs a) {
     U[e] = un;
 }
 
+// Final step of the tile form of AB3-AM4: the transport update of the last
+// substep (pending at the end of the last launch) into the caller's U, and the
+// final elevation into the caller's eta.  U1: U^{M-1}, Uab: U_ab^{M-1}, etaA:
+// eta_am^{M-1}, eta1: eta^M (global numbering, written by the last launch).
+template <typename T, bool F32>
+__global__ void __launch_bounds__(256) k_sesm_fin(PlainArgs a) {
+    using T2 = typename Vec2<T>::type;
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const StepC &c = a.c;
+    if (i < a.nv) static_cast<T *>(a.eta)[i] = static_cast<const T *>(a.eta1)[i];
+    if (i >= a.ne) return;
+    const int64_t e = i;
+    const bool linear_h = (c.flags & KF_LINEAR_H) != 0;
+    const T *eA = static_cast<const T *>(a.etaA);
+    const T *H0 = static_cast<const T *>(a.H0);
+    const T *geom = static_cast<const T *>(a.geom);
+    const int32_t va = a.tri[3 * e], vb = a.tri[3 * e + 1], vc = a.tri[3 * e + 2];
+    const T2 u = static_cast<const T2 *>(a.U1)[e];
+    const T2 ab = static_cast<const T2 *>(a.Uab)[e];
+    const T2 r = static_cast<const T2 *>(a.R)[e];
+    const T fc = static_cast<const T *>(a.f)[e];
+    T Unx, Uny;
+    bool dry;
+    if constexpr (F32) {
+        const float rH = (H0[va] + H0[vb] + H0[vc]) * (1.0f / 3.0f) + (linear_h ? 0.0f : c.eta_ref_f);
+        sesm_u_f32(linear_h, eA[va], eA[vb], eA[vc], rH, geom[e], geom[a.ne + e],
+                   geom[2 * a.ne + e], geom[3 * a.ne + e], fc * c.dts_f, c.dts_f * r.x,
+                   c.dts_f * r.y, c.g_f * c.dts_f, u.x, u.y, ab.x, ab.y, Unx, Uny, dry);
+    } else {
+        sesm_u_f64(c, linear_h, eA[va], eA[vb], eA[vc], H0[va], H0[vb], H0[vc], geom[e],
+                   geom[a.ne + e], geom[2 * a.ne + e], geom[3 * a.ne + e], fc, r.x, r.y, u.x,
+                   u.y, ab.x, ab.y, Unx, Uny, dry);
+    }
+    if (dry) set_fault(a.faults, 1u);
+    T2 un;
+    un.x = Unx;
+    un.y = Uny;
+    static_cast<T2 *>(a.U)[e] = un;
+}
+
 // ---------------------------------------------------------------------------
 // Temporally blocked tile kernel: up to K substeps of one tile per launch
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int align16(int b) { return (b + 15) & ~15; }
 
-template <typename T, bool F32, int EPT, int BLOCK>
+// SM: the AB3-AM4 (SESM) substep instead of the forward-backward one.  The state a
+// launch hands to the next is (eta, eta^{-1}, eta^{-2}, eta_am) at vertices and
+// (U, U^{-1}, U_ab) at triangles, with the transport update of the last substep
+// still pending (it needs eta_am on a ring the launch does not hold); the next
+// launch, or k_sesm_fin after the last one, applies it.
+template <typename T, bool F32, int EPT, int BLOCK, bool SM>
 __global__ void __launch_bounds__(BLOCK) k_tile(TileArgs a) {
     using T2 = typename Vec2<T>::type;
     constexpr int NW = BLOCK / 64;
@@ -527,6 +572,15 @@ __global__ void __launch_bounds__(BLOCK) k_tile(TileArgs a) {
     int off = 0;
     T *sEta = reinterpret_cast<T *>(smem + off);
     off = align16(off + (int)sizeof(T) * a.cap_nv);
+    T *sE1 = nullptr, *sE2 = nullptr, *sEA = nullptr;   // SM: eta^{-1}, eta^{-2}, eta_am
+    if constexpr (SM) {
+        sE1 = reinterpret_cast<T *>(smem + off);
+        off = align16(off + (int)sizeof(T) * a.cap_nv);
+        sE2 = reinterpret_cast<T *>(smem + off);
+        off = align16(off + (int)sizeof(T) * a.cap_nv);
+        sEA = reinterpret_cast<T *>(smem + off);
+        off = align16(off + (int)sizeof(T) * a.cap_nv);
+    }
     T *sH = reinterpret_cast<T *>(smem + off);
     off = align16(off + (int)sizeof(T) * a.cap_nv);
     T *sAv = reinterpret_cast<T *>(smem + off);   // FP64: A_v; FP32: 1 / A_v
@@ -547,7 +601,15 @@ __global__ void __launch_bounds__(BLOCK) k_tile(TileArgs a) {
     // FP32 vertex gathers go straight to LDS (global_load_lds, the LDS address from
     // M0), FP64 ones through registers.
     constexpr bool dma = F32;
-    const T *eta_in = static_cast<const T *>(even ? a.eta_u : a.eta_w);
+    // inputs: SE ping-pongs (caller's arrays, workspace); SM reads the caller's
+    // arrays at the member's first chunk, else the set the previous chunk wrote
+    const int rs = (ch - 1) & 1;
+    const bool pend = SM && ch > 0;   // SM: transport update of the previous substep pending
+    const T *eta_in = static_cast<const T *>(
+        SM ? (ch == 0 ? a.eta_u : a.sm_v[rs][0]) : (even ? a.eta_u : a.eta_w));
+    const T *e1_in = SM ? static_cast<const T *>(ch == 0 ? a.eta_u : a.sm_v[rs][1]) : nullptr;
+    const T *e2_in = SM ? static_cast<const T *>(ch == 0 ? a.eta_u : a.sm_v[rs][2]) : nullptr;
+    const T *eA_in = SM ? static_cast<const T *>(a.sm_v[rs][3]) : nullptr;
     const T *H0 = static_cast<const T *>(a.H0);
     const T *Wt = static_cast<const T *>(a.W);
     const T *lav = static_cast<const T *>(a.lv_av) + h.lv_off;   // FP64: A_v; FP32: 1/A_v
@@ -562,12 +624,17 @@ __global__ void __launch_bounds__(BLOCK) k_tile(TileArgs a) {
     const uint4 *lrec = reinterpret_cast<const uint4 *>(a.le_rec) + h.le_off;
     const T *lgeo = static_cast<const T *>(a.lgeo) + 4 * (int64_t)h.le_off;
     const T *lae = static_cast<const T *>(a.lae) + h.le_off;
-    const T2 *Uin = static_cast<const T2 *>(even ? a.U_u : a.U_w);
+    const T2 *Uin = static_cast<const T2 *>(
+        SM ? (ch == 0 ? a.U_u : a.sm_e[rs][0]) : (even ? a.U_u : a.U_w));
+    const T2 *U1in = SM ? static_cast<const T2 *>(ch == 0 ? a.U_u : a.sm_e[rs][1]) : nullptr;
+    const T2 *UAin = SM ? static_cast<const T2 *>(a.sm_e[rs][2]) : nullptr;
     const T2 *Rg = static_cast<const T2 *>(a.R);
     const T *fg = static_cast<const T *>(a.f);
     const T dts = cdts<T>(c);
     T rUx[EPT], rUy[EPT], rRx[EPT], rRy[EPT], rf[EPT], rk[EPT], g0[EPT], g1[EPT], g2[EPT],
         g3[EPT], g4[EPT];
+    // SM: U^{-1} and the AB3 transport of the previous substep
+    T pUx[SM ? EPT : 1], pUy[SM ? EPT : 1], aUx[SM ? EPT : 1], aUy[SM ? EPT : 1];
     uint32_t t0[EPT], t1[EPT], t2[EPT];   // local vertices and flux positions, 16 bits each
     int gt[EPT];
     SumT<F32> sm[EPT];
@@ -623,6 +690,13 @@ __global__ void __launch_bounds__(BLOCK) k_tile(TileArgs a) {
         const T ve = eta_in[g], vh = H0[g];
         const T va = i < nvu ? lav[i] : T(0);
         const T vw = (i < nvu && hasW) ? Wt[g] : T(0);
+        if constexpr (SM) {
+            const T v1 = e1_in[g], v2 = e2_in[g];
+            const T vA = pend ? eA_in[g] : T(0);
+            sE1[i] = v1;
+            sE2[i] = v2;
+            sEA[i] = vA;
+        }
         sEta[i] = ve;
         sH[i] = vh;
         if (i < nvu) {
@@ -636,6 +710,15 @@ __global__ void __launch_bounds__(BLOCK) k_tile(TileArgs a) {
                                          (__attribute__((address_space(3))) void *)(sEta + i0), 4, 0, 0);
         __builtin_amdgcn_global_load_lds((__attribute__((address_space(1))) void *)(H0 + g),
                                          (__attribute__((address_space(3))) void *)(sH + i0), 4, 0, 0);
+        if constexpr (SM) {
+            __builtin_amdgcn_global_load_lds((__attribute__((address_space(1))) void *)(e1_in + g),
+                                             (__attribute__((address_space(3))) void *)(sE1 + i0), 4, 0, 0);
+            __builtin_amdgcn_global_load_lds((__attribute__((address_space(1))) void *)(e2_in + g),
+                                             (__attribute__((address_space(3))) void *)(sE2 + i0), 4, 0, 0);
+            if (pend)
+                __builtin_amdgcn_global_load_lds((__attribute__((address_space(1))) void *)(eA_in + g),
+                                                 (__attribute__((address_space(3))) void *)(sEA + i0), 4, 0, 0);
+        }
         if (i < nvu) {
             __builtin_amdgcn_global_load_lds((__attribute__((address_space(1))) void *)(lav + i),
                                              (__attribute__((address_space(3))) void *)(sAv + i0), 4, 0, 0);
@@ -667,6 +750,19 @@ __global__ void __launch_bounds__(BLOCK) k_tile(TileArgs a) {
             rRx[r] = rr.x;
             rRy[r] = rr.y;
             rf[r] = fg[g];
+            if constexpr (SM) {
+                const T2 u1 = U1in[g];
+                pUx[r] = u1.x;
+                pUy[r] = u1.y;
+                if (pend) {
+                    const T2 ua = UAin[g];
+                    aUx[r] = ua.x;
+                    aUy[r] = ua.y;
+                } else {
+                    aUx[r] = T(0);
+                    aUy[r] = T(0);
+                }
+            }
         }
     }
     {
@@ -695,7 +791,7 @@ __global__ void __launch_bounds__(BLOCK) k_tile(TileArgs a) {
         stage_vertex(i, lv[i]);
     }
     for (int i = tid + BLOCK; i < nrow4; i += BLOCK) reinterpret_cast<uint2 *>(sRow)[i] = crow[i];
-    if (first) {
+    if (first && !SM) {
 #pragma unroll
         for (int r = 0; r < EPT; ++r) {
             const int le = tid + r * BLOCK;
@@ -715,10 +811,14 @@ __global__ void __launch_bounds__(BLOCK) k_tile(TileArgs a) {
         for (int r = 0; r < EPT; ++r) {
             const int le = tid + r * BLOCK;
             if (le < ne_load) {
-                float al, kk;
-                tri_consts_f32(rf[r], dts, al, kk);
-                rk[r] = kk;
-                rf[r] = al;
+                if constexpr (SM) {
+                    rf[r] = rf[r] * dts;   // f dt
+                } else {
+                    float al, kk;
+                    tri_consts_f32(rf[r], dts, al, kk);
+                    rk[r] = kk;
+                    rf[r] = al;
+                }
                 rRx[r] = dts * rRx[r];
                 rRy[r] = dts * rRy[r];
                 g4[r] = -g4[r];
@@ -756,6 +856,54 @@ __global__ void __launch_bounds__(BLOCK) k_tile(TileArgs a) {
             const int le = tid + r * BLOCK;
             if (le < ne_act) {
                 const int ia = t0[r] & 0xffffu, ib = t0[r] >> 16, ic = t1[r] & 0xffffu;
+                if constexpr (SM) {
+                    // pending transport update of the previous substep, then U_ab
+                    T Px = rUx[r], Py = rUy[r], Qx = pUx[r], Qy = pUy[r], abx, aby;
+                    if (pend || j > 0) {
+                        T Unx, Uny;
+                        bool dry;
+                        const T eAa = sEA[ia], eAb = sEA[ib], eAc = sEA[ic];
+                        if constexpr (F32)
+                            sesm_u_f32(linear_h, eAa, eAb, eAc, rH[r], g0[r], g1[r], g2[r], g3[r],
+                                       rf[r], rRx[r], rRy[r], gd, Px, Py, aUx[r], aUy[r], Unx,
+                                       Uny, dry);
+                        else
+                            sesm_u_f64(c, linear_h, eAa, eAb, eAc, sH[ia], sH[ib], sH[ic], g0[r],
+                                       g1[r], g2[r], g3[r], rf[r], rRx[r], rRy[r], Px, Py,
+                                       aUx[r], aUy[r], Unx, Uny, dry);
+                        dry_any |= dry;
+                        abx = sesm_ab<T>(c, Unx, Px, Qx);
+                        aby = sesm_ab<T>(c, Uny, Py, Qy);
+                        Qx = Px;
+                        Qy = Py;
+                        Px = Unx;
+                        Py = Uny;
+                    } else {   // first substep: the histories equal U^0
+                        abx = sesm_ab<T>(c, Px, Qx, Qx);
+                        aby = sesm_ab<T>(c, Py, Qy, Qy);
+                    }
+                    T pa, pb, pc;
+                    if constexpr (F32)
+                        slot_fluxes_f32(abx, aby, g0[r], g1[r], g2[r], g3[r], g4[r], pa, pb, pc);
+                    else
+                        slot_fluxes(abx, aby, g0[r], g1[r], g2[r], g3[r], g4[r], pa, pb, pc);
+                    sAcc[t1[r] >> 16] = pa;
+                    sAcc[t2[r] & 0xffffu] = pb;
+                    sAcc[t2[r] >> 16] = pc;
+                    rUx[r] = Px;
+                    rUy[r] = Py;
+                    pUx[r] = Qx;
+                    pUy[r] = Qy;
+                    aUx[r] = abx;
+                    aUy[r] = aby;
+                    if (le < h.nown) {
+                        if (first && j == 0)
+                            sm[r].init(abx, aby);
+                        else
+                            sm[r].add(abx, aby);
+                    }
+                    continue;
+                }
                 T Unx, Uny, pa, pb, pc;
                 if constexpr (F32) {
                     bool dry;
@@ -809,6 +957,12 @@ __global__ void __launch_bounds__(BLOCK) k_tile(TileArgs a) {
                 en = vtx_update_f32(sEta[i], acc, sAv[i], sW[i], dts);
             else
                 en = sEta[i] - dts * (acc / sAv[i] + sW[i]);
+            if constexpr (SM) {
+                const T e0 = sEta[i], e1 = sE1[i], e2 = sE2[i];
+                sEA[i] = sesm_am<T>(c, en, e0, e1, e2);
+                sE2[i] = e1;
+                sE1[i] = e0;
+            }
             sEta[i] = en;
             bad_any |= !finite_val(en);
             return en;
@@ -837,6 +991,47 @@ __global__ void __launch_bounds__(BLOCK) k_tile(TileArgs a) {
     if (bad_any) set_fault(a.faults, 2u);
 
     // write back owned vertices and triangles
+    if constexpr (SM) {
+        const int wsel = ch & 1;
+        T *o0 = static_cast<T *>(a.sm_v[wsel][0]) + h.vbase;
+        T *o1 = static_cast<T *>(a.sm_v[wsel][1]) + h.vbase;
+        T *o2 = static_cast<T *>(a.sm_v[wsel][2]) + h.vbase;
+        T *o3 = static_cast<T *>(a.sm_v[wsel][3]) + h.vbase;
+        for (int i = tid; i < h.nv0; i += BLOCK) {
+            o0[i] = sEta[i];
+            o1[i] = sE1[i];
+            o2[i] = sE2[i];
+            o3[i] = sEA[i];
+        }
+        T2 *u0 = static_cast<T2 *>(a.sm_e[wsel][0]);
+        T2 *u1 = static_cast<T2 *>(a.sm_e[wsel][1]);
+        T2 *u2 = static_cast<T2 *>(a.sm_e[wsel][2]);
+#pragma unroll
+        for (int r = 0; r < EPT; ++r) {
+            const int le = tid + r * BLOCK;
+            if (le < h.nown) {
+                const int g = h.ebase + le;
+                T2 v;
+                v.x = rUx[r];
+                v.y = rUy[r];
+                u0[g] = v;
+                v.x = pUx[r];
+                v.y = pUy[r];
+                u1[g] = v;
+                v.x = aUx[r];
+                v.y = aUy[r];
+                u2[g] = v;
+                if (last) {
+                    if (a.Uavg) {
+                        a.Uavg[2 * g] = sm[r].vx() / c.Mdbl;
+                        a.Uavg[2 * g + 1] = sm[r].vy() / c.Mdbl;
+                    }
+                } else {
+                    sm[r].store(a.sum, g);
+                }
+            }
+        }
+    } else {
     T *eta_out = static_cast<T *>(even ? a.eta_w : a.eta_u);
     for (int i = tid; i < h.nv0; i += BLOCK) eta_out[h.vbase + i] = sEta[i];
     T2 *Uout = static_cast<T2 *>(even ? a.U_w : a.U_u);
@@ -860,6 +1055,7 @@ __global__ void __launch_bounds__(BLOCK) k_tile(TileArgs a) {
                 }
             }
         }
+    }
     }
     // volume partials of this tile
     if (first) {
@@ -1024,9 +1220,9 @@ __global__ void __launch_bounds__(256) k_vol_reduce(const double *part, int64_t 
     if (threadIdx.x == 0) out[r] = add + ((red[0] + red[1]) + (red[2] + red[3]));
 }
 
-template <typename T, bool F32, int EPT, int BLOCK>
+template <typename T, bool F32, int EPT, int BLOCK, bool SM>
 hipError_t launch_tile_t(const TileArgs *a, int grid, size_t lds, hipStream_t s) {
-    auto *kern = k_tile<T, F32, EPT, BLOCK>;
+    auto *kern = k_tile<T, F32, EPT, BLOCK, SM>;
     if (!a)   // prepare only
         return hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                    hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
@@ -1034,58 +1230,69 @@ hipError_t launch_tile_t(const TileArgs *a, int grid, size_t lds, hipStream_t s)
     return hipGetLastError();
 }
 
-template <typename T, bool F32, int BLOCK>
+template <typename T, bool F32, int BLOCK, bool SM>
 hipError_t launch_tile_ept(int ept, const TileArgs *a, int grid, size_t lds, hipStream_t s) {
     switch (ept) {
-        case 1: return launch_tile_t<T, F32, 1, BLOCK>(a, grid, lds, s);
-        case 2: return launch_tile_t<T, F32, 2, BLOCK>(a, grid, lds, s);
-        case 3: return launch_tile_t<T, F32, 3, BLOCK>(a, grid, lds, s);
-        case 4: return launch_tile_t<T, F32, 4, BLOCK>(a, grid, lds, s);
-        case 6: return launch_tile_t<T, F32, 6, BLOCK>(a, grid, lds, s);
-        case 8: return launch_tile_t<T, F32, 8, BLOCK>(a, grid, lds, s);
+        case 1: return launch_tile_t<T, F32, 1, BLOCK, SM>(a, grid, lds, s);
+        case 2: return launch_tile_t<T, F32, 2, BLOCK, SM>(a, grid, lds, s);
+        case 3: return launch_tile_t<T, F32, 3, BLOCK, SM>(a, grid, lds, s);
+        case 4: return launch_tile_t<T, F32, 4, BLOCK, SM>(a, grid, lds, s);
+        case 6: return launch_tile_t<T, F32, 6, BLOCK, SM>(a, grid, lds, s);
+        case 8: return launch_tile_t<T, F32, 8, BLOCK, SM>(a, grid, lds, s);
         default: return hipErrorInvalidValue;
     }
 }
 
 // 1024-thread workgroups must fit 128 VGPRs: FP32 up to 4 triangles per thread,
 // FP64 one.
-template <typename T, bool F32>
+template <typename T, bool F32, bool SM>
 hipError_t launch_tile_1024(int ept, const TileArgs *a, int grid, size_t lds, hipStream_t s) {
     if constexpr (F32) {
         switch (ept) {
-            case 1: return launch_tile_t<T, F32, 1, 1024>(a, grid, lds, s);
-            case 2: return launch_tile_t<T, F32, 2, 1024>(a, grid, lds, s);
-            case 3: return launch_tile_t<T, F32, 3, 1024>(a, grid, lds, s);
-            case 4: return launch_tile_t<T, F32, 4, 1024>(a, grid, lds, s);
+            case 1: return launch_tile_t<T, F32, 1, 1024, SM>(a, grid, lds, s);
+            case 2: return launch_tile_t<T, F32, 2, 1024, SM>(a, grid, lds, s);
+            case 3: return launch_tile_t<T, F32, 3, 1024, SM>(a, grid, lds, s);
+            case 4: return launch_tile_t<T, F32, 4, 1024, SM>(a, grid, lds, s);
             default: return hipErrorInvalidValue;
         }
     } else {
-        return ept == 1 ? launch_tile_t<T, F32, 1, 1024>(a, grid, lds, s) : hipErrorInvalidValue;
+        return ept == 1 ? launch_tile_t<T, F32, 1, 1024, SM>(a, grid, lds, s) : hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_tile_any(bool f32, int ept, int block, const TileArgs *a, int grid, size_t lds,
-                           hipStream_t s) {
+template <bool SM>
+hipError_t launch_tile_sm(bool f32, int ept, int block, const TileArgs *a, int grid, size_t lds,
+                          hipStream_t s) {
     if (block == 1024)
-        return f32 ? launch_tile_1024<float, true>(ept, a, grid, lds, s)
-                   : launch_tile_1024<double, false>(ept, a, grid, lds, s);
+        return f32 ? launch_tile_1024<float, true, SM>(ept, a, grid, lds, s)
+                   : launch_tile_1024<double, false, SM>(ept, a, grid, lds, s);
     if (block == 256)
-        return f32 ? launch_tile_ept<float, true, 256>(ept, a, grid, lds, s)
-                   : launch_tile_ept<double, false, 256>(ept, a, grid, lds, s);
+        return f32 ? launch_tile_ept<float, true, 256, SM>(ept, a, grid, lds, s)
+                   : launch_tile_ept<double, false, 256, SM>(ept, a, grid, lds, s);
     if (block == 512)
-        return f32 ? launch_tile_ept<float, true, 512>(ept, a, grid, lds, s)
-                   : launch_tile_ept<double, false, 512>(ept, a, grid, lds, s);
+        return f32 ? launch_tile_ept<float, true, 512, SM>(ept, a, grid, lds, s)
+                   : launch_tile_ept<double, false, 512, SM>(ept, a, grid, lds, s);
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_tile_any(bool f32, bool sm, int ept, int block, const TileArgs *a, int grid,
+                           size_t lds, hipStream_t s) {
+    return sm ? launch_tile_sm<true>(f32, ept, block, a, grid, lds, s)
+              : launch_tile_sm<false>(f32, ept, block, a, grid, lds, s);
 }
 
 }  // namespace
 
-int tile_lds_bytes(bool f32, int block, int K, int cap_nv, int cap_ne, int cap_nvu, int cap_cs) {
+int tile_lds_bytes(bool f32, bool sm, int block, int K, int cap_nv, int cap_ne, int cap_nvu,
+                   int cap_cs) {
     (void)K;
+    (void)cap_ne;
     const int ts = f32 ? 4 : 8;
     int off = 0;
     auto al = [](int b) { return (b + 15) & ~15; };
     off = al(off + ts * cap_nv);
+    if (sm)
+        for (int k = 0; k < 3; ++k) off = al(off + ts * cap_nv);
     off = al(off + ts * cap_nv);
     off = al(off + ts * cap_nvu);
     off = al(off + ts * cap_nvu);
@@ -1096,13 +1303,13 @@ int tile_lds_bytes(bool f32, int block, int K, int cap_nv, int cap_ne, int cap_n
     return off;
 }
 
-hipError_t prepare_tile(bool f32, int ept, int block) {
-    return launch_tile_any(f32, ept, block, nullptr, 0, 0, nullptr);
+hipError_t prepare_tile(bool f32, bool sm, int ept, int block) {
+    return launch_tile_any(f32, sm, ept, block, nullptr, 0, 0, nullptr);
 }
 
-hipError_t launch_tile(bool f32, int ept, int block, const TileArgs &a, int grid, size_t lds,
-                       hipStream_t s) {
-    return launch_tile_any(f32, ept, block, &a, grid, lds, s);
+hipError_t launch_tile(bool f32, bool sm, int ept, int block, const TileArgs &a, int grid,
+                       size_t lds, hipStream_t s) {
+    return launch_tile_any(f32, sm, ept, block, &a, grid, lds, s);
 }
 
 hipError_t launch_plain_step(bool f32, const PlainArgs &a, hipStream_t s) {
@@ -1114,6 +1321,15 @@ hipError_t launch_plain_step(bool f32, const PlainArgs &a, hipStream_t s) {
         hipLaunchKernelGGL((k_plain_tri<double, false>), dim3(ge), dim3(256), 0, s, a);
         hipLaunchKernelGGL((k_plain_vtx<double, false>), dim3(gv), dim3(256), 0, s, a);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_sesm_fin(bool f32, const PlainArgs &a, hipStream_t s) {
+    const int g = static_cast<int>((std::max(a.nv, a.ne) + 255) / 256);
+    if (f32)
+        hipLaunchKernelGGL((k_sesm_fin<float, true>), dim3(g), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_sesm_fin<double, false>), dim3(g), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

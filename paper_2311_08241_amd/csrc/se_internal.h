@@ -86,6 +86,12 @@ struct DevTiles {
     int32_t max_nv = 0, max_ne = 0, max_nvu = 0, max_cs = 0;
     size_t lds_bytes64 = 0, lds_bytes32 = 0;
     bool ok32 = false, ok64 = false;
+    size_t lds_sm64 = 0, lds_sm32 = 0;   // AB3-AM4 scheme
+    bool ok_sm32 = false, ok_sm64 = false;
+    size_t lds(bool f32, bool sm) const {
+        return sm ? (f32 ? lds_sm32 : lds_sm64) : (f32 ? lds_bytes32 : lds_bytes64);
+    }
+    bool ok(bool f32, bool sm) const { return sm ? (f32 ? ok_sm32 : ok_sm64) : (f32 ? ok32 : ok64); }
     std::vector<TileHdr> hdr_host;
     DevBuf hdr, nV, nE, lv_gid, le_rec, cs_row;
     DevBuf geo64, geo32, ae64, ae32;   // per local triangle: 4 gradient values; A_e

@@ -153,3 +153,58 @@ def test_sesm_cfl_check_uses_the_sesm_limit():
             assert e.status == L.SE_ERR_CFL
             raised = True
         assert raised == (not ok)
+
+
+PLANS = [(64, 1, 256), (64, 3, 256), (128, 4, 256), (256, 2, 512), (96, 8, 256)]
+
+
+def _plans_ok(mesh, prec):
+    out = []
+    for pl in PLANS:
+        if mesh.plan_stats(*pl)["ok_sesm_" + prec]:
+            out.append(pl)
+    assert out, "no plan fits"
+    return out
+
+
+@pytest.mark.parametrize("name", ["jitter76", "chan54", "sphere86", "torus43", "C1", "C2s", "C3s"])
+def test_sesm_fp64_tile_matches_oracle(name):
+    from paper_2311_08241_amd import Mesh
+    case = _case(name)
+    nsteps = 2
+    W = 1e-5 * sesynth.rng(5).standard_normal(case["x"].size) if name == "jitter76" else None
+    mesh = Mesh.from_dict(case, device=0)
+    eta_r, U_r, Uavg_r, vol_r = _run_oracle(case, nsteps, W=W)
+    for pl in _plans_ok(mesh, "f64"):
+        eta, U, Uavg, vol = _run_gpu(case, mesh, _params(case), nsteps, plain=False, W=W, plan=pl)
+        assert _rel(eta, eta_r) <= 1e-12, pl
+        assert _rel(U, U_r) <= 1e-12, pl
+        assert _rel(Uavg, Uavg_r) <= 1e-12, pl
+        assert np.abs(vol - vol_r).max() <= 1e-12 * np.abs(vol_r).max(), pl
+
+
+def test_sesm_fp32_tile_identical_to_plain_and_across_plans():
+    from paper_2311_08241_amd import Mesh
+    case = _case("C2s")
+    mesh = Mesh.from_dict(case, device=0)
+    p = _params(case, "f32")
+    ref = _run_gpu(case, mesh, p, 2, plain=True)
+    for pl in _plans_ok(mesh, "f32"):
+        out = _run_gpu(case, mesh, p, 2, plain=False, plan=pl)
+        for a, b in zip(out[:3], ref[:3]):
+            assert np.array_equal(a, b), pl
+
+
+@pytest.mark.parametrize("nsub", [1, 5, 7])
+def test_sesm_tile_partial_chunks(nsub):
+    """nsub below, between and not divisible by the substeps per launch."""
+    from paper_2311_08241_amd import Mesh
+    case = dict(_case("jitter76"))
+    case["tau"] = case["tau"] / case["nsub"] * nsub
+    case["nsub"] = nsub
+    mesh = Mesh.from_dict(case, device=0)
+    eta_r, U_r, Uavg_r, _ = _run_oracle(case, 1)
+    for pl in _plans_ok(mesh, "f64"):
+        eta, U, Uavg, _ = _run_gpu(case, mesh, _params(case), 1, plain=False, plan=pl)
+        assert _rel(eta, eta_r) <= 1e-12 and _rel(U, U_r) <= 1e-12, (pl, nsub)
+        assert _rel(Uavg, Uavg_r) <= 1e-12, (pl, nsub)
