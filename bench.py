@@ -202,6 +202,75 @@ def bench_adjoint(args, log):
     return out
 
 
+def bench_sesm(args, log, mesh, case, stream, with_oracle):
+    """The AB3-AM4 scheme (eqs. (eq4_7)-(eq4_8)) on the same lat-lon workload: FP32
+    on the tile kernel (autotuned), FP64 on the plain three-kernel path, FP32 error
+    against the FP64 oracle after one step."""
+    import torch
+
+    from paper_2311_08241_amd import Params, device_inputs
+    from paper_2311_08241_amd.api import sesm_coefficients
+    from paper_2311_08241_amd.autotune import autotune
+    nsub, tau = case["nsub"], case["tau"]
+    co = sesm_coefficients(case["theta"])
+    out = {"coefficients": {"beta": co[0], "delta": co[1], "gamma": co[2], "zeta": co[3]}}
+    p32 = Params(g=case["g"], theta=case["theta"], precision="f32", eta_ref=case["eta_ref"],
+                 scheme="sesm", sesm=co)
+    p64 = Params(g=case["g"], theta=case["theta"], precision="f64", scheme="sesm", sesm=co)
+    Uavg = torch.empty((mesh.ne, 2), dtype=torch.float64, device="cuda:0")
+    res = {}
+    for label, p, plain in (("fp32_tile", p32, False), ("fp64_plain", p64, True)):
+        d = device_inputs(mesh, case, p)
+        e0_, u0_ = d["eta"].clone(), d["U"].clone()
+        ws = mesh.workspace(p, nsub)
+
+        def step(dd=d, pp=p, w=ws, pl=plain):
+            mesh.subcycle(dd["eta"], dd["U"], R=dd["R"], f=dd["f"], H0=dd["H0"], nsub=nsub,
+                          dt=tau, params=pp, Uavg=Uavg, workspace=w, plain=pl)
+
+        def reset(dd=d, a=e0_, b=u0_):
+            dd["eta"].copy_(a)
+            dd["U"].copy_(b)
+        with torch.cuda.stream(stream):
+            if not plain:
+                t = autotune(mesh, step, "f32-sesm", nsub, top=24, log=log, reset=reset,
+                             use_cache=not args.retune)
+                out["plan"] = t["plan"]
+            reset()
+            step()
+            torch.cuda.synchronize()
+            res[label] = (mesh.v_out(d["eta"].double().cpu().numpy() + p.eta_ref),
+                          mesh.e_out(Uavg.cpu().numpy()))
+            n = max(2, args.steps // 2)
+            ms = _time(step, n, stream)
+        out[label] = {"value": float(mesh.nv) * nsub / (ms * 1e-3), "ms_per_step": ms}
+        log(f"[bench] sesm {label}: {out[label]['value']:.3e} vertex-substeps/s ({ms:.2f} ms/step)")
+        del d, ws
+    if mesh.check_faults():
+        raise RuntimeError("kernel fault flags set (sesm)")
+    if with_oracle:
+        import oracle
+        om = oracle.Mesh(case, reordered=True)
+        b, dl, g, z = co
+        t0 = time.perf_counter()
+        eta_o, _, ua_o, _ = om.subcycle_sesm(om.v_in(case["eta0"]), om.e_in(case["U0"]),
+                                             H0=om.v_in(case["H0"]), f=om.e_in(case["f"]),
+                                             R=om.e_in(case["R"]), g=case["g"], beta=b,
+                                             delta=dl, gamma=g, zeta=z, nsub=nsub, tau=tau,
+                                             volume=False)
+        log(f"[bench] sesm oracle step {time.perf_counter() - t0:.1f}s")
+        eta_r, ua_r = om.v_out(eta_o), om.e_out(ua_o)
+        for label in res:
+            eta_g, ua_g = res[label]
+            ref = case["eta_ref"]
+            out[label]["eta_max_err"] = float(np.abs(eta_g - eta_r).max() /
+                                              np.abs(eta_r - ref).max())
+            out[label]["Uavg_max_err"] = float(np.abs(ua_g - ua_r).max() / np.abs(ua_r).max())
+        log(f"[bench] sesm errors vs oracle: "
+            f"{ {k: (out[k]['eta_max_err'], out[k]['Uavg_max_err']) for k in res} }")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -347,6 +416,7 @@ def main():
             log(f"[bench] {label}: {extra[label]['value']:.3e} vertex-substeps/s")
         extra["speedup_vs_fp64_plain"] = value / extra["fp64_plain"]["value"]
         del d64, ws64
+        extra["sesm"] = bench_sesm(args, log, mesh, case, stream, not args.no_cpu)
 
     cpu = None
     errors = None

@@ -28,13 +28,34 @@ CACHE = os.environ.get("SESUB_TUNE_CACHE",
 SHIPPED = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_plans.json")
 
 
+def _split(precision: str):
+    """'f32' / 'f64', optionally with '-sesm' for the AB3-AM4 scheme."""
+    prec, _, scheme = precision.partition("-")
+    if prec not in ("f32", "f64") or scheme not in ("", "sesm"):
+        raise ValueError(f"precision {precision!r}: expected f32, f64, f32-sesm or f64-sesm")
+    return prec, scheme == "sesm"
+
+
 def _tier_ok(precision: str, ept: int, block: int) -> bool:
     """Register tiers the library runs without spills (mirror of its plan check)."""
+    prec, sm = _split(precision)
     if block == 256:
-        return ept <= (8 if precision == "f32" else 6)
+        return ept <= (8 if prec == "f32" else 6)
     if block == 512:
-        return ept <= (8 if precision == "f32" else 4)
-    return ept <= (4 if precision == "f32" else 1)
+        return ept <= (8 if prec == "f32" else 4)
+    return ept <= ((3 if sm else 4) if prec == "f32" else 1)
+
+
+def _vgprs(precision: str, ept: int) -> int:
+    """Approximate VGPRs of the tile kernel per register tier (measured from the
+    compiler's resource report: about 24 per triangle slot in FP32, 45 in FP64;
+    26 and 51 with the two extra transports of the AB3-AM4 scheme)."""
+    prec, sm = _split(precision)
+    if prec == "f32":
+        v = 37 + 26 * ept if sm else 32 + 24 * ept
+    else:
+        v = 52 + 51 * ept if sm else 44 + 45 * ept
+    return -(-v // 8) * 8
 
 
 def mesh_signature(mesh) -> str:
@@ -47,13 +68,6 @@ def mesh_signature(mesh) -> str:
     return h.hexdigest()[:20]
 
 
-def _vgprs(precision: str, ept: int) -> int:
-    """Approximate VGPRs of the tile kernel per register tier (measured from the
-    compiler's resource report: about 24 per triangle slot in FP32, 45 in FP64)."""
-    v = 32 + 24 * ept if precision == "f32" else 44 + 45 * ept
-    return -(-v // 8) * 8
-
-
 def candidates(mesh, precision: str, nsub: int, top: int = 30):
     """Feasible plans, ranked by a latency/occupancy model of one tile.
 
@@ -64,7 +78,8 @@ def candidates(mesh, precision: str, nsub: int, top: int = 30):
     the shortlist is then timed.  One se_plan_stats call per (tile, k) gives the
     largest triangle count and the LDS size.
     """
-    lkey = "lds_f32" if precision == "f32" else "lds_f64"
+    prec, sm = _split(precision)
+    lkey = ("lds_sesm_" if sm else "lds_") + prec
     lat_us, sub_us = 5.8, 0.45      # load + write-back; per substep and triangle/thread
     rows = []
     for K in KS:

@@ -8,6 +8,8 @@ benchmark selects (tile plans of the autotuner's shortlist).
   adjoint basin 256x256: FP64 adjoint equal to the oracle's to 1e-12
   ensemble of 64 basins: FP32 batched within 1e-5 of the FP64 batched run
       (itself bit-identical to standalone runs) after 10 steps
+  AB3-AM4 (SESM) scheme: lat-lon FP64 one step equal to the oracle to 1e-12;
+      channel FP32 within 1e-5 of the oracle after 1020 substeps
 """
 import numpy as np
 import pytest
@@ -151,3 +153,52 @@ def test_c4_ensemble_fp32_budget_10_steps():
         a, b = res["f32"][vo[i]:vo[i + 1]], res["f64"][vo[i]:vo[i + 1]]
         e = np.abs(a - b).max() / np.abs(b - eta_ref).max()
         assert e <= 1e-5, (i, nsub[i] * 10, e)
+
+
+def _sesm_gpu(mesh, case, prec, plan, nsteps):
+    from paper_2311_08241_amd import Params, device_inputs
+    from paper_2311_08241_amd.api import sesm_coefficients
+    mesh.set_plan(*plan)
+    p = Params(precision=prec, eta_ref=case["eta_ref"] if prec == "f32" else 0.0, scheme="sesm",
+               sesm=sesm_coefficients(case["theta"]))
+    d = device_inputs(mesh, case, p)
+    Uavg = torch.empty((mesh.ne, 2), dtype=torch.float64, device="cuda:0")
+    ws = mesh.workspace(p, case["nsub"])
+    for _ in range(nsteps):
+        mesh.subcycle(d["eta"], d["U"], R=d["R"], f=d["f"], H0=d["H0"], nsub=case["nsub"],
+                      dt=case["tau"], params=p, Uavg=Uavg, workspace=ws)
+    torch.cuda.synchronize()
+    assert mesh.check_faults() == 0
+    eta = d["eta"].double().cpu().numpy() + p.eta_ref
+    return mesh.v_out(eta), mesh.e_out(Uavg.cpu().numpy())
+
+
+def _sesm_oracle(om, case, nsteps):
+    from oracle import analytic
+    b, d, g, z = analytic.sesm_params(case["theta"])
+    H0, f, R = om.v_in(case["H0"]), om.e_in(case["f"]), om.e_in(case["R"])
+    eta, U = om.v_in(case["eta0"]), om.e_in(case["U0"])
+    for _ in range(nsteps):
+        eta, U, Uavg, _ = om.subcycle_sesm(eta, U, H0=H0, f=f, R=R, g=case["g"], beta=b, delta=d,
+                                           gamma=g, zeta=z, nsub=case["nsub"], tau=case["tau"],
+                                           volume=False)
+    return om.v_out(eta), om.e_out(Uavg)
+
+
+def test_c3_sesm_fp64_one_step_equals_oracle():
+    case, mesh, om = _c3()
+    eta_r, ua_r = _sesm_oracle(om, case, 1)
+    eta, ua = _sesm_gpu(mesh, case, "f64", (384, 4, 512), 1)
+    assert np.abs(eta - eta_r).max() <= 1e-12 * np.abs(eta_r).max()
+    assert np.abs(ua - ua_r).max() <= 1e-12 * np.abs(ua_r).max()
+
+
+def test_c2_sesm_fp32_1020_substep_budget():
+    from paper_2311_08241_amd import Mesh
+    case = sesynth.channel_c2(nsteps=17)
+    mesh = Mesh.from_dict(case, device=0)
+    om = oracle.Mesh(case, reordered=True)
+    eta, ua = _sesm_gpu(mesh, case, "f32", (448, 4, 512), 17)
+    eta_r, ua_r = _sesm_oracle(om, case, 17)
+    e_max = np.abs(eta - eta_r).max() / np.abs(eta_r - case["eta_ref"]).max()
+    assert e_max <= 1e-5, e_max

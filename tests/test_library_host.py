@@ -141,3 +141,21 @@ def test_workspace_size_grows_with_substeps():
     b = m.workspace_bytes(Params(), 100)
     c = m.workspace_bytes(Params(precision="f32"), 10)
     assert b > a > c > 0 and a % 256 == 0
+
+
+def test_autotune_candidates_and_signature_on_a_host_mesh():
+    """The tuner's host side: plan ranking for both schemes and the cache key."""
+    from paper_2311_08241_amd import Mesh
+    from paper_2311_08241_amd import autotune as A
+    case = sesynth.channel_c2(nx=64, ny=48, nsteps=1)
+    m = Mesh.from_dict(case, device=-1)
+    for prec in ("f32", "f64", "f32-sesm", "f64-sesm"):
+        c = A.candidates(m, prec, case["nsub"], top=8)
+        assert c and all(len(r) == 5 for r in c)
+        assert [r[0] for r in c] == sorted(r[0] for r in c)
+        lkey = "lds_" + ("sesm_" if prec.endswith("sesm") else "") + prec[:3]
+        assert all(r[4][lkey] <= A.LDS_MAX for r in c)
+    sig = A.mesh_signature(m)
+    assert isinstance(sig, str) and len(sig) == 20 and sig == A.mesh_signature(m)
+    with pytest.raises(ValueError):
+        A._split("f16")
