@@ -6,7 +6,7 @@ this package imports nothing from it.
 
 Contents
   oracle.c     plain C definition (reorder, geometry, forward SE and SESM, TLM,
-               adjoint)
+               adjoint, trim of layer transports and z* thicknesses)
   brute.py     dense operators from an independent median-dual construction
   analytic.py  closed forms of the paper's Sec. 3 (amplification matrix,
                characteristic polynomial, small-c expansions)
@@ -174,6 +174,23 @@ class Mesh:
                 ctypes.c_int32(nsub), ctypes.c_double(tau), _p(eta), _p(U), _p(Uavg), _p(vol))
         _check(L.orc_subcycle_sesm(*args))
         return eta, U, Uavg, vol
+
+    def trim_zstar(self, *, H0, eta_new, Uavg, Ustar, hn, h0, W=None, tau):
+        """Trim of the layer transports to <<U>> (eq. (eq4_13)), z* thicknesses and the
+        diasurface velocity.  Ustar [ne][K][2], hn/h0 [nv][K].  Returns (U, hnew, w[nv][K+1])."""
+        L = _load()
+        Ustar = np.ascontiguousarray(Ustar, np.float64)
+        K = Ustar.shape[1]
+        U = np.empty_like(Ustar)
+        hnew = np.empty((self.nv, K))
+        w = np.empty((self.nv, K + 1))
+        _check(L.orc_trim_zstar(ctypes.c_int64(self.nv), ctypes.c_int64(self.ne), _p(self.tri),
+                                _p(self.Ae), _p(self.gN), _p(self.Av), ctypes.c_int32(K),
+                                _p(_f64(H0)), _p(_f64(eta_new)), _p(_f64(Uavg, (self.ne, 2))),
+                                _p(Ustar), _p(_f64(hn, (self.nv, K))), _p(_f64(h0, (self.nv, K))),
+                                _p(None if W is None else _f64(W)), ctypes.c_double(tau), _p(U),
+                                _p(hnew), _p(w)))
+        return U, hnew, w
 
     def tlm(self, eta0, U0, d_eta0, d_U0, d_R, d_H0, *, H0, f, R, W=None, g, theta, nsub,
             tau, linear_h=False):

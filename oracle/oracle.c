@@ -430,6 +430,80 @@ int orc_subcycle_sesm(int64_t nv, int64_t ne, const int32_t *tri, const double *
 }
 
 /* ------------------------------------------------------------------------ */
+/* Consumer of the averaged transport (Sec. 2.3, eq. (eq4_13); Sec. 2.4):     */
+/* K layers, thicknesses h at vertices (layer 0 at the surface), layer        */
+/* transports on triangles.                                                   */
+/*  1. z* target: h^{n+1}_k = h^0_k (H0 + eta^{n+1}) / H0 at each vertex.      */
+/*  2. h^{n+1/2} = (h^n + h^{n+1}) / 2; on a triangle, the mean of its three   */
+/*     vertices.                                                              */
+/*  3. trim: U_k = U*_k - h^{n+1/2}_k / sum_j h^{n+1/2}_j                      */
+/*               * (sum_j U*_j - <<U>>)                                       */
+/*  4. diasurface velocity from the thickness equation, bottom up:            */
+/*     w_bottom of the deepest layer is 0, and for each layer                 */
+/*       w_top = w_bottom - (h^{n+1}_k - h^n_k)/tau - div U_k - W [k = 0],    */
+/*     w[v][k] the velocity through the top of layer k, w[v][K] = 0.          */
+/*     w[v][0] vanishes to rounding when the column thickness H0 + eta^{n+1}  */
+/*     is the one the averaged transport carried (eq. (eq4_11)).              */
+/* Readings: thickness of a layer on a triangle = mean of its vertices; W     */
+/* enters the top layer; the divergence is the median-dual one of the         */
+/* barotropic path.                                                           */
+/* ------------------------------------------------------------------------ */
+int orc_trim_zstar(int64_t nv, int64_t ne, const int32_t *tri, const double *Ae,
+                   const double *gN, const double *Av, int32_t K, const double *H0,
+                   const double *eta_new, const double *Uavg, const double *Ustar,
+                   const double *hn, const double *h0, const double *W, double tau,
+                   double *U, double *hnew, double *w)
+{
+    if (K <= 0 || nv <= 0 || ne <= 0 || !(tau > 0.0)) return ORC_ERR_ARG;
+    orc_mesh m = {nv, ne, tri, Ae, gN, Av};
+    /* 1. z* target */
+    for (int64_t v = 0; v < nv; ++v)
+        for (int32_t k = 0; k < K; ++k)
+            hnew[v * K + k] = h0[v * K + k] * (H0[v] + eta_new[v]) / H0[v];
+    /* 2-3. trim per triangle */
+    double *hh = (double *)malloc(sizeof(double) * K);
+    double *div = (double *)malloc(sizeof(double) * nv * K);
+    if (!hh || !div) {
+        free(hh); free(div);
+        return ORC_ERR_OOM;
+    }
+    for (int64_t e = 0; e < ne; ++e) {
+        const int32_t *t = tri + 3 * e;
+        double hs = 0.0, sx = 0.0, sy = 0.0;
+        for (int32_t k = 0; k < K; ++k) {
+            double a = 0.5 * (hn[t[0] * K + k] + hnew[t[0] * K + k]);
+            double b = 0.5 * (hn[t[1] * K + k] + hnew[t[1] * K + k]);
+            double c = 0.5 * (hn[t[2] * K + k] + hnew[t[2] * K + k]);
+            hh[k] = (a + b + c) / 3.0;
+            hs += hh[k];
+            sx += Ustar[(e * K + k) * 2];
+            sy += Ustar[(e * K + k) * 2 + 1];
+        }
+        double ex = sx - Uavg[2 * e], ey = sy - Uavg[2 * e + 1];
+        for (int32_t k = 0; k < K; ++k) {
+            U[(e * K + k) * 2] = Ustar[(e * K + k) * 2] - hh[k] / hs * ex;
+            U[(e * K + k) * 2 + 1] = Ustar[(e * K + k) * 2 + 1] - hh[k] / hs * ey;
+        }
+    }
+    /* 4. layer divergences (ascending triangle order per vertex) and w */
+    for (int64_t i = 0; i < nv * K; ++i) div[i] = 0.0;
+    for (int64_t e = 0; e < ne; ++e)
+        for (int j = 0; j < 3; ++j)
+            for (int32_t k = 0; k < K; ++k)
+                div[tri[3 * e + j] * K + k] += slot_flux(&m, e, j, U + (e * K + k) * 2);
+    for (int64_t v = 0; v < nv; ++v) {
+        w[v * (K + 1) + K] = 0.0;
+        for (int32_t k = K - 1; k >= 0; --k)
+            w[v * (K + 1) + k] = w[v * (K + 1) + k + 1] -
+                                 (hnew[v * K + k] - hn[v * K + k]) / tau -
+                                 div[v * K + k] / Av[v] - (k == 0 && W ? W[v] : 0.0);
+    }
+    free(hh);
+    free(div);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Tangent-linear model: derivative of the subcycle map along                */
 /* (d_eta0, d_U0, d_R, d_H0); the state is advanced alongside.               */
 /* ------------------------------------------------------------------------ */

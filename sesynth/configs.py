@@ -270,6 +270,24 @@ def random_case(mesh: dict, seed: int = 0, *, H=(500.0, 4000.0), eta_amp=0.5,
                  linear_h=linear_h, name="random")
 
 
+def layers(case: dict, K: int = 40, seed: int = 0, *, U_amp: float = 0.5):
+    """Synthetic K-layer inputs for the consumer of the averaged transport.
+
+    frac [K]: reference layer fractions of the column (thin at the surface,
+    stretched with depth, summing to 1; the shape of a z* grid with 40 levels);
+    Ustar [ne][K][2]: layer transports before the trim, a smooth vertical
+    profile times random horizontal structure (m^2/s).
+    """
+    r = M.rng(1300 + seed)
+    z = np.arange(K, dtype=np.float64)
+    frac = 1.0 + 0.08 * z + 0.002 * z ** 2
+    frac = frac / frac.sum()
+    ne = case["tri"].shape[0]
+    prof = np.cos(np.pi * (z + 0.5) / K)[None, :, None]
+    Ustar = U_amp * prof * r.standard_normal((ne, 1, 2)) + 0.1 * U_amp * r.standard_normal((ne, K, 2))
+    return dict(frac=frac, Ustar=Ustar, K=K)
+
+
 BUILDERS = {"C1": basin_c1, "C2": channel_c2, "C3": latlon_c3, "C4": batch_c4,
             "C5": adjoint_c5}
 
