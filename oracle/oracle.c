@@ -433,7 +433,7 @@ int orc_subcycle_sesm(int64_t nv, int64_t ne, const int32_t *tri, const double *
 /* Consumer of the averaged transport (Sec. 2.3, eq. (eq4_13); Sec. 2.4):     */
 /* K layers, thicknesses h at vertices (layer 0 at the surface), layer        */
 /* transports on triangles.                                                   */
-/*  1. z* target: h^{n+1}_k = h^0_k (H0 + eta^{n+1}) / H0 at each vertex.      */
+/*  1. z* target: h^{n+1}_k = h^0_k (H / H0), H = H0 + eta^{n+1}, per vertex.  */
 /*  2. h^{n+1/2} = (h^n + h^{n+1}) / 2; on a triangle, the mean of its three   */
 /*     vertices.                                                              */
 /*  3. trim: U_k = U*_k - h^{n+1/2}_k / sum_j h^{n+1/2}_j                      */
@@ -459,7 +459,7 @@ int orc_trim_zstar(int64_t nv, int64_t ne, const int32_t *tri, const double *Ae,
     /* 1. z* target */
     for (int64_t v = 0; v < nv; ++v)
         for (int32_t k = 0; k < K; ++k)
-            hnew[v * K + k] = h0[v * K + k] * (H0[v] + eta_new[v]) / H0[v];
+            hnew[v * K + k] = h0[v * K + k] * ((H0[v] + eta_new[v]) / H0[v]);
     /* 2-3. trim per triangle */
     double *hh = (double *)malloc(sizeof(double) * K);
     double *div = (double *)malloc(sizeof(double) * nv * K);
