@@ -258,6 +258,26 @@ se_status se_plan_stats(const void *mesh_or_batch, int32_t kind, int32_t tile, i
 se_status se_check_faults(void *mesh_or_batch, int32_t kind, void *stream,
                           uint32_t *fault_bits);
 
+/* Consumer of the averaged transport (Sec. 2.3, eq. (eq4_13); Sec. 2.4,
+ * z* coordinate), FP64, K layers (1 <= K <= 64; layer 0 at the surface):
+ *   z* target      hnew[v][k] = h0[v][k] (H / H0[v]),  H = H0[v] + eta_new[v]
+ *   mid thickness  h[k] on a triangle = mean over its vertices of (hn + hnew) / 2
+ *   trim           U[e][k] = Ustar[e][k] - h[k] / sum_j h[j] (sum_j Ustar[e][j] - Uavg[e])
+ *   diasurface velocity from the thickness equation, bottom up:
+ *                  w[v][K] = 0,  w[v][k] = w[v][k+1] - (hnew - hn)[v][k] / tau
+ *                                 - (div U[.][k])[v] - W[v] (k = 0 only)
+ * with the median-dual divergence of the subcycle.  w[v][k] is the velocity
+ * through the top of layer k; w[v][0] vanishes to rounding when eta_new and Uavg
+ * come from the same subcycle (eq. (eq4_11)).  Device arrays, mesh numbering:
+ * H0, eta_new [nv] (absolute eta), Uavg [ne][2], Ustar and U [ne][K][2] (U may
+ * alias Ustar), hn, h0, hnew [nv][K], W [nv] or NULL, w [nv][K+1].
+ * Results equal the FP64 CPU definition bit for bit (same operations, same order).
+ * Errors: SE_ERR_ARG (NULL array, K outside 1..64, tau <= 0, host-only mesh). */
+se_status se_trim_zstar(se_mesh *mesh, int32_t K, const double *H0, const double *eta_new,
+                        const double *Uavg, const double *Ustar, const double *hn,
+                        const double *h0, const double *W, double tau, double *U, double *hnew,
+                        double *w, void *stream);
+
 /* Thread-local text of the last error. */
 const char *se_last_error(void);
 

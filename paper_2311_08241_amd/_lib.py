@@ -89,6 +89,8 @@ _SIGS = {
                                       ctypes.POINTER(Forcing), c_int32, c_double, c_int32,
                                       c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                       c_void_p, c_void_p, c_void_p, c_void_p]),
+    "se_trim_zstar": (c_int32, [c_void_p, c_int32] + [c_void_p] * 7 + [c_double] +
+                      [c_void_p] * 4),
     "se_batch_create": (c_int32, [c_void_p, c_int32, ctypes.POINTER(c_void_p)]),
     "se_batch_destroy": (None, [c_void_p]),
     "se_batch_info": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),

@@ -227,6 +227,32 @@ class Mesh:
                    float(dt), _ptr(workspace), _stream_ptr(stream)))
         return eta, U, Uavg, volume
 
+    def trim_zstar(self, *, H0, eta_new, Uavg, Ustar, hn, h0, tau: float, W=None, U=None,
+                   hnew=None, w=None, stream=None):
+        """se_trim_zstar (FP64): trim of the layer transports Ustar [ne][K][2] to Uavg
+        (eq. (eq4_13)), z* thicknesses and the diasurface velocity.  Outputs that are
+        None are allocated (U may be Ustar itself).  Returns (U, hnew, w)."""
+        torch = _torch()
+        f64 = torch.float64
+        K = int(Ustar.shape[1])
+        for t, n, name in ((H0, self.nv, "H0"), (eta_new, self.nv, "eta_new")):
+            self._check_tensor(t, n, name, f64)
+        self._check_tensor(Uavg, self.ne, "Uavg", f64, 2)
+        self._check_tensor(W, self.nv, "W", f64, allow_none=True)
+        if tuple(Ustar.shape) != (self.ne, K, 2) or Ustar.dtype != f64 or not Ustar.is_contiguous():
+            raise ValueError("Ustar must be a contiguous float64 tensor [ne][K][2]")
+        for t, name in ((hn, "hn"), (h0, "h0")):
+            if tuple(t.shape) != (self.nv, K) or t.dtype != f64 or not t.is_contiguous():
+                raise ValueError(f"{name} must be a contiguous float64 tensor [nv][K]")
+        dev = Ustar.device
+        U = torch.empty_like(Ustar) if U is None else U
+        hnew = torch.empty((self.nv, K), dtype=f64, device=dev) if hnew is None else hnew
+        w = torch.empty((self.nv, K + 1), dtype=f64, device=dev) if w is None else w
+        L.check(L.lib().se_trim_zstar(self._h, K, _ptr(H0), _ptr(eta_new), _ptr(Uavg),
+                                      _ptr(Ustar), _ptr(hn), _ptr(h0), _ptr(W), float(tau),
+                                      _ptr(U), _ptr(hnew), _ptr(w), _stream_ptr(stream)))
+        return U, hnew, w
+
     def adjoint(self, eta0, U0, *, R, f, H0, W=None, nsub: int, dt: float, params: Params,
                 ckpt_every: int = 5, lam_eta=None, lam_U=None, lam_Uavg=None, g_eta0=None,
                 g_U0=None, g_R=None, g_H0=None, workspace=None, stream=None):

@@ -865,6 +865,44 @@ se_status se_subcycle_plain(se_mesh *m, const se_params *p, se_state *st, const 
     return SE_OK;
 }
 
+se_status se_trim_zstar(se_mesh *m, int32_t K, const double *H0, const double *eta_new,
+                        const double *Uavg, const double *Ustar, const double *hn,
+                        const double *h0, const double *W, double tau, double *U, double *hnew,
+                        double *w, void *stream) {
+    if (!m || !H0 || !eta_new || !Uavg || !Ustar || !hn || !h0 || !U || !hnew || !w) {
+        set_error("se_trim_zstar: null argument");
+        return SE_ERR_ARG;
+    }
+    if (K < 1 || K > 64 || !(tau > 0.0) || !std::isfinite(tau)) {
+        set_error("se_trim_zstar: need 1 <= K <= 64 and a finite tau > 0");
+        return SE_ERR_ARG;
+    }
+    SE_TRY(check_device(m));
+    DeviceGuard dg(m->device);
+    TrimArgs a{};
+    a.nv = m->h.nv;
+    a.ne = m->h.ne;
+    a.K = K;
+    a.tau = tau;
+    a.tri = m->d.tri.as<const int32_t>();
+    a.row_ptr = m->d.row_ptr.as<const int32_t>();
+    a.pcol = m->d.pcol.as<const int32_t>();
+    a.geom = m->d.geom64.as<const double>();
+    a.Av = m->d.Av64.as<const double>();
+    a.H0 = H0;
+    a.eta_new = eta_new;
+    a.Uavg = Uavg;
+    a.Ustar = Ustar;
+    a.hn = hn;
+    a.h0 = h0;
+    a.W = W;
+    a.U = U;
+    a.hnew = hnew;
+    a.w = w;
+    HIP_TRY(launch_trim(a, static_cast<hipStream_t>(stream)), "se_trim_zstar launch");
+    return SE_OK;
+}
+
 se_status se_check_faults(void *obj, int32_t kind, void *stream, uint32_t *bits) {
     if (obj && bits && kind == 1) return se_batch_faults_impl(static_cast<se_batch *>(obj), stream, bits);
     if (!obj || !bits || kind != 0) {

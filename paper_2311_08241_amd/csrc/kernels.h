@@ -109,4 +109,19 @@ int tile_lds_bytes(bool f32, bool sm, int block, int K, int cap_nv, int cap_ne, 
                    int cap_cs);
 hipError_t launch_sesm_fin(bool f32, const PlainArgs &a, hipStream_t s);
 
+// Consumer of the averaged transport (FP64): trim of K layer transports, z*
+// thicknesses, diasurface velocity.  One wavefront per triangle / vertex, lane =
+// layer (K <= 64).
+struct TrimArgs {
+    int64_t nv, ne;
+    int32_t K;
+    double tau;
+    const int32_t *tri, *row_ptr, *pcol;
+    const double *geom;         // 5 SoA arrays [ne]: gbx gby gcx gcy A_e
+    const double *Av;
+    const double *H0, *eta_new, *Uavg, *Ustar, *hn, *h0, *W;
+    double *U, *hnew, *w;
+};
+hipError_t launch_trim(const TrimArgs &a, hipStream_t s);
+
 }  // namespace sesub

@@ -510,6 +510,95 @@ __global__ void __launch_bounds__(256) k_sesm_fin(PlainArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// Consumer of the averaged transport (FP64), in the operation order of the
+// definition: z* target h0 (H / H0), mid thickness on triangles, trim of the
+// layer transports to <<U>>, layer divergences in ascending triangle order, and
+// the diasurface velocity from the bottom up.  Sums over layers and the vertical
+// recursion run in layer order in one lane (values staged in LDS); everything
+// else is one lane per layer.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double zstar_h(const TrimArgs &a, int64_t v, int k) {
+    return a.h0[v * a.K + k] * ((a.H0[v] + a.eta_new[v]) / a.H0[v]);
+}
+
+__global__ void __launch_bounds__(256) k_trim(TrimArgs a) {
+    __shared__ double s_hh[4][64], s_ux[4][64], s_uy[4][64], s_tot[4][3];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * 4 + wv;
+    const int K = a.K, k = lane;
+    const bool act = e < a.ne && k < K;
+    double hh = 0.0, ux = 0.0, uy = 0.0;
+    if (act) {
+        const int32_t *t = a.tri + 3 * e;
+        const double ha = 0.5 * (a.hn[t[0] * (int64_t)K + k] + zstar_h(a, t[0], k));
+        const double hb = 0.5 * (a.hn[t[1] * (int64_t)K + k] + zstar_h(a, t[1], k));
+        const double hc = 0.5 * (a.hn[t[2] * (int64_t)K + k] + zstar_h(a, t[2], k));
+        hh = (ha + hb + hc) / 3.0;
+        ux = a.Ustar[(e * K + k) * 2];
+        uy = a.Ustar[(e * K + k) * 2 + 1];
+        s_hh[wv][k] = hh;
+        s_ux[wv][k] = ux;
+        s_uy[wv][k] = uy;
+    }
+    __syncthreads();
+    if (lane == 0 && e < a.ne) {
+        double hs = 0.0, sx = 0.0, sy = 0.0;
+        for (int j = 0; j < K; ++j) {
+            hs += s_hh[wv][j];
+            sx += s_ux[wv][j];
+            sy += s_uy[wv][j];
+        }
+        s_tot[wv][0] = hs;
+        s_tot[wv][1] = sx - a.Uavg[2 * e];
+        s_tot[wv][2] = sy - a.Uavg[2 * e + 1];
+    }
+    __syncthreads();
+    if (act) {
+        const double hs = s_tot[wv][0], ex = s_tot[wv][1], ey = s_tot[wv][2];
+        a.U[(e * K + k) * 2] = ux - hh / hs * ex;
+        a.U[(e * K + k) * 2 + 1] = uy - hh / hs * ey;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_zstar_w(TrimArgs a) {
+    __shared__ double s_a[4][64], s_b[4][64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t v = static_cast<int64_t>(blockIdx.x) * 4 + wv;
+    const int K = a.K, k = lane;
+    const bool act = v < a.nv && k < K;
+    if (act) {
+        const double hnew = zstar_h(a, v, k);
+        a.hnew[v * K + k] = hnew;
+        double div = 0.0;
+        const int32_t j1 = a.row_ptr[v + 1];
+        for (int32_t j = a.row_ptr[v]; j < j1; ++j) {
+            const int32_t pc = a.pcol[j];
+            const int64_t e = pc / 3;
+            const int slot = pc - 3 * (pc / 3);
+            const double Ae = a.geom[4 * a.ne + e];
+            const double gbx = a.geom[e], gby = a.geom[a.ne + e], gcx = a.geom[2 * a.ne + e],
+                         gcy = a.geom[3 * a.ne + e];
+            const double Fx = a.U[(e * K + k) * 2], Fy = a.U[(e * K + k) * 2 + 1];
+            double pa, pb, pc3;
+            slot_fluxes(Fx, Fy, gbx, gby, gcx, gcy, Ae, pa, pb, pc3);
+            div += slot == 0 ? pa : (slot == 1 ? pb : pc3);
+        }
+        s_a[wv][k] = (hnew - a.hn[v * K + k]) / a.tau;
+        s_b[wv][k] = div / a.Av[v];
+    }
+    __syncthreads();
+    if (lane == 0 && v < a.nv) {
+        double *w = a.w + v * (K + 1);
+        double wk = 0.0;
+        w[K] = wk;
+        for (int j = K - 1; j >= 0; --j) {
+            wk = wk - s_a[wv][j] - s_b[wv][j] - (j == 0 && a.W ? a.W[v] : 0.0);
+            w[j] = wk;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Temporally blocked tile kernel: up to K substeps of one tile per launch
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int align16(int b) { return (b + 15) & ~15; }
@@ -1321,6 +1410,15 @@ hipError_t launch_plain_step(bool f32, const PlainArgs &a, hipStream_t s) {
         hipLaunchKernelGGL((k_plain_tri<double, false>), dim3(ge), dim3(256), 0, s, a);
         hipLaunchKernelGGL((k_plain_vtx<double, false>), dim3(gv), dim3(256), 0, s, a);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_trim(const TrimArgs &a, hipStream_t s) {
+    if (a.ne > 0)
+        hipLaunchKernelGGL(k_trim, dim3(static_cast<unsigned>((a.ne + 3) / 4)), dim3(256), 0, s, a);
+    if (a.nv > 0)
+        hipLaunchKernelGGL(k_zstar_w, dim3(static_cast<unsigned>((a.nv + 3) / 4)), dim3(256), 0, s,
+                           a);
     return hipGetLastError();
 }
 

@@ -1,0 +1,84 @@
+"""GPU parity of the consumer of the averaged transport (trim of layer
+transports, eq. (eq4_13); z* thicknesses and diasurface velocity, Sec. 2.4)
+against the FP64 oracle through the C ABI: the same operations in the same
+order, bar 1e-12 relative (bit-identical in practice).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import sesynth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _inputs(case, K, seed, with_w):
+    om = oracle.Mesh(case, reordered=True)
+    H0 = om.v_in(case["H0"])
+    eta0 = om.v_in(case["eta0"])
+    W = 1e-5 * sesynth.rng(31).standard_normal(case["x"].size) if with_w else None
+    Wi = None if W is None else om.v_in(W)
+    eta1, _, Uavg, _ = om.subcycle(eta0, om.e_in(case["U0"]), H0=H0, f=om.e_in(case["f"]),
+                                   R=om.e_in(case["R"]), W=Wi, g=case["g"], theta=case["theta"],
+                                   nsub=case["nsub"], tau=case["tau"], volume=False)
+    lay = sesynth.layers(case, K=K, seed=seed)
+    Ustar = lay["Ustar"][om.eperm]
+    h0 = H0[:, None] * lay["frac"][None, :]
+    hn = h0 * ((H0 + eta0) / H0)[:, None]
+    return om, dict(H0=H0, eta_new=eta1, Uavg=Uavg, Ustar=np.ascontiguousarray(Ustar), hn=hn,
+                    h0=h0, W=Wi, tau=case["tau"])
+
+
+def _gpu(mesh, inp, inplace=False):
+    t = {k: (None if v is None else
+             torch.tensor(v, dtype=torch.float64, device="cuda:0") if isinstance(v, np.ndarray)
+             else v) for k, v in inp.items()}
+    U = t["Ustar"] if inplace else None
+    U, hnew, w = mesh.trim_zstar(H0=t["H0"], eta_new=t["eta_new"], Uavg=t["Uavg"],
+                                 Ustar=t["Ustar"], hn=t["hn"], h0=t["h0"], W=t["W"],
+                                 tau=t["tau"], U=U)
+    torch.cuda.synchronize()
+    return U.cpu().numpy(), hnew.cpu().numpy(), w.cpu().numpy()
+
+
+def _rel(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+@pytest.mark.parametrize("kind", ["jitter76", "chan54", "sphere86"])
+@pytest.mark.parametrize("with_w", [False, True])
+def test_trim_matches_oracle_small(kind, with_w):
+    from paper_2311_08241_amd import Mesh
+    case = sesynth.random_case(sesynth.tiny_mesh(kind), seed=4, nsub=24)
+    om, inp = _inputs(case, 12, 1, with_w)
+    mesh = Mesh.from_dict(case, device=0)
+    ref = om.trim_zstar(**inp)
+    out = _gpu(mesh, inp)
+    for a, b in zip(out, ref):
+        assert _rel(a, b) <= 1e-12
+
+
+def test_trim_c2_forty_layers_inplace_and_closure():
+    from paper_2311_08241_amd import Mesh
+    case = sesynth.channel_c2(nsteps=1)
+    om, inp = _inputs(case, 40, 2, True)
+    mesh = Mesh.from_dict(case, device=0)
+    ref = om.trim_zstar(**inp)
+    out = _gpu(mesh, inp, inplace=True)
+    for a, b in zip(out, ref):
+        assert _rel(a, b) <= 1e-12
+    # column closure at the surface (eq. (eq4_11)-(eq4_13))
+    assert np.abs(out[2][:, 0]).max() <= 1e-12 * inp["H0"].max() / inp["tau"]
+
+
+def test_trim_rejects_bad_arguments():
+    import paper_2311_08241_amd._lib as L
+    from paper_2311_08241_amd import Mesh
+    case = sesynth.random_case(sesynth.tiny_mesh("jitter76"), seed=4, nsub=24)
+    om, inp = _inputs(case, 12, 1, False)
+    mesh = Mesh.from_dict(case, device=0)
+    inp["tau"] = 0.0
+    with pytest.raises(L.SeError):
+        _gpu(mesh, inp)
