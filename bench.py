@@ -271,6 +271,46 @@ def bench_sesm(args, log, mesh, case, stream, with_oracle):
     return out
 
 
+def bench_trim(args, log, mesh, case, stream, K=40):
+    """Consumer of <<U>> on the lat-lon mesh with K layers (FP64): trim of the layer
+    transports (eq. (eq4_13)), z* thicknesses, diasurface velocity; HBM-bound, once
+    per baroclinic step.  Compulsory bytes: 32 per vertex-layer (hn, h0 in; hnew,
+    w out), 32 per triangle-layer (Ustar in, U out), 16 per vertex and triangle."""
+    import torch
+
+    import sesynth
+    lay = sesynth.layers(case, K=K, seed=0)
+    dev = "cuda:0"
+    f64 = torch.float64
+    H0 = torch.tensor(mesh.v_in(case["H0"]), dtype=f64, device=dev)
+    eta0 = torch.tensor(mesh.v_in(case["eta0"]), dtype=f64, device=dev)
+    frac = torch.tensor(lay["frac"], dtype=f64, device=dev)
+    h0 = (H0[:, None] * frac[None, :]).contiguous()
+    hn = (h0 * ((H0 + eta0) / H0)[:, None]).contiguous()
+    Ustar = torch.tensor(np.ascontiguousarray(mesh.e_in(lay["Ustar"])), dtype=f64, device=dev)
+    Uavg = Ustar.sum(1).contiguous() * 0.999
+    eta_new = eta0 * 0.999
+    U = torch.empty_like(Ustar)
+    hnew = torch.empty_like(hn)
+    w = torch.empty((mesh.nv, K + 1), dtype=f64, device=dev)
+
+    def call():
+        mesh.trim_zstar(H0=H0, eta_new=eta_new, Uavg=Uavg, Ustar=Ustar, hn=hn, h0=h0,
+                        tau=case["tau"], U=U, hnew=hnew, w=w, stream=stream)
+    with torch.cuda.stream(stream):
+        call()
+        torch.cuda.synchronize()
+        ms = _time(call, 10, stream)
+    nbytes = 32.0 * K * (mesh.nv + mesh.ne) + 16.0 * (mesh.nv + mesh.ne)
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    log(f"[bench] trim/z* K={K}: {ms:.3f} ms per call, {gbs:.0f} GB/s ({gbs / HBM_PEAK_GBS:.2f} of peak)")
+    del Ustar, U, hn, h0, hnew, w
+    return {"workload": f"lat-lon mesh, {K} layers, FP64", "ms_per_call": ms,
+            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+                         "bytes_per_call": nbytes}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -417,6 +457,7 @@ def main():
         extra["speedup_vs_fp64_plain"] = value / extra["fp64_plain"]["value"]
         del d64, ws64
         extra["sesm"] = bench_sesm(args, log, mesh, case, stream, not args.no_cpu)
+        extra["trim_zstar"] = bench_trim(args, log, mesh, case, stream)
 
     cpu = None
     errors = None

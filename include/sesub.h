@@ -271,7 +271,8 @@ se_status se_check_faults(void *mesh_or_batch, int32_t kind, void *stream,
  * come from the same subcycle (eq. (eq4_11)).  Device arrays, mesh numbering:
  * H0, eta_new [nv] (absolute eta), Uavg [ne][2], Ustar and U [ne][K][2] (U may
  * alias Ustar), hn, h0, hnew [nv][K], W [nv] or NULL, w [nv][K+1].
- * Results equal the FP64 CPU definition bit for bit (same operations, same order).
+ * Results equal the FP64 CPU definition to rounding: the sums over layers are
+ * tree reductions and the vertical recursion a parallel suffix sum.
  * Errors: SE_ERR_ARG (NULL array, K outside 1..64, tau <= 0, host-only mesh). */
 se_status se_trim_zstar(se_mesh *mesh, int32_t K, const double *H0, const double *eta_new,
                         const double *Uavg, const double *Ustar, const double *hn,

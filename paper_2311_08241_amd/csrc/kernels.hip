@@ -510,90 +510,118 @@ __global__ void __launch_bounds__(256) k_sesm_fin(PlainArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Consumer of the averaged transport (FP64), in the operation order of the
-// definition: z* target h0 (H / H0), mid thickness on triangles, trim of the
-// layer transports to <<U>>, layer divergences in ascending triangle order, and
-// the diasurface velocity from the bottom up.  Sums over layers and the vertical
-// recursion run in layer order in one lane (values staged in LDS); everything
-// else is one lane per layer.
+// Consumer of the averaged transport (FP64): z* target h0 (H / H0), mid thickness
+// on triangles, trim of the layer transports to <<U>>, layer divergences in
+// ascending triangle order, and the diasurface velocity from the bottom up.  One
+// wavefront per triangle / vertex, lane = layer: the sums over layers are wave
+// reductions and the vertical recursion a suffix scan across lanes (so results
+// equal the definition to rounding, not bit for bit); every load and store of
+// layer data is one coalesced wave access.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double zstar_h(const TrimArgs &a, int64_t v, int k) {
     return a.h0[v * a.K + k] * ((a.H0[v] + a.eta_new[v]) / a.H0[v]);
 }
 
+__device__ __forceinline__ double wave_allsum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Each wavefront handles EU elements at a time (independent load chains in flight).
+// Workgroups are dealt round-robin to the XCDs; each owns a contiguous range.
+constexpr int EU = 4;
+
 __global__ void __launch_bounds__(256) k_trim(TrimArgs a) {
-    __shared__ double s_hh[4][64], s_ux[4][64], s_uy[4][64], s_tot[4][3];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int64_t e = static_cast<int64_t>(blockIdx.x) * 4 + wv;
+    const int lane = threadIdx.x & 63;
     const int K = a.K, k = lane;
-    const bool act = e < a.ne && k < K;
-    double hh = 0.0, ux = 0.0, uy = 0.0;
-    if (act) {
-        const int32_t *t = a.tri + 3 * e;
-        const double ha = 0.5 * (a.hn[t[0] * (int64_t)K + k] + zstar_h(a, t[0], k));
-        const double hb = 0.5 * (a.hn[t[1] * (int64_t)K + k] + zstar_h(a, t[1], k));
-        const double hc = 0.5 * (a.hn[t[2] * (int64_t)K + k] + zstar_h(a, t[2], k));
-        hh = (ha + hb + hc) / 3.0;
-        ux = a.Ustar[(e * K + k) * 2];
-        uy = a.Ustar[(e * K + k) * 2 + 1];
-        s_hh[wv][k] = hh;
-        s_ux[wv][k] = ux;
-        s_uy[wv][k] = uy;
-    }
-    __syncthreads();
-    if (lane == 0 && e < a.ne) {
-        double hs = 0.0, sx = 0.0, sy = 0.0;
-        for (int j = 0; j < K; ++j) {
-            hs += s_hh[wv][j];
-            sx += s_ux[wv][j];
-            sy += s_uy[wv][j];
+    const bool act = k < K;
+    // each workgroup owns a contiguous range of triangles (its vertices' layer data
+    // then stays in one XCD's L2); its four wavefronts interleave over the range
+    const int64_t chunk = (a.ne + gridDim.x - 1) / gridDim.x;
+    const int64_t beg = static_cast<int64_t>(blockIdx.x) * chunk;
+    const int64_t end = min(a.ne, beg + chunk);
+    const int wv = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+    for (int64_t e0 = beg + wv; e0 < end; e0 += 4 * EU) {
+        double hh[EU], ux[EU], uy[EU];
+#pragma unroll
+        for (int u = 0; u < EU; ++u) {
+            const int64_t e = e0 + u * 4;
+            hh[u] = 0.0;
+            ux[u] = 0.0;
+            uy[u] = 0.0;
+            if (act && e < end) {
+                const int32_t *t = a.tri + 3 * e;
+                const double ha = 0.5 * (a.hn[t[0] * (int64_t)K + k] + zstar_h(a, t[0], k));
+                const double hb = 0.5 * (a.hn[t[1] * (int64_t)K + k] + zstar_h(a, t[1], k));
+                const double hc = 0.5 * (a.hn[t[2] * (int64_t)K + k] + zstar_h(a, t[2], k));
+                hh[u] = (ha + hb + hc) / 3.0;
+                ux[u] = a.Ustar[(e * K + k) * 2];
+                uy[u] = a.Ustar[(e * K + k) * 2 + 1];
+            }
         }
-        s_tot[wv][0] = hs;
-        s_tot[wv][1] = sx - a.Uavg[2 * e];
-        s_tot[wv][2] = sy - a.Uavg[2 * e + 1];
-    }
-    __syncthreads();
-    if (act) {
-        const double hs = s_tot[wv][0], ex = s_tot[wv][1], ey = s_tot[wv][2];
-        a.U[(e * K + k) * 2] = ux - hh / hs * ex;
-        a.U[(e * K + k) * 2 + 1] = uy - hh / hs * ey;
+#pragma unroll
+        for (int u = 0; u < EU; ++u) {
+            const int64_t e = e0 + u * 4;
+            if (e >= end) break;   // wave-uniform
+            const double hs = wave_allsum(hh[u]);
+            const double ex = wave_allsum(ux[u]) - a.Uavg[2 * e];
+            const double ey = wave_allsum(uy[u]) - a.Uavg[2 * e + 1];
+            if (act) {
+                a.U[(e * K + k) * 2] = ux[u] - hh[u] / hs * ex;
+                a.U[(e * K + k) * 2 + 1] = uy[u] - hh[u] / hs * ey;
+            }
+        }
     }
 }
 
 __global__ void __launch_bounds__(256) k_zstar_w(TrimArgs a) {
-    __shared__ double s_a[4][64], s_b[4][64];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int64_t v = static_cast<int64_t>(blockIdx.x) * 4 + wv;
+    const int lane = threadIdx.x & 63;
     const int K = a.K, k = lane;
-    const bool act = v < a.nv && k < K;
-    if (act) {
-        const double hnew = zstar_h(a, v, k);
-        a.hnew[v * K + k] = hnew;
-        double div = 0.0;
-        const int32_t j1 = a.row_ptr[v + 1];
-        for (int32_t j = a.row_ptr[v]; j < j1; ++j) {
-            const int32_t pc = a.pcol[j];
-            const int64_t e = pc / 3;
-            const int slot = pc - 3 * (pc / 3);
-            const double Ae = a.geom[4 * a.ne + e];
-            const double gbx = a.geom[e], gby = a.geom[a.ne + e], gcx = a.geom[2 * a.ne + e],
-                         gcy = a.geom[3 * a.ne + e];
-            const double Fx = a.U[(e * K + k) * 2], Fy = a.U[(e * K + k) * 2 + 1];
-            double pa, pb, pc3;
-            slot_fluxes(Fx, Fy, gbx, gby, gcx, gcy, Ae, pa, pb, pc3);
-            div += slot == 0 ? pa : (slot == 1 ? pb : pc3);
+    const bool act = k < K;
+    const int64_t chunk = (a.nv + gridDim.x - 1) / gridDim.x;
+    const int64_t beg = static_cast<int64_t>(blockIdx.x) * chunk;
+    const int64_t end = min(a.nv, beg + chunk);
+    const int wv = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+    for (int64_t v0 = beg + wv; v0 < end; v0 += 4 * EU) {
+        double t[EU];
+#pragma unroll
+        for (int u = 0; u < EU; ++u) {
+            const int64_t v = v0 + u * 4;
+            t[u] = 0.0;
+            if (act && v < end) {
+                const double hnew = zstar_h(a, v, k);
+                a.hnew[v * K + k] = hnew;
+                double div = 0.0;
+                const int32_t j1 = a.row_ptr[v + 1];
+                for (int32_t j = a.row_ptr[v]; j < j1; ++j) {
+                    const int32_t pcl = a.pcol[j];
+                    const int64_t e = pcl / 3;
+                    const int slot = pcl - 3 * (pcl / 3);
+                    const double Ae = a.geom[4 * a.ne + e];
+                    const double gbx = a.geom[e], gby = a.geom[a.ne + e],
+                                 gcx = a.geom[2 * a.ne + e], gcy = a.geom[3 * a.ne + e];
+                    const double Fx = a.U[(e * K + k) * 2], Fy = a.U[(e * K + k) * 2 + 1];
+                    double pa, pb, pc;
+                    slot_fluxes(Fx, Fy, gbx, gby, gcx, gcy, Ae, pa, pb, pc);
+                    div += slot == 0 ? pa : (slot == 1 ? pb : pc);
+                }
+                t[u] = (hnew - a.hn[v * K + k]) / a.tau + div / a.Av[v] +
+                       (k == 0 && a.W ? a.W[v] : 0.0);
+            }
         }
-        s_a[wv][k] = (hnew - a.hn[v * K + k]) / a.tau;
-        s_b[wv][k] = div / a.Av[v];
-    }
-    __syncthreads();
-    if (lane == 0 && v < a.nv) {
-        double *w = a.w + v * (K + 1);
-        double wk = 0.0;
-        w[K] = wk;
-        for (int j = K - 1; j >= 0; --j) {
-            wk = wk - s_a[wv][j] - s_b[wv][j] - (j == 0 && a.W ? a.W[v] : 0.0);
-            w[j] = wk;
+#pragma unroll
+        for (int u = 0; u < EU; ++u) {
+            const int64_t v = v0 + u * 4;
+            if (v >= end) break;   // wave-uniform
+            // w[k] = -(t_k + t_{k+1} + ... + t_{K-1}): inclusive suffix scan across lanes
+            double tt = t[u];
+            for (int o = 1; o < 64; o <<= 1) {
+                const double x = __shfl_down(tt, o, 64);
+                if (lane + o < 64) tt += x;
+            }
+            double *w = a.w + v * (K + 1);
+            if (act) w[k] = -tt;
+            if (lane == 0) w[K] = 0.0;
         }
     }
 }
@@ -1414,11 +1442,12 @@ hipError_t launch_plain_step(bool f32, const PlainArgs &a, hipStream_t s) {
 }
 
 hipError_t launch_trim(const TrimArgs &a, hipStream_t s) {
-    if (a.ne > 0)
-        hipLaunchKernelGGL(k_trim, dim3(static_cast<unsigned>((a.ne + 3) / 4)), dim3(256), 0, s, a);
-    if (a.nv > 0)
-        hipLaunchKernelGGL(k_zstar_w, dim3(static_cast<unsigned>((a.nv + 3) / 4)), dim3(256), 0, s,
-                           a);
+    // wavefronts loop over elements: at most 16 workgroups of 4 wavefronts per CU
+    auto grid = [](int64_t n) {
+        return static_cast<unsigned>(std::min<int64_t>((n + 4 * EU - 1) / (4 * EU), 256 * 16));
+    };
+    if (a.ne > 0) hipLaunchKernelGGL(k_trim, dim3(grid(a.ne)), dim3(256), 0, s, a);
+    if (a.nv > 0) hipLaunchKernelGGL(k_zstar_w, dim3(grid(a.nv)), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

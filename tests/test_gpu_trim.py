@@ -1,7 +1,8 @@
 """GPU parity of the consumer of the averaged transport (trim of layer
 transports, eq. (eq4_13); z* thicknesses and diasurface velocity, Sec. 2.4)
-against the FP64 oracle through the C ABI: the same operations in the same
-order, bar 1e-12 relative (bit-identical in practice).
+against the FP64 oracle through the C ABI, bar 1e-12 relative (the sums over
+layers and the vertical recursion differ from the definition only in rounding
+order).
 """
 import numpy as np
 import pytest
