@@ -6,7 +6,8 @@ this package imports nothing from it.
 
 Contents
   oracle.c     plain C definition (reorder, geometry, forward SE and SESM, TLM,
-               adjoint, trim of layer transports and z* thicknesses)
+               adjoint, trim of layer transports and z* thicknesses, vertically
+               integrated baroclinic forcing)
   brute.py     dense operators from an independent median-dual construction
   analytic.py  closed forms of the paper's Sec. 3 (amplification matrix,
                characteristic polynomial, small-c expansions)
@@ -59,6 +60,22 @@ def _check(rc):
 def _f64(a, shape=None):
     a = np.ascontiguousarray(a, dtype=np.float64)
     return a.reshape(shape) if shape is not None else a
+
+
+def forcing(*, K, nlev=None, RA=None, RP=None, RhV=None, tau_s=None, u=None, Cd=0.0):
+    """Vertically integrated baroclinic forcing of eq. (eq4_4): per element the sum over
+    its nlev layers of RA + RP + RhV, plus the surface stress tau_s, minus the bottom drag
+    Cd |u_b| u_b on the velocity of the deepest layer.  Layer arrays [ne][K][2]."""
+    L = _load()
+    arrs = [a for a in (RA, RP, RhV, u) if a is not None]
+    ne = np.asarray(arrs[0]).shape[0] if arrs else np.asarray(tau_s).shape[0]
+    lay = lambda a: None if a is None else _f64(a, (ne, K, 2))
+    nl = None if nlev is None else np.ascontiguousarray(nlev, np.int32)
+    R = np.empty((ne, 2))
+    _check(L.orc_forcing(ctypes.c_int64(ne), ctypes.c_int32(K), _p(nl), _p(lay(RA)), _p(lay(RP)),
+                         _p(lay(RhV)), _p(None if tau_s is None else _f64(tau_s, (ne, 2))),
+                         _p(lay(u)), ctypes.c_double(Cd), _p(R)))
+    return R
 
 
 def mesh_flags(mesh: dict) -> int:

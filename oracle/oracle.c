@@ -504,6 +504,49 @@ int orc_trim_zstar(int64_t nv, int64_t ne, const int32_t *tri, const double *Ae,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Vertically integrated baroclinic forcing, eq. (eq4_4) (Sec. 2.1, end):      */
+/*   R_e = sum_{k < nlev_e} (RA + RP + RhV)_k + tau_s - Cd |u_b| u_b            */
+/* The vertical-viscosity tendencies of a column telescope to the stress at    */
+/* the surface minus the stress at the bottom; the bottom stress is the        */
+/* quadratic drag on the velocity of the element's deepest layer (Sec. 2.1).   */
+/* RA, RP, RhV, u: [ne][K][2], any of RA/RP/RhV/tau_s may be NULL (term absent);*/
+/* nlev NULL means K layers everywhere.  Layers at or beyond nlev_e are never  */
+/* read.                                                                        */
+/* ------------------------------------------------------------------------ */
+int orc_forcing(int64_t ne, int32_t K, const int32_t *nlev, const double *RA,
+                const double *RP, const double *RhV, const double *tau_s, const double *u,
+                double Cd, double *R)
+{
+    if (ne <= 0 || K <= 0 || !(Cd >= 0.0) || (Cd > 0.0 && !u)) return ORC_ERR_ARG;
+    for (int64_t e = 0; e < ne; ++e) {
+        int32_t n = nlev ? nlev[e] : K;
+        if (n < 1 || n > K) return ORC_ERR_ARG;
+    }
+    for (int64_t e = 0; e < ne; ++e) {
+        int32_t n = nlev ? nlev[e] : K;
+        for (int c = 0; c < 2; ++c) {
+            double s = 0.0;
+            for (int32_t k = 0; k < n; ++k) {
+                size_t i = ((size_t)e * K + k) * 2 + c;
+                double layer = 0.0;
+                if (RA) layer += RA[i];
+                if (RP) layer += RP[i];
+                if (RhV) layer += RhV[i];
+                s += layer;
+            }
+            if (tau_s) s += tau_s[2 * e + c];
+            if (Cd > 0.0) {
+                const double *ub = u + ((size_t)e * K + (n - 1)) * 2;
+                double speed = sqrt(ub[0] * ub[0] + ub[1] * ub[1]);
+                s -= Cd * speed * ub[c];
+            }
+            R[2 * e + c] = s;
+        }
+    }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Tangent-linear model: derivative of the subcycle map along                */
 /* (d_eta0, d_U0, d_R, d_H0); the state is advanced alongside.               */
 /* ------------------------------------------------------------------------ */

@@ -288,6 +288,42 @@ def layers(case: dict, K: int = 40, seed: int = 0, *, U_amp: float = 0.5):
     return dict(frac=frac, Ustar=Ustar, K=K)
 
 
+def column_forcing(case: dict, K: int = 40, seed: int = 0, *, Cd: float = 2.5e-3):
+    """Synthetic baroclinic layer tendencies for the vertically integrated forcing.
+
+    Layer interfaces follow the z* fractions of :func:`layers` over the deepest
+    column; an element keeps the layers whose top lies above its depth (mean H0
+    of its vertices), so nlev [ne] follows the bathymetry (at least 1).
+    RA, RP, RhV [ne][K][2]: advective, pressure (without eta) and horizontal
+    viscous transport tendencies, layer thickness times an acceleration of
+    order 1e-5, 1e-5 and 1e-6 m/s^2 decaying with depth (m^2/s^2); u [ne][K][2]:
+    layer velocities (0.1 m/s scale); tau_s [ne][2]: kinematic surface stress
+    (0.1 N/m^2 over 1025 kg/m^3).  Layers at or below nlev hold zeros.
+    """
+    r = M.rng(1400 + seed)
+    frac = layers(case, K=K)["frac"]
+    H0 = np.asarray(case["H0"], np.float64)
+    He = H0[case["tri"]].mean(axis=1)
+    Hmax = H0.max()
+    top = Hmax * np.concatenate([[0.0], np.cumsum(frac)[:-1]])
+    nlev = np.clip(np.searchsorted(top, He, side="left"), 1, K).astype(np.int32)
+    ne = He.size
+    h = (Hmax * frac)[None, :, None]
+    decay = np.exp(-np.arange(K) / (0.3 * K))[None, :, None]
+    mask = (np.arange(K)[None, :] < nlev[:, None])[:, :, None]
+
+    def field(scale, prof):
+        a = r.standard_normal((ne, 1, 2)) * prof + 0.3 * r.standard_normal((ne, K, 2))
+        return np.where(mask, scale * a, 0.0)
+
+    RA = field(1e-5, decay) * h
+    RP = field(1e-5, 1.0 - 0.5 * decay) * h
+    RhV = field(1e-6, decay) * h
+    u = field(0.1, 0.3 + decay)
+    tau_s = 1e-4 * r.standard_normal((ne, 2))
+    return dict(K=K, nlev=nlev, RA=RA, RP=RP, RhV=RhV, u=u, tau_s=tau_s, Cd=Cd)
+
+
 BUILDERS = {"C1": basin_c1, "C2": channel_c2, "C3": latlon_c3, "C4": batch_c4,
             "C5": adjoint_c5}
 
