@@ -311,6 +311,38 @@ def bench_trim(args, log, mesh, case, stream, K=40):
                          "bytes_per_call": nbytes}}
 
 
+def bench_forcing(args, log, mesh, case, stream, K=40):
+    """Vertically integrated baroclinic forcing (eq. (eq4_4)) on the lat-lon mesh with
+    K layers following the bathymetry (FP64 in, FP64 out); HBM-bound, once per
+    baroclinic step.  Compulsory bytes: 48 per active triangle-layer (RA, RP, RhV),
+    16 each for tau_s, the bottom velocity and R, 4 for the layer count."""
+    import torch
+
+    import sesynth
+    d = sesynth.column_forcing(case, K=K, seed=0)
+    dev = "cuda:0"
+    t = {k: torch.tensor(d.pop(k), dtype=torch.float64, device=dev)
+         for k in ("RA", "RP", "RhV", "u", "tau_s")}
+    nlev = torch.tensor(d["nlev"], dtype=torch.int32, device=dev)
+    R = torch.empty((mesh.ne, 2), dtype=torch.float64, device=dev)
+
+    def call():
+        mesh.forcing(K=K, nlev=nlev, Cd=d["Cd"], R=R, stream=stream, **t)
+    with torch.cuda.stream(stream):
+        call()
+        torch.cuda.synchronize()
+        ms = _time(call, 10, stream)
+    nbytes = 48.0 * float(d["nlev"].sum()) + 52.0 * mesh.ne
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    log(f"[bench] forcing K={K}: {ms:.3f} ms per call, {gbs:.0f} GB/s ({gbs / HBM_PEAK_GBS:.2f} of peak)")
+    del t, R
+    return {"workload": f"lat-lon mesh, {K} layers (mean {d['nlev'].mean():.1f} active), FP64",
+            "ms_per_call": ms,
+            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+                         "bytes_per_call": nbytes}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -458,6 +490,7 @@ def main():
         del d64, ws64
         extra["sesm"] = bench_sesm(args, log, mesh, case, stream, not args.no_cpu)
         extra["trim_zstar"] = bench_trim(args, log, mesh, case, stream)
+        extra["forcing"] = bench_forcing(args, log, mesh, case, stream)
 
     cpu = None
     errors = None

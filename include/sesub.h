@@ -92,6 +92,7 @@ typedef enum { SE_SCHEME_SE = 0, SE_SCHEME_SESM = 1 } se_scheme;
 /* fault bits (se_check_faults) */
 #define SE_FAULT_DRY 1u       /* a triangle saw H = mean(H0 + eta) <= 0              */
 #define SE_FAULT_NONFINITE 2u /* eta became NaN or Inf                               */
+#define SE_FAULT_LAYERS 4u    /* se_forcing_assemble met a layer count outside 1..K            */
 
 typedef struct se_mesh se_mesh;
 typedef struct se_batch se_batch;
@@ -278,6 +279,28 @@ se_status se_trim_zstar(se_mesh *mesh, int32_t K, const double *H0, const double
                         const double *Uavg, const double *Ustar, const double *hn,
                         const double *h0, const double *W, double tau, double *U, double *hnew,
                         double *w, void *stream);
+
+/* Vertically integrated baroclinic forcing of eq. (eq4_4) (Sec. 2.1, end), the
+ * R the subcycle takes, per triangle e with nlev[e] layers (layer 0 at the surface):
+ *   R[e] = sum_{k < nlev[e]} (RA + RP + RhV)[e][k] + tau_s[e] - Cd |u_b| u_b,
+ *   u_b = u[e][nlev[e] - 1]
+ * RA, RP, RhV: advective, pressure (without the eta part) and horizontal viscous
+ * layer transport tendencies; the vertical viscous tendencies enter through their
+ * column sum, surface stress minus bottom stress, with the quadratic drag on the
+ * deepest layer's velocity as the bottom stress.  Device arrays, mesh triangle
+ * numbering, FP64: RA, RP, RhV, u [ne][K][2]; tau_s [ne][2] (kinematic stress,
+ * m^2/s^2); nlev [ne] int32.  Any of RA, RP, RhV, tau_s may be NULL (term absent);
+ * nlev NULL means K layers everywhere; u may be NULL when Cd == 0.  Layers at or
+ * below nlev[e] are never read.  R [ne][2] is written as double (SE_F64) or as the
+ * float rounding of the FP64 sum (SE_F32_MIXED, the FP32 subcycle's R).
+ * Results equal the FP64 CPU definition to rounding (the layer sum is a tree of
+ * eight partial sums).  A triangle whose nlev lies outside 1..K gets NaN and sets
+ * SE_FAULT_LAYERS (se_check_faults).
+ * Errors: SE_ERR_ARG (R NULL, K < 1, Cd < 0 or not finite, Cd > 0 without u,
+ * bad precision, host-only mesh), SE_ERR_HIP. */
+se_status se_forcing_assemble(se_mesh *mesh, int32_t K, const int32_t *nlev, const double *RA,
+                     const double *RP, const double *RhV, const double *tau_s, const double *u,
+                     double Cd, int32_t precision, void *R, void *stream);
 
 /* Thread-local text of the last error. */
 const char *se_last_error(void);

@@ -23,7 +23,7 @@ SE_F64, SE_F32_MIXED = 0, 1
 SE_SCHEME_SE, SE_SCHEME_SESM = 0, 1
 SE_PERIODIC_X, SE_PERIODIC_Y, SE_SPHERICAL = 1, 2, 4
 SE_LINEAR_H, SE_CHECK_CFL, SE_TRACK_VOLUME = 1, 2, 4
-SE_FAULT_DRY, SE_FAULT_NONFINITE = 1, 2
+SE_FAULT_DRY, SE_FAULT_NONFINITE, SE_FAULT_LAYERS = 1, 2, 4
 
 STATUS_NAMES = {0: "SE_OK", 1: "SE_ERR_ARG", 2: "SE_ERR_MESH", 3: "SE_ERR_HIP", 4: "SE_ERR_OOM",
                 5: "SE_ERR_CFL", 6: "SE_ERR_DRY", 7: "SE_ERR_NONFINITE", 8: "SE_ERR_UNSUPPORTED"}
@@ -91,6 +91,8 @@ _SIGS = {
                                       c_void_p, c_void_p, c_void_p, c_void_p]),
     "se_trim_zstar": (c_int32, [c_void_p, c_int32] + [c_void_p] * 7 + [c_double] +
                       [c_void_p] * 4),
+    "se_forcing_assemble": (c_int32, [c_void_p, c_int32] + [c_void_p] * 6 + [c_double, c_int32] +
+                   [c_void_p] * 2),
     "se_batch_create": (c_int32, [c_void_p, c_int32, ctypes.POINTER(c_void_p)]),
     "se_batch_destroy": (None, [c_void_p]),
     "se_batch_info": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),

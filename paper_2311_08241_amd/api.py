@@ -253,6 +253,37 @@ class Mesh:
                                       _ptr(U), _ptr(hnew), _ptr(w), _stream_ptr(stream)))
         return U, hnew, w
 
+    def forcing(self, *, K: int, nlev=None, RA=None, RP=None, RhV=None, tau_s=None, u=None,
+                Cd: float = 0.0, precision: str = "f64", R=None, stream=None):
+        """se_forcing_assemble: vertically integrated baroclinic forcing of eq. (eq4_4) per triangle,
+        the sum over its nlev layers of RA + RP + RhV ([ne][K][2] float64 each, any may be
+        None), plus the surface stress tau_s [ne][2], minus Cd |u_b| u_b on the deepest
+        layer's velocity u [ne][K][2].  Returns R [ne][2] (float64, or float32 for
+        precision "f32", the FP32 subcycle's forcing)."""
+        torch = _torch()
+        f64 = torch.float64
+        K = int(K)
+        for t, name in ((RA, "RA"), (RP, "RP"), (RhV, "RhV"), (u, "u")):
+            if t is not None and (tuple(t.shape) != (self.ne, K, 2) or t.dtype != f64
+                                  or not t.is_contiguous() or not t.is_cuda):
+                raise ValueError(f"{name} must be a contiguous float64 CUDA tensor [ne][K][2]")
+        self._check_tensor(tau_s, self.ne, "tau_s", f64, 2, allow_none=True)
+        if nlev is not None and (tuple(nlev.shape) != (self.ne,) or nlev.dtype != torch.int32
+                                 or not nlev.is_contiguous() or not nlev.is_cuda):
+            raise ValueError("nlev must be a contiguous int32 CUDA tensor [ne]")
+        if precision not in ("f64", "f32"):
+            raise ValueError("precision must be 'f64' or 'f32'")
+        dt = f64 if precision == "f64" else torch.float32
+        if R is None:
+            dev = next(t.device for t in (RA, RP, RhV, u, tau_s, nlev) if t is not None)
+            R = torch.empty((self.ne, 2), dtype=dt, device=dev)
+        self._check_tensor(R, self.ne, "R", dt, 2)
+        L.check(L.lib().se_forcing_assemble(self._h, K, _ptr(nlev), _ptr(RA), _ptr(RP), _ptr(RhV),
+                                   _ptr(tau_s), _ptr(u), float(Cd),
+                                   L.SE_F64 if precision == "f64" else L.SE_F32_MIXED, _ptr(R),
+                                   _stream_ptr(stream)))
+        return R
+
     def adjoint(self, eta0, U0, *, R, f, H0, W=None, nsub: int, dt: float, params: Params,
                 ckpt_every: int = 5, lam_eta=None, lam_U=None, lam_Uavg=None, g_eta0=None,
                 g_U0=None, g_R=None, g_H0=None, workspace=None, stream=None):

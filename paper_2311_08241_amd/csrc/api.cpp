@@ -903,6 +903,44 @@ se_status se_trim_zstar(se_mesh *m, int32_t K, const double *H0, const double *e
     return SE_OK;
 }
 
+se_status se_forcing_assemble(se_mesh *m, int32_t K, const int32_t *nlev, const double *RA,
+                     const double *RP, const double *RhV, const double *tau_s, const double *u,
+                     double Cd, int32_t precision, void *R, void *stream) {
+    if (!m || !R) {
+        set_error("se_forcing_assemble: null mesh or output");
+        return SE_ERR_ARG;
+    }
+    if (K < 1 || !(Cd >= 0.0) || !std::isfinite(Cd) || (Cd > 0.0 && !u)) {
+        set_error("se_forcing_assemble: need K >= 1, a finite Cd >= 0, and u when Cd > 0");
+        return SE_ERR_ARG;
+    }
+    if (precision != SE_F64 && precision != SE_F32_MIXED) {
+        set_error("se_forcing_assemble: precision must be SE_F64 or SE_F32_MIXED");
+        return SE_ERR_ARG;
+    }
+    if (static_cast<int64_t>(m->h.ne) * K > (int64_t(1) << 40)) {
+        set_error("se_forcing_assemble: ne * K too large");
+        return SE_ERR_ARG;
+    }
+    SE_TRY(check_device(m));
+    DeviceGuard dg(m->device);
+    ForcingArgs a{};
+    a.ne = m->h.ne;
+    a.K = K;
+    a.out_f32 = precision == SE_F32_MIXED;
+    a.Cd = Cd;
+    a.nlev = nlev;
+    a.RA = RA;
+    a.RP = RP;
+    a.RhV = RhV;
+    a.u = u;
+    a.tau_s = tau_s;
+    a.R = R;
+    a.faults = m->d.faults.as<uint32_t>();
+    HIP_TRY(launch_forcing(a, static_cast<hipStream_t>(stream)), "se_forcing_assemble launch");
+    return SE_OK;
+}
+
 se_status se_check_faults(void *obj, int32_t kind, void *stream, uint32_t *bits) {
     if (obj && bits && kind == 1) return se_batch_faults_impl(static_cast<se_batch *>(obj), stream, bits);
     if (!obj || !bits || kind != 0) {

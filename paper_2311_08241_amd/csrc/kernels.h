@@ -124,4 +124,17 @@ struct TrimArgs {
 };
 hipError_t launch_trim(const TrimArgs &a, hipStream_t s);
 
+struct ForcingArgs {
+    int64_t ne;
+    int32_t K;
+    int32_t out_f32;
+    double Cd;
+    const int32_t *nlev;        // [ne] or null (K everywhere)
+    const double *RA, *RP, *RhV, *u;   // [ne][K][2], any may be null
+    const double *tau_s;        // [ne][2] or null
+    void *R;                    // [ne][2] double or float
+    uint32_t *faults;
+};
+hipError_t launch_forcing(const ForcingArgs &a, hipStream_t s);
+
 }  // namespace sesub

@@ -627,6 +627,71 @@ __global__ void __launch_bounds__(256) k_zstar_w(TrimArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// Vertically integrated baroclinic forcing: eight lanes per triangle column.  Lane
+// j of a group adds the layers k = j, j + 8, ... (each group load is one 128-byte
+// run of (x, y) pairs), the group then combines its eight partial sums by a
+// butterfly, and its first lane adds the surface stress and the bottom drag.
+// ---------------------------------------------------------------------------
+constexpr int FG = 8;   // lanes per column
+
+template <bool OUT32>
+__global__ void __launch_bounds__(256) k_forcing(ForcingArgs a) {
+    const int j = threadIdx.x & (FG - 1);
+    const int64_t e = (static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x) / FG;
+    if (e >= a.ne) return;   // whole groups leave together (256 is a multiple of FG)
+    const int K = a.K;
+    const int n = a.nlev ? a.nlev[e] : K;
+    double rx, ry;
+    if (n < 1 || n > K) {
+        if (j == 0) set_fault(a.faults, 4u);
+        rx = ry = __builtin_nan("");
+    } else {
+        double sx = 0.0, sy = 0.0;
+        const int64_t base = e * K;
+#pragma unroll 4
+        for (int k = j; k < n; k += FG) {
+            const int64_t i = (base + k) * 2;
+            double lx = 0.0, ly = 0.0;
+            if (a.RA) { const double2 v = *reinterpret_cast<const double2 *>(a.RA + i); lx += v.x; ly += v.y; }
+            if (a.RP) { const double2 v = *reinterpret_cast<const double2 *>(a.RP + i); lx += v.x; ly += v.y; }
+            if (a.RhV) { const double2 v = *reinterpret_cast<const double2 *>(a.RhV + i); lx += v.x; ly += v.y; }
+            sx += lx;
+            sy += ly;
+        }
+#pragma unroll
+        for (int o = 1; o < FG; o <<= 1) {
+            sx += __shfl_xor(sx, o, 64);
+            sy += __shfl_xor(sy, o, 64);
+        }
+        if (a.tau_s) {
+            sx += a.tau_s[2 * e];
+            sy += a.tau_s[2 * e + 1];
+        }
+        if (a.Cd > 0.0) {
+            const double2 ub = *reinterpret_cast<const double2 *>(a.u + (base + n - 1) * 2);
+            const double sp = sqrt(ub.x * ub.x + ub.y * ub.y);
+            sx -= a.Cd * sp * ub.x;
+            sy -= a.Cd * sp * ub.y;
+        }
+        rx = sx;
+        ry = sy;
+    }
+    if (j == 0) {
+        if (OUT32) {
+            float2 r;
+            r.x = static_cast<float>(rx);
+            r.y = static_cast<float>(ry);
+            static_cast<float2 *>(a.R)[e] = r;
+        } else {
+            double2 r;
+            r.x = rx;
+            r.y = ry;
+            static_cast<double2 *>(a.R)[e] = r;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Temporally blocked tile kernel: up to K substeps of one tile per launch
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int align16(int b) { return (b + 15) & ~15; }
@@ -1438,6 +1503,14 @@ hipError_t launch_plain_step(bool f32, const PlainArgs &a, hipStream_t s) {
         hipLaunchKernelGGL((k_plain_tri<double, false>), dim3(ge), dim3(256), 0, s, a);
         hipLaunchKernelGGL((k_plain_vtx<double, false>), dim3(gv), dim3(256), 0, s, a);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_forcing(const ForcingArgs &a, hipStream_t s) {
+    if (a.ne <= 0) return hipSuccess;
+    const unsigned g = static_cast<unsigned>((a.ne * FG + 255) / 256);
+    if (a.out_f32) hipLaunchKernelGGL(k_forcing<true>, dim3(g), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(k_forcing<false>, dim3(g), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

@@ -10,6 +10,8 @@ benchmark selects (tile plans of the autotuner's shortlist).
       (itself bit-identical to standalone runs) after 10 steps
   AB3-AM4 (SESM) scheme: lat-lon FP64 one step equal to the oracle to 1e-12;
       channel FP32 within 1e-5 of the oracle after 1020 substeps
+  consumers at 40 layers on the lat-lon mesh: vertically integrated forcing within
+      the summation bound of the oracle; trim/z* within 1e-12
 """
 import numpy as np
 import pytest
@@ -202,3 +204,53 @@ def test_c2_sesm_fp32_1020_substep_budget():
     eta_r, ua_r = _sesm_oracle(om, case, 17)
     e_max = np.abs(eta - eta_r).max() / np.abs(eta_r - case["eta_ref"]).max()
     assert e_max <= 1e-5, e_max
+
+
+def test_c3_forcing_40_layers_matches_oracle():
+    """Vertically integrated forcing on the lat-lon mesh, 40 layers following the
+    bathymetry, in the launch the benchmark times; bar as in test_gpu_forcing."""
+    case, mesh, _ = _c3()
+    K = 40
+    d = sesynth.column_forcing(case, K=K, seed=0)
+    dev = {k: torch.tensor(d[k], dtype=torch.float64, device="cuda:0")
+           for k in ("RA", "RP", "RhV", "tau_s", "u")}
+    nlev = torch.tensor(d["nlev"], dtype=torch.int32, device="cuda:0")
+    R = mesh.forcing(K=K, nlev=nlev, Cd=d["Cd"], **dev)
+    torch.cuda.synchronize()
+    R = R.cpu().numpy()
+    del dev
+    ref = oracle.forcing(K=K, nlev=d["nlev"], RA=d["RA"], RP=d["RP"], RhV=d["RhV"],
+                         tau_s=d["tau_s"], u=d["u"], Cd=d["Cd"])
+    n = d["nlev"]
+    act = (np.arange(K)[None, :] < n[:, None])[:, :, None]
+    S = sum(np.where(act, np.abs(d[k]), 0.0).sum(axis=1) for k in ("RA", "RP", "RhV"))
+    ub = d["u"][np.arange(n.size), n - 1]
+    S = S + np.abs(d["tau_s"]) + d["Cd"] * np.hypot(ub[:, 0], ub[:, 1])[:, None] * np.abs(ub)
+    assert np.all(np.abs(R - ref) <= 2.0 * (3 * n[:, None] + 6) * 2.0 ** -53 * S)
+    assert mesh.check_faults() == 0
+
+
+def test_c3_trim_zstar_40_layers_matches_oracle():
+    """Trim/z* consumer on the lat-lon mesh at 40 layers (the benchmark's launch);
+    1e-12 relative as in test_gpu_trim."""
+    case, mesh, om = _c3()
+    K = 40
+    r = sesynth.rng(55)
+    H0 = om.v_in(case["H0"])
+    eta0 = om.v_in(case["eta0"])
+    eta_new = eta0 + 0.01 * r.standard_normal(eta0.size)
+    Uavg = r.standard_normal((om.ne, 2))
+    lay = sesynth.layers(case, K=K, seed=0)
+    Ustar = np.ascontiguousarray(lay["Ustar"][om.eperm])
+    h0 = H0[:, None] * lay["frac"][None, :]
+    hn = h0 * ((H0 + eta0) / H0)[:, None]
+    tau = case["tau"]
+    t = lambda a: torch.tensor(a, dtype=torch.float64, device="cuda:0")
+    U, hnew, w = mesh.trim_zstar(H0=t(H0), eta_new=t(eta_new), Uavg=t(Uavg), Ustar=t(Ustar),
+                                 hn=t(hn), h0=t(h0), tau=tau)
+    torch.cuda.synchronize()
+    out = (U.cpu().numpy(), hnew.cpu().numpy(), w.cpu().numpy())
+    del U, hnew, w
+    ref = om.trim_zstar(H0=H0, eta_new=eta_new, Uavg=Uavg, Ustar=Ustar, hn=hn, h0=h0, tau=tau)
+    for a, b in zip(out, ref):
+        assert np.abs(a - b).max() <= 1e-12 * np.abs(b).max()
