@@ -7,7 +7,7 @@ this package imports nothing from it.
 Contents
   oracle.c     plain C definition (reorder, geometry, forward SE and SESM, TLM,
                adjoint, trim of layer transports and z* thicknesses, vertically
-               integrated baroclinic forcing)
+               integrated baroclinic forcing, barotropic viscous regularization)
   brute.py     dense operators from an independent median-dual construction
   analytic.py  closed forms of the paper's Sec. 3 (amplification matrix,
                characteristic polynomial, small-c expansions)
@@ -162,17 +162,56 @@ class Mesh:
                 _p(_f64(R, (self.ne, 2))), _p(None if W is None else _f64(W)))
 
     def subcycle(self, eta, U, *, H0, f, R, W=None, g, theta, nsub, tau, linear_h=False,
-                 volume=True):
-        """One baroclinic step in this mesh's numbering.  Returns (eta, U, Uavg, volume)."""
+                 volume=True, visc=None):
+        """One baroclinic step in this mesh's numbering.  Returns (eta, U, Uavg, volume).
+        visc = (A0, Cv) adds the barotropic viscous regularization (eq. (eq:viscosity_BT))
+        and subtracts its initial value from R."""
         L = _load()
         eta = _f64(eta).copy()
         U = _f64(U, (self.ne, 2)).copy()
         Uavg = np.empty((self.ne, 2))
         vol = np.empty(nsub + 1) if volume else None
-        _check(L.orc_subcycle(*self._common(g, theta, linear_h, H0, f, R, W),
-                              ctypes.c_int32(nsub), ctypes.c_double(tau), _p(eta), _p(U),
-                              _p(Uavg), _p(vol)))
+        args = self._common(g, theta, linear_h, H0, f, R, W) + (
+            ctypes.c_int32(nsub), ctypes.c_double(tau), _p(eta), _p(U), _p(Uavg), _p(vol))
+        if visc is None:
+            _check(L.orc_subcycle(*args))
+        else:
+            nb, elen, lod = self.visc_geometry()
+            _check(L.orc_subcycle_visc(*args, _p(nb), _p(elen), _p(lod),
+                                       ctypes.c_double(visc[0]), ctypes.c_double(visc[1])))
         return eta, U, Uavg, vol
+
+    def visc_geometry(self):
+        """(nb [ne][3], l [ne][3], l/d [ne][3]): the triangle across local edge j
+        (t_j, t_{j+1}) or -1 on a coast, the edge length and the edge length over the
+        distance between the two centroids."""
+        if not hasattr(self, "_visc_geo"):
+            L = _load()
+            nb = np.empty((self.ne, 3), np.int32)
+            _check(L.orc_edge_neighbours(ctypes.c_int64(self.ne), _p(self.tri), _p(nb)))
+            elen = np.empty((self.ne, 3))
+            lod = np.empty((self.ne, 3))
+            m = self.src
+            _check(L.orc_visc_geometry(ctypes.c_int64(self.nv), ctypes.c_int64(self.ne),
+                                       _p(self.x), _p(self.y), _p(self.tri),
+                                       ctypes.c_uint32(mesh_flags(m)),
+                                       ctypes.c_double(m["period_x"]),
+                                       ctypes.c_double(m["period_y"]),
+                                       ctypes.c_double(m.get("radius", 0.0)), _p(nb), _p(elen),
+                                       _p(lod)))
+            self._visc_geo = (nb, elen, lod)
+        return self._visc_geo
+
+    def visc(self, eta, U, *, H0, A0, Cv, linear_h=False):
+        """The barotropic viscous term R^hV(eta, U) of eq. (eq:viscosity_BT) [ne][2]."""
+        L = _load()
+        nb, elen, lod = self.visc_geometry()
+        V = np.empty((self.ne, 2))
+        _check(L.orc_visc_apply(ctypes.c_int64(self.nv), ctypes.c_int64(self.ne), _p(self.tri),
+                                _p(self.Ae), _p(nb), _p(elen), _p(lod), ctypes.c_double(A0),
+                                ctypes.c_double(Cv), ctypes.c_int(1 if linear_h else 0),
+                                _p(_f64(H0)), _p(_f64(eta)), _p(_f64(U, (self.ne, 2))), _p(V)))
+        return V
 
     def subcycle_sesm(self, eta, U, *, H0, f, R, W=None, g, beta, delta, gamma, zeta, nsub,
                       tau, linear_h=False, volume=True):

@@ -11,6 +11,12 @@ used by ``oracle.c``:
     formula; its outward flux through the two interior segments from the
     segment vectors rotated clockwise (coastline segments carry no flux).
 
+The barotropic viscous term of eq. (eq:viscosity_BT) is rebuilt edge by edge: the
+interior edges come from a dictionary of vertex pairs, each edge's two-point flux
+is added to one triangle and subtracted from the other, the centroid distance
+is a third of the distance between the two vertices opposite the edge, and the
+triangle areas come from the shoelace formula.
+
 The substep then follows eq. (eq4_10) of the paper with dense matrices and
 numpy.linalg.solve for the Crank-Nicolson Coriolis system (pressure sign of
 eq. (eq4_5), see oracle.c); the AB3-AM4 substep of eqs. (eq4_7)-(eq4_8) is
@@ -106,13 +112,85 @@ def substep(ops, eta, U, *, H0, f, R, W=None, g, theta, dts, linear_h=False):
     return eta_n, Un
 
 
-def subcycle(ops, eta, U, *, H0, f, R, W=None, g, theta, nsub, tau, linear_h=False):
-    """nsub substeps; returns (eta^M, U^M, Uavg) with Uavg per eq. (eq4_12)."""
+def _edge_vec(mesh, p, r, clat):
+    """Vector from vertex p to vertex r in the metric of an edge (cos of its latitude)."""
+    x, y = mesh["x"], mesh["y"]
+    d = np.array([x[r] - x[p], y[r] - y[p]], dtype=float)
+    if mesh.get("spherical"):
+        d[0] = (d[0] + np.pi) % (2 * np.pi) - np.pi
+        if d[0] == -np.pi:
+            d[0] = np.pi
+        return np.array([mesh["radius"] * clat * d[0], mesh["radius"] * d[1]])
+    for ax, key in ((0, "period_x"), (1, "period_y")):
+        per = mesh.get(key, 0.0)
+        if per and per > 0.0:
+            if d[ax] > per / 2:
+                d[ax] -= per
+            elif d[ax] <= -per / 2:
+                d[ax] += per
+    return d
+
+
+def interior_edges(mesh):
+    """[(e1, e2, p, q)] for every edge shared by two triangles (p, q its vertices)."""
+    tri = np.asarray(mesh["tri"])
+    pairs = {}
+    for e in range(tri.shape[0]):
+        for j in range(3):
+            p, q = int(tri[e, j]), int(tri[e, (j + 1) % 3])
+            pairs.setdefault((min(p, q), max(p, q)), []).append(e)
+    out = []
+    for (p, q), es in pairs.items():
+        assert len(es) <= 2, "edge shared by more than two triangles"
+        if len(es) == 2:
+            out.append((es[0], es[1], p, q))
+    return out
+
+
+def visc_operator(mesh, eta, U, *, H0, A0, Cv, linear_h=False, return_energy=False):
+    """R^hV = div(H A grad(U/H)) per triangle: two-point fluxes H_j A_j (l/d) (u_2 - u_1)
+    through interior edges, A_j = A0 + Cv l |u_2 - u_1|, H_j the mean depth at the edge's
+    vertices, u = U / H_e (H_e the triangle mean depth).  With return_energy, also
+    -sum over edges of H_j A_j (l/d) |u_2 - u_1|^2."""
+    tri = np.asarray(mesh["tri"])
+    ne = tri.shape[0]
+    U = np.asarray(U, float).reshape(ne, 2)
+    Hv = H0 if linear_h else H0 + eta
+    He = Hv[tri].mean(axis=1)
+    u = U / He[:, None]
+    Ae = np.array([_shoelace(_local_coords(mesh, tri[e])) for e in range(ne)])
+    V = np.zeros((ne, 2))
+    energy = 0.0
+    y = mesh["y"]
+    for e1, e2, p, q in interior_edges(mesh):
+        clat = np.cos(0.5 * (y[p] + y[q])) if mesh.get("spherical") else 1.0
+        r1 = [v for v in tri[e1] if v not in (p, q)][0]
+        r2 = [v for v in tri[e2] if v not in (p, q)][0]
+        l = np.linalg.norm(_edge_vec(mesh, p, q, clat))
+        d = np.linalg.norm(_edge_vec(mesh, p, r2, clat) - _edge_vec(mesh, p, r1, clat)) / 3.0
+        du = u[e2] - u[e1]
+        A = A0 + Cv * l * np.linalg.norm(du)
+        F = 0.5 * (Hv[p] + Hv[q]) * A * (l / d) * du
+        V[e1] += F / Ae[e1]
+        V[e2] -= F / Ae[e2]
+        energy -= 0.5 * (Hv[p] + Hv[q]) * A * (l / d) * (du @ du)
+    return (V, energy) if return_energy else V
+
+
+def subcycle(ops, eta, U, *, H0, f, R, W=None, g, theta, nsub, tau, linear_h=False,
+             visc=None, mesh=None):
+    """nsub substeps; returns (eta^M, U^M, Uavg) with Uavg per eq. (eq4_12).  visc =
+    (A0, Cv) with the mesh adds the viscous term at each substep and subtracts its
+    value at the start from R."""
     dts = tau / nsub
     U0 = np.asarray(U, float).reshape(-1, 2).copy()
     s = np.zeros_like(U0)
+    if visc is not None:
+        Rb = R - visc_operator(mesh, eta, U0, H0=H0, A0=visc[0], Cv=visc[1], linear_h=linear_h)
     for _ in range(nsub):
-        eta, U = substep(ops, eta, U, H0=H0, f=f, R=R, W=W, g=g, theta=theta, dts=dts,
+        Rm = R if visc is None else Rb + visc_operator(mesh, eta, U, H0=H0, A0=visc[0],
+                                                       Cv=visc[1], linear_h=linear_h)
+        eta, U = substep(ops, eta, U, H0=H0, f=f, R=Rm, W=W, g=g, theta=theta, dts=dts,
                          linear_h=linear_h)
         s += U
     Uavg = s / nsub + theta / nsub * (U - U0)

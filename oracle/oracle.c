@@ -303,11 +303,22 @@ static double volume_of(const orc_mesh *m, const double *eta)
  * Uavg [ne][2] receives the averaged transport, volume [nsub+1] (optional)
  * the volume sum_v A_v eta_v after each substep (entry 0: initial state).
  */
-int orc_subcycle(int64_t nv, int64_t ne, const int32_t *tri, const double *Ae,
-                 const double *gN, const double *Av, double g, double theta,
-                 int linear_h, const double *H0, const double *f, const double *R,
-                 const double *W, int32_t nsub, double tau, double *eta, double *U,
-                 double *Uavg, double *volume)
+/* Barotropic viscous regularization (eq. (eq:viscosity_BT)) on the element
+ * neighbours of each triangle; see orc_visc_apply below. */
+typedef struct {
+    const int32_t *nb;
+    const double *elen, *lod;
+    double A0, Cv;
+} orc_visc;
+
+static void visc_apply(const orc_mesh *m, const orc_visc *vs, int linear_h, const double *H0,
+                       const double *eta, const double *U, double *V);
+
+static int subcycle_core(int64_t nv, int64_t ne, const int32_t *tri, const double *Ae,
+                         const double *gN, const double *Av, double g, double theta,
+                         int linear_h, const double *H0, const double *f, const double *R,
+                         const double *W, int32_t nsub, double tau, double *eta, double *U,
+                         double *Uavg, double *volume, const orc_visc *vs)
 {
     if (nsub <= 0 || nv <= 0 || ne <= 0) return ORC_ERR_ARG;
     orc_mesh m = {nv, ne, tri, Ae, gN, Av};
@@ -317,17 +328,30 @@ int orc_subcycle(int64_t nv, int64_t ne, const int32_t *tri, const double *Ae,
     double *U0 = (double *)malloc(sizeof(double) * 2 * ne);
     double *sum = (double *)calloc((size_t)(2 * ne), sizeof(double));
     double *div = (double *)malloc(sizeof(double) * nv);
-    if (!Un || !F || !U0 || !sum || !div) {
-        free(Un); free(F); free(U0); free(sum); free(div);
+    /* with viscosity: Rb = R - V(eta^0, U^0) once, Rm = Rb + V(eta^m, U^m) per substep */
+    double *Rb = vs ? (double *)malloc(sizeof(double) * 2 * ne) : NULL;
+    double *Rm = vs ? (double *)malloc(sizeof(double) * 2 * ne) : NULL;
+    if (!Un || !F || !U0 || !sum || !div || (vs && (!Rb || !Rm))) {
+        free(Un); free(F); free(U0); free(sum); free(div); free(Rb); free(Rm);
         return ORC_ERR_OOM;
     }
     memcpy(U0, U, sizeof(double) * 2 * ne);
+    if (vs) {
+        visc_apply(&m, vs, linear_h, H0, eta, U, Rb);
+        for (int64_t i = 0; i < 2 * ne; ++i) Rb[i] = R[i] - Rb[i];
+    }
     if (volume) volume[0] = volume_of(&m, eta);
     for (int32_t s = 0; s < nsub; ++s) {
+        const double *Rs = R;
+        if (vs) {
+            visc_apply(&m, vs, linear_h, H0, eta, U, Rm);
+            for (int64_t i = 0; i < 2 * ne; ++i) Rm[i] = Rb[i] + Rm[i];
+            Rs = Rm;
+        }
         for (int64_t e = 0; e < ne; ++e) {
             orc_elem q;
             elem_quantities(&m, e, eta, H0, f[e], dts, linear_h, &q);
-            transport_update(&q, g, dts, U + 2 * e, R + 2 * e, Un + 2 * e);
+            transport_update(&q, g, dts, U + 2 * e, Rs + 2 * e, Un + 2 * e);
             F[2 * e] = (1.0 + theta) * Un[2 * e] - theta * U[2 * e];
             F[2 * e + 1] = (1.0 + theta) * Un[2 * e + 1] - theta * U[2 * e + 1];
         }
@@ -344,7 +368,194 @@ int orc_subcycle(int64_t nv, int64_t ne, const int32_t *tri, const double *Ae,
     }
     for (int64_t i = 0; i < 2 * ne; ++i)
         Uavg[i] = sum[i] / (double)nsub + theta / (double)nsub * (U[i] - U0[i]);
-    free(Un); free(F); free(U0); free(sum); free(div);
+    free(Un); free(F); free(U0); free(sum); free(div); free(Rb); free(Rm);
+    return ORC_OK;
+}
+
+int orc_subcycle(int64_t nv, int64_t ne, const int32_t *tri, const double *Ae,
+                 const double *gN, const double *Av, double g, double theta,
+                 int linear_h, const double *H0, const double *f, const double *R,
+                 const double *W, int32_t nsub, double tau, double *eta, double *U,
+                 double *Uavg, double *volume)
+{
+    return subcycle_core(nv, ne, tri, Ae, gN, Av, g, theta, linear_h, H0, f, R, W, nsub, tau,
+                         eta, U, Uavg, volume, NULL);
+}
+
+/* The subcycle with the barotropic viscous regularization of eq. (eq:viscosity_BT)
+ * added to the transport equation, evaluated explicitly at substep m, and its
+ * value at the start of the subcycle subtracted from R (Sec. 2.2, after eq. (eq4_5)). */
+int orc_subcycle_visc(int64_t nv, int64_t ne, const int32_t *tri, const double *Ae,
+                      const double *gN, const double *Av, double g, double theta,
+                      int linear_h, const double *H0, const double *f, const double *R,
+                      const double *W, int32_t nsub, double tau, double *eta, double *U,
+                      double *Uavg, double *volume, const int32_t *nb, const double *elen,
+                      const double *lod, double A0, double Cv)
+{
+    if (!nb || !elen || !lod || !(A0 >= 0.0) || !(Cv >= 0.0)) return ORC_ERR_ARG;
+    orc_visc vs = {nb, elen, lod, A0, Cv};
+    return subcycle_core(nv, ne, tri, Ae, gN, Av, g, theta, linear_h, H0, f, R, W, nsub, tau,
+                         eta, U, Uavg, volume, &vs);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Barotropic viscous regularization, eq. (eq:viscosity_BT):                 */
+/*   R^hV = div(H A grad(U / H))                                             */
+/* integrated over each triangle as a sum of two-point fluxes through its     */
+/* edges shared with another triangle (no viscous flux through coastlines):   */
+/*   V_e = (1/A_e) sum_j H_j A_j (u_n - u_e) l_j / d_j,   u = U / H_e         */
+/* with H_e the triangle mean of H0 + eta (as in the transport update), H_j   */
+/* the mean of H0 + eta at the edge's two vertices, l_j the edge length, d_j  */
+/* the distance between the two centroids, and the coefficient a background   */
+/* value plus a part proportional to the velocity difference across the      */
+/* edge (Sec. 2.2, after eq. (eq:viscosity_BT)): A_j = A0 + Cv l_j |u_n - u_e|. */
+/* Local edge j of triangle (t0, t1, t2) joins t_j and t_{(j+1) mod 3}.       */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t lo, hi;
+    int64_t slot;   /* 3 e + j */
+} orc_edge;
+
+static int cmp_edge(const void *a, const void *b)
+{
+    const orc_edge *p = (const orc_edge *)a, *q = (const orc_edge *)b;
+    if (p->lo != q->lo) return p->lo < q->lo ? -1 : 1;
+    if (p->hi != q->hi) return p->hi < q->hi ? -1 : 1;
+    return p->slot < q->slot ? -1 : (p->slot > q->slot ? 1 : 0);
+}
+
+/* nb[3 e + j] = the other triangle on local edge j of e, or -1 (coast). */
+int orc_edge_neighbours(int64_t ne, const int32_t *tri, int32_t *nb)
+{
+    if (ne <= 0) return ORC_ERR_ARG;
+    orc_edge *ed = (orc_edge *)malloc(sizeof(orc_edge) * 3 * ne);
+    if (!ed) return ORC_ERR_OOM;
+    for (int64_t e = 0; e < ne; ++e)
+        for (int j = 0; j < 3; ++j) {
+            int32_t a = tri[3 * e + j], b = tri[3 * e + (j + 1) % 3];
+            ed[3 * e + j].lo = a < b ? a : b;
+            ed[3 * e + j].hi = a < b ? b : a;
+            ed[3 * e + j].slot = 3 * e + j;
+        }
+    qsort(ed, (size_t)(3 * ne), sizeof(orc_edge), cmp_edge);
+    int status = ORC_OK;
+    for (int64_t i = 0; i < 3 * ne;) {
+        int64_t k = i + 1;
+        while (k < 3 * ne && ed[k].lo == ed[i].lo && ed[k].hi == ed[i].hi) ++k;
+        if (k - i == 1) {
+            nb[ed[i].slot] = -1;
+        } else if (k - i == 2) {
+            nb[ed[i].slot] = (int32_t)(ed[i + 1].slot / 3);
+            nb[ed[i + 1].slot] = (int32_t)(ed[i].slot / 3);
+        } else {
+            status = ORC_ERR_MESH;   /* an edge shared by more than two triangles */
+            for (int64_t t = i; t < k; ++t) nb[ed[t].slot] = -1;
+        }
+        i = k;
+    }
+    free(ed);
+    return status;
+}
+
+/* Vector from vertex p to vertex r in metres: planar differences wrapped across
+ * periodic seams; on the sphere dlon wrapped and scaled by R cos(lat0), dlat by R. */
+static void edge_vec(const double *x, const double *y, uint32_t flags, double px, double py,
+                     double radius, double clat0, int32_t p, int32_t r, double *dx, double *dy)
+{
+    double ax = x[r] - x[p], ay = y[r] - y[p];
+    if (flags & ORC_SPHERICAL) {
+        ax = wrap_half(ax, 2.0 * 3.14159265358979323846);
+        *dx = radius * clat0 * ax;
+        *dy = radius * ay;
+    } else {
+        if (flags & ORC_PERIODIC_X) ax = wrap_half(ax, px);
+        if (flags & ORC_PERIODIC_Y) ay = wrap_half(ay, py);
+        *dx = ax;
+        *dy = ay;
+    }
+}
+
+/* Per local edge: l (length) and l/d (d: centroid distance), zero on coasts.
+ * Both centroids are placed relative to the edge's first vertex p, in the metric
+ * of the edge (on the sphere: cos of the mean latitude of its two vertices). */
+int orc_visc_geometry(int64_t nv, int64_t ne, const double *x, const double *y,
+                      const int32_t *tri, uint32_t flags, double period_x, double period_y,
+                      double radius, const int32_t *nb, double *elen, double *lod)
+{
+    if (nv <= 0 || ne <= 0) return ORC_ERR_ARG;
+    for (int64_t e = 0; e < ne; ++e)
+        for (int j = 0; j < 3; ++j) {
+            int64_t i = 3 * e + j;
+            int32_t n = nb[i];
+            elen[i] = 0.0;
+            lod[i] = 0.0;
+            if (n < 0) continue;
+            int32_t p = tri[3 * e + j], q = tri[3 * e + (j + 1) % 3];
+            double c0 = (flags & ORC_SPHERICAL) ? cos(0.5 * (y[p] + y[q])) : 1.0;
+            double ex, ey;
+            edge_vec(x, y, flags, period_x, period_y, radius, c0, p, q, &ex, &ey);
+            double cex = 0.0, cey = 0.0, cnx = 0.0, cny = 0.0;
+            for (int k = 0; k < 3; ++k) {
+                double dx, dy;
+                edge_vec(x, y, flags, period_x, period_y, radius, c0, p, tri[3 * e + k], &dx, &dy);
+                cex += dx;
+                cey += dy;
+                edge_vec(x, y, flags, period_x, period_y, radius, c0, p, tri[3 * (int64_t)n + k],
+                         &dx, &dy);
+                cnx += dx;
+                cny += dy;
+            }
+            double ddx = (cnx - cex) / 3.0, ddy = (cny - cey) / 3.0;
+            double l = sqrt(ex * ex + ey * ey), d = sqrt(ddx * ddx + ddy * ddy);
+            if (!(d > 0.0)) return ORC_ERR_MESH;
+            elen[i] = l;
+            lod[i] = l / d;
+        }
+    return ORC_OK;
+}
+
+static void visc_apply(const orc_mesh *m, const orc_visc *vs, int linear_h, const double *H0,
+                       const double *eta, const double *U, double *V)
+{
+    for (int64_t e = 0; e < m->ne; ++e) {
+        const int32_t *t = m->tri + 3 * e;
+        double He = linear_h ? (H0[t[0]] + H0[t[1]] + H0[t[2]]) / 3.0
+                             : ((H0[t[0]] + eta[t[0]]) + (H0[t[1]] + eta[t[1]]) +
+                                (H0[t[2]] + eta[t[2]])) / 3.0;
+        double ux = U[2 * e] / He, uy = U[2 * e + 1] / He;
+        double sx = 0.0, sy = 0.0;
+        for (int j = 0; j < 3; ++j) {
+            int32_t n = vs->nb[3 * e + j];
+            if (n < 0) continue;
+            const int32_t *tn = m->tri + 3 * (int64_t)n;
+            double Hn = linear_h ? (H0[tn[0]] + H0[tn[1]] + H0[tn[2]]) / 3.0
+                                 : ((H0[tn[0]] + eta[tn[0]]) + (H0[tn[1]] + eta[tn[1]]) +
+                                    (H0[tn[2]] + eta[tn[2]])) / 3.0;
+            int32_t p = t[j], q = t[(j + 1) % 3];
+            double Hj = linear_h ? 0.5 * (H0[p] + H0[q])
+                                 : 0.5 * ((H0[p] + eta[p]) + (H0[q] + eta[q]));
+            double dux = U[2 * n] / Hn - ux, duy = U[2 * n + 1] / Hn - uy;
+            double A = vs->A0 + vs->Cv * vs->elen[3 * e + j] * sqrt(dux * dux + duy * duy);
+            double c = Hj * A * vs->lod[3 * e + j];
+            sx += c * dux;
+            sy += c * duy;
+        }
+        V[2 * e] = sx / m->Ae[e];
+        V[2 * e + 1] = sy / m->Ae[e];
+    }
+}
+
+/* V [ne][2] = R^hV(eta, U) as defined above (nb, elen, lod from the two
+ * functions above; Ae from orc_geometry). */
+int orc_visc_apply(int64_t nv, int64_t ne, const int32_t *tri, const double *Ae,
+                   const int32_t *nb, const double *elen, const double *lod, double A0,
+                   double Cv, int linear_h, const double *H0, const double *eta, const double *U,
+                   double *V)
+{
+    if (nv <= 0 || ne <= 0 || !(A0 >= 0.0) || !(Cv >= 0.0)) return ORC_ERR_ARG;
+    orc_mesh m = {nv, ne, tri, Ae, NULL, NULL};
+    orc_visc vs = {nb, elen, lod, A0, Cv};
+    visc_apply(&m, &vs, linear_h, H0, eta, U, V);
     return ORC_OK;
 }
 

@@ -255,6 +255,24 @@ def torus(nx: int, ny: int, dx: float, dy: float, *, H=4000.0, f=0.0, tau=60.0,
                  name=f"torus-{nx}x{ny}", eta_ref=0.0)
 
 
+def equilateral_torus(n: int, s: float, *, H=4000.0, tau=60.0, nsub=10):
+    """Doubly periodic mesh of equilateral triangles with side s: n x 2n vertices
+    (rows sheared by half a side each, so that 2n rows close the torus), uniform
+    depth, no rotation or forcing."""
+    nx, ny = n, 2 * n
+    i, j = np.meshgrid(np.arange(nx, dtype=float), np.arange(ny, dtype=float))
+    Px, Py = nx * s, ny * s * np.sqrt(3.0) / 2.0
+    x = np.mod(i * s - j * s / 2.0, Px).ravel()
+    y = (j * s * np.sqrt(3.0) / 2.0).ravel()
+    mesh = dict(x=x, y=y, tri=M.grid_triangles(nx, ny, True, True), periodic_x=True,
+                periodic_y=True, period_x=float(Px), period_y=float(Py), spherical=False,
+                radius=0.0, nx=nx, ny=ny, dx=s, dy=s * np.sqrt(3.0) / 2.0)
+    ne = mesh["tri"].shape[0]
+    return _pack(mesh, np.full(nx * ny, H), np.zeros(ne), np.zeros((ne, 2)), np.zeros(nx * ny),
+                 None, tau=tau, nsub=nsub, nsteps=1, linear_h=True,
+                 name=f"equilateral-torus-{nx}x{ny}", eta_ref=0.0)
+
+
 def random_case(mesh: dict, seed: int = 0, *, H=(500.0, 4000.0), eta_amp=0.5,
                 U_amp=50.0, R_amp=0.05, f=(5e-5, 1.4e-4), tau=24.0, nsub=12,
                 linear_h=False):
