@@ -311,6 +311,60 @@ def bench_trim(args, log, mesh, case, stream, K=40):
                          "bytes_per_call": nbytes}}
 
 
+def bench_visc(args, log, mesh, case, stream, visc=(2.0e3, 0.1)):
+    """Barotropic viscous regularization (eq. (eq:viscosity_BT)) on the lat-lon workload:
+    the plain subcycle carrying it (FP32 and FP64, one viscous evaluation per substep),
+    and the operator alone (FP64).  Compulsory bytes of the operator per triangle: U,
+    the velocity scratch written and read, base and result (16 each), neighbours 16,
+    edge geometry 48, A_e 8, connectivity 12, and per vertex eta and H0 (16, about
+    8 per triangle)."""
+    import torch
+
+    from paper_2311_08241_amd import Params, device_inputs
+    nsub, tau = case["nsub"], case["tau"]
+    out = {"A0": visc[0], "Cv": visc[1]}
+    Uavg = torch.empty((mesh.ne, 2), dtype=torch.float64, device="cuda:0")
+    for label, prec in (("fp32_plain", "f32"), ("fp64_plain", "f64")):
+        p = Params(g=case["g"], theta=case["theta"], precision=prec,
+                   eta_ref=case["eta_ref"] if prec == "f32" else 0.0, visc=visc)
+        d = device_inputs(mesh, case, p)
+        ws = mesh.workspace(p, nsub)
+
+        def step(dd=d, pp=p, w=ws):
+            mesh.subcycle(dd["eta"], dd["U"], R=dd["R"], f=dd["f"], H0=dd["H0"], nsub=nsub,
+                          dt=tau, params=pp, Uavg=Uavg, workspace=w, plain=True)
+        with torch.cuda.stream(stream):
+            step()
+            torch.cuda.synchronize()
+            ms = _time(step, max(2, args.steps // 4), stream)
+        out[label] = {"value": float(mesh.nv) * nsub / (ms * 1e-3), "ms_per_step": ms}
+        log(f"[bench] visc {label}: {out[label]['value']:.3e} vertex-substeps/s ({ms:.2f} ms/step)")
+        if prec == "f64":
+            V = torch.empty_like(d["U"])
+            scratch = torch.empty_like(d["U"])
+
+            def op(dd=d):
+                mesh.visc(dd["eta"], dd["U"], H0=dd["H0"], A0=visc[0], Cv=visc[1], V=V,
+                          workspace=scratch, stream=stream)
+            with torch.cuda.stream(stream):
+                op()
+                torch.cuda.synchronize()
+                ms = _time(op, 20, stream)
+            nbytes = 176.0 * mesh.ne
+            gbs = nbytes / (ms * 1e-3) / 1e9
+            out["operator_fp64"] = {
+                "ms_per_call": ms,
+                "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+                             "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+                             "bytes_per_call": nbytes}}
+            log(f"[bench] visc operator fp64: {ms:.3f} ms, {gbs:.0f} GB/s")
+            del V, scratch
+        del d, ws
+    if mesh.check_faults():
+        raise RuntimeError("kernel fault flags set (viscous subcycle)")
+    return out
+
+
 def bench_forcing(args, log, mesh, case, stream, K=40):
     """Vertically integrated baroclinic forcing (eq. (eq4_4)) on the lat-lon mesh with
     K layers following the bathymetry (FP64 in, FP64 out); HBM-bound, once per
@@ -491,6 +545,7 @@ def main():
         extra["sesm"] = bench_sesm(args, log, mesh, case, stream, not args.no_cpu)
         extra["trim_zstar"] = bench_trim(args, log, mesh, case, stream)
         extra["forcing"] = bench_forcing(args, log, mesh, case, stream)
+        extra["visc"] = bench_visc(args, log, mesh, case, stream)
 
     cpu = None
     errors = None

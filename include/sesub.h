@@ -133,6 +133,13 @@ se_status se_mesh_perm(const se_mesh *mesh, int32_t *vperm, int32_t *eperm);
  * CSR: row_ptr [nv+1], col [3 ne] = (triangle << 2) | local slot, triangles
  * ascending within a row. */
 se_status se_mesh_csr(const se_mesh *mesh, int32_t *tri, int32_t *row_ptr, int32_t *col);
+/* Host copies of the element neighbours of the barotropic viscous term (computed
+ * on the host here; see se_barotropic_visc): nb [ne][3] the triangle across local
+ * edge j = (tri[j], tri[(j+1) mod 3]) or -1 on a coast, edge length l [ne][3] and
+ * l / d [ne][3] (d: distance between the two centroids; 0 on coasts).  Any output
+ * may be NULL.  Errors: SE_ERR_ARG (NULL mesh), SE_ERR_MESH (an edge shared by more
+ * than two triangles). */
+se_status se_mesh_neighbours(const se_mesh *mesh, int32_t *nb, double *l, double *lod);
 /* Host copies of the FP64 geometry: Av [nv] median-dual areas, Ae [ne]
  * triangle areas, gN [ne][3][2] P1 basis gradients. */
 se_status se_mesh_geometry(const se_mesh *mesh, double *Av, double *Ae, double *gN);
@@ -148,6 +155,14 @@ typedef struct {
     int32_t scheme;    /* se_scheme (zero: SE_SCHEME_SE)                            */
     int32_t reserved;  /* must be 0                                                 */
     double beta, delta, gamma, zeta;   /* SE_SCHEME_SESM coefficients, eq. (eq4_7)  */
+    /* Barotropic viscous regularization, eq. (eq:viscosity_BT) (Sec. 2.2): on when
+     * either is > 0 (both finite, >= 0).  Coefficient A = visc_A0 + visc_Cv l |du|
+     * (m^2/s) on an edge of length l with velocity difference du (see
+     * se_barotropic_visc).  The term is evaluated at every substep from (eta^m, U^m)
+     * and its value at the start of the subcycle is subtracted from R.  Only
+     * se_subcycle_plain with SE_SCHEME_SE carries it; se_subcycle, the adjoint and
+     * the batched form return SE_ERR_UNSUPPORTED when it is on. */
+    double visc_A0, visc_Cv;
 } se_params;
 
 /* State, device arrays, updated in place. */
@@ -279,6 +294,27 @@ se_status se_trim_zstar(se_mesh *mesh, int32_t K, const double *H0, const double
                         const double *Uavg, const double *Ustar, const double *hn,
                         const double *h0, const double *W, double tau, double *U, double *hnew,
                         double *w, void *stream);
+
+/* Barotropic viscous term of eq. (eq:viscosity_BT), R^hV = div(H A grad(U / H)),
+ * per triangle e as a sum of two-point fluxes through its edges shared with
+ * another triangle (no viscous flux through coasts):
+ *   V[e] = (1/A_e) sum_j H_j A_j (l_j / d_j) (u_n - u_e),   u = U / H_e
+ *   A_j  = A0 + Cv l_j |u_n - u_e|    (background plus a part proportional to the
+ *                                      velocity difference across the edge)
+ * H_e is the triangle mean of H0 + eta (mean H0 with SE_LINEAR_H), H_j the mean of
+ * H0 + eta at the edge's two vertices, l_j the edge length and d_j the distance
+ * between the centroids of e and its neighbour n.  precision SE_F64 or
+ * SE_F32_MIXED (arrays of that type; eta of F32 holds eta - eta_ref); flags: only
+ * SE_LINEAR_H is read.  Device arrays in mesh numbering: H0, eta [nv]; U, V [ne][2];
+ * ws: scratch of 2 ne elements of the precision's type.  The first viscous call on
+ * a mesh builds and uploads its neighbour tables (synchronously).
+ * FP64 results follow the CPU definition operation for operation.
+ * Errors: SE_ERR_ARG (NULL array, A0 or Cv negative or not finite, bad precision,
+ * host-only mesh), SE_ERR_MESH (an edge shared by more than two triangles),
+ * SE_ERR_OOM, SE_ERR_HIP. */
+se_status se_barotropic_visc(se_mesh *mesh, int32_t precision, uint32_t flags, double eta_ref,
+                             double A0, double Cv, const void *H0, const void *eta,
+                             const void *U, void *V, void *ws, void *stream);
 
 /* Vertically integrated baroclinic forcing of eq. (eq4_4) (Sec. 2.1, end), the
  * R the subcycle takes, per triangle e with nlev[e] layers (layer 0 at the surface):

@@ -39,7 +39,8 @@ class Params(ctypes.Structure):
     _fields_ = [("g", c_double), ("theta", c_double), ("precision", c_int32),
                 ("flags", c_uint32), ("eta_ref", c_double), ("h_max", c_double),
                 ("scheme", c_int32), ("reserved", c_int32), ("beta", c_double),
-                ("delta", c_double), ("gamma", c_double), ("zeta", c_double)]
+                ("delta", c_double), ("gamma", c_double), ("zeta", c_double),
+                ("visc_A0", c_double), ("visc_Cv", c_double)]
 
 
 class State(ctypes.Structure):
@@ -77,6 +78,7 @@ _SIGS = {
     "se_mesh_info": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "se_mesh_perm": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "se_mesh_csr": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
+    "se_mesh_neighbours": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "se_mesh_geometry": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "se_workspace_bytes": (c_int32, [c_void_p, ctypes.POINTER(Params), c_int32, c_int32,
                                      ctypes.POINTER(ctypes.c_size_t)]),
@@ -91,6 +93,8 @@ _SIGS = {
                                       c_void_p, c_void_p, c_void_p, c_void_p]),
     "se_trim_zstar": (c_int32, [c_void_p, c_int32] + [c_void_p] * 7 + [c_double] +
                       [c_void_p] * 4),
+    "se_barotropic_visc": (c_int32, [c_void_p, c_int32, ctypes.c_uint32, c_double, c_double,
+                                     c_double] + [c_void_p] * 6),
     "se_forcing_assemble": (c_int32, [c_void_p, c_int32] + [c_void_p] * 6 + [c_double, c_int32] +
                    [c_void_p] * 2),
     "se_batch_create": (c_int32, [c_void_p, c_int32, ctypes.POINTER(c_void_p)]),

@@ -43,8 +43,9 @@ def sesm_coefficients(theta: float = 0.14, beta: float = 0.281105):
 @dataclass
 class Params:
     """se_params: g, theta (eq. (eq4_10)), precision, flags, eta_ref, h_max, scheme
-    ("se" or "sesm", eqs. (eq4_7)-(eq4_8)) and the SESM coefficients (default: those
-    of sesm_coefficients(theta))."""
+    ("se" or "sesm", eqs. (eq4_7)-(eq4_8)), the SESM coefficients (default: those
+    of sesm_coefficients(theta)) and the barotropic viscous regularization
+    visc = (A0, Cv) of eq. (eq:viscosity_BT) (plain SE path only)."""
     g: float = 9.81
     theta: float = 0.14
     precision: str = "f64"          # "f64" | "f32" (FP32 bulk, FP64 volume and average)
@@ -55,6 +56,7 @@ class Params:
     h_max: float = 0.0
     scheme: str = "se"
     sesm: tuple | None = None       # (beta, delta, gamma, zeta)
+    visc: tuple | None = None       # (A0, Cv): background and flow-dependent coefficients
 
     @property
     def dtype(self):
@@ -75,7 +77,8 @@ class Params:
                         L.SE_F64 if self.precision == "f64" else L.SE_F32_MIXED, flags,
                         self.eta_ref, self.h_max,
                         L.SE_SCHEME_SESM if self.scheme == "sesm" else L.SE_SCHEME_SE, 0,
-                        *[float(v) for v in co])
+                        *[float(v) for v in co],
+                        *([0.0, 0.0] if self.visc is None else [float(v) for v in self.visc]))
 
 
 class Mesh:
@@ -146,6 +149,16 @@ class Mesh:
                                          Ae.ctypes.data_as(ctypes.c_void_p),
                                          gN.ctypes.data_as(ctypes.c_void_p)))
         return Av, Ae, gN
+
+    def neighbours(self):
+        """(nb [ne][3], l [ne][3], l/d [ne][3]) of the barotropic viscous term."""
+        nb = np.empty((self.ne, 3), np.int32)
+        ln = np.empty((self.ne, 3))
+        lod = np.empty((self.ne, 3))
+        L.check(L.lib().se_mesh_neighbours(self._h, nb.ctypes.data_as(ctypes.c_void_p),
+                                           ln.ctypes.data_as(ctypes.c_void_p),
+                                           lod.ctypes.data_as(ctypes.c_void_p)))
+        return nb, ln, lod
 
     # ---- numbering helpers (caller numbering <-> internal) ----
     def v_in(self, a):
@@ -252,6 +265,28 @@ class Mesh:
                                       _ptr(Ustar), _ptr(hn), _ptr(h0), _ptr(W), float(tau),
                                       _ptr(U), _ptr(hnew), _ptr(w), _stream_ptr(stream)))
         return U, hnew, w
+
+    def visc(self, eta, U, *, H0, A0: float, Cv: float, precision: str = "f64",
+             linear_h: bool = False, eta_ref: float = 0.0, V=None, workspace=None, stream=None):
+        """se_barotropic_visc: the barotropic viscous term R^hV(eta, U) of
+        eq. (eq:viscosity_BT) per triangle, [ne][2] in the precision's dtype."""
+        torch = _torch()
+        dt = torch.float64 if precision == "f64" else torch.float32
+        if precision not in ("f64", "f32"):
+            raise ValueError("precision must be 'f64' or 'f32'")
+        self._check_tensor(H0, self.nv, "H0", dt)
+        self._check_tensor(eta, self.nv, "eta", dt)
+        self._check_tensor(U, self.ne, "U", dt, 2)
+        V = torch.empty((self.ne, 2), dtype=dt, device=U.device) if V is None else V
+        self._check_tensor(V, self.ne, "V", dt, 2)
+        ws = torch.empty((self.ne, 2), dtype=dt, device=U.device) if workspace is None \
+            else workspace
+        L.check(L.lib().se_barotropic_visc(self._h, L.SE_F64 if precision == "f64" else
+                                           L.SE_F32_MIXED, L.SE_LINEAR_H if linear_h else 0,
+                                           float(eta_ref), float(A0), float(Cv), _ptr(H0),
+                                           _ptr(eta), _ptr(U), _ptr(V), _ptr(ws),
+                                           _stream_ptr(stream)))
+        return V
 
     def forcing(self, *, K: int, nlev=None, RA=None, RP=None, RhV=None, tau_s=None, u=None,
                 Cd: float = 0.0, precision: str = "f64", R=None, stream=None):

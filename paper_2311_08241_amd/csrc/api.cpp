@@ -254,11 +254,12 @@ se_status make_plan(const std::vector<const HostMesh *> &members, const std::vec
 
 struct Layout {
     size_t eta_alt, U_alt, sum, U0c, phi, vol, total;
+    size_t vub, vRb, vRe;  // viscous term: U / H_e, R - V^0, R - V^0 + V^m
     size_t sv[8], se[7];   // AB3-AM4 only: 8 vertex arrays, 7 triangle (transport) arrays
 };
 
 Layout fwd_layout(int64_t nv, int64_t ne, bool f32, int32_t nsub, int64_t width,
-                  bool sesm = false) {
+                  bool sesm = false, bool visc = false) {
     const size_t s = f32 ? 4 : 8;
     Layout L{};
     size_t o = 0;
@@ -284,6 +285,14 @@ Layout fwd_layout(int64_t nv, int64_t ne, bool f32, int32_t nsub, int64_t width,
     o += al(3 * ne * s);
     L.vol = o;
     o += al(static_cast<size_t>(nsub + 1) * width * 8);
+    if (visc) {
+        L.vub = o;
+        o += al(2 * ne * s);
+        L.vRb = o;
+        o += al(2 * ne * s);
+        L.vRe = o;
+        o += al(2 * ne * s);
+    }
     L.total = o;
     return L;
 }
@@ -366,6 +375,8 @@ bool sesm_stable_upto(double c, double b, double d, double g, double z) {
     return true;
 }
 
+inline bool visc_on(const se_params *p) { return p->visc_A0 > 0.0 || p->visc_Cv > 0.0; }
+
 se_status check_params(const se_mesh *m, const se_params *p, int32_t nsub, double dt) {
     if (!m || !p) {
         set_error("null mesh or params");
@@ -390,6 +401,11 @@ se_status check_params(const se_mesh *m, const se_params *p, int32_t nsub, doubl
     }
     if (p->reserved != 0) {
         set_error("se_params.reserved must be 0");
+        return SE_ERR_ARG;
+    }
+    if (!(p->visc_A0 >= 0.0) || !std::isfinite(p->visc_A0) || !(p->visc_Cv >= 0.0) ||
+        !std::isfinite(p->visc_Cv)) {
+        set_error("visc_A0 and visc_Cv must be finite and >= 0");
         return SE_ERR_ARG;
     }
     const bool sesm = p->scheme == SE_SCHEME_SESM;
@@ -494,6 +510,10 @@ se_status ensure_plan(se_mesh *m) {
 
 using namespace sesub;
 
+static se_status ensure_visc(se_mesh *m);
+static ViscArgs visc_args(const se_mesh *m, bool f32, const se_params *p, const void *H0,
+                          const void *eta, const void *U, void *ubar);
+
 extern "C" {
 
 const char *se_last_error(void) { return g_err.c_str(); }
@@ -581,6 +601,23 @@ se_status se_mesh_csr(const se_mesh *m, int32_t *tri, int32_t *row_ptr, int32_t 
     return SE_OK;
 }
 
+se_status se_mesh_neighbours(const se_mesh *m, int32_t *nb, double *l, double *lod) {
+    if (!m) {
+        set_error("se_mesh_neighbours: null mesh");
+        return SE_ERR_ARG;
+    }
+    std::vector<int32_t> nb4;
+    std::vector<double> vg;
+    SE_TRY(build_visc_tables(m->h, nb4, vg));
+    for (int64_t e = 0; e < m->h.ne; ++e)
+        for (int j = 0; j < 3; ++j) {
+            if (nb) nb[3 * e + j] = nb4[4 * e + j];
+            if (l) l[3 * e + j] = vg[6 * e + 2 * j];
+            if (lod) lod[3 * e + j] = vg[6 * e + 2 * j + 1];
+        }
+    return SE_OK;
+}
+
 se_status se_mesh_geometry(const se_mesh *m, double *Av, double *Ae, double *gN) {
     if (!m) {
         set_error("se_mesh_geometry: null mesh");
@@ -664,7 +701,7 @@ se_status se_workspace_bytes(const se_mesh *m, const se_params *p, int32_t nsub,
     }
     const bool f32 = p->precision == SE_F32_MIXED;
     const Layout L = fwd_layout(m->h.nv, m->h.ne, f32, nsub, vol_width(m->h.nv),
-                                p->scheme == SE_SCHEME_SESM);
+                                p->scheme == SE_SCHEME_SESM, visc_on(p));
     *bytes = L.total;
     if (ckpt_every > 0) {
         const int32_t k = std::min(ckpt_every, nsub);
@@ -688,6 +725,10 @@ static se_status check_state(const se_state *st, const se_forcing *fo, const voi
 se_status se_subcycle(se_mesh *m, const se_params *p, se_state *st, const se_forcing *fo,
                       int32_t nsub, double dt, void *ws, void *stream) {
     SE_TRY(check_params(m, p, nsub, dt));
+    if (visc_on(p)) {
+        set_error("se_subcycle: the barotropic viscous term runs on se_subcycle_plain");
+        return SE_ERR_UNSUPPORTED;
+    }
     SE_TRY(check_state(st, fo, ws));
     SE_TRY(check_device(m));
     DeviceGuard dg(m->device);
@@ -802,9 +843,15 @@ se_status se_subcycle_plain(se_mesh *m, const se_params *p, se_state *st, const 
     DeviceGuard dg(m->device);
     const bool f32 = p->precision == SE_F32_MIXED;
     const bool sesm = p->scheme == SE_SCHEME_SESM;
+    const bool visc = visc_on(p);
+    if (sesm && visc) {
+        set_error("se_subcycle_plain: the viscous term is implemented for SE_SCHEME_SE only");
+        return SE_ERR_UNSUPPORTED;
+    }
+    if (visc) SE_TRY(ensure_visc(m));
     const hipStream_t s = static_cast<hipStream_t>(stream);
     const int64_t nv = m->h.nv, ne = m->h.ne;
-    const Layout L = fwd_layout(nv, ne, f32, nsub, vol_width(nv), sesm);
+    const Layout L = fwd_layout(nv, ne, f32, nsub, vol_width(nv), sesm, visc);
     char *w = static_cast<char *>(ws);
     PlainArgs a{};
     a.nv = nv;
@@ -845,6 +892,22 @@ se_status se_subcycle_plain(se_mesh *m, const se_params *p, se_state *st, const 
         for (int mm = 0; mm < nsub; ++mm) {
             a.m = mm;
             HIP_TRY(launch_sesm_step(f32, a, s), "se_subcycle_plain launch");
+        }
+    } else if (visc) {
+        // R^hV of eq. (eq:viscosity_BT) at every substep, its initial value subtracted
+        ViscArgs va = visc_args(m, f32, p, fo->H0, st->eta, st->U, w + L.vub);
+        va.base = fo->R;
+        va.sign = -1;
+        va.out = w + L.vRb;
+        HIP_TRY(launch_visc(f32, va, s), "se_subcycle_plain viscous term");
+        va.base = w + L.vRb;
+        va.sign = 1;
+        va.out = w + L.vRe;
+        a.R = w + L.vRe;
+        for (int mm = 0; mm < nsub; ++mm) {
+            a.m = mm;
+            HIP_TRY(launch_visc(f32, va, s), "se_subcycle_plain viscous term");
+            HIP_TRY(launch_plain_step(f32, a, s), "se_subcycle_plain launch");
         }
     } else {
         for (int mm = 0; mm < nsub; ++mm) {
@@ -900,6 +963,71 @@ se_status se_trim_zstar(se_mesh *m, int32_t K, const double *H0, const double *e
     a.hnew = hnew;
     a.w = w;
     HIP_TRY(launch_trim(a, static_cast<hipStream_t>(stream)), "se_trim_zstar launch");
+    return SE_OK;
+}
+
+// Neighbour tables of the viscous term, built on first use.
+static se_status ensure_visc(se_mesh *m) {
+    if (m->d.vnb.p) return SE_OK;
+    std::vector<int32_t> nb4;
+    std::vector<double> vg;
+    SE_TRY(build_visc_tables(m->h, nb4, vg));
+    std::vector<float> vg32(vg.begin(), vg.end());
+    SE_TRY(m->d.vgeo64.upload(vg.data(), vg.size() * 8));
+    SE_TRY(m->d.vgeo32.upload(vg32.data(), vg32.size() * 4));
+    SE_TRY(m->d.vnb.upload(nb4.data(), nb4.size() * 4));
+    return SE_OK;
+}
+
+static ViscArgs visc_args(const se_mesh *m, bool f32, const se_params *p, const void *H0,
+                          const void *eta, const void *U, void *ubar) {
+    ViscArgs va{};
+    va.ne = m->h.ne;
+    va.tri = m->d.tri.as<const int32_t>();
+    va.nb = m->d.vnb.as<const int32_t>();
+    va.vgeo = f32 ? m->d.vgeo32.p : m->d.vgeo64.p;
+    va.geom = f32 ? m->d.geom32.p : m->d.geom64.p;
+    va.H0 = H0;
+    va.eta = eta;
+    va.U = U;
+    va.ubar = ubar;
+    va.A0 = p->visc_A0;
+    va.Cv = p->visc_Cv;
+    va.eta_ref = f32 ? p->eta_ref : 0.0;
+    va.linear_h = (p->flags & SE_LINEAR_H) ? 1 : 0;
+    va.sign = 1;
+    return va;
+}
+
+se_status se_barotropic_visc(se_mesh *m, int32_t precision, uint32_t flags, double eta_ref,
+                             double A0, double Cv, const void *H0, const void *eta,
+                             const void *U, void *V, void *ws, void *stream) {
+    if (!m || !H0 || !eta || !U || !V || !ws) {
+        set_error("se_barotropic_visc: null argument");
+        return SE_ERR_ARG;
+    }
+    if (!(A0 >= 0.0) || !std::isfinite(A0) || !(Cv >= 0.0) || !std::isfinite(Cv) ||
+        !std::isfinite(eta_ref)) {
+        set_error("se_barotropic_visc: A0, Cv must be finite and >= 0, eta_ref finite");
+        return SE_ERR_ARG;
+    }
+    if (precision != SE_F64 && precision != SE_F32_MIXED) {
+        set_error("se_barotropic_visc: precision must be SE_F64 or SE_F32_MIXED");
+        return SE_ERR_ARG;
+    }
+    SE_TRY(check_device(m));
+    DeviceGuard dg(m->device);
+    SE_TRY(ensure_visc(m));
+    se_params p{};
+    p.precision = precision;
+    p.flags = flags & SE_LINEAR_H;
+    p.eta_ref = eta_ref;
+    p.visc_A0 = A0;
+    p.visc_Cv = Cv;
+    const bool f32 = precision == SE_F32_MIXED;
+    ViscArgs va = visc_args(m, f32, &p, H0, eta, U, ws);
+    va.out = V;
+    HIP_TRY(launch_visc(f32, va, static_cast<hipStream_t>(stream)), "se_barotropic_visc launch");
     return SE_OK;
 }
 
@@ -967,8 +1095,9 @@ se_status se_subcycle_adjoint(se_mesh *m, const se_params *p, const void *eta0, 
                               void *g_eta0, void *g_U0, void *g_R, void *g_H0, void *ws,
                               void *stream) {
     SE_TRY(check_params(m, p, nsub, dt));
-    if (p->scheme != SE_SCHEME_SE) {
-        set_error("se_subcycle_adjoint: only the forward-backward scheme has an adjoint");
+    if (p->scheme != SE_SCHEME_SE || visc_on(p)) {
+        set_error("se_subcycle_adjoint: only the forward-backward scheme without the viscous "
+                  "term has an adjoint");
         return SE_ERR_UNSUPPORTED;
     }
     if (!eta0 || !U0 || !fo || !fo->R || !fo->f || !fo->H0 || !ws) {
@@ -1285,8 +1414,9 @@ se_status se_subcycle_batched(se_batch *b, const se_params *p, se_state *st, con
         set_error("se_subcycle_batched: null argument");
         return SE_ERR_ARG;
     }
-    if (p->scheme != SE_SCHEME_SE) {
-        set_error("se_subcycle_batched: only the forward-backward scheme is batched");
+    if (p->scheme != SE_SCHEME_SE || visc_on(p)) {
+        set_error("se_subcycle_batched: only the forward-backward scheme without the viscous "
+                  "term is batched");
         return SE_ERR_UNSUPPORTED;
     }
     SE_TRY(check_state(st, fo, ws));

@@ -124,6 +124,24 @@ struct TrimArgs {
 };
 hipError_t launch_trim(const TrimArgs &a, hipStream_t s);
 
+// Barotropic viscous term: V = div(H A grad(U / H)) per triangle (two-point fluxes
+// through edges shared with a neighbour); out = base + sign V (base may be null).
+struct ViscArgs {
+    int64_t ne;
+    const int32_t *tri;
+    const int32_t *nb;          // [ne][4] neighbour across local edge j, -1 on coasts
+    const void *vgeo;           // [ne][3][2] (l, l/d) in the path's precision
+    const void *geom;           // 5 SoA arrays [ne] (A_e is the fifth)
+    const void *H0, *eta, *U;   // eta: FP32 holds eta - eta_ref
+    void *ubar;                 // [ne][2] scratch: U / H_e
+    const void *base;           // [ne][2] or null
+    void *out;                  // [ne][2]
+    double A0, Cv, eta_ref;
+    int32_t linear_h;
+    int32_t sign;               // +1 or -1
+};
+hipError_t launch_visc(bool f32, const ViscArgs &a, hipStream_t s);
+
 struct ForcingArgs {
     int64_t ne;
     int32_t K;

@@ -627,6 +627,96 @@ __global__ void __launch_bounds__(256) k_zstar_w(TrimArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// Barotropic viscous regularization: one thread per triangle.  k_visc_u stores the
+// velocity U / H_e of every triangle; k_visc sums the two-point fluxes
+// H_j A_j (l/d)_j (u_n - u_e) over the triangle's edges shared with a neighbour,
+// A_j = A0 + Cv l_j |u_n - u_e|, H_j the mean depth at the edge's two vertices.
+// Each edge flux is evaluated by both of its triangles with the same operations
+// and opposite sign.  FP64 follows the CPU definition operation for operation.
+// ---------------------------------------------------------------------------
+template <typename T, bool F32>
+__device__ __forceinline__ T visc_He(const ViscArgs &a, const T *H0, const T *eta, int32_t va,
+                                     int32_t vb, int32_t vc) {
+    if constexpr (F32) {
+        const float h = (H0[va] + H0[vb] + H0[vc]) * (1.0f / 3.0f);
+        if (a.linear_h) return h;
+        return h + (static_cast<float>(a.eta_ref) + (eta[va] + eta[vb] + eta[vc]) * (1.0f / 3.0f));
+    } else {
+        if (a.linear_h) return (H0[va] + H0[vb] + H0[vc]) / 3.0;
+        return ((H0[va] + eta[va]) + (H0[vb] + eta[vb]) + (H0[vc] + eta[vc])) / 3.0;
+    }
+}
+
+template <typename T, bool F32>
+__global__ void __launch_bounds__(256) k_visc_u(ViscArgs a) {
+    using T2 = typename Vec2<T>::type;
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= a.ne) return;
+    const T *H0 = static_cast<const T *>(a.H0);
+    const T *eta = static_cast<const T *>(a.eta);
+    const int32_t *t = a.tri + 3 * e;
+    const T He = visc_He<T, F32>(a, H0, eta, t[0], t[1], t[2]);
+    const T2 u = static_cast<const T2 *>(a.U)[e];
+    T2 r;
+    r.x = u.x / He;
+    r.y = u.y / He;
+    static_cast<T2 *>(a.ubar)[e] = r;
+}
+
+template <typename T, bool F32>
+__global__ void __launch_bounds__(256) k_visc(ViscArgs a) {
+    using T2 = typename Vec2<T>::type;
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= a.ne) return;
+    const T *H0 = static_cast<const T *>(a.H0);
+    const T *eta = static_cast<const T *>(a.eta);
+    const T2 *ub = static_cast<const T2 *>(a.ubar);
+    const T *vg = static_cast<const T *>(a.vgeo) + 6 * e;
+    const int4 nb = *reinterpret_cast<const int4 *>(a.nb + 4 * e);
+    const int32_t t[3] = {a.tri[3 * e], a.tri[3 * e + 1], a.tri[3 * e + 2]};
+    const T2 ue = ub[e];
+    const T A0 = static_cast<T>(a.A0), Cv = static_cast<T>(a.Cv);
+    T Hv[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        if constexpr (F32)
+            Hv[k] = a.linear_h ? H0[t[k]] : H0[t[k]] + (eta[t[k]] + static_cast<float>(a.eta_ref));
+        else
+            Hv[k] = a.linear_h ? H0[t[k]] : H0[t[k]] + eta[t[k]];
+    }
+    const int32_t nbs[3] = {nb.x, nb.y, nb.z};
+    T sx = 0, sy = 0;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const int32_t n = nbs[j];
+        if (n < 0) continue;
+        const T2 un = ub[n];
+        const T Hj = static_cast<T>(0.5) * (Hv[j] + Hv[(j + 1) % 3]);
+        const T dux = un.x - ue.x, duy = un.y - ue.y;
+        const T A = A0 + Cv * vg[2 * j] * sqrt(dux * dux + duy * duy);
+        const T c = Hj * A * vg[2 * j + 1];
+        sx += c * dux;
+        sy += c * duy;
+    }
+    const T Ae = static_cast<const T *>(a.geom)[4 * a.ne + e];
+    T vx = sx / Ae, vy = sy / Ae;
+    if (a.base) {
+        const T2 b = static_cast<const T2 *>(a.base)[e];
+        if (a.sign > 0) {
+            vx = b.x + vx;
+            vy = b.y + vy;
+        } else {
+            vx = b.x - vx;
+            vy = b.y - vy;
+        }
+    }
+    T2 r;
+    r.x = vx;
+    r.y = vy;
+    static_cast<T2 *>(a.out)[e] = r;
+}
+
+// ---------------------------------------------------------------------------
 // Vertically integrated baroclinic forcing: eight lanes per triangle column.  Lane
 // j of a group adds the layers k = j, j + 8, ... (each group load is one 128-byte
 // run of (x, y) pairs), the group then combines its eight partial sums by a
@@ -1502,6 +1592,19 @@ hipError_t launch_plain_step(bool f32, const PlainArgs &a, hipStream_t s) {
     } else {
         hipLaunchKernelGGL((k_plain_tri<double, false>), dim3(ge), dim3(256), 0, s, a);
         hipLaunchKernelGGL((k_plain_vtx<double, false>), dim3(gv), dim3(256), 0, s, a);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_visc(bool f32, const ViscArgs &a, hipStream_t s) {
+    if (a.ne <= 0) return hipSuccess;
+    const unsigned g = static_cast<unsigned>((a.ne + 255) / 256);
+    if (f32) {
+        hipLaunchKernelGGL((k_visc_u<float, true>), dim3(g), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((k_visc<float, true>), dim3(g), dim3(256), 0, s, a);
+    } else {
+        hipLaunchKernelGGL((k_visc_u<double, false>), dim3(g), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((k_visc<double, false>), dim3(g), dim3(256), 0, s, a);
     }
     return hipGetLastError();
 }

@@ -258,6 +258,75 @@ se_status build_host_mesh(const se_mesh_desc &d, HostMesh &m) {
 // ---------------------------------------------------------------------------
 // Tiles and their K-ring level sets
 // ---------------------------------------------------------------------------
+// Element neighbours and edge geometry of the barotropic viscous term: for local
+// edge j = (t_j, t_{j+1}) of triangle e, the other triangle through that edge (or
+// -1 on a coast), found by scanning the CSR row of t_j for a triangle that also
+// holds t_{j+1}; the edge length l and l / d, d the distance between the two
+// centroids, both placed relative to t_j in the metric of the edge (on the sphere:
+// cos of the mean latitude of its two vertices).
+se_status build_visc_tables(const HostMesh &m, std::vector<int32_t> &nb4,
+                            std::vector<double> &vg) {
+    const int64_t ne = m.ne;
+    nb4.assign(4 * ne, -1);
+    vg.assign(6 * ne, 0.0);
+    const bool sph = (m.flags & SE_SPHERICAL) != 0;
+    auto rel = [&](int32_t p, int32_t r, double c0, double &dx, double &dy) {
+        double ax = m.x[r] - m.x[p], ay = m.y[r] - m.y[p];
+        if (sph) {
+            ax = wrap_period(ax, 2.0 * M_PI);
+            dx = m.radius * c0 * ax;
+            dy = m.radius * ay;
+        } else {
+            if (m.flags & SE_PERIODIC_X) ax = wrap_period(ax, m.period_x);
+            if (m.flags & SE_PERIODIC_Y) ay = wrap_period(ay, m.period_y);
+            dx = ax;
+            dy = ay;
+        }
+    };
+    for (int64_t e = 0; e < ne; ++e) {
+        for (int j = 0; j < 3; ++j) {
+            const int32_t p = m.tri[3 * e + j], q = m.tri[3 * e + (j + 1) % 3];
+            int32_t nb = -1;
+            for (int32_t i = m.row_ptr[p]; i < m.row_ptr[p + 1]; ++i) {
+                const int32_t t = m.col[i] >> 2;
+                if (t == e) continue;
+                const int32_t *tt = &m.tri[3 * static_cast<int64_t>(t)];
+                if (tt[0] == q || tt[1] == q || tt[2] == q) {
+                    if (nb >= 0) {
+                        set_error("mesh edge shared by more than two triangles");
+                        return SE_ERR_MESH;
+                    }
+                    nb = t;
+                }
+            }
+            nb4[4 * e + j] = nb;
+            if (nb < 0) continue;
+            const double c0 = sph ? std::cos(0.5 * (m.y[p] + m.y[q])) : 1.0;
+            double ex, ey;
+            rel(p, q, c0, ex, ey);
+            double cex = 0.0, cey = 0.0, cnx = 0.0, cny = 0.0;
+            for (int k = 0; k < 3; ++k) {
+                double dx, dy;
+                rel(p, m.tri[3 * e + k], c0, dx, dy);
+                cex += dx;
+                cey += dy;
+                rel(p, m.tri[3 * static_cast<int64_t>(nb) + k], c0, dx, dy);
+                cnx += dx;
+                cny += dy;
+            }
+            const double ddx = (cnx - cex) / 3.0, ddy = (cny - cey) / 3.0;
+            const double l = std::sqrt(ex * ex + ey * ey), d = std::sqrt(ddx * ddx + ddy * ddy);
+            if (!(d > 0.0)) {
+                set_error("coincident centroids of neighbouring triangles");
+                return SE_ERR_MESH;
+            }
+            vg[6 * e + 2 * j] = l;
+            vg[6 * e + 2 * j + 1] = l / d;
+        }
+    }
+    return SE_OK;
+}
+
 namespace {
 
 // Tiles [t0, t1) of member mi appended to `out` (offsets local to `out`).

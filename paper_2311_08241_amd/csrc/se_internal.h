@@ -33,6 +33,11 @@ struct HostMesh {
 // Build the reordered mesh; returns SE_OK or an error with set_error().
 se_status build_host_mesh(const se_mesh_desc &d, HostMesh &m);
 
+// Element neighbours across each local edge (nb4 [ne][4], -1 on coasts, slot 3
+// unused) and per edge (length, length / centroid distance) (vg [ne][6]).
+se_status build_visc_tables(const HostMesh &m, std::vector<int32_t> &nb4,
+                            std::vector<double> &vg);
+
 // ---------------------------------------------------------------------------
 // Tile plan of the temporally blocked kernel (one mesh or a disjoint union).
 // Tile t owns vertices [vbase, vbase + nv0) and the triangles whose smallest
@@ -105,6 +110,9 @@ struct DevMesh {
     DevBuf geom64, geom32;        // 5 SoA arrays [ne]: gbx gby gcx gcy Ae
     DevBuf Av64, Av32;
     DevBuf faults;                // uint32 fault word
+    // barotropic viscous term, built on first use: neighbours int32 [ne][4],
+    // edge (l, l/d) [ne][3][2] in FP64 and FP32
+    DevBuf vnb, vgeo64, vgeo32;
 };
 
 }  // namespace sesub

@@ -49,6 +49,18 @@ def test_reorder_and_geometry_match_oracle_exactly(name, mesh):
     assert np.array_equal(Av, om.Av) and np.array_equal(Ae, om.Ae) and np.array_equal(gN, om.gN)
 
 
+@pytest.mark.parametrize("name,mesh", list(_cases())[:6])
+def test_viscous_neighbours_and_edge_geometry_match_oracle_exactly(name, mesh):
+    """The library finds neighbours through its CSR rows, the oracle by sorting
+    vertex pairs; the edge geometry is the same written definition in both."""
+    m = Mesh.from_dict(mesh, device=-1)
+    nb, ln, lod = m.neighbours()
+    om = oracle.Mesh(mesh, reordered=True)
+    nb2, ln2, lod2 = om.visc_geometry()
+    assert np.array_equal(nb, nb2)
+    assert np.array_equal(ln, ln2) and np.array_equal(lod, lod2)
+
+
 @pytest.mark.parametrize("kind", ["jitter65", "chan54", "torus43", "grid3"])
 def test_mu_max_bounds_the_spectrum(kind):
     mesh = sesynth.tiny_mesh(kind)
