@@ -40,10 +40,15 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+SUBCYCLE_SOURCES = ("kernels.hip", "kernels.h", "device_common.h")
+
+
 def kernel_source_hash():
+    """Hash of the subcycle kernels' sources (the tile kernel and what it includes)."""
     h = hashlib.sha256()
-    with open(os.path.join(ROOT, "paper_2311_08241_amd", "csrc", "kernels.hip"), "rb") as f:
-        h.update(f.read())
+    for name in SUBCYCLE_SOURCES:
+        with open(os.path.join(ROOT, "paper_2311_08241_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
     return h.hexdigest()[:16]
 
 
@@ -58,7 +63,7 @@ def read_traffic(workload_tag, plan):
         if "=" in line and not line.startswith("#"):
             k, v = line.split("=", 1)
             kv[k.strip()] = v.strip()
-    if kv.get("kernels_hip_sha256_16") != kernel_source_hash():
+    if kv.get("subcycle_sources_sha256_16") != kernel_source_hash():
         return None
     if kv.get("plan") != ",".join(str(v) for v in plan):
         return None
@@ -409,6 +414,8 @@ def main():
     ap.add_argument("--small", action="store_true", help="reduced mesh (testing the script)")
     ap.add_argument("--retune", action="store_true",
                     help="time the plan candidates even if a tuned plan is cached or shipped")
+    ap.add_argument("--consumers-only", action="store_true",
+                    help="time only the trim/z*, forcing and viscous-term kernels (profiling)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only; multi-GPU sharding is designed "
@@ -435,6 +442,13 @@ def main():
     t0 = time.time()
     mesh = Mesh.from_dict(case, device=0)
     log(f"[bench] mesh create {time.time() - t0:.1f}s, mu_max={mesh.mu_max:.3e}")
+    if args.consumers_only:
+        stream = torch.cuda.Stream()
+        res = {"trim_zstar": bench_trim(args, log, mesh, case, stream),
+               "forcing": bench_forcing(args, log, mesh, case, stream),
+               "visc": bench_visc(args, log, mesh, case, stream)}
+        print(json.dumps({"consumers": res, "workload": case["name"]}), flush=True)
+        return
     t0 = time.time()
     nsub, tau = case["nsub"], case["tau"]
     prec = args.precision

@@ -6,6 +6,7 @@
 #include <cstring>
 #include <string>
 
+#include "consumers.h"
 #include "kernels.h"
 #include "se_internal.h"
 
