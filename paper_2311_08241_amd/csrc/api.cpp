@@ -963,7 +963,12 @@ se_status se_trim_zstar(se_mesh *m, int32_t K, const double *H0, const double *e
     a.U = U;
     a.hnew = hnew;
     a.w = w;
-    HIP_TRY(launch_trim(a, static_cast<hipStream_t>(stream)), "se_trim_zstar launch");
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    if (!m->d.slotS.p) {
+        SE_TRY(m->d.slotS.alloc(static_cast<size_t>(48) * a.ne));
+        HIP_TRY(launch_slot_vectors(a, m->d.slotS.as<double>(), s), "se_trim_zstar setup");
+    }
+    HIP_TRY(launch_trim(a, m->d.slotS.as<const double>(), s), "se_trim_zstar launch");
     return SE_OK;
 }
 

@@ -19,115 +19,191 @@ namespace {
 // ---------------------------------------------------------------------------
 // Consumer of the averaged transport (FP64): z* target h0 (H / H0), mid thickness
 // on triangles, trim of the layer transports to <<U>>, layer divergences in
-// ascending triangle order, and the diasurface velocity from the bottom up.  One
-// wavefront per triangle / vertex, lane = layer: the sums over layers are wave
-// reductions and the vertical recursion a suffix scan across lanes (so results
-// equal the definition to rounding, not bit for bit); every load and store of
-// layer data is one coalesced wave access.
+// ascending triangle order, and the diasurface velocity from the bottom up.
+//   k_zstar_h       h^{n+1} = h0 (H0 + eta) / H0, one thread per vertex-layer
+//   k_trim          one wavefront per EU consecutive triangles, lane = layer:
+//                   6 x the mid thickness (the common factor cancels in the trim
+//                   weights), layer sums by lane shuffles, trimmed transports
+//   k_zstar_w       one wavefront per vertex, lane = layer: the CSR row's fluxes
+//                   AB triangles at a time (all loads of a batch in flight), then
+//                   w by a suffix scan across lanes
+// Indices a wavefront needs (triangle vertices, CSR columns) are loaded by its
+// lanes in one access and broadcast with readlane, so no scalar-load chain sits
+// between an element and its layer data.  Results equal the definition to rounding
+// (tree sums, reciprocals), not bit for bit.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double zstar_h(const TrimArgs &a, int64_t v, int k) {
-    return a.h0[v * a.K + k] * ((a.H0[v] + a.eta_new[v]) / a.H0[v]);
+// Rotation right by n lanes within each row of 16 (DPP row_ror), on an FP64 value.
+template <int N> __device__ __forceinline__ double row_ror(double v) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(b), 0x120 + N, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(b >> 32), 0x120 + N, 0xf, 0xf,
+                                               false);
+    return __builtin_bit_cast(double, (static_cast<uint64_t>(static_cast<uint32_t>(hi)) << 32) |
+                                          static_cast<uint32_t>(lo));
 }
 
+__device__ __forceinline__ double lane_value(double v, int lane) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = __builtin_amdgcn_readlane(static_cast<int>(b), lane);
+    const uint32_t hi = __builtin_amdgcn_readlane(static_cast<int>(b >> 32), lane);
+    return __builtin_bit_cast(double, (static_cast<uint64_t>(hi) << 32) | lo);
+}
+
+// Sum over the 64 lanes, returned to every lane: rotations within each row of 16,
+// then the four row sums.
 __device__ __forceinline__ double wave_allsum(double v) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    v += row_ror<8>(v);
+    v += row_ror<4>(v);
+    v += row_ror<2>(v);
+    v += row_ror<1>(v);
+    return (lane_value(v, 0) + lane_value(v, 16)) + (lane_value(v, 32) + lane_value(v, 48));
 }
 
-// Each wavefront handles EU elements at a time (independent load chains in flight).
-// Workgroups are dealt round-robin to the XCDs; each owns a contiguous range.
-constexpr int EU = 4;
+__device__ __forceinline__ int32_t bcast(int32_t v, int lane) {
+    return __builtin_amdgcn_readlane(v, lane);
+}
+
+// Sub-cell flux vectors S_{e,k} = -A_e grad N_k of every triangle (three pairs).
+__global__ void __launch_bounds__(256) k_slot_vectors(TrimArgs a, double *S) {
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= a.ne) return;
+    const int64_t ne = a.ne;
+    const double Ae = a.geom[4 * ne + e];
+    const double gbx = a.geom[e], gby = a.geom[ne + e];
+    const double gcx = a.geom[2 * ne + e], gcy = a.geom[3 * ne + e];
+    const double gax = -(gbx + gcx), gay = -(gby + gcy);
+    double *o = S + 6 * e;
+    o[0] = -Ae * gax;
+    o[1] = -Ae * gay;
+    o[2] = -Ae * gbx;
+    o[3] = -Ae * gby;
+    o[4] = -Ae * gcx;
+    o[5] = -Ae * gcy;
+}
+
+__global__ void __launch_bounds__(256) k_zstar_h(TrimArgs a) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= a.nv * a.K) return;
+    const int64_t v = i / a.K;
+    a.hnew[i] = a.h0[i] * ((a.H0[v] + a.eta_new[v]) / a.H0[v]);
+}
+
+// wave-level contiguous range of n elements
+__device__ __forceinline__ void wave_range(int64_t n, int64_t &beg, int64_t &end) {
+    const int64_t nw = static_cast<int64_t>(gridDim.x) * (blockDim.x >> 6);
+    const int64_t gw = static_cast<int64_t>(blockIdx.x) * (blockDim.x >> 6) +
+                       __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+    const int64_t chunk = (n + nw - 1) / nw;
+    beg = gw * chunk;
+    end = min(n, beg + chunk);
+}
+
+constexpr int EU = 8;   // triangles per wavefront iteration of k_trim
 
 __global__ void __launch_bounds__(256) k_trim(TrimArgs a) {
     const int lane = threadIdx.x & 63;
     const int K = a.K, k = lane;
     const bool act = k < K;
-    // each workgroup owns a contiguous range of triangles (its vertices' layer data
-    // then stays in one XCD's L2); its four wavefronts interleave over the range
-    const int64_t chunk = (a.ne + gridDim.x - 1) / gridDim.x;
-    const int64_t beg = static_cast<int64_t>(blockIdx.x) * chunk;
-    const int64_t end = min(a.ne, beg + chunk);
-    const int wv = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
-    for (int64_t e0 = beg + wv; e0 < end; e0 += 4 * EU) {
+    int64_t beg, end;
+    wave_range(a.ne, beg, end);
+    if (beg >= end) return;
+    // triangle indices of an iteration, one per lane (lane 3u + c: vertex c of e0 + u),
+    // loaded one iteration ahead
+    int32_t myt = a.tri[3 * beg + min<int64_t>(lane, 3 * (end - beg) - 1)];
+    for (int64_t e0 = beg; e0 < end; e0 += EU) {
+        const int nu = static_cast<int>(min<int64_t>(EU, end - e0));
         double hh[EU], ux[EU], uy[EU];
 #pragma unroll
         for (int u = 0; u < EU; ++u) {
-            const int64_t e = e0 + u * 4;
+            const int uu = min(u, nu - 1);   // past the range: repeat the last triangle
+            const int64_t ta = bcast(myt, 3 * uu), tb = bcast(myt, 3 * uu + 1),
+                          tc = bcast(myt, 3 * uu + 2);
             hh[u] = 0.0;
             ux[u] = 0.0;
             uy[u] = 0.0;
-            if (act && e < end) {
-                const int32_t *t = a.tri + 3 * e;
-                const double ha = 0.5 * (a.hn[t[0] * (int64_t)K + k] + zstar_h(a, t[0], k));
-                const double hb = 0.5 * (a.hn[t[1] * (int64_t)K + k] + zstar_h(a, t[1], k));
-                const double hc = 0.5 * (a.hn[t[2] * (int64_t)K + k] + zstar_h(a, t[2], k));
-                hh[u] = (ha + hb + hc) / 3.0;
-                ux[u] = a.Ustar[(e * K + k) * 2];
-                uy[u] = a.Ustar[(e * K + k) * 2 + 1];
+            if (act) {
+                hh[u] = ((a.hn[ta * K + k] + a.hnew[ta * K + k]) +
+                         (a.hn[tb * K + k] + a.hnew[tb * K + k])) +
+                        (a.hn[tc * K + k] + a.hnew[tc * K + k]);
+                const double2 us = reinterpret_cast<const double2 *>(a.Ustar)[(e0 + uu) * K + k];
+                ux[u] = us.x;
+                uy[u] = us.y;
             }
         }
+        const int64_t e1 = e0 + EU;
+        if (e1 < end) myt = a.tri[3 * e1 + min<int64_t>(lane, 3 * (end - e1) - 1)];
 #pragma unroll
         for (int u = 0; u < EU; ++u) {
-            const int64_t e = e0 + u * 4;
-            if (e >= end) break;   // wave-uniform
+            if (u >= nu) break;   // wave-uniform
+            const int64_t e = e0 + u;
             const double hs = wave_allsum(hh[u]);
             const double ex = wave_allsum(ux[u]) - a.Uavg[2 * e];
             const double ey = wave_allsum(uy[u]) - a.Uavg[2 * e + 1];
+            const double q = hh[u] * (1.0 / hs);
             if (act) {
-                a.U[(e * K + k) * 2] = ux[u] - hh[u] / hs * ex;
-                a.U[(e * K + k) * 2 + 1] = uy[u] - hh[u] / hs * ey;
+                double2 r;
+                r.x = ux[u] - q * ex;
+                r.y = uy[u] - q * ey;
+                reinterpret_cast<double2 *>(a.U)[e * K + k] = r;
             }
         }
     }
 }
 
-__global__ void __launch_bounds__(256) k_zstar_w(TrimArgs a) {
+constexpr int AB = 8;   // triangles of a CSR row whose loads are issued together
+
+__global__ void __launch_bounds__(256) k_zstar_w(TrimArgs a, const double *S) {
     const int lane = threadIdx.x & 63;
     const int K = a.K, k = lane;
     const bool act = k < K;
-    const int64_t chunk = (a.nv + gridDim.x - 1) / gridDim.x;
-    const int64_t beg = static_cast<int64_t>(blockIdx.x) * chunk;
-    const int64_t end = min(a.nv, beg + chunk);
-    const int wv = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
-    for (int64_t v0 = beg + wv; v0 < end; v0 += 4 * EU) {
-        double t[EU];
-#pragma unroll
-        for (int u = 0; u < EU; ++u) {
-            const int64_t v = v0 + u * 4;
-            t[u] = 0.0;
-            if (act && v < end) {
-                const double hnew = zstar_h(a, v, k);
-                a.hnew[v * K + k] = hnew;
-                double div = 0.0;
-                const int32_t j1 = a.row_ptr[v + 1];
-                for (int32_t j = a.row_ptr[v]; j < j1; ++j) {
-                    const int32_t pcl = a.pcol[j];
-                    const int64_t e = pcl / 3;
-                    const int slot = pcl - 3 * (pcl / 3);
-                    const double Ae = a.geom[4 * a.ne + e];
-                    const double gbx = a.geom[e], gby = a.geom[a.ne + e],
-                                 gcx = a.geom[2 * a.ne + e], gcy = a.geom[3 * a.ne + e];
-                    const double Fx = a.U[(e * K + k) * 2], Fy = a.U[(e * K + k) * 2 + 1];
-                    double pa, pb, pc;
-                    slot_fluxes(Fx, Fy, gbx, gby, gcx, gcy, Ae, pa, pb, pc);
-                    div += slot == 0 ? pa : (slot == 1 ? pb : pc);
-                }
-                t[u] = (hnew - a.hn[v * K + k]) / a.tau + div / a.Av[v] +
-                       (k == 0 && a.W ? a.W[v] : 0.0);
+    const double inv_tau = 1.0 / a.tau;
+    const double2 *S2 = reinterpret_cast<const double2 *>(S);
+    const double2 *U2 = reinterpret_cast<const double2 *>(a.U);
+    int64_t beg, end;
+    wave_range(a.nv, beg, end);
+    for (int64_t vb = beg; vb < end; vb += 63) {
+        // row bounds of up to 63 vertices: lane u holds row_ptr[vb + u]
+        const int nvb = static_cast<int>(min<int64_t>(63, end - vb));
+        const int32_t rp = a.row_ptr[vb + min(lane, nvb)];
+        const int32_t jend = bcast(rp, nvb);
+        // CSR columns, 64 at a time: lane i holds pcol[cbase + i]
+        int32_t cbase = bcast(rp, 0);
+        int32_t pc = a.pcol[min(cbase + lane, jend - 1)];
+        for (int u = 0; u < nvb; ++u) {
+            const int64_t v = vb + u;
+            const int32_t j0 = bcast(rp, u), j1 = bcast(rp, u + 1);
+            if (j1 > cbase + 64) {   // row not in the loaded columns (wave-uniform)
+                cbase = j0;
+                pc = a.pcol[min(cbase + lane, jend - 1)];
             }
-        }
+            const double hnew = act ? a.hnew[v * K + k] : 0.0;
+            const double hn = act ? a.hn[v * K + k] : 0.0;
+            double div = 0.0;
+            for (int32_t j = j0; j < j1; j += AB) {
+                double fl[AB];
 #pragma unroll
-        for (int u = 0; u < EU; ++u) {
-            const int64_t v = v0 + u * 4;
-            if (v >= end) break;   // wave-uniform
+                for (int q = 0; q < AB; ++q) {
+                    // past the row's end: repeat its last triangle (valid loads, not added)
+                    const int32_t pcl = bcast(pc, min(j + q, j1 - 1) - cbase);
+                    const int64_t e = pcl / 3;
+                    const double2 sv = S2[pcl];   // pcl = 3 e + slot
+                    const double2 F = act ? U2[e * K + k] : make_double2(0.0, 0.0);
+                    fl[q] = F.x * sv.x + F.y * sv.y;
+                }
+#pragma unroll
+                for (int q = 0; q < AB; ++q)
+                    if (j + q < j1) div += fl[q];
+            }
+            double t = (hnew - hn) * inv_tau + div * (1.0 / a.Av[v]) +
+                       (k == 0 && a.W ? a.W[v] : 0.0);
+            if (!act) t = 0.0;
             // w[k] = -(t_k + t_{k+1} + ... + t_{K-1}): inclusive suffix scan across lanes
-            double tt = t[u];
             for (int o = 1; o < 64; o <<= 1) {
-                const double x = __shfl_down(tt, o, 64);
-                if (lane + o < 64) tt += x;
+                const double x = __shfl_down(t, o, 64);
+                if (lane + o < 64) t += x;
             }
             double *w = a.w + v * (K + 1);
-            if (act) w[k] = -tt;
+            if (act) w[k] = -t;
             if (lane == 0) w[K] = 0.0;
         }
     }
@@ -311,13 +387,24 @@ hipError_t launch_forcing(const ForcingArgs &a, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_trim(const TrimArgs &a, hipStream_t s) {
-    // wavefronts loop over elements: at most 16 workgroups of 4 wavefronts per CU
-    auto grid = [](int64_t n) {
-        return static_cast<unsigned>(std::min<int64_t>((n + 4 * EU - 1) / (4 * EU), 256 * 16));
+hipError_t launch_slot_vectors(const TrimArgs &a, double *S, hipStream_t s) {
+    if (a.ne <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_slot_vectors, dim3(static_cast<unsigned>((a.ne + 255) / 256)), dim3(256),
+                       0, s, a, S);
+    return hipGetLastError();
+}
+
+hipError_t launch_trim(const TrimArgs &a, const double *S, hipStream_t s) {
+    // wavefronts loop over contiguous ranges: at most 16 workgroups of 4 per CU
+    auto grid = [](int64_t n, int per_wave) {
+        return static_cast<unsigned>(
+            std::min<int64_t>((n + 4 * per_wave - 1) / (4 * per_wave), 256 * 16));
     };
-    if (a.ne > 0) hipLaunchKernelGGL(k_trim, dim3(grid(a.ne)), dim3(256), 0, s, a);
-    if (a.nv > 0) hipLaunchKernelGGL(k_zstar_w, dim3(grid(a.nv)), dim3(256), 0, s, a);
+    if (a.nv > 0)
+        hipLaunchKernelGGL(k_zstar_h, dim3(static_cast<unsigned>((a.nv * a.K + 255) / 256)),
+                           dim3(256), 0, s, a);
+    if (a.ne > 0) hipLaunchKernelGGL(k_trim, dim3(grid(a.ne, EU)), dim3(256), 0, s, a);
+    if (a.nv > 0) hipLaunchKernelGGL(k_zstar_w, dim3(grid(a.nv, 4)), dim3(256), 0, s, a, S);
     return hipGetLastError();
 }
 

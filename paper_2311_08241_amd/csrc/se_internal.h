@@ -113,6 +113,8 @@ struct DevMesh {
     // barotropic viscous term, built on first use: neighbours int32 [ne][4],
     // edge (l, l/d) [ne][3][2] in FP64 and FP32
     DevBuf vnb, vgeo64, vgeo32;
+    // trim/z* consumer, built on first use: sub-cell flux vectors [ne][3][2] FP64
+    DevBuf slotS;
 };
 
 }  // namespace sesub

@@ -211,3 +211,46 @@ def test_nonfinite_sets_fault():
     mesh.subcycle(d["eta"], d["U"], R=d["R"], f=d["f"], H0=d["H0"], nsub=2, dt=4.0, params=params)
     from paper_2311_08241_amd import _lib as L
     assert mesh.check_faults() & L.SE_FAULT_NONFINITE
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_restart_from_saved_state_is_bitwise_identical(precision):
+    """Four chained steps equal two steps, a save of (eta, U) to host memory, a restore
+    into fresh device arrays (and a fresh workspace), and two more steps."""
+    from paper_2311_08241_amd import device_inputs
+    case = _case("C2s")
+    mesh = _lib_mesh(case)
+    p = _params(case, precision)
+    straight = _run_gpu(case, mesh, p, 4)
+    d = device_inputs(mesh, case, p)
+    Uavg = torch.empty((mesh.ne, 2), dtype=torch.float64, device="cuda:0")
+
+    def steps(dd, n):
+        ws = mesh.workspace(p, case["nsub"])
+        for _ in range(n):
+            mesh.subcycle(dd["eta"], dd["U"], R=dd["R"], f=dd["f"], H0=dd["H0"],
+                          nsub=case["nsub"], dt=case["tau"], params=p, Uavg=Uavg, workspace=ws)
+    steps(d, 2)
+    torch.cuda.synchronize()
+    saved = (d["eta"].cpu().numpy().copy(), d["U"].cpu().numpy().copy())
+    d2 = device_inputs(mesh, case, p)
+    d2["eta"].copy_(torch.from_numpy(saved[0]))
+    d2["U"].copy_(torch.from_numpy(saved[1]))
+    steps(d2, 2)
+    torch.cuda.synchronize()
+    eta = d2["eta"].cpu().numpy()
+    if precision == "f32":
+        eta = eta.astype(np.float64) + p.eta_ref
+    assert np.array_equal(mesh.v_out(eta), straight[0])
+    assert np.array_equal(mesh.e_out(d2["U"].cpu().numpy().astype(np.float64)), straight[1])
+    assert np.array_equal(mesh.e_out(Uavg.cpu().numpy()), straight[2])
+
+
+def test_fp32_volume_within_rounding_budget():
+    """FP32 bulk with FP64 volume: |V^m - V^0| <= 10 nsub 2^-24 A_tot max|eta|."""
+    case = _case("C1")
+    mesh = _lib_mesh(case)
+    _, _, _, vol = _run_gpu(case, mesh, _params(case, "f32"), 3)
+    atot = mesh.geometry()[0].sum()
+    nsub = 3 * case["nsub"]
+    assert np.abs(vol - vol[0]).max() <= 10 * nsub * 2.0 ** -24 * atot * np.abs(case["eta0"]).max()
