@@ -20,7 +20,8 @@ namespace {
 // Consumer of the averaged transport (FP64): z* target h0 (H / H0), mid thickness
 // on triangles, trim of the layer transports to <<U>>, layer divergences in
 // ascending triangle order, and the diasurface velocity from the bottom up.
-//   k_zstar_h       h^{n+1} = h0 (H0 + eta) / H0, one thread per vertex-layer
+//   k_zstar_h       h^{n+1} = h0 (H0 + eta) / H0, one thread per vertex-layer; also
+//                   hn + h^{n+1}, parked in w until k_zstar_w overwrites it
 //   k_trim          one wavefront per EU consecutive triangles, lane = layer:
 //                   6 x the mid thickness (the common factor cancels in the trim
 //                   weights), layer sums by lane shuffles, trimmed transports
@@ -81,11 +82,15 @@ __global__ void __launch_bounds__(256) k_slot_vectors(TrimArgs a, double *S) {
     o[5] = -Ae * gcy;
 }
 
+// Also parks hn + hnew of every vertex-layer in w (same [v][k] place, row stride
+// K + 1) for k_trim; k_zstar_w overwrites it with the diasurface velocity.
 __global__ void __launch_bounds__(256) k_zstar_h(TrimArgs a) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= a.nv * a.K) return;
     const int64_t v = i / a.K;
-    a.hnew[i] = a.h0[i] * ((a.H0[v] + a.eta_new[v]) / a.H0[v]);
+    const double h = a.h0[i] * ((a.H0[v] + a.eta_new[v]) / a.H0[v]);
+    a.hnew[i] = h;
+    a.w[i + v] = a.hn[i] + h;
 }
 
 // wave-level contiguous range of n elements
@@ -98,7 +103,7 @@ __device__ __forceinline__ void wave_range(int64_t n, int64_t &beg, int64_t &end
     end = min(n, beg + chunk);
 }
 
-constexpr int EU = 8;   // triangles per wavefront iteration of k_trim
+constexpr int EU = 4;   // triangles per wavefront iteration of k_trim
 
 __global__ void __launch_bounds__(256) k_trim(TrimArgs a) {
     const int lane = threadIdx.x & 63;
@@ -122,9 +127,8 @@ __global__ void __launch_bounds__(256) k_trim(TrimArgs a) {
             ux[u] = 0.0;
             uy[u] = 0.0;
             if (act) {
-                hh[u] = ((a.hn[ta * K + k] + a.hnew[ta * K + k]) +
-                         (a.hn[tb * K + k] + a.hnew[tb * K + k])) +
-                        (a.hn[tc * K + k] + a.hnew[tc * K + k]);
+                const double *hm = a.w;   // hn + hnew, row stride K + 1
+                hh[u] = (hm[ta * (K + 1) + k] + hm[tb * (K + 1) + k]) + hm[tc * (K + 1) + k];
                 const double2 us = reinterpret_cast<const double2 *>(a.Ustar)[(e0 + uu) * K + k];
                 ux[u] = us.x;
                 uy[u] = us.y;
@@ -157,7 +161,9 @@ __global__ void __launch_bounds__(256) k_zstar_w(TrimArgs a, const double *S) {
     const int K = a.K, k = lane;
     const bool act = k < K;
     const double inv_tau = 1.0 / a.tau;
-    const double2 *S2 = reinterpret_cast<const double2 *>(S);
+    // read-only table indexed by wave-uniform values: scalar loads
+    const __attribute__((address_space(4))) double *S4 =
+        (const __attribute__((address_space(4))) double *)(S);
     const double2 *U2 = reinterpret_cast<const double2 *>(a.U);
     int64_t beg, end;
     wave_range(a.nv, beg, end);
@@ -172,23 +178,25 @@ __global__ void __launch_bounds__(256) k_zstar_w(TrimArgs a, const double *S) {
         for (int u = 0; u < nvb; ++u) {
             const int64_t v = vb + u;
             const int32_t j0 = bcast(rp, u), j1 = bcast(rp, u + 1);
-            if (j1 > cbase + 64) {   // row not in the loaded columns (wave-uniform)
-                cbase = j0;
-                pc = a.pcol[min(cbase + lane, jend - 1)];
-            }
             const double hnew = act ? a.hnew[v * K + k] : 0.0;
             const double hn = act ? a.hn[v * K + k] : 0.0;
             double div = 0.0;
             for (int32_t j = j0; j < j1; j += AB) {
+                // this batch's columns j .. min(j + AB, j1) - 1 must lie in the loaded
+                // window [cbase, cbase + 64) (wave-uniform; rows of any length)
+                if (min(j + AB, j1) > cbase + 64) {
+                    cbase = j;
+                    pc = a.pcol[min(cbase + lane, jend - 1)];
+                }
                 double fl[AB];
 #pragma unroll
                 for (int q = 0; q < AB; ++q) {
                     // past the row's end: repeat its last triangle (valid loads, not added)
                     const int32_t pcl = bcast(pc, min(j + q, j1 - 1) - cbase);
                     const int64_t e = pcl / 3;
-                    const double2 sv = S2[pcl];   // pcl = 3 e + slot
+                    const double svx = S4[2 * pcl], svy = S4[2 * pcl + 1];   // pcl = 3 e + slot
                     const double2 F = act ? U2[e * K + k] : make_double2(0.0, 0.0);
-                    fl[q] = F.x * sv.x + F.y * sv.y;
+                    fl[q] = F.x * svx + F.y * svy;
                 }
 #pragma unroll
                 for (int q = 0; q < AB; ++q)
@@ -403,7 +411,10 @@ hipError_t launch_trim(const TrimArgs &a, const double *S, hipStream_t s) {
     if (a.nv > 0)
         hipLaunchKernelGGL(k_zstar_h, dim3(static_cast<unsigned>((a.nv * a.K + 255) / 256)),
                            dim3(256), 0, s, a);
-    if (a.ne > 0) hipLaunchKernelGGL(k_trim, dim3(grid(a.ne, EU)), dim3(256), 0, s, a);
+    if (a.ne > 0)
+        hipLaunchKernelGGL(k_trim, dim3(static_cast<unsigned>(std::min<int64_t>(
+                                        (a.ne + 4 * EU - 1) / (4 * EU), 256 * 64))),
+                           dim3(256), 0, s, a);
     if (a.nv > 0) hipLaunchKernelGGL(k_zstar_w, dim3(grid(a.nv, 4)), dim3(256), 0, s, a, S);
     return hipGetLastError();
 }

@@ -172,6 +172,17 @@ def tiny_mesh(kind: str, seed: int = 0):
         return planar_grid(7, 6, 1500.0, 1300.0, jitter=0.3, r=r)
     if kind == "chan54":
         return planar_grid(5, 4, 1000.0, 900.0, periodic_x=True, jitter=0.3, r=r)
+    if kind == "fan100":
+        # one vertex shared by 100 triangles (a long CSR row), on a jittered disc
+        n = 100
+        ang = 2 * np.pi * (np.arange(n) + 0.3 * r.random(n)) / n
+        rad = 1000.0 * (1.0 + 0.2 * r.random(n))
+        x = np.concatenate([[0.0], rad * np.cos(ang)])
+        y = np.concatenate([[0.0], rad * np.sin(ang)])
+        i = np.arange(1, n + 1)
+        tri = np.stack([np.zeros(n, np.int64), i, i % n + 1], -1).astype(np.int32)
+        return dict(x=x, y=y, tri=tri, periodic_x=False, periodic_y=False, period_x=0.0,
+                    period_y=0.0, spherical=False, radius=0.0, nx=n + 1, ny=1, dx=60.0, dy=60.0)
     if kind == "sphere86":
         m = latlon_grid(8, 6, -60.0, 60.0, radius=1.0e6)
         return m

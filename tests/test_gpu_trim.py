@@ -61,6 +61,19 @@ def test_trim_matches_oracle_small(kind, with_w):
         assert _rel(a, b) <= 1e-12
 
 
+def test_trim_long_csr_row():
+    """A vertex shared by 100 triangles: its CSR row spans more than one window of
+    columns."""
+    from paper_2311_08241_amd import Mesh
+    case = sesynth.random_case(sesynth.tiny_mesh("fan100"), seed=4, nsub=24, tau=4.0)
+    om, inp = _inputs(case, 40, 1, True)
+    mesh = Mesh.from_dict(case, device=0)
+    ref = om.trim_zstar(**inp)
+    out = _gpu(mesh, inp)
+    for a, b in zip(out, ref):
+        assert _rel(a, b) <= 1e-12
+
+
 def test_trim_c2_forty_layers_inplace_and_closure():
     from paper_2311_08241_amd import Mesh
     case = sesynth.channel_c2(nsteps=1)
