@@ -36,6 +36,16 @@ HBM_PEAK_GBS = 8000.0
 B_ALG = {"f32": 236.0, "f64": 356.0}
 
 
+def host_cpu():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -487,6 +497,7 @@ def main():
         raise RuntimeError("kernel fault flags set")
     eta_1 = d["eta"].double().cpu().numpy() + (params.eta_ref if prec == "f32" else 0.0)
     Uavg_1 = Uavg.cpu().numpy()
+    vol_0 = float(vol[0].item())   # volume of the initial state
     log(f"[bench] plan tile,k,block={plan}; first step done ({time.time() - t0:.1f}s)")
 
     for _ in range(args.warmup):
@@ -505,6 +516,11 @@ def main():
         raise RuntimeError("kernel fault flags set")
     vsub = float(mesh.nv) * nsub * args.steps
     value = vsub / (ms * 1e-3)
+    # volume drift over every step run so far (first, warm-up and timed), FP64 accumulator
+    atot = float(mesh.geometry()[0].sum())
+    volume_drift = {"steps": 1 + args.warmup + args.steps,
+                    "rel": abs(float(vol[-1].item()) - vol_0) /
+                    (atot * float(np.abs(case["eta0"]).max()))}
     log(f"[bench] timed {args.steps} steps: {ms:.2f} ms, {value:.3e} vertex-substeps/s")
 
     # roofline of the dominant kernel: the tile kernel runs ceil(nsub/k) launches per step
@@ -576,7 +592,7 @@ def main():
                                             linear_h=False, volume=True)
         tcpu = time.perf_counter() - t0
         cpu = {"value": om.nv * nsub / tcpu, "unit": "vertex-substeps/s", "cores": 1,
-               "kind": "oracle",
+               "kind": "oracle", "host_cpu": host_cpu(), "host_cpus": os.cpu_count(),
                "sample": f"one baroclinic step ({nsub} substeps) of the same mesh, FP64, "
                          f"1 thread, {tcpu:.1f} s"}
         log(f"[bench] oracle: {tcpu:.1f}s, {cpu['value']:.3e} vertex-substeps/s")
@@ -615,7 +631,7 @@ def main():
                                  if prec == "f32" else "FP64"),
                    "plan": {"tile": plan[0], "k_fused": plan[1], "block": plan[2]}},
         "roofline": roofline, "cpu_baseline": cpu, "errors": errors,
-        "hbm_gbs_algorithmic": round(achieved, 1),
+        "volume_drift": volume_drift, "hbm_gbs_algorithmic": round(achieved, 1),
     }
     out.update(extra)
     print(json.dumps(out), flush=True)

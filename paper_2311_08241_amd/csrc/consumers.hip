@@ -154,8 +154,12 @@ __global__ void __launch_bounds__(256) k_trim(TrimArgs a) {
     }
 }
 
-constexpr int AB = 8;   // triangles of a CSR row whose loads are issued together
+// k_zstar_w: VU consecutive vertices per wavefront iteration (their CSR rows inside one
+// 64-column window), AB triangles of each row per batch of loads; other groups take
+// the one-vertex form.
+constexpr int ZW_VU = 2, ZW_AB = 6;
 
+template <int VU, int AB>
 __global__ void __launch_bounds__(256) k_zstar_w(TrimArgs a, const double *S) {
     const int lane = threadIdx.x & 63;
     const int K = a.K, k = lane;
@@ -165,6 +169,27 @@ __global__ void __launch_bounds__(256) k_zstar_w(TrimArgs a, const double *S) {
     const __attribute__((address_space(4))) double *S4 =
         (const __attribute__((address_space(4))) double *)(S);
     const double2 *U2 = reinterpret_cast<const double2 *>(a.U);
+    // flux of the trimmed transport of CSR entry pcl = 3 e + slot through the slot's
+    // sub-cell boundary, layer k
+    auto flux = [&](int32_t pcl) {
+        const int64_t e = pcl / 3;
+        const double svx = S4[2 * pcl], svy = S4[2 * pcl + 1];
+        const double2 F = act ? U2[e * K + k] : make_double2(0.0, 0.0);
+        return F.x * svx + F.y * svy;
+    };
+    // w[k] = -(t_k + t_{k+1} + ... + t_{K-1}): inclusive suffix scan across lanes
+    auto finish = [&](int64_t v, double hnew, double hn, double div) {
+        double t = (hnew - hn) * inv_tau + div * (1.0 / a.Av[v]) +
+                   (k == 0 && a.W ? a.W[v] : 0.0);
+        if (!act) t = 0.0;
+        for (int o = 1; o < 64; o <<= 1) {
+            const double x = __shfl_down(t, o, 64);
+            if (lane + o < 64) t += x;
+        }
+        double *w = a.w + v * (K + 1);
+        if (act) w[k] = -t;
+        if (lane == 0) w[K] = 0.0;
+    };
     int64_t beg, end;
     wave_range(a.nv, beg, end);
     for (int64_t vb = beg; vb < end; vb += 63) {
@@ -172,47 +197,70 @@ __global__ void __launch_bounds__(256) k_zstar_w(TrimArgs a, const double *S) {
         const int nvb = static_cast<int>(min<int64_t>(63, end - vb));
         const int32_t rp = a.row_ptr[vb + min(lane, nvb)];
         const int32_t jend = bcast(rp, nvb);
-        // CSR columns, 64 at a time: lane i holds pcol[cbase + i]
+        // CSR columns, 64 at a time: lane i holds pcol[cbase + i]; cbase only moves
+        // forward, so it never passes the start of a later row
         int32_t cbase = bcast(rp, 0);
         int32_t pc = a.pcol[min(cbase + lane, jend - 1)];
-        for (int u = 0; u < nvb; ++u) {
-            const int64_t v = vb + u;
-            const int32_t j0 = bcast(rp, u), j1 = bcast(rp, u + 1);
-            const double hnew = act ? a.hnew[v * K + k] : 0.0;
-            const double hn = act ? a.hn[v * K + k] : 0.0;
-            double div = 0.0;
-            for (int32_t j = j0; j < j1; j += AB) {
-                // this batch's columns j .. min(j + AB, j1) - 1 must lie in the loaded
-                // window [cbase, cbase + 64) (wave-uniform; rows of any length)
-                if (min(j + AB, j1) > cbase + 64) {
-                    cbase = j;
+        for (int u0 = 0; u0 < nvb; u0 += VU) {
+            const int nu = min(VU, nvb - u0);
+            const int32_t jf = bcast(rp, u0), jl = bcast(rp, u0 + nu);
+            if (nu == VU && jl - jf <= 64) {
+                if (jl > cbase + 64) {
+                    cbase = jf;
                     pc = a.pcol[min(cbase + lane, jend - 1)];
                 }
-                double fl[AB];
+                int32_t j0[VU], len[VU];
+                double hnew[VU], hn[VU], div[VU];
+                int maxlen = 0;
 #pragma unroll
-                for (int q = 0; q < AB; ++q) {
-                    // past the row's end: repeat its last triangle (valid loads, not added)
-                    const int32_t pcl = bcast(pc, min(j + q, j1 - 1) - cbase);
-                    const int64_t e = pcl / 3;
-                    const double svx = S4[2 * pcl], svy = S4[2 * pcl + 1];   // pcl = 3 e + slot
-                    const double2 F = act ? U2[e * K + k] : make_double2(0.0, 0.0);
-                    fl[q] = F.x * svx + F.y * svy;
+                for (int u = 0; u < VU; ++u) {
+                    const int64_t v = vb + u0 + u;
+                    j0[u] = bcast(rp, u0 + u);
+                    len[u] = bcast(rp, u0 + u + 1) - j0[u];   // >= 1: every vertex has a triangle
+                    maxlen = max(maxlen, len[u]);
+                    hnew[u] = act ? a.hnew[v * K + k] : 0.0;
+                    hn[u] = act ? a.hn[v * K + k] : 0.0;
+                    div[u] = 0.0;
+                }
+                for (int off = 0; off < maxlen; off += AB) {
+                    double fl[VU][AB];
+#pragma unroll
+                    for (int u = 0; u < VU; ++u)
+#pragma unroll
+                        for (int q = 0; q < AB; ++q)   // past a row's end: its last entry again
+                            fl[u][q] = flux(bcast(pc, j0[u] + min(off + q, len[u] - 1) - cbase));
+#pragma unroll
+                    for (int u = 0; u < VU; ++u)
+#pragma unroll
+                        for (int q = 0; q < AB; ++q)
+                            if (off + q < len[u]) div[u] += fl[u][q];
                 }
 #pragma unroll
-                for (int q = 0; q < AB; ++q)
-                    if (j + q < j1) div += fl[q];
+                for (int u = 0; u < VU; ++u) finish(vb + u0 + u, hnew[u], hn[u], div[u]);
+                continue;
             }
-            double t = (hnew - hn) * inv_tau + div * (1.0 / a.Av[v]) +
-                       (k == 0 && a.W ? a.W[v] : 0.0);
-            if (!act) t = 0.0;
-            // w[k] = -(t_k + t_{k+1} + ... + t_{K-1}): inclusive suffix scan across lanes
-            for (int o = 1; o < 64; o <<= 1) {
-                const double x = __shfl_down(t, o, 64);
-                if (lane + o < 64) t += x;
+            for (int u = u0; u < u0 + nu; ++u) {
+                const int64_t v = vb + u;
+                const int32_t j0 = bcast(rp, u), j1 = bcast(rp, u + 1);
+                const double hnew = act ? a.hnew[v * K + k] : 0.0;
+                const double hn = act ? a.hn[v * K + k] : 0.0;
+                double div = 0.0;
+                for (int32_t j = j0; j < j1; j += AB) {
+                    // this batch's columns j .. min(j + AB, j1) - 1 inside the window
+                    // [cbase, cbase + 64) (wave-uniform; rows of any length)
+                    if (min(j + AB, j1) > cbase + 64) {
+                        cbase = j;
+                        pc = a.pcol[min(cbase + lane, jend - 1)];
+                    }
+                    double fl[AB];
+#pragma unroll
+                    for (int q = 0; q < AB; ++q) fl[q] = flux(bcast(pc, min(j + q, j1 - 1) - cbase));
+#pragma unroll
+                    for (int q = 0; q < AB; ++q)
+                        if (j + q < j1) div += fl[q];
+                }
+                finish(v, hnew, hn, div);
             }
-            double *w = a.w + v * (K + 1);
-            if (act) w[k] = -t;
-            if (lane == 0) w[K] = 0.0;
         }
     }
 }
@@ -403,11 +451,8 @@ hipError_t launch_slot_vectors(const TrimArgs &a, double *S, hipStream_t s) {
 }
 
 hipError_t launch_trim(const TrimArgs &a, const double *S, hipStream_t s) {
-    // wavefronts loop over contiguous ranges: at most 16 workgroups of 4 per CU
-    auto grid = [](int64_t n, int per_wave) {
-        return static_cast<unsigned>(
-            std::min<int64_t>((n + 4 * per_wave - 1) / (4 * per_wave), 256 * 16));
-    };
+    // wavefronts loop over contiguous ranges; up to 64 workgroups of 4 per CU (more than
+    // fit at once: short ranges balance the tail)
     if (a.nv > 0)
         hipLaunchKernelGGL(k_zstar_h, dim3(static_cast<unsigned>((a.nv * a.K + 255) / 256)),
                            dim3(256), 0, s, a);
@@ -415,7 +460,10 @@ hipError_t launch_trim(const TrimArgs &a, const double *S, hipStream_t s) {
         hipLaunchKernelGGL(k_trim, dim3(static_cast<unsigned>(std::min<int64_t>(
                                         (a.ne + 4 * EU - 1) / (4 * EU), 256 * 64))),
                            dim3(256), 0, s, a);
-    if (a.nv > 0) hipLaunchKernelGGL(k_zstar_w, dim3(grid(a.nv, 4)), dim3(256), 0, s, a, S);
+    if (a.nv > 0)
+        hipLaunchKernelGGL((k_zstar_w<ZW_VU, ZW_AB>),
+                           dim3(static_cast<unsigned>(std::min<int64_t>((a.nv + 63) / 64, 256 * 64))),
+                           dim3(256), 0, s, a, S);
     return hipGetLastError();
 }
 
