@@ -93,10 +93,18 @@ __global__ void __launch_bounds__(256) k_zstar_h(TrimArgs a) {
     a.w[i + v] = a.hn[i] + h;
 }
 
+// Workgroups are dealt round-robin to the 8 XCDs; renumber them so that each XCD owns
+// one contiguous eighth of the ranges (neighbouring elements then share an L2).
+__device__ __forceinline__ int64_t xcd_block() {
+    const int G = gridDim.x, b = blockIdx.x, x = b & 7, q = b >> 3;
+    const int base = G >> 3, rem = G & 7;
+    return static_cast<int64_t>(x) * base + (x < rem ? x : rem) + q;
+}
+
 // wave-level contiguous range of n elements
 __device__ __forceinline__ void wave_range(int64_t n, int64_t &beg, int64_t &end) {
     const int64_t nw = static_cast<int64_t>(gridDim.x) * (blockDim.x >> 6);
-    const int64_t gw = static_cast<int64_t>(blockIdx.x) * (blockDim.x >> 6) +
+    const int64_t gw = xcd_block() * (blockDim.x >> 6) +
                        __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
     const int64_t chunk = (n + nw - 1) / nw;
     beg = gw * chunk;
