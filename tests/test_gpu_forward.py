@@ -76,6 +76,8 @@ def _case(name):
             c = sesynth.random_case(sesynth.tiny_mesh(name), seed=3, nsub=9)
             if name == "sphere86":
                 c["tau"] = 9 * 20.0
+        elif name == "fan100":   # one vertex shared by 100 triangles
+            c = sesynth.random_case(sesynth.tiny_mesh("fan100"), seed=3, nsub=9, tau=1.5)
         elif name == "grid45":
             c = sesynth.random_case(sesynth.planar_grid(45, 37, 1200.0, 1000.0, jitter=0.3,
                                                         r=sesynth.rng(77)), seed=4, nsub=11)
@@ -97,7 +99,7 @@ def _case(name):
 PLANS = [(64, 1, 256), (64, 3, 256), (128, 4, 256), (256, 2, 512), (96, 8, 256)]
 
 
-@pytest.mark.parametrize("name", ["jitter76", "chan54", "sphere86", "torus43", "grid45"])
+@pytest.mark.parametrize("name", ["jitter76", "chan54", "sphere86", "torus43", "grid45", "fan100"])
 @pytest.mark.parametrize("plan", PLANS[:3] + ["plain"])
 def test_fp64_matches_oracle_small(name, plan):
     case = _case(name)
