@@ -159,9 +159,11 @@ typedef struct {
      * either is > 0 (both finite, >= 0).  Coefficient A = visc_A0 + visc_Cv l |du|
      * (m^2/s) on an edge of length l with velocity difference du (see
      * se_barotropic_visc).  The term is evaluated at every substep from (eta^m, U^m)
-     * and its value at the start of the subcycle is subtracted from R.  Only
-     * se_subcycle_plain with SE_SCHEME_SE carries it; se_subcycle, the adjoint and
-     * the batched form return SE_ERR_UNSUPPORTED when it is on. */
+     * and its value at the start of the subcycle is subtracted from R.  SE_SCHEME_SE
+     * only: se_subcycle_plain, and se_subcycle, whose tile plan then runs k_fused / 2
+     * substeps per launch (a neighbour across an edge lies one ring further out; the
+     * plan needs k_fused >= 2); the adjoint, the batched form and SE_SCHEME_SESM return
+     * SE_ERR_UNSUPPORTED when it is on. */
     double visc_A0, visc_Cv;
 } se_params;
 

@@ -200,6 +200,8 @@ se_status make_plan(const std::vector<const HostMesh *> &members, const std::vec
     p->ok_sm32 = st.ok_sesm_f32;
     p->ok_sm64 = st.ok_sesm_f64;
     p->hdr_host = ht.hdr;
+    p->le_gid_host = ht.le_gid;
+    p->nE_host = ht.nE;
     static_assert(sizeof(TileHdr) == sizeof(TileHdrK), "tile header layouts differ");
     SE_TRY(p->hdr.upload(ht.hdr.data(), ht.hdr.size() * sizeof(TileHdr)));
     SE_TRY(p->nV.upload(ht.nV.data(), ht.nV.size() * 4));
@@ -512,6 +514,7 @@ se_status ensure_plan(se_mesh *m) {
 using namespace sesub;
 
 static se_status ensure_visc(se_mesh *m);
+static se_status ensure_tile_visc(se_mesh *m);
 static ViscArgs visc_args(const se_mesh *m, bool f32, const se_params *p, const void *H0,
                           const void *eta, const void *U, void *ubar);
 
@@ -726,8 +729,9 @@ static se_status check_state(const se_state *st, const se_forcing *fo, const voi
 se_status se_subcycle(se_mesh *m, const se_params *p, se_state *st, const se_forcing *fo,
                       int32_t nsub, double dt, void *ws, void *stream) {
     SE_TRY(check_params(m, p, nsub, dt));
-    if (visc_on(p)) {
-        set_error("se_subcycle: the barotropic viscous term runs on se_subcycle_plain");
+    const bool visc = visc_on(p);
+    if (visc && p->scheme != SE_SCHEME_SE) {
+        set_error("se_subcycle: the viscous term is implemented for SE_SCHEME_SE only");
         return SE_ERR_UNSUPPORTED;
     }
     SE_TRY(check_state(st, fo, ws));
@@ -742,10 +746,28 @@ se_status se_subcycle(se_mesh *m, const se_params *p, se_state *st, const se_for
                   "precision and scheme (see se_plan_stats)");
         return SE_ERR_ARG;
     }
+    const size_t es = f32 ? 4 : 8;
+    size_t lds = P.lds(f32, sm);
+    if (visc) {
+        // two rings per substep; the velocities u = U / H_e of the tile's triangles in LDS
+        lds += 2 * es * static_cast<size_t>(P.max_ne);
+        // register budget of the viscous form (no spills): 1024-thread workgroups up to
+        // two triangles per thread, 512-thread ones up to six (FP32) or four (FP64)
+        const bool regs_ok = P.block == 1024 ? P.ept <= 2
+                             : P.block == 512 ? P.ept <= (f32 ? 6 : 4) : true;
+        if (P.K < 2 || lds > 160 * 1024 || !regs_ok) {
+            set_error("se_subcycle: with the viscous term the plan needs k_fused >= 2, " +
+                      std::to_string(lds) + " bytes of LDS within 160 KiB and at most " +
+                      "2 (1024 threads) or 6 / 4 (512 threads, FP32 / FP64) triangles per "
+                      "thread");
+            return SE_ERR_ARG;
+        }
+        SE_TRY(ensure_visc(m));
+        SE_TRY(ensure_tile_visc(m));
+    }
     const hipStream_t s = static_cast<hipStream_t>(stream);
     const int64_t nv = m->h.nv, ne = m->h.ne;
-    const size_t es = f32 ? 4 : 8;
-    const Layout L = fwd_layout(nv, ne, f32, nsub, vol_width(nv), sm);
+    const Layout L = fwd_layout(nv, ne, f32, nsub, vol_width(nv), sm, visc);
     char *w = static_cast<char *>(ws);
     StepC c = make_step(p, nsub, dt);
     c.ntiles = P.ntiles;
@@ -775,6 +797,7 @@ se_status se_subcycle(se_mesh *m, const se_params *p, se_state *st, const se_for
     a.vol_part = reinterpret_cast<double *>(w + L.vol);
     a.faults = m->d.faults.as<uint32_t>();
     a.K = P.K;
+    a.ksub = visc ? P.K / 2 : P.K;
     a.ntiles = P.ntiles;
     a.xcd = 1;
     a.cap_nv = P.max_nv;
@@ -783,9 +806,22 @@ se_status se_subcycle(se_mesh *m, const se_params *p, se_state *st, const se_for
     a.cap_cs = P.max_cs;
     void *eta_u = st->eta, *U_u = st->U;
     void *eta_w = w + L.eta_alt, *U_w = w + L.U_alt;
-    const int nlaunch = (nsub + P.K - 1) / P.K;
-    const size_t lds = P.lds(f32, sm);
-    HIP_TRY(prepare_tile(f32, sm, P.ept, P.block), "se_subcycle prepare");
+    const int nlaunch = (nsub + a.ksub - 1) / a.ksub;
+    const int mode = sm ? 1 : (visc ? 2 : 0);
+    if (visc) {
+        // R - V(eta^0, U^0), read by every launch in place of R
+        ViscArgs va = visc_args(m, f32, p, fo->H0, st->eta, st->U, w + L.vub);
+        va.base = fo->R;
+        va.sign = -1;
+        va.out = w + L.vRb;
+        HIP_TRY(launch_visc(f32, va, s), "se_subcycle viscous term");
+        a.R = w + L.vRb;
+        a.vnb = P.vnb.as<const uint32_t>();
+        a.vgeo = f32 ? P.vgeo32.p : P.vgeo64.p;
+        a.vA0 = p->visc_A0;
+        a.vCv = p->visc_Cv;
+    }
+    HIP_TRY(prepare_tile(f32, mode, P.ept, P.block), "se_subcycle prepare");
     a.eta_u = eta_u;
     a.eta_w = eta_w;
     a.U_u = U_u;
@@ -797,7 +833,7 @@ se_status se_subcycle(se_mesh *m, const se_params *p, se_state *st, const se_for
         }
     for (int ch = 0; ch < nlaunch; ++ch) {
         a.chunk = ch;
-        HIP_TRY(launch_tile(f32, sm, P.ept, P.block, a, P.ntiles, lds, s), "se_subcycle launch");
+        HIP_TRY(launch_tile(f32, mode, P.ept, P.block, a, P.ntiles, lds, s), "se_subcycle launch");
     }
     if (sm) {
         // the last substep's transport update (pending) and the final elevation
@@ -982,6 +1018,47 @@ static se_status ensure_visc(se_mesh *m) {
     SE_TRY(m->d.vgeo64.upload(vg.data(), vg.size() * 8));
     SE_TRY(m->d.vgeo32.upload(vg32.data(), vg32.size() * 4));
     SE_TRY(m->d.vnb.upload(nb4.data(), nb4.size() * 4));
+    return SE_OK;
+}
+
+// Tile-local neighbour tables of the viscous term for the mesh's current plan: for
+// every local triangle, the local index of the triangle across each edge when it
+// belongs to the tile (0xffff otherwise: a coast, or a neighbour beyond the loaded
+// rings, which no updated triangle uses), and the edge geometry.
+static se_status ensure_tile_visc(se_mesh *m) {
+    DevTiles &P = *m->plan;
+    if (P.vnb.p) return SE_OK;
+    std::vector<int32_t> nb4;
+    std::vector<double> vg;
+    SE_TRY(build_visc_tables(m->h, nb4, vg));
+    const int64_t nle = static_cast<int64_t>(P.le_gid_host.size());
+    std::vector<uint32_t> tnb(2 * nle);
+    std::vector<double> tg64(6 * nle);
+    std::vector<float> tg32(6 * nle);
+    std::vector<int32_t> eloc(m->h.ne, -1);
+    for (int32_t t = 0; t < P.ntiles; ++t) {
+        const int64_t off = P.hdr_host[t].le_off;
+        const int32_t n = P.nE_host[static_cast<size_t>(t) * (P.K + 1) + P.K];
+        for (int32_t q = 0; q < n; ++q) eloc[P.le_gid_host[off + q]] = q;
+        for (int32_t q = 0; q < n; ++q) {
+            const int64_t e = P.le_gid_host[off + q];
+            uint32_t l3[3];
+            for (int j = 0; j < 3; ++j) {
+                const int32_t g = nb4[4 * e + j];
+                l3[j] = (g >= 0 && eloc[g] >= 0) ? static_cast<uint32_t>(eloc[g]) : 0xffffu;
+                for (int k = 0; k < 2; ++k) {
+                    tg64[6 * (off + q) + 2 * j + k] = vg[6 * e + 2 * j + k];
+                    tg32[6 * (off + q) + 2 * j + k] = static_cast<float>(vg[6 * e + 2 * j + k]);
+                }
+            }
+            tnb[2 * (off + q)] = l3[0] | (l3[1] << 16);
+            tnb[2 * (off + q) + 1] = l3[2] | (0xffffu << 16);
+        }
+        for (int32_t q = 0; q < n; ++q) eloc[P.le_gid_host[off + q]] = -1;
+    }
+    SE_TRY(P.vgeo64.upload(tg64.data(), tg64.size() * 8));
+    SE_TRY(P.vgeo32.upload(tg32.data(), tg32.size() * 4));
+    SE_TRY(P.vnb.upload(tnb.data(), tnb.size() * 4));
     return SE_OK;
 }
 
@@ -1530,6 +1607,7 @@ se_status se_subcycle_batched(se_batch *b, const se_params *p, se_state *st, con
     a.vol_part = reinterpret_cast<double *>(w + L.vol);
     a.faults = b->faults.as<uint32_t>();
     a.K = K;
+    a.ksub = K;
     a.xcd = 1;
     a.cap_nv = P.max_nv;
     a.cap_ne = P.max_ne;
@@ -1541,7 +1619,7 @@ se_status se_subcycle_batched(se_batch *b, const se_params *p, se_state *st, con
     a.U_w = w + L.U_alt;
     const size_t es = f32 ? 4 : 8;
     const size_t lds = f32 ? P.lds_bytes32 : P.lds_bytes64;
-    HIP_TRY(prepare_tile(f32, false, P.ept, P.block), "batched prepare");
+    HIP_TRY(prepare_tile(f32, 0, P.ept, P.block), "batched prepare");
 
     auto enqueue = [&]() -> se_status {
         for (int32_t c = 0; c < Lmax; ++c) {
@@ -1550,7 +1628,7 @@ se_status se_subcycle_batched(se_batch *b, const se_params *p, se_state *st, con
             a.chunk = c;
             a.tile_list = b->lists.as<const int32_t>() + b->list_off[c];
             a.ntiles = cnt;
-            HIP_TRY(launch_tile(f32, false, P.ept, P.block, a, cnt, lds, s), "batched launch");
+            HIP_TRY(launch_tile(f32, 0, P.ept, P.block, a, cnt, lds, s), "batched launch");
         }
         int64_t vout = 0;
         for (size_t i = 0; i < n; ++i) {

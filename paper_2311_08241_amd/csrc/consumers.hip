@@ -282,19 +282,6 @@ __global__ void __launch_bounds__(256) k_zstar_w(TrimArgs a, const double *S) {
 // and opposite sign.  FP64 follows the CPU definition operation for operation.
 // ---------------------------------------------------------------------------
 template <typename T, bool F32>
-__device__ __forceinline__ T visc_He(const ViscArgs &a, const T *H0, const T *eta, int32_t va,
-                                     int32_t vb, int32_t vc) {
-    if constexpr (F32) {
-        const float h = (H0[va] + H0[vb] + H0[vc]) * (1.0f / 3.0f);
-        if (a.linear_h) return h;
-        return h + (static_cast<float>(a.eta_ref) + (eta[va] + eta[vb] + eta[vc]) * (1.0f / 3.0f));
-    } else {
-        if (a.linear_h) return (H0[va] + H0[vb] + H0[vc]) / 3.0;
-        return ((H0[va] + eta[va]) + (H0[vb] + eta[vb]) + (H0[vc] + eta[vc])) / 3.0;
-    }
-}
-
-template <typename T, bool F32>
 __global__ void __launch_bounds__(256) k_visc_u(ViscArgs a) {
     using T2 = typename Vec2<T>::type;
     const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -302,7 +289,8 @@ __global__ void __launch_bounds__(256) k_visc_u(ViscArgs a) {
     const T *H0 = static_cast<const T *>(a.H0);
     const T *eta = static_cast<const T *>(a.eta);
     const int32_t *t = a.tri + 3 * e;
-    const T He = visc_He<T, F32>(a, H0, eta, t[0], t[1], t[2]);
+    const T He = visc_tri_depth<T, F32>(a.linear_h, static_cast<float>(a.eta_ref), H0[t[0]],
+                                        H0[t[1]], H0[t[2]], eta[t[0]], eta[t[1]], eta[t[2]]);
     const T2 u = static_cast<const T2 *>(a.U)[e];
     T2 r;
     r.x = u.x / He;
@@ -323,14 +311,10 @@ __global__ void __launch_bounds__(256) k_visc(ViscArgs a) {
     const int32_t t[3] = {a.tri[3 * e], a.tri[3 * e + 1], a.tri[3 * e + 2]};
     const T2 ue = ub[e];
     const T A0 = static_cast<T>(a.A0), Cv = static_cast<T>(a.Cv);
+    const float eref = static_cast<float>(a.eta_ref);
     T Hv[3];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        if constexpr (F32)
-            Hv[k] = a.linear_h ? H0[t[k]] : H0[t[k]] + (eta[t[k]] + static_cast<float>(a.eta_ref));
-        else
-            Hv[k] = a.linear_h ? H0[t[k]] : H0[t[k]] + eta[t[k]];
-    }
+    for (int k = 0; k < 3; ++k) Hv[k] = visc_vtx_depth<T, F32>(a.linear_h, eref, H0[t[k]], eta[t[k]]);
     const int32_t nbs[3] = {nb.x, nb.y, nb.z};
     T sx = 0, sy = 0;
 #pragma unroll
@@ -338,12 +322,8 @@ __global__ void __launch_bounds__(256) k_visc(ViscArgs a) {
         const int32_t n = nbs[j];
         if (n < 0) continue;
         const T2 un = ub[n];
-        const T Hj = static_cast<T>(0.5) * (Hv[j] + Hv[(j + 1) % 3]);
-        const T dux = un.x - ue.x, duy = un.y - ue.y;
-        const T A = A0 + Cv * vg[2 * j] * sqrt(dux * dux + duy * duy);
-        const T c = Hj * A * vg[2 * j + 1];
-        sx += c * dux;
-        sy += c * duy;
+        visc_edge<T>(A0, Cv, static_cast<T>(0.5) * (Hv[j] + Hv[(j + 1) % 3]), vg[2 * j],
+                     vg[2 * j + 1], un.x - ue.x, un.y - ue.y, sx, sy);
     }
     const T Ae = static_cast<const T *>(a.geom)[4 * a.ne + e];
     T vx = sx / Ae, vy = sy / Ae;

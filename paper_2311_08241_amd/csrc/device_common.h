@@ -36,5 +36,44 @@ __device__ __forceinline__ void slot_fluxes(double Fx, double Fy, double gbx, do
     pc = Fx * (-Ae * gcx) + Fy * (-Ae * gcy);
 }
 
+
+// Barotropic viscous term (eq. (eq:viscosity_BT)), shared by the plain kernels and the
+// tile kernel so that both evaluate the same operations in the same order.
+// Triangle depth H_e: mean of H0 + eta at its vertices (mean H0 with linear_h); FP32
+// eta holds eta - eta_ref.
+template <typename T, bool F32>
+__device__ __forceinline__ T visc_tri_depth(bool linear_h, float eta_ref, T h0a, T h0b, T h0c,
+                                            T ea, T eb, T ec) {
+    if constexpr (F32) {
+        const float h = (h0a + h0b + h0c) * (1.0f / 3.0f);
+        if (linear_h) return h;
+        return h + (eta_ref + (ea + eb + ec) * (1.0f / 3.0f));
+    } else {
+        if (linear_h) return (h0a + h0b + h0c) / 3.0;
+        return ((h0a + ea) + (h0b + eb) + (h0c + ec)) / 3.0;
+    }
+}
+
+// Depth H0 + eta at a vertex (H0 with linear_h).
+template <typename T, bool F32>
+__device__ __forceinline__ T visc_vtx_depth(bool linear_h, float eta_ref, T h0, T e) {
+    if (linear_h) return h0;
+    if constexpr (F32)
+        return h0 + (e + eta_ref);
+    else
+        return h0 + e;
+}
+
+// Two-point flux through one edge: coefficient A = A0 + Cv l |du|, flux
+// H_j A (l/d) du added to (sx, sy).
+template <typename T>
+__device__ __forceinline__ void visc_edge(T A0, T Cv, T Hj, T l, T lod, T dux, T duy, T &sx,
+                                          T &sy) {
+    const T A = A0 + Cv * l * sqrt(dux * dux + duy * duy);
+    const T c = Hj * A * lod;
+    sx += c * dux;
+    sy += c * duy;
+}
+
 }  // namespace
 }  // namespace sesub

@@ -47,7 +47,13 @@ struct TileArgs {
     uint32_t *faults;
     const int32_t *tile_list;   // tiles of this launch (nullptr: all ntiles)
     int32_t K, chunk, ntiles, xcd;
+    int32_t ksub;               // substeps per launch (K; K / 2 with the viscous term)
     int32_t cap_nv, cap_ne, cap_nvu, cap_cs;
+    // viscous term only: per local triangle the local neighbours across its three
+    // edges (16 bits each, 0xffff: none in the tile) and (l, l/d) of the three edges
+    const uint32_t *vnb;
+    const void *vgeo;
+    double vA0, vCv;
     // AB3-AM4 only: two sets of (eta, eta^{-1}, eta^{-2}, eta_am) and of
     // (U, U^{-1}, U_ab), global numbering; chunk ch writes set ch & 1 and reads
     // set (ch - 1) & 1 (the caller's eta_u / U_u at the member's first chunk)
@@ -90,7 +96,8 @@ struct AdjArgs {
 };
 
 // Host launchers (kernels.hip)
-hipError_t launch_tile(bool f32, bool sm, int ept, int block, const TileArgs &a, int grid,
+// mode: 0 forward-backward, 1 AB3-AM4, 2 forward-backward with the viscous term
+hipError_t launch_tile(bool f32, int mode, int ept, int block, const TileArgs &a, int grid,
                        size_t lds, hipStream_t s);
 hipError_t launch_plain_step(bool f32, const PlainArgs &a, hipStream_t s);
 hipError_t launch_vol_reduce(const double *part, int64_t width, int32_t rows, double add,
@@ -103,7 +110,7 @@ hipError_t launch_adj_init(bool f32, const AdjArgs &a, const void *seed_eta, con
 hipError_t launch_adj_final(bool f32, const AdjArgs &a, hipStream_t s);
 // Raise the dynamic-LDS limit of a tile kernel instantiation (call before any
 // stream capture that launches it).
-hipError_t prepare_tile(bool f32, bool sm, int ept, int block);
+hipError_t prepare_tile(bool f32, int mode, int ept, int block);
 hipError_t launch_sesm_step(bool f32, const PlainArgs &a, hipStream_t s);
 int tile_lds_bytes(bool f32, bool sm, int block, int K, int cap_nv, int cap_ne, int cap_nvu,
                    int cap_cs);

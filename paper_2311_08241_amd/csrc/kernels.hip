@@ -499,8 +499,14 @@ __device__ __forceinline__ int align16(int b) { return (b + 15) & ~15; }
 // (U, U^{-1}, U_ab) at triangles, with the transport update of the last substep
 // still pending (it needs eta_am on a ring the launch does not hold); the next
 // launch, or k_sesm_fin after the last one, applies it.
-template <typename T, bool F32, int EPT, int BLOCK, bool SM>
+// MODE 2: the forward-backward substep with the barotropic viscous term, whose
+// evaluation on a triangle needs its edge neighbours one ring further out: a launch
+// loading K rings runs K / 2 substeps, each with a velocity phase (u = U / H_e of the
+// triangles one ring beyond those updated) before the triangle phase; R holds
+// R - V(eta^0, U^0) and the triangle phase adds V(eta^m, U^m).
+template <typename T, bool F32, int EPT, int BLOCK, int MODE>
 __global__ void __launch_bounds__(BLOCK) k_tile(TileArgs a) {
+    constexpr bool SM = MODE == 1, VI = MODE == 2;
     using T2 = typename Vec2<T>::type;
     constexpr int NW = BLOCK / 64;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -532,20 +538,21 @@ __global__ void __launch_bounds__(BLOCK) k_tile(TileArgs a) {
         }
         __builtin_memcpy(&c, wd, sizeof(StepC));
     }
-    const int K = a.K;
+    const int K = a.K, KS = a.ksub;   // rings per tile, substeps per launch
     const int ch = a.chunk - c.chunk0;   // this member's chunk index
     if (ch < 0) return;
-    const int m0 = ch * K;
+    const int m0 = ch * KS;
     if (m0 >= c.nsub) return;
     const bool even = (ch & 1) == 0;
-    const int cnt = min(K, c.nsub - m0);
+    const int cnt = min(KS, c.nsub - m0);
+    const int rings = VI ? 2 * cnt : cnt;   // rings this launch needs
     const bool first = m0 == 0, last = m0 + cnt == c.nsub;
     const bool track = (c.flags & KF_TRACK_VOLUME) != 0;
     const bool linear_h = (c.flags & KF_LINEAR_H) != 0;
     const bool hasW = a.W != nullptr;
     const int *nV = a.nV + b * (K + 1);   // level counts of the tile (uniform loads)
     const int *nE = a.nE + b * (K + 1);
-    const int nv_load = nV[cnt], ne_load = nE[cnt], nvu = nV[cnt - 1];
+    const int nv_load = nV[rings], ne_load = nE[rings], nvu = nV[rings - 1 - (VI ? 1 : 0)];
     const int tid = threadIdx.x;
 
     // LDS carve-up: the vertex arrays filled by direct-to-LDS loads come first
@@ -574,6 +581,8 @@ __global__ void __launch_bounds__(BLOCK) k_tile(TileArgs a) {
     T *sAcc = reinterpret_cast<T *>(smem + off);   // sub-cell fluxes in local CSR order
     off = align16(off + (int)sizeof(T) * a.cap_cs);
     uint16_t *sRow = reinterpret_cast<uint16_t *>(smem + off);
+    // VI: u = U / H_e per local triangle (after the row offsets)
+    T *sUb = reinterpret_cast<T *>(smem + align16(off + 2 * (a.cap_nvu + 4)));
 
     // ---- load phase in two rounds of independent loads: (A) index and static data
     // (local vertex ids, triangle records, geometry, row offsets, running sums), one
@@ -799,8 +808,10 @@ __global__ void __launch_bounds__(BLOCK) k_tile(TileArgs a) {
                     rk[r] = kk;
                     rf[r] = al;
                 }
-                rRx[r] = dts * rRx[r];
-                rRy[r] = dts * rRy[r];
+                if constexpr (!VI) {   // VI: R + V, scaled at every substep
+                    rRx[r] = dts * rRx[r];
+                    rRy[r] = dts * rRy[r];
+                }
                 g4[r] = -g4[r];
             }
         }
@@ -828,9 +839,27 @@ __global__ void __launch_bounds__(BLOCK) k_tile(TileArgs a) {
     }
     bool dry_any = false, bad_any = false;
     const T gd = cg<T>(c) * dts, th = cth<T>(c);
+    const float eref = F32 ? c.eta_ref_f : 0.0f;
     for (int j = 0; j < cnt; ++j) {
-        const int lev = cnt - j;
+        // levels: triangles updated through ring lev, vertices through lev - 1; VI also
+        // needs the velocities of ring lev + 1
+        const int lev = VI ? 2 * (cnt - j) - 1 : cnt - j;
         const int ne_act = sLev[9 + lev], nv_act = sLev[lev - 1];
+        if constexpr (VI) {
+            const int ne_u = sLev[9 + lev + 1];
+#pragma unroll
+            for (int r = 0; r < EPT; ++r) {
+                const int le = tid + r * BLOCK;
+                if (le < ne_u) {
+                    const int ia = t0[r] & 0xffffu, ib = t0[r] >> 16, ic = t1[r] & 0xffffu;
+                    const T He = visc_tri_depth<T, F32>(linear_h, eref, sH[ia], sH[ib], sH[ic],
+                                                        sEta[ia], sEta[ib], sEta[ic]);
+                    sUb[2 * le] = rUx[r] / He;
+                    sUb[2 * le + 1] = rUy[r] / He;
+                }
+            }
+            __syncthreads();
+        }
 #pragma unroll
         for (int r = 0; r < EPT; ++r) {
             const int le = tid + r * BLOCK;
@@ -885,17 +914,49 @@ __global__ void __launch_bounds__(BLOCK) k_tile(TileArgs a) {
                     continue;
                 }
                 T Unx, Uny, pa, pb, pc;
+                T rx = rRx[r], ry = rRy[r];
+                if constexpr (VI) {
+                    // V(eta^m, U^m): edges to local neighbours (0xffff: coast)
+                    const uint2 nbp = reinterpret_cast<const uint2 *>(a.vnb)[h.le_off + le];
+                    const T *vg = static_cast<const T *>(a.vgeo) + 6 * (int64_t)(h.le_off + le);
+                    const int nbs[3] = {static_cast<int>(nbp.x & 0xffffu),
+                                        static_cast<int>(nbp.x >> 16),
+                                        static_cast<int>(nbp.y & 0xffffu)};
+                    const int iv[3] = {ia, ib, ic};
+                    const T uex = sUb[2 * le], uey = sUb[2 * le + 1];
+                    const T A0 = static_cast<T>(a.vA0), Cv = static_cast<T>(a.vCv);
+                    T Hv[3];
+#pragma unroll
+                    for (int k = 0; k < 3; ++k)
+                        Hv[k] = visc_vtx_depth<T, F32>(linear_h, eref, sH[iv[k]], sEta[iv[k]]);
+                    T sx = 0, sy = 0;
+#pragma unroll
+                    for (int q = 0; q < 3; ++q) {
+                        const int n = nbs[q];
+                        if (n == 0xffff) continue;
+                        visc_edge<T>(A0, Cv, static_cast<T>(0.5) * (Hv[q] + Hv[(q + 1) % 3]),
+                                     vg[2 * q], vg[2 * q + 1], sUb[2 * n] - uex,
+                                     sUb[2 * n + 1] - uey, sx, sy);
+                    }
+                    const T Ae = F32 ? -g4[r] : g4[r];
+                    rx = rRx[r] + sx / Ae;
+                    ry = rRy[r] + sy / Ae;
+                    if constexpr (F32) {
+                        rx = dts * rx;
+                        ry = dts * ry;
+                    }
+                }
                 if constexpr (F32) {
                     bool dry;
                     tri_update_f32(sEta[ia], sEta[ib], sEta[ic], rH[r], g0[r], g1[r], g2[r],
-                                   g3[r], g4[r], rUx[r], rUy[r], rRx[r], rRy[r], rf[r], rk[r],
+                                   g3[r], g4[r], rUx[r], rUy[r], rx, ry, rf[r], rk[r],
                                    gd, th, linear_h, Unx, Uny, pa, pb, pc, dry);
                     dry_any |= dry;
                 } else {
                     bool dry;
                     tri_update<T, F32>(sEta[ia], sEta[ib], sEta[ic], sH[ia], sH[ib], sH[ic],
                                        g0[r], g1[r], g2[r], g3[r], g4[r], rUx[r], rUy[r],
-                                       rRx[r], rRy[r], rf[r], c, linear_h, Unx, Uny, pa, pb,
+                                       rx, ry, rf[r], c, linear_h, Unx, Uny, pa, pb,
                                        pc, dry);
                     dry_any |= dry;
                 }
@@ -1200,7 +1261,7 @@ __global__ void __launch_bounds__(256) k_vol_reduce(const double *part, int64_t 
     if (threadIdx.x == 0) out[r] = add + ((red[0] + red[1]) + (red[2] + red[3]));
 }
 
-template <typename T, bool F32, int EPT, int BLOCK, bool SM>
+template <typename T, bool F32, int EPT, int BLOCK, int SM>
 hipError_t launch_tile_t(const TileArgs *a, int grid, size_t lds, hipStream_t s) {
     auto *kern = k_tile<T, F32, EPT, BLOCK, SM>;
     if (!a)   // prepare only
@@ -1210,7 +1271,7 @@ hipError_t launch_tile_t(const TileArgs *a, int grid, size_t lds, hipStream_t s)
     return hipGetLastError();
 }
 
-template <typename T, bool F32, int BLOCK, bool SM>
+template <typename T, bool F32, int BLOCK, int SM>
 hipError_t launch_tile_ept(int ept, const TileArgs *a, int grid, size_t lds, hipStream_t s) {
     switch (ept) {
         case 1: return launch_tile_t<T, F32, 1, BLOCK, SM>(a, grid, lds, s);
@@ -1225,7 +1286,7 @@ hipError_t launch_tile_ept(int ept, const TileArgs *a, int grid, size_t lds, hip
 
 // 1024-thread workgroups must fit 128 VGPRs: FP32 up to 4 triangles per thread,
 // FP64 one.
-template <typename T, bool F32, bool SM>
+template <typename T, bool F32, int SM>
 hipError_t launch_tile_1024(int ept, const TileArgs *a, int grid, size_t lds, hipStream_t s) {
     if constexpr (F32) {
         switch (ept) {
@@ -1240,7 +1301,7 @@ hipError_t launch_tile_1024(int ept, const TileArgs *a, int grid, size_t lds, hi
     }
 }
 
-template <bool SM>
+template <int SM>
 hipError_t launch_tile_sm(bool f32, int ept, int block, const TileArgs *a, int grid, size_t lds,
                           hipStream_t s) {
     if (block == 1024)
@@ -1255,10 +1316,14 @@ hipError_t launch_tile_sm(bool f32, int ept, int block, const TileArgs *a, int g
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_tile_any(bool f32, bool sm, int ept, int block, const TileArgs *a, int grid,
+hipError_t launch_tile_any(bool f32, int mode, int ept, int block, const TileArgs *a, int grid,
                            size_t lds, hipStream_t s) {
-    return sm ? launch_tile_sm<true>(f32, ept, block, a, grid, lds, s)
-              : launch_tile_sm<false>(f32, ept, block, a, grid, lds, s);
+    switch (mode) {
+        case 0: return launch_tile_sm<0>(f32, ept, block, a, grid, lds, s);
+        case 1: return launch_tile_sm<1>(f32, ept, block, a, grid, lds, s);
+        case 2: return launch_tile_sm<2>(f32, ept, block, a, grid, lds, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace
@@ -1283,13 +1348,13 @@ int tile_lds_bytes(bool f32, bool sm, int block, int K, int cap_nv, int cap_ne, 
     return off;
 }
 
-hipError_t prepare_tile(bool f32, bool sm, int ept, int block) {
-    return launch_tile_any(f32, sm, ept, block, nullptr, 0, 0, nullptr);
+hipError_t prepare_tile(bool f32, int mode, int ept, int block) {
+    return launch_tile_any(f32, mode, ept, block, nullptr, 0, 0, nullptr);
 }
 
-hipError_t launch_tile(bool f32, bool sm, int ept, int block, const TileArgs &a, int grid,
+hipError_t launch_tile(bool f32, int mode, int ept, int block, const TileArgs &a, int grid,
                        size_t lds, hipStream_t s) {
-    return launch_tile_any(f32, sm, ept, block, &a, grid, lds, s);
+    return launch_tile_any(f32, mode, ept, block, &a, grid, lds, s);
 }
 
 hipError_t launch_plain_step(bool f32, const PlainArgs &a, hipStream_t s) {

@@ -101,6 +101,12 @@ struct DevTiles {
     DevBuf hdr, nV, nE, lv_gid, le_rec, cs_row;
     DevBuf geo64, geo32, ae64, ae32;   // per local triangle: 4 gradient values; A_e
     DevBuf lav64, lav32;          // per local vertex: A_v (FP64), 1 / A_v (FP32)
+    // host copies for tables built on first use: global id of each local triangle,
+    // level counts [ntiles][K+1]
+    std::vector<int32_t> le_gid_host, nE_host;
+    // viscous term, built on first use: local edge neighbours (uint2 per local
+    // triangle) and edge (l, l/d) [3][2] per local triangle
+    DevBuf vnb, vgeo64, vgeo32;
 };
 
 // Mesh geometry and connectivity on the device (global numbering).

@@ -150,18 +150,96 @@ def test_viscous_term_is_refused_where_not_implemented():
     p = _params(c, "f64", (100.0, 0.1))
     d = device_inputs(mesh, c, p)
     ws = mesh.workspace(p, c["nsub"])
+    # the tile form needs two rings per substep
+    mesh.set_plan(64, 1, 256)
     with pytest.raises(L.SeError) as ei:
         mesh.subcycle(d["eta"], d["U"], R=d["R"], f=d["f"], H0=d["H0"], nsub=c["nsub"],
                       dt=c["tau"], params=p, workspace=ws, plain=False)
-    assert ei.value.status == L.SE_ERR_UNSUPPORTED
+    assert ei.value.status == L.SE_ERR_ARG
     ps = Params(g=c["g"], theta=c["theta"], scheme="sesm", visc=(100.0, 0.1))
-    with pytest.raises(L.SeError) as ei:
-        mesh.subcycle(d["eta"], d["U"], R=d["R"], f=d["f"], H0=d["H0"], nsub=c["nsub"],
-                      dt=c["tau"], params=ps, workspace=mesh.workspace(ps, c["nsub"]), plain=True)
-    assert ei.value.status == L.SE_ERR_UNSUPPORTED
+    for plain in (True, False):
+        with pytest.raises(L.SeError) as ei:
+            mesh.subcycle(d["eta"], d["U"], R=d["R"], f=d["f"], H0=d["H0"], nsub=c["nsub"],
+                          dt=c["tau"], params=ps, workspace=mesh.workspace(ps, c["nsub"]),
+                          plain=plain)
+        assert ei.value.status == L.SE_ERR_UNSUPPORTED
     bad = _params(c, "f64", (-1.0, 0.0))
     with pytest.raises(L.SeError) as ei:
         mesh.subcycle(d["eta"], d["U"], R=d["R"], f=d["f"], H0=d["H0"], nsub=c["nsub"],
                       dt=c["tau"], params=bad, workspace=ws, plain=True)
     assert ei.value.status == L.SE_ERR_ARG
     torch.cuda.synchronize()
+
+
+# tile plans with at least two rings: (64, 3) and (256, 2) run one viscous substep per
+# launch, (128, 4) two, (96, 8) four
+VPLANS = [(64, 3, 256), (128, 4, 256), (256, 2, 512), (96, 8, 256)]
+
+
+def _run_tile(case, mesh, p, nsteps, plan, W=None):
+    mesh.set_plan(*plan)
+    from paper_2311_08241_amd import device_inputs
+    d = device_inputs(mesh, case, p)
+    Wd = None if W is None else torch.tensor(mesh.v_in(W), dtype=p.dtype, device="cuda:0")
+    Uavg = torch.empty((mesh.ne, 2), dtype=torch.float64, device="cuda:0")
+    ws = mesh.workspace(p, case["nsub"])
+    vols = []
+    for _ in range(nsteps):
+        vol = torch.empty(case["nsub"] + 1, dtype=torch.float64, device="cuda:0")
+        mesh.subcycle(d["eta"], d["U"], R=d["R"], f=d["f"], H0=d["H0"], W=Wd, nsub=case["nsub"],
+                      dt=case["tau"], params=p, Uavg=Uavg, volume=vol, workspace=ws, plain=False)
+        vols.append(vol)
+    torch.cuda.synchronize()
+    assert mesh.check_faults() == 0
+    eta = d["eta"].cpu().numpy().astype(np.float64)
+    if p.precision == "f32":
+        eta = eta + p.eta_ref
+    vol = torch.cat([vols[0]] + [v[1:] for v in vols[1:]]).cpu().numpy()
+    return (mesh.v_out(eta), mesh.e_out(d["U"].cpu().numpy().astype(np.float64)),
+            mesh.e_out(Uavg.cpu().numpy()), vol)
+
+
+@pytest.mark.parametrize("name", KINDS + ["C1", "C2s", "C3s"])
+def test_viscous_tile_fp64_matches_oracle(name):
+    from paper_2311_08241_amd import Mesh
+    case, visc = _case(name)
+    W = 1e-5 * sesynth.rng(5).standard_normal(case["x"].size) if name == "jitter76" else None
+    mesh = Mesh.from_dict(case, device=0)
+    ref = _run_oracle(case, 2, visc, W=W)
+    for pl in VPLANS:
+        if not mesh.plan_stats(*pl)["ok_f64"]:
+            continue
+        out = _run_tile(case, mesh, _params(case, "f64", visc), 2, pl, W=W)
+        for a, b in zip(out[:3], ref[:3]):
+            assert _rel(a, b) <= 1e-12, pl
+        assert np.abs(out[3] - ref[3]).max() <= 1e-12 * np.abs(ref[3]).max(), pl
+
+
+def test_viscous_tile_fp32_identical_to_plain():
+    from paper_2311_08241_amd import Mesh
+    case, visc = _case("C2s")
+    mesh = Mesh.from_dict(case, device=0)
+    p = _params(case, "f32", visc)
+    ref = _run_gpu(case, mesh, p, 2)
+    for pl in VPLANS:
+        if not mesh.plan_stats(*pl)["ok_f32"]:
+            continue
+        out = _run_tile(case, mesh, p, 2, pl)
+        for a, b in zip(out[:3], ref[:3]):
+            assert np.array_equal(a, b), pl
+
+
+@pytest.mark.parametrize("nsub", [1, 3, 5])
+def test_viscous_tile_partial_chunks(nsub):
+    """nsub below, at and not divisible by the substeps per launch."""
+    from paper_2311_08241_amd import Mesh
+    case, visc = _case("jitter76")
+    case = dict(case)
+    case["tau"] = case["tau"] / case["nsub"] * nsub
+    case["nsub"] = nsub
+    mesh = Mesh.from_dict(case, device=0)
+    ref = _run_oracle(case, 1, visc)
+    for pl in VPLANS:
+        out = _run_tile(case, mesh, _params(case, "f64", visc), 1, pl)
+        for a, b in zip(out[:3], ref[:3]):
+            assert _rel(a, b) <= 1e-12, (pl, nsub)
