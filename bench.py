@@ -380,7 +380,7 @@ def bench_visc(args, log, mesh, case, stream, visc=(2.0e3, 0.1)):
             ms = _time(step, max(2, args.steps // 4), stream)
         out[label] = {"value": float(mesh.nv) * nsub / (ms * 1e-3), "ms_per_step": ms}
         log(f"[bench] visc {label}: {out[label]['value']:.3e} vertex-substeps/s ({ms:.2f} ms/step)")
-        if prec == "f64":
+        if label == "fp64_plain":
             V = torch.empty_like(d["U"])
             scratch = torch.empty_like(d["U"])
 
