@@ -326,22 +326,18 @@ def bench_trim(args, log, mesh, case, stream, K=40):
                          "bytes_per_call": nbytes}}
 
 
-VISC_PLANS = [(448, 4, 512), (256, 4, 256), (384, 4, 256), (448, 4, 256), (320, 6, 256),
-              (512, 6, 256), (256, 8, 256), (384, 8, 256), (192, 8, 256), (512, 8, 512)]
-
-
 def bench_visc(args, log, mesh, case, stream, visc=(2.0e3, 0.1)):
     """Barotropic viscous regularization (eq. (eq:viscosity_BT)) on the lat-lon workload:
-    the subcycle carrying it on the tile kernel (two rings per substep, plan from a short
-    sweep) and on the plain path (FP32 and FP64, one viscous evaluation per substep),
+    the subcycle carrying it on the tile kernel (two rings per substep, plan from the
+    autotuner) and on the plain path (FP32 and FP64, one viscous evaluation per substep),
     and the operator alone (FP64).  Compulsory bytes of the operator per triangle: U,
     the velocity scratch written and read, base and result (16 each), neighbours 16,
     edge geometry 48, A_e 8, connectivity 12, and per vertex eta and H0 (16, about
     8 per triangle)."""
     import torch
 
-    import paper_2311_08241_amd._lib as L
     from paper_2311_08241_amd import Params, device_inputs
+    from paper_2311_08241_amd.autotune import autotune
     nsub, tau = case["nsub"], case["tau"]
     out = {"A0": visc[0], "Cv": visc[1]}
     Uavg = torch.empty((mesh.ne, 2), dtype=torch.float64, device="cuda:0")
@@ -357,24 +353,10 @@ def bench_visc(args, log, mesh, case, stream, visc=(2.0e3, 0.1)):
                           dt=tau, params=pp, Uavg=Uavg, workspace=w, plain=pl)
         with torch.cuda.stream(stream):
             if not plain:
-                # tile plans for two rings per substep: a short sweep (register budget
-                # and occupancy differ from the forward-backward kernel's)
-                best = None
-                for pl in VISC_PLANS:
-                    if not mesh.plan_stats(*pl)["ok_" + prec]:
-                        continue
-                    mesh.set_plan(*pl)
-                    try:
-                        step()
-                    except L.SeError:   # plan outside the viscous register/LDS budget
-                        continue
-                    torch.cuda.synchronize()
-                    t = _time(step, 2, stream)
-                    log(f"[bench] visc {label} plan {pl}: {t:.2f} ms/step")
-                    if best is None or t < best[0]:
-                        best = (t, pl)
-                mesh.set_plan(*best[1])
-                out[label + "_plan"] = list(best[1])
+                # plans for two rings per substep (the autotuner's viscous model)
+                t = autotune(mesh, step, prec + "-visc", nsub, top=12, reps=2, final=2,
+                             final_reps=4, log=log, use_cache=not args.retune)
+                out[label + "_plan"] = list(t["plan"])
             step()
             torch.cuda.synchronize()
             ms = _time(step, max(2, args.steps // 4), stream)

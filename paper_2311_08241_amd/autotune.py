@@ -18,6 +18,7 @@ import numpy as np
 
 TILES = (256, 320, 384, 448, 512, 576, 640, 768, 1024)
 KS = (2, 3, 4, 5, 6)
+VISC_KS = (2, 4, 6, 8)
 BLOCKS = (256, 512, 1024)
 EPT_TIERS = (1, 2, 3, 4, 6, 8)
 LDS_MAX = 160 * 1024
@@ -29,16 +30,26 @@ SHIPPED = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_plans.
 
 
 def _split(precision: str):
-    """'f32' / 'f64', optionally with '-sesm' for the AB3-AM4 scheme."""
+    """'f32' / 'f64', optionally with '-sesm' (the AB3-AM4 scheme) or '-visc' (the
+    forward-backward scheme with the barotropic viscous term)."""
     prec, _, scheme = precision.partition("-")
-    if prec not in ("f32", "f64") or scheme not in ("", "sesm"):
-        raise ValueError(f"precision {precision!r}: expected f32, f64, f32-sesm or f64-sesm")
+    if prec not in ("f32", "f64") or scheme not in ("", "sesm", "visc"):
+        raise ValueError(f"precision {precision!r}: expected f32 or f64, optionally with "
+                         "-sesm or -visc")
     return prec, scheme == "sesm"
+
+
+def _visc(precision: str) -> bool:
+    return precision.endswith("-visc")
 
 
 def _tier_ok(precision: str, ept: int, block: int) -> bool:
     """Register tiers the library runs without spills (mirror of its plan check)."""
     prec, sm = _split(precision)
+    if _visc(precision):   # the library's viscous-form check
+        if block == 1024:
+            return ept <= 2
+        return ept <= (6 if prec == "f32" else 4) if block == 512 else True
     if block == 256:
         return ept <= (8 if prec == "f32" else 6)
     if block == 512:
@@ -51,7 +62,10 @@ def _vgprs(precision: str, ept: int) -> int:
     compiler's resource report: about 24 per triangle slot in FP32, 45 in FP64;
     26 and 51 with the two extra transports of the AB3-AM4 scheme)."""
     prec, sm = _split(precision)
-    if prec == "f32":
+    if _visc(precision):   # viscous form: about 32 (FP32) and 53 (FP64) per slot; the
+        # compiler fits the FP64 tiers it allows into 256 registers
+        v = 44 + 32 * ept if prec == "f32" else min(256, 70 + 53 * ept)
+    elif prec == "f32":
         v = 37 + 26 * ept if sm else 32 + 24 * ept
     else:
         v = 52 + 51 * ept if sm else 44 + 45 * ept
@@ -79,19 +93,23 @@ def candidates(mesh, precision: str, nsub: int, top: int = 30):
     largest triangle count and the LDS size.
     """
     prec, sm = _split(precision)
+    visc = _visc(precision)
     lkey = ("lds_sesm_" if sm else "lds_") + prec
+    es = 4 if prec == "f32" else 8
     lat_us, sub_us = 5.8, 0.45      # load + write-back; per substep and triangle/thread
     rows = []
-    for K in KS:
-        if K > nsub:
+    for K in (VISC_KS if visc else KS):
+        ks = K // 2 if visc else K     # substeps per launch (two rings each with the term)
+        if ks > nsub:
             continue
-        waste = (-(-nsub // K) * K) / nsub     # short last chunk of the launch sequence
+        waste = (-(-nsub // ks) * ks) / nsub     # short last chunk of the launch sequence
         for T in TILES:
             try:
                 st = mesh.plan_stats(T, K, 256)
             except Exception:
                 continue
-            if st[lkey] > LDS_MAX:
+            lds = st[lkey] + (2 * es * st["max_tri"] if visc else 0)
+            if lds > LDS_MAX:
                 continue
             for B in BLOCKS:
                 need = -(-st["max_tri"] // B)
@@ -99,11 +117,11 @@ def candidates(mesh, precision: str, nsub: int, top: int = 30):
                 if ept is None or not _tier_ok(precision, ept, B):
                     continue
                 waves = min(8, 512 // _vgprs(precision, ept))
-                resident = min((4 * waves) // (B // 64), LDS_MAX // max(1, st[lkey]))
+                resident = min((4 * waves) // (B // 64), LDS_MAX // max(1, lds))
                 if resident < 1:
                     continue
-                tile_us = lat_us + K * sub_us * st["max_tri"] / B
-                score = tile_us / (T * K * resident) * waste * 1e3
+                tile_us = lat_us + ks * (1.5 if visc else 1.0) * sub_us * st["max_tri"] / B
+                score = tile_us / (T * ks * resident) * waste * 1e3
                 rows.append((score, T, K, B, st))
     rows.sort(key=lambda r: r[0])
     return rows[:top]
@@ -170,9 +188,15 @@ def autotune(mesh, run_step, precision: str, nsub: int, *, top: int = 30, reps: 
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / n
 
+    from ._lib import SeError
     for model, T, K, B, st in candidates(mesh, precision, nsub, top):
         t0 = time.time()
-        ms = timed(T, K, B, reps)
+        try:
+            ms = timed(T, K, B, reps)
+        except SeError as err:   # outside the library's own budget check: skip
+            if log:
+                log(f"[tune] T={T} K={K} B={B}: skipped ({err})")
+            continue
         table.append({"plan": [T, K, B], "ms": ms, "score": model,
                       "tri_overhead": st["tri_overhead"]})
         if log:
