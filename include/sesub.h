@@ -312,7 +312,9 @@ se_status se_trim_zstar(se_mesh *mesh, int32_t K, const double *H0, const double
  * SE_F32_MIXED (arrays of that type; eta of F32 holds eta - eta_ref); flags: only
  * SE_LINEAR_H is read.  Device arrays in mesh numbering: H0, eta [nv]; U, V [ne][2];
  * ws: scratch of 2 ne elements of the precision's type.  The first viscous call on
- * a mesh builds and uploads its neighbour tables (synchronously).
+ * a mesh (and, for se_subcycle, the first after a plan change) builds and uploads
+ * its neighbour tables synchronously; calls on one mesh must not run concurrently
+ * from several host threads.
  * FP64 results follow the CPU definition operation for operation.
  * Errors: SE_ERR_ARG (NULL array, A0 or Cv negative or not finite, bad precision,
  * host-only mesh), SE_ERR_MESH (an edge shared by more than two triangles),
