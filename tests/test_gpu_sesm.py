@@ -79,6 +79,8 @@ def _case(name):
             c = sesynth.random_case(sesynth.tiny_mesh(name), seed=3, nsub=18)
             if name == "sphere86":
                 c["tau"] = 18 * 20.0
+        elif name == "fan100":   # one vertex shared by 100 triangles
+            c = sesynth.random_case(sesynth.tiny_mesh("fan100"), seed=3, nsub=18, tau=2.7)
         elif name == "C1":
             c = sesynth.basin_c1()
         elif name == "C2s":
@@ -97,7 +99,8 @@ def test_library_coefficients_match_the_paper_settings():
     assert np.allclose(sesm_coefficients(0.14), COEF, rtol=0, atol=1e-15)
 
 
-@pytest.mark.parametrize("name", ["jitter76", "chan54", "sphere86", "torus43", "C1", "C2s", "C3s"])
+@pytest.mark.parametrize("name", ["jitter76", "chan54", "sphere86", "torus43", "fan100", "C1", "C2s",
+                                  "C3s"])
 def test_sesm_fp64_plain_matches_oracle(name):
     from paper_2311_08241_amd import Mesh
     case = _case(name)
@@ -167,7 +170,8 @@ def _plans_ok(mesh, prec):
     return out
 
 
-@pytest.mark.parametrize("name", ["jitter76", "chan54", "sphere86", "torus43", "C1", "C2s", "C3s"])
+@pytest.mark.parametrize("name", ["jitter76", "chan54", "sphere86", "torus43", "fan100", "C1", "C2s",
+                                  "C3s"])
 def test_sesm_fp64_tile_matches_oracle(name):
     from paper_2311_08241_amd import Mesh
     case = _case(name)

@@ -61,6 +61,25 @@ def test_trim_matches_oracle_small(kind, with_w):
         assert _rel(a, b) <= 1e-12
 
 
+@pytest.mark.parametrize("K", [1, 2, 63, 64])
+def test_trim_layer_count_limits(K):
+    """One layer (the trim is then U = <<U>>), and the largest column the kernels take."""
+    from paper_2311_08241_amd import Mesh
+    case = sesynth.random_case(sesynth.tiny_mesh("chan54"), seed=4, nsub=24)
+    om, inp = _inputs(case, K, 3, True)
+    mesh = Mesh.from_dict(case, device=0)
+    ref = om.trim_zstar(**inp)
+    out = _gpu(mesh, inp)
+    for a, b in zip(out[:2], ref[:2]):
+        assert _rel(a, b) <= 1e-12
+    # w: with one layer only the surface value exists, the column closure, which is
+    # rounding noise; measure against the size of the terms it sums
+    wscale = max(np.abs(ref[2]).max(), np.abs(ref[1] - inp["hn"]).sum(1).max() / inp["tau"])
+    assert np.abs(out[2] - ref[2]).max() <= 1e-12 * wscale
+    if K == 1:
+        assert _rel(out[0][:, 0], inp["Uavg"]) <= 1e-14
+
+
 def test_trim_long_csr_row():
     """A vertex shared by 100 triangles: its CSR row spans more than one window of
     columns."""
