@@ -234,7 +234,8 @@ def bench_sesm(args, log, mesh, case, stream, with_oracle):
     p64 = Params(g=case["g"], theta=case["theta"], precision="f64", scheme="sesm", sesm=co)
     Uavg = torch.empty((mesh.ne, 2), dtype=torch.float64, device="cuda:0")
     res = {}
-    for label, p, plain in (("fp32_tile", p32, False), ("fp64_plain", p64, True)):
+    for label, p, plain in (("fp32_tile", p32, False), ("fp64_tile", p64, False),
+                            ("fp64_plain", p64, True)):
         d = device_inputs(mesh, case, p)
         e0_, u0_ = d["eta"].clone(), d["U"].clone()
         ws = mesh.workspace(p, nsub)
@@ -248,9 +249,11 @@ def bench_sesm(args, log, mesh, case, stream, with_oracle):
             dd["U"].copy_(b)
         with torch.cuda.stream(stream):
             if not plain:
-                t = autotune(mesh, step, "f32-sesm", nsub, top=24, log=log, reset=reset,
+                key = p.precision + "-sesm"
+                t = autotune(mesh, step, key, nsub, top=24 if key == "f32-sesm" else 12,
+                             reps=3 if key == "f32-sesm" else 2, log=log, reset=reset,
                              use_cache=not args.retune)
-                out["plan"] = t["plan"]
+                out["plan" if key == "f32-sesm" else "plan_fp64"] = t["plan"]
             reset()
             step()
             torch.cuda.synchronize()
