@@ -48,7 +48,7 @@ def _tier_ok(precision: str, ept: int, block: int) -> bool:
     prec, sm = _split(precision)
     if _visc(precision):   # the library's viscous-form check
         if block == 1024:
-            return ept <= 2
+            return ept <= (3 if prec == "f32" else 1)
         return ept <= (6 if prec == "f32" else 4) if block == 512 else True
     if block == 256:
         return ept <= (8 if prec == "f32" else 6)
@@ -62,9 +62,9 @@ def _vgprs(precision: str, ept: int) -> int:
     compiler's resource report: about 24 per triangle slot in FP32, 45 in FP64;
     26 and 51 with the two extra transports of the AB3-AM4 scheme)."""
     prec, sm = _split(precision)
-    if _visc(precision):   # viscous form: about 32 (FP32) and 53 (FP64) per slot; the
+    if _visc(precision):   # viscous form: about 26 (FP32) and 50 (FP64) per slot; the
         # compiler fits the FP64 tiers it allows into 256 registers
-        v = 44 + 32 * ept if prec == "f32" else min(256, 70 + 53 * ept)
+        v = 44 + 26 * ept if prec == "f32" else min(256, 75 + 50 * ept)
     elif prec == "f32":
         v = 37 + 26 * ept if sm else 32 + 24 * ept
     else:

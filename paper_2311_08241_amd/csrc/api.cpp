@@ -752,14 +752,15 @@ se_status se_subcycle(se_mesh *m, const se_params *p, se_state *st, const se_for
         // two rings per substep; the velocities u = U / H_e of the tile's triangles in LDS
         lds += 2 * es * static_cast<size_t>(P.max_ne);
         // register budget of the viscous form (no spills): 1024-thread workgroups up to
-        // two triangles per thread, 512-thread ones up to six (FP32) or four (FP64)
-        const bool regs_ok = P.block == 1024 ? P.ept <= 2
+        // three triangles per thread (FP32; FP64 one), 512-thread ones up to six (FP32)
+        // or four (FP64)
+        const bool regs_ok = P.block == 1024 ? P.ept <= (f32 ? 3 : 1)
                              : P.block == 512 ? P.ept <= (f32 ? 6 : 4) : true;
         if (P.K < 2 || lds > 160 * 1024 || !regs_ok) {
             set_error("se_subcycle: with the viscous term the plan needs k_fused >= 2, " +
                       std::to_string(lds) + " bytes of LDS within 160 KiB and at most " +
-                      "2 (1024 threads) or 6 / 4 (512 threads, FP32 / FP64) triangles per "
-                      "thread");
+                      "3 / 1 (1024 threads) or 6 / 4 (512 threads) triangles per thread "
+                      "(FP32 / FP64)");
             return SE_ERR_ARG;
         }
         SE_TRY(ensure_visc(m));

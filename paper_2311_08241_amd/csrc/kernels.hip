@@ -845,6 +845,15 @@ __global__ void __launch_bounds__(BLOCK) k_tile(TileArgs a) {
         // needs the velocities of ring lev + 1
         const int lev = VI ? 2 * (cnt - j) - 1 : cnt - j;
         const int ne_act = sLev[9 + lev], nv_act = sLev[lev - 1];
+        // VI: the thread index and the packed local indices pass through an empty asm
+        // once per substep, so addresses and indices derived from them are recomputed
+        // instead of held in registers for every triangle across the loop
+        int tidv = tid;
+        if constexpr (VI) {
+            asm volatile("" : "+v"(tidv));
+#pragma unroll
+            for (int r = 0; r < EPT; ++r) asm volatile("" : "+v"(t0[r]), "+v"(t1[r]));
+        }
         if constexpr (VI) {
             const int ne_u = sLev[9 + lev + 1];
 #pragma unroll
@@ -917,8 +926,9 @@ __global__ void __launch_bounds__(BLOCK) k_tile(TileArgs a) {
                 T rx = rRx[r], ry = rRy[r];
                 if constexpr (VI) {
                     // V(eta^m, U^m): edges to local neighbours (0xffff: coast)
-                    const uint2 nbp = reinterpret_cast<const uint2 *>(a.vnb)[h.le_off + le];
-                    const T *vg = static_cast<const T *>(a.vgeo) + 6 * (int64_t)(h.le_off + le);
+                    const int lq = h.le_off + tidv + r * BLOCK;   // = h.le_off + le
+                    const uint2 nbp = reinterpret_cast<const uint2 *>(a.vnb)[lq];
+                    const T *vg = static_cast<const T *>(a.vgeo) + 6 * (int64_t)lq;
                     const int nbs[3] = {static_cast<int>(nbp.x & 0xffffu),
                                         static_cast<int>(nbp.x >> 16),
                                         static_cast<int>(nbp.y & 0xffffu)};

@@ -174,7 +174,7 @@ def test_autotune_candidates_and_signature_on_a_host_mesh():
         assert c and all(r[2] >= 2 and r[2] % 2 == 0 for r in c)
         es = 4 if prec.startswith("f32") else 8
         assert all(r[4]["lds_" + prec[:3]] + 2 * es * r[4]["max_tri"] <= A.LDS_MAX for r in c)
-    assert not A._tier_ok("f32-visc", 3, 1024) and A._tier_ok("f32-visc", 2, 1024)
+    assert not A._tier_ok("f32-visc", 4, 1024) and A._tier_ok("f32-visc", 3, 1024)
     sig = A.mesh_signature(m)
     assert isinstance(sig, str) and len(sig) == 20 and sig == A.mesh_signature(m)
     with pytest.raises(ValueError):
