@@ -27,6 +27,12 @@
  *  - Averaged transport: eq. (eq4_12), with the sum over m = 1..M and the
  *    endpoint term theta/M (U^M - U^0), the only reading that makes the summed
  *    elevation equation eq. (eq4_11) exact.
+ *  - Alternatives and companions of the subcycle, each documented at its
+ *    function: the AB3-AM4 substep of eqs. (eq4_7)-(eq4_8); the barotropic
+ *    viscous regularization of eq. (eq:viscosity_BT) with its initial value
+ *    subtracted from R; the vertically integrated baroclinic forcing of
+ *    eq. (eq4_4); the trim of layer transports (eq. (eq4_13)) with z*
+ *    thicknesses and the diasurface velocity (Sec. 2.4).
  *  - Space-filling-curve reordering (not part of the paper's method): a
  *    Hilbert index on a 2^16 x 2^16 quantisation of the coordinates, used to
  *    check the GPU library's reordering integer for integer.
