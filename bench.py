@@ -205,6 +205,22 @@ def bench_adjoint(args, log):
         adj()
         torch.cuda.synchronize()
         ms = _time(adj, 5)
+        # the same call captured in a graph (kernels and device copies only): launch
+        # overhead dominates at this size
+        ref = [x.clone() for x in g]
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            adj()
+        torch.cuda.current_stream().wait_stream(side)
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            adj()
+        graph.replay()
+        torch.cuda.synchronize()
+        if not all(torch.equal(a, b) for a, b in zip(g, ref)):
+            raise RuntimeError("adjoint graph replay differs from the eager gradients")
+        ms_graph = _time(graph.replay, 10)
         e, U = d["eta"].clone(), d["U"].clone()
 
         def fwd():
@@ -212,8 +228,10 @@ def bench_adjoint(args, log):
                           dt=case["tau"], params=p, workspace=ws)
         fwd()
         msf = _time(fwd, 5)
-        out[prec] = {"ms_adjoint": ms, "ms_forward": msf, "adjoint_over_forward": ms / msf}
-        log(f"[bench] adjoint {prec}: {ms:.3f} ms (forward {msf:.3f} ms)")
+        out[prec] = {"ms_adjoint": ms, "ms_adjoint_graph": ms_graph, "ms_forward": msf,
+                     "adjoint_over_forward": ms / msf}
+        log(f"[bench] adjoint {prec}: {ms:.3f} ms, graph replay {ms_graph:.3f} ms "
+            f"(forward {msf:.3f} ms)")
     return out
 
 

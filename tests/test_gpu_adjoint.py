@@ -158,3 +158,48 @@ def test_autograd_function_matches_direct_adjoint():
                                   ckpt_every=5, lam_eta=w1, lam_Uavg=w2)
     for a, b in ((eta0.grad, ge), (U0.grad, gU), (R.grad, gR), (H0.grad, gH)):
         assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_adjoint_captured_in_a_graph_replays_bitwise(precision):
+    """se_subcycle_adjoint issues only kernels and device-to-device copies on the caller's
+    stream, so a caller can capture it in a graph; every replay (with eager adjoint runs
+    and synchronizations in between) equals the eager gradients bit for bit."""
+    from paper_2311_08241_amd import Mesh, Params, device_inputs
+    case = sesynth.adjoint_c5(n=64)
+    mesh = Mesh.from_dict(case, device=0)
+    p = Params(precision=precision, eta_ref=case["eta_ref"] if precision == "f32" else 0.0)
+    d = device_inputs(mesh, case, p)
+    lam = torch.linspace(0.5, 1.5, mesh.nv, dtype=p.dtype, device="cuda:0")
+    ws = mesh.workspace(p, case["nsub"], case["ckpt_every"])
+    g = [torch.empty_like(d["eta"]), torch.empty_like(d["U"]), torch.empty_like(d["R"]),
+         torch.empty_like(d["H0"])]
+
+    def adj(out):
+        mesh.adjoint(d["eta"], d["U"], R=d["R"], f=d["f"], H0=d["H0"], nsub=case["nsub"],
+                     dt=case["tau"], params=p, ckpt_every=case["ckpt_every"], lam_eta=lam,
+                     g_eta0=out[0], g_U0=out[1], g_R=out[2], g_H0=out[3], workspace=ws)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        adj(g)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    ref = [x.clone() for x in g]
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        adj(g)
+    for rep in range(3):
+        for x in g:
+            x.fill_(float("nan"))
+        graph.replay()
+        torch.cuda.synchronize()
+        for a, b in zip(g, ref):
+            assert torch.equal(a, b), rep
+        # eager work between replays, on its own outputs
+        other = [torch.empty_like(x) for x in g]
+        adj(other)
+        torch.cuda.synchronize()
+        for a, b in zip(other, ref):
+            assert torch.equal(a, b), rep
+    assert mesh.check_faults() == 0
