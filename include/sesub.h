@@ -290,8 +290,8 @@ se_status se_check_faults(void *mesh_or_batch, int32_t kind, void *stream,
  * H0, eta_new [nv] (absolute eta), Uavg [ne][2], Ustar and U [ne][K][2] (U may
  * alias Ustar; no other output may alias an input), hn, h0, hnew [nv][K], W [nv] or
  * NULL, w [nv][K+1] (also scratch between the kernels of the call).  The first call
- * on a mesh builds a table of its sub-cell flux vectors (48 bytes per triangle,
- * device memory owned by the mesh).
+ * on a mesh builds a table of its sub-cell flux vectors on the host and uploads
+ * it synchronously (48 bytes per triangle, device memory owned by the mesh).
  * Results equal the FP64 CPU definition to rounding: the sums over layers are
  * tree reductions and the vertical recursion a parallel suffix sum.
  * Errors: SE_ERR_ARG (NULL array, K outside 1..64, tau <= 0, host-only mesh). */

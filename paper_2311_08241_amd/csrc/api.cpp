@@ -1002,8 +1002,13 @@ se_status se_trim_zstar(se_mesh *m, int32_t K, const double *H0, const double *e
     a.w = w;
     const hipStream_t s = static_cast<hipStream_t>(stream);
     if (!m->d.slotS.p) {
-        SE_TRY(m->d.slotS.alloc(static_cast<size_t>(48) * a.ne));
-        HIP_TRY(launch_slot_vectors(a, m->d.slotS.as<double>(), s), "se_trim_zstar setup");
+        // sub-cell flux vectors S_k = -A_e grad N_k of every triangle, built on the host
+        // and uploaded synchronously (visible to calls on any stream)
+        const HostMesh &h = m->h;
+        std::vector<double> S(6 * static_cast<size_t>(h.ne));
+        for (int64_t e = 0; e < h.ne; ++e)
+            for (int q = 0; q < 6; ++q) S[6 * e + q] = -h.Ae[e] * h.gN[6 * e + q];
+        SE_TRY(m->d.slotS.upload(S.data(), S.size() * 8));
     }
     HIP_TRY(launch_trim(a, m->d.slotS.as<const double>(), s), "se_trim_zstar launch");
     return SE_OK;

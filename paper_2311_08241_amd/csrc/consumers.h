@@ -20,8 +20,7 @@ struct TrimArgs {
     const double *H0, *eta_new, *Uavg, *Ustar, *hn, *h0, *W;
     double *U, *hnew, *w;
 };
-// S: per-triangle sub-cell flux vectors [ne][3][2] from launch_slot_vectors
-hipError_t launch_slot_vectors(const TrimArgs &a, double *S, hipStream_t s);
+// S: per-triangle sub-cell flux vectors [ne][3][2], S_k = -A_e grad N_k
 hipError_t launch_trim(const TrimArgs &a, const double *S, hipStream_t s);
 
 // Barotropic viscous term: V = div(H A grad(U / H)) per triangle (two-point fluxes

@@ -64,24 +64,6 @@ __device__ __forceinline__ int32_t bcast(int32_t v, int lane) {
     return __builtin_amdgcn_readlane(v, lane);
 }
 
-// Sub-cell flux vectors S_{e,k} = -A_e grad N_k of every triangle (three pairs).
-__global__ void __launch_bounds__(256) k_slot_vectors(TrimArgs a, double *S) {
-    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (e >= a.ne) return;
-    const int64_t ne = a.ne;
-    const double Ae = a.geom[4 * ne + e];
-    const double gbx = a.geom[e], gby = a.geom[ne + e];
-    const double gcx = a.geom[2 * ne + e], gcy = a.geom[3 * ne + e];
-    const double gax = -(gbx + gcx), gay = -(gby + gcy);
-    double *o = S + 6 * e;
-    o[0] = -Ae * gax;
-    o[1] = -Ae * gay;
-    o[2] = -Ae * gbx;
-    o[3] = -Ae * gby;
-    o[4] = -Ae * gcx;
-    o[5] = -Ae * gcy;
-}
-
 // Also parks hn + hnew of every vertex-layer in w (same [v][k] place, row stride
 // K + 1) for k_trim; k_zstar_w overwrites it with the diasurface velocity.
 __global__ void __launch_bounds__(256) k_zstar_h(TrimArgs a) {
@@ -428,13 +410,6 @@ hipError_t launch_forcing(const ForcingArgs &a, hipStream_t s) {
     const unsigned g = static_cast<unsigned>((a.ne * FG + 255) / 256);
     if (a.out_f32) hipLaunchKernelGGL(k_forcing<true>, dim3(g), dim3(256), 0, s, a);
     else hipLaunchKernelGGL(k_forcing<false>, dim3(g), dim3(256), 0, s, a);
-    return hipGetLastError();
-}
-
-hipError_t launch_slot_vectors(const TrimArgs &a, double *S, hipStream_t s) {
-    if (a.ne <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_slot_vectors, dim3(static_cast<unsigned>((a.ne + 255) / 256)), dim3(256),
-                       0, s, a, S);
     return hipGetLastError();
 }
 
