@@ -22,48 +22,16 @@ namespace {
 // ascending triangle order, and the diasurface velocity from the bottom up.
 //   k_zstar_h       h^{n+1} = h0 (H0 + eta) / H0, one thread per vertex-layer; also
 //                   hn + h^{n+1}, parked in w until k_zstar_w overwrites it
-//   k_trim          one wavefront per EU consecutive triangles, lane = layer:
-//                   6 x the mid thickness (the common factor cancels in the trim
-//                   weights), layer sums by lane shuffles, trimmed transports
-//   k_zstar_w       one wavefront per vertex, lane = layer: the CSR row's fluxes
-//                   AB triangles at a time (all loads of a batch in flight), then
-//                   w by a suffix scan across lanes
-// Indices a wavefront needs (triangle vertices, CSR columns) are loaded by its
-// lanes in one access and broadcast with readlane, so no scalar-load chain sits
-// between an element and its layer data.  Results equal the definition to rounding
-// (tree sums, reciprocals), not bit for bit.
+//   k_trim          8 lanes per triangle, 8 triangles per wavefront iteration;
+//                   lane g holds layers g, g + 8, ...: 6 x the mid thickness (the
+//                   common factor cancels in the trim weights), layer sums by
+//                   butterflies over the 8 lanes, trimmed transports
+//   k_zstar_w       8 lanes per vertex in the same layer layout: the CSR row's
+//                   fluxes a few triangles at a time (all loads of a batch in
+//                   flight), then w by suffix sums over the lanes, bottom up
+// Every access of a group reads 8 consecutive layers (64 or 128 contiguous bytes).
+// Results equal the definition to rounding (tree sums, reciprocals), not bit for bit.
 // ---------------------------------------------------------------------------
-// Rotation right by n lanes within each row of 16 (DPP row_ror), on an FP64 value.
-template <int N> __device__ __forceinline__ double row_ror(double v) {
-    const uint64_t b = __builtin_bit_cast(uint64_t, v);
-    const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(b), 0x120 + N, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(b >> 32), 0x120 + N, 0xf, 0xf,
-                                               false);
-    return __builtin_bit_cast(double, (static_cast<uint64_t>(static_cast<uint32_t>(hi)) << 32) |
-                                          static_cast<uint32_t>(lo));
-}
-
-__device__ __forceinline__ double lane_value(double v, int lane) {
-    const uint64_t b = __builtin_bit_cast(uint64_t, v);
-    const uint32_t lo = __builtin_amdgcn_readlane(static_cast<int>(b), lane);
-    const uint32_t hi = __builtin_amdgcn_readlane(static_cast<int>(b >> 32), lane);
-    return __builtin_bit_cast(double, (static_cast<uint64_t>(hi) << 32) | lo);
-}
-
-// Sum over the 64 lanes, returned to every lane: rotations within each row of 16,
-// then the four row sums.
-__device__ __forceinline__ double wave_allsum(double v) {
-    v += row_ror<8>(v);
-    v += row_ror<4>(v);
-    v += row_ror<2>(v);
-    v += row_ror<1>(v);
-    return (lane_value(v, 0) + lane_value(v, 16)) + (lane_value(v, 32) + lane_value(v, 48));
-}
-
-__device__ __forceinline__ int32_t bcast(int32_t v, int lane) {
-    return __builtin_amdgcn_readlane(v, lane);
-}
-
 // Also parks hn + hnew of every vertex-layer in w (same [v][k] place, row stride
 // K + 1) for k_trim; k_zstar_w overwrites it with the diasurface velocity.
 __global__ void __launch_bounds__(256) k_zstar_h(TrimArgs a) {
@@ -83,175 +51,220 @@ __device__ __forceinline__ int64_t xcd_block() {
     return static_cast<int64_t>(x) * base + (x < rem ? x : rem) + q;
 }
 
-// wave-level contiguous range of n elements
-__device__ __forceinline__ void wave_range(int64_t n, int64_t &beg, int64_t &end) {
-    const int64_t nw = static_cast<int64_t>(gridDim.x) * (blockDim.x >> 6);
-    const int64_t gw = xcd_block() * (blockDim.x >> 6) +
-                       __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
-    const int64_t chunk = (n + nw - 1) / nw;
-    beg = gw * chunk;
-    end = min(n, beg + chunk);
+// Groups of 8 lanes (aligned in each row of 16) share one element; lane g of a group
+// holds layers g, g + 8, g + 16, ...  Butterflies over the group by DPP: exchange with
+// lane g ^ 1 and g ^ 2 (quad permutations), then with the mirrored lane 7 - g of the
+// other quad (row_half_mirror), whose running total equals that of g ^ 4.
+template <int CTRL> __device__ __forceinline__ double dpp64(double v) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(b), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(b >> 32), CTRL, 0xf, 0xf, false);
+    return __builtin_bit_cast(double, (static_cast<uint64_t>(static_cast<uint32_t>(hi)) << 32) |
+                                          static_cast<uint32_t>(lo));
+}
+constexpr int DPP_XOR1 = 0xB1;          // quad_perm [1, 0, 3, 2]
+constexpr int DPP_XOR2 = 0x4E;          // quad_perm [2, 3, 0, 1]
+constexpr int DPP_HALF_MIRROR = 0x141;  // row_half_mirror: lane 7 - g of each 8
+
+// Sum over the group, the same bits in all 8 lanes (each step adds two equal partial
+// sums in either order).
+__device__ __forceinline__ double grp_sum(double v) {
+    v += dpp64<DPP_XOR1>(v);
+    v += dpp64<DPP_XOR2>(v);
+    return v + dpp64<DPP_HALF_MIRROR>(v);
 }
 
-constexpr int EU = 4;   // triangles per wavefront iteration of k_trim
+// Inclusive suffix sum over the group (lane g: sum over g' >= g) and the group total.
+__device__ __forceinline__ double grp_suffix(double v, int g, double &tot) {
+    double s = v;
+    double y = dpp64<DPP_XOR1>(v);
+    if (!(g & 1)) s += y;
+    v += y;
+    y = dpp64<DPP_XOR2>(v);
+    if (!(g & 2)) s += y;
+    v += y;
+    y = dpp64<DPP_HALF_MIRROR>(v);
+    if (!(g & 4)) s += y;
+    tot = v + y;
+    return s;
+}
 
+// Blocks of 8 elements dealt to the wavefronts of each XCD in turn (workgroups go
+// round-robin to the 8 XCDs; the grid is a multiple of 8 and small enough to be
+// resident at once): the wavefronts of an XCD work on one compact window that moves
+// along that XCD's eighth of the range, so elements sharing vertices (neighbours
+// along the curve) meet in the XCD's L2 before streaming data evicts them.
+struct Sweep {
+    int64_t blk, step, lim;
+};
+__device__ __forceinline__ Sweep xcd_sweep(int64_t n) {
+    const int G = gridDim.x, b = blockIdx.x, x = b & 7;
+    const int wpb = blockDim.x >> 6;
+    const int64_t gx = (G - x + 7) >> 3;   // workgroups on XCD x
+    const int64_t wx = static_cast<int64_t>(b >> 3) * wpb +
+                       __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+    const int64_t nblk = (n + 7) >> 3;
+    return {nblk * x / 8 + wx, gx * wpb, nblk * (x + 1) / 8};
+}
+
+// Streaming accesses (each byte once): non-temporal, leaving L2 to the shared rows.
+typedef double d2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ d2v ld_stream(const double *p) {
+    return __builtin_nontemporal_load(reinterpret_cast<const d2v *>(p));
+}
+__device__ __forceinline__ void st_stream(double *p, d2v v) {
+    __builtin_nontemporal_store(v, reinterpret_cast<d2v *>(p));
+}
+
+// L = ceil(K / 8) layers per lane.  Eight triangles per wavefront iteration: 6 x the
+// mid thickness per layer (hn + hnew summed over the three vertices; the common factor
+// cancels in the weights), the layer sums of thickness and transport by group sums,
+// then the trimmed transport of each layer.
+template <int L>
 __global__ void __launch_bounds__(256) k_trim(TrimArgs a) {
-    const int lane = threadIdx.x & 63;
-    const int K = a.K, k = lane;
-    const bool act = k < K;
-    int64_t beg, end;
-    wave_range(a.ne, beg, end);
-    if (beg >= end) return;
-    // triangle indices of an iteration, one per lane (lane 3u + c: vertex c of e0 + u),
-    // loaded one iteration ahead
-    int32_t myt = a.tri[3 * beg + min<int64_t>(lane, 3 * (end - beg) - 1)];
-    for (int64_t e0 = beg; e0 < end; e0 += EU) {
-        const int nu = static_cast<int>(min<int64_t>(EU, end - e0));
-        double hh[EU], ux[EU], uy[EU];
+    const int lane = threadIdx.x & 63, g = lane & 7, slot = lane >> 3;
+    const int K = a.K;
+    const int64_t ne = a.ne;
+    const Sweep sw = xcd_sweep(ne);
+    if (sw.blk >= sw.lim) return;
+    // vertex indices of this lane's triangle, loaded one block ahead; past the end of
+    // the range the last triangle stands in (its results are not stored)
+    int64_t ec = min(8 * sw.blk + slot, ne - 1);
+    int32_t ta = a.tri[3 * ec], tb = a.tri[3 * ec + 1], tc = a.tri[3 * ec + 2];
+    for (int64_t bk = sw.blk; bk < sw.lim; bk += sw.step) {
+        const bool live = 8 * bk + slot < ne;
+        double hh[L], ux[L], uy[L];
+        double hs = 0.0, sx = 0.0, sy = 0.0;
+        const double *wa = a.w + static_cast<int64_t>(ta) * (K + 1);
+        const double *wb = a.w + static_cast<int64_t>(tb) * (K + 1);
+        const double *wc = a.w + static_cast<int64_t>(tc) * (K + 1);
 #pragma unroll
-        for (int u = 0; u < EU; ++u) {
-            const int uu = min(u, nu - 1);   // past the range: repeat the last triangle
-            const int64_t ta = bcast(myt, 3 * uu), tb = bcast(myt, 3 * uu + 1),
-                          tc = bcast(myt, 3 * uu + 2);
-            hh[u] = 0.0;
-            ux[u] = 0.0;
-            uy[u] = 0.0;
-            if (act) {
-                const double *hm = a.w;   // hn + hnew, row stride K + 1
-                hh[u] = (hm[ta * (K + 1) + k] + hm[tb * (K + 1) + k]) + hm[tc * (K + 1) + k];
-                const double2 us = reinterpret_cast<const double2 *>(a.Ustar)[(e0 + uu) * K + k];
-                ux[u] = us.x;
-                uy[u] = us.y;
+        for (int l = 0; l < L; ++l) {
+            const int k = 8 * l + g;
+            hh[l] = 0.0;
+            ux[l] = 0.0;
+            uy[l] = 0.0;
+            if (k < K) {
+                hh[l] = (wa[k] + wb[k]) + wc[k];
+                const d2v u = ld_stream(a.Ustar + 2 * (ec * K + k));
+                ux[l] = u.x;
+                uy[l] = u.y;
             }
         }
-        const int64_t e1 = e0 + EU;
-        if (e1 < end) myt = a.tri[3 * e1 + min<int64_t>(lane, 3 * (end - e1) - 1)];
+        const int64_t bn = bk + sw.step;
+        const int64_t en = bn < sw.lim ? min(8 * bn + slot, ne - 1) : ec;
+        const int32_t na = a.tri[3 * en], nb = a.tri[3 * en + 1], nc = a.tri[3 * en + 2];
 #pragma unroll
-        for (int u = 0; u < EU; ++u) {
-            if (u >= nu) break;   // wave-uniform
-            const int64_t e = e0 + u;
-            const double hs = wave_allsum(hh[u]);
-            const double ex = wave_allsum(ux[u]) - a.Uavg[2 * e];
-            const double ey = wave_allsum(uy[u]) - a.Uavg[2 * e + 1];
-            const double q = hh[u] * (1.0 / hs);
-            if (act) {
-                double2 r;
-                r.x = ux[u] - q * ex;
-                r.y = uy[u] - q * ey;
-                reinterpret_cast<double2 *>(a.U)[e * K + k] = r;
+        for (int l = 0; l < L; ++l) {
+            hs += hh[l];
+            sx += ux[l];
+            sy += uy[l];
+        }
+        hs = grp_sum(hs);
+        const double ex = grp_sum(sx) - a.Uavg[2 * ec];
+        const double ey = grp_sum(sy) - a.Uavg[2 * ec + 1];
+        const double rh = 1.0 / hs;
+        if (live) {
+#pragma unroll
+            for (int l = 0; l < L; ++l) {
+                const int k = 8 * l + g;
+                if (k < K) {
+                    const double q = hh[l] * rh;
+                    d2v r;
+                    r.x = ux[l] - q * ex;
+                    r.y = uy[l] - q * ey;
+                    st_stream(a.U + 2 * (ec * K + k), r);
+                }
             }
         }
+        ec = en;
+        ta = na;
+        tb = nb;
+        tc = nc;
     }
 }
 
-// k_zstar_w: VU consecutive vertices per wavefront iteration (their CSR rows inside one
-// 64-column window), AB triangles of each row per batch of loads; other groups take
-// the one-vertex form.
-constexpr int ZW_VU = 2, ZW_AB = 6;
+// Eight vertices per wavefront iteration, CSR entries DB at a time (all their loads in
+// flight): per layer the flux of the trimmed transport through the vertex's sub-cell
+// boundary, then t_k = (hnew - hn) / tau + div_k / A_v (+ W at the top) and
+// w_k = -(t_k + ... + t_{K-1}) by group suffix sums, layer blocks from the bottom up.
+// The next block's row bounds and first 8 CSR columns (one per lane of the group,
+// passed to the others by lane shuffles) are loaded while this block gathers.  Plain
+// (temporal) accesses here: the 328-byte rows of w are not line aligned.
+constexpr int ZW_DB = 3;
 
-template <int VU, int AB>
+template <int L>
 __global__ void __launch_bounds__(256) k_zstar_w(TrimArgs a, const double *S) {
-    const int lane = threadIdx.x & 63;
-    const int K = a.K, k = lane;
-    const bool act = k < K;
+    const int lane = threadIdx.x & 63, g = lane & 7, slot = lane >> 3;
+    const int gbase = lane & ~7;
+    const int K = a.K;
     const double inv_tau = 1.0 / a.tau;
-    // read-only table indexed by wave-uniform values: scalar loads
-    const __attribute__((address_space(4))) double *S4 =
-        (const __attribute__((address_space(4))) double *)(S);
     const double2 *U2 = reinterpret_cast<const double2 *>(a.U);
-    // flux of the trimmed transport of CSR entry pcl = 3 e + slot through the slot's
-    // sub-cell boundary, layer k
-    auto flux = [&](int32_t pcl) {
-        const int64_t e = pcl / 3;
-        const double svx = S4[2 * pcl], svy = S4[2 * pcl + 1];
-        const double2 F = act ? U2[e * K + k] : make_double2(0.0, 0.0);
-        return F.x * svx + F.y * svy;
-    };
-    // w[k] = -(t_k + t_{k+1} + ... + t_{K-1}): inclusive suffix scan across lanes
-    auto finish = [&](int64_t v, double hnew, double hn, double div) {
-        double t = (hnew - hn) * inv_tau + div * (1.0 / a.Av[v]) +
-                   (k == 0 && a.W ? a.W[v] : 0.0);
-        if (!act) t = 0.0;
-        for (int o = 1; o < 64; o <<= 1) {
-            const double x = __shfl_down(t, o, 64);
-            if (lane + o < 64) t += x;
+    const double2 *S2 = reinterpret_cast<const double2 *>(S);
+    const int64_t nv = a.nv;
+    const Sweep sw = xcd_sweep(nv);
+    if (sw.blk >= sw.lim) return;
+    // row bounds of this lane's vertex and entry g of its CSR row (the group's lanes
+    // hold the first 8 entries), loaded a block ahead
+    int64_t vc = min(8 * sw.blk + slot, nv - 1);
+    int32_t j0 = a.row_ptr[vc], j1 = a.row_ptr[vc + 1];   // j1 > j0: no empty rows
+    int32_t pq = a.pcol[min(j0 + g, j1 - 1)];
+    for (int64_t bk = sw.blk; bk < sw.lim; bk += sw.step) {
+        const bool live = 8 * bk + slot < nv;
+        double dh[L];
+#pragma unroll
+        for (int l = 0; l < L; ++l) {
+            const int k = 8 * l + g;
+            dh[l] = k < K ? (a.hnew[vc * K + k] - a.hn[vc * K + k]) * inv_tau : 0.0;
         }
-        double *w = a.w + v * (K + 1);
-        if (act) w[k] = -t;
-        if (lane == 0) w[K] = 0.0;
-    };
-    int64_t beg, end;
-    wave_range(a.nv, beg, end);
-    for (int64_t vb = beg; vb < end; vb += 63) {
-        // row bounds of up to 63 vertices: lane u holds row_ptr[vb + u]
-        const int nvb = static_cast<int>(min<int64_t>(63, end - vb));
-        const int32_t rp = a.row_ptr[vb + min(lane, nvb)];
-        const int32_t jend = bcast(rp, nvb);
-        // CSR columns, 64 at a time: lane i holds pcol[cbase + i]; cbase only moves
-        // forward, so it never passes the start of a later row
-        int32_t cbase = bcast(rp, 0);
-        int32_t pc = a.pcol[min(cbase + lane, jend - 1)];
-        for (int u0 = 0; u0 < nvb; u0 += VU) {
-            const int nu = min(VU, nvb - u0);
-            const int32_t jf = bcast(rp, u0), jl = bcast(rp, u0 + nu);
-            if (nu == VU && jl - jf <= 64) {
-                if (jl > cbase + 64) {
-                    cbase = jf;
-                    pc = a.pcol[min(cbase + lane, jend - 1)];
+        const int64_t bn = bk + sw.step;
+        const int64_t vn = bn < sw.lim ? min(8 * bn + slot, nv - 1) : vc;
+        const int32_t n0 = a.row_ptr[vn], n1 = a.row_ptr[vn + 1];
+        double div[L];
+#pragma unroll
+        for (int l = 0; l < L; ++l) div[l] = 0.0;
+        const int len = j1 - j0;
+        for (int q0 = 0; q0 < len; q0 += ZW_DB) {
+            double2 sv[ZW_DB];
+            double2 F[ZW_DB][L];
+#pragma unroll
+            for (int q = 0; q < ZW_DB; ++q) {
+                const int qq = min(q0 + q, len - 1);
+                const int32_t pc = qq < 8 ? __shfl(pq, gbase + min(qq, 7), 64) : a.pcol[j0 + qq];
+                sv[q] = S2[pc];
+                const int64_t eK = static_cast<int64_t>(pc / 3) * K;
+#pragma unroll
+                for (int l = 0; l < L; ++l) {
+                    const int k = 8 * l + g;
+                    F[q][l] = k < K ? U2[eK + k] : make_double2(0.0, 0.0);
                 }
-                int32_t j0[VU], len[VU];
-                double hnew[VU], hn[VU], div[VU];
-                int maxlen = 0;
-#pragma unroll
-                for (int u = 0; u < VU; ++u) {
-                    const int64_t v = vb + u0 + u;
-                    j0[u] = bcast(rp, u0 + u);
-                    len[u] = bcast(rp, u0 + u + 1) - j0[u];   // >= 1: every vertex has a triangle
-                    maxlen = max(maxlen, len[u]);
-                    hnew[u] = act ? a.hnew[v * K + k] : 0.0;
-                    hn[u] = act ? a.hn[v * K + k] : 0.0;
-                    div[u] = 0.0;
-                }
-                for (int off = 0; off < maxlen; off += AB) {
-                    double fl[VU][AB];
-#pragma unroll
-                    for (int u = 0; u < VU; ++u)
-#pragma unroll
-                        for (int q = 0; q < AB; ++q)   // past a row's end: its last entry again
-                            fl[u][q] = flux(bcast(pc, j0[u] + min(off + q, len[u] - 1) - cbase));
-#pragma unroll
-                    for (int u = 0; u < VU; ++u)
-#pragma unroll
-                        for (int q = 0; q < AB; ++q)
-                            if (off + q < len[u]) div[u] += fl[u][q];
-                }
-#pragma unroll
-                for (int u = 0; u < VU; ++u) finish(vb + u0 + u, hnew[u], hn[u], div[u]);
-                continue;
             }
-            for (int u = u0; u < u0 + nu; ++u) {
-                const int64_t v = vb + u;
-                const int32_t j0 = bcast(rp, u), j1 = bcast(rp, u + 1);
-                const double hnew = act ? a.hnew[v * K + k] : 0.0;
-                const double hn = act ? a.hn[v * K + k] : 0.0;
-                double div = 0.0;
-                for (int32_t j = j0; j < j1; j += AB) {
-                    // this batch's columns j .. min(j + AB, j1) - 1 inside the window
-                    // [cbase, cbase + 64) (wave-uniform; rows of any length)
-                    if (min(j + AB, j1) > cbase + 64) {
-                        cbase = j;
-                        pc = a.pcol[min(cbase + lane, jend - 1)];
-                    }
-                    double fl[AB];
 #pragma unroll
-                    for (int q = 0; q < AB; ++q) fl[q] = flux(bcast(pc, min(j + q, j1 - 1) - cbase));
+            for (int q = 0; q < ZW_DB; ++q)
+                if (q0 + q < len)
 #pragma unroll
-                    for (int q = 0; q < AB; ++q)
-                        if (j + q < j1) div += fl[q];
-                }
-                finish(v, hnew, hn, div);
-            }
+                    for (int l = 0; l < L; ++l)
+                        div[l] += F[q][l].x * sv[q].x + F[q][l].y * sv[q].y;
         }
+        const int32_t pn = a.pcol[min(n0 + g, n1 - 1)];
+        const double rA = 1.0 / a.Av[vc];
+        const double Wv = a.W ? a.W[vc] : 0.0;
+        double *w = a.w + vc * (K + 1);
+        double run = 0.0;   // sum of t over the layer blocks below
+#pragma unroll
+        for (int l = L - 1; l >= 0; --l) {
+            const int k = 8 * l + g;
+            const double t = k < K ? dh[l] + div[l] * rA + (k == 0 ? Wv : 0.0) : 0.0;
+            double tot;
+            const double sfx = grp_suffix(t, g, tot);
+            if (live && k < K) w[k] = -(sfx + run);
+            run += tot;
+        }
+        if (live && g == 0) w[K] = 0.0;
+        vc = vn;
+        j0 = n0;
+        j1 = n1;
+        pq = pn;
     }
 }
 
@@ -413,20 +426,29 @@ hipError_t launch_forcing(const ForcingArgs &a, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Grids of 4 (k_trim) and 3 (k_zstar_w) workgroups per CU, all resident at once: the
+// fastest of 2 to 7 per CU on a 2.2M-vertex, 40-layer mesh (fewer wavefronts per XCD
+// keep the sweep's window, and its rows, inside L2; more overlap more loads).
+template <int L> void launch_trim_layers(const TrimArgs &a, const double *S, hipStream_t s) {
+    if (a.ne > 0) hipLaunchKernelGGL(k_trim<L>, dim3(256 * 4), dim3(256), 0, s, a);
+    if (a.nv > 0) hipLaunchKernelGGL(k_zstar_w<L>, dim3(256 * 3), dim3(256), 0, s, a, S);
+}
+
 hipError_t launch_trim(const TrimArgs &a, const double *S, hipStream_t s) {
-    // wavefronts loop over contiguous ranges; up to 64 workgroups of 4 per CU (more than
-    // fit at once: short ranges balance the tail)
+    if (a.K < 1 || a.K > 64) return hipErrorInvalidValue;
     if (a.nv > 0)
         hipLaunchKernelGGL(k_zstar_h, dim3(static_cast<unsigned>((a.nv * a.K + 255) / 256)),
                            dim3(256), 0, s, a);
-    if (a.ne > 0)
-        hipLaunchKernelGGL(k_trim, dim3(static_cast<unsigned>(std::min<int64_t>(
-                                        (a.ne + 4 * EU - 1) / (4 * EU), 256 * 64))),
-                           dim3(256), 0, s, a);
-    if (a.nv > 0)
-        hipLaunchKernelGGL((k_zstar_w<ZW_VU, ZW_AB>),
-                           dim3(static_cast<unsigned>(std::min<int64_t>((a.nv + 63) / 64, 256 * 64))),
-                           dim3(256), 0, s, a, S);
+    switch ((a.K + 7) / 8) {
+        case 1: launch_trim_layers<1>(a, S, s); break;
+        case 2: launch_trim_layers<2>(a, S, s); break;
+        case 3: launch_trim_layers<3>(a, S, s); break;
+        case 4: launch_trim_layers<4>(a, S, s); break;
+        case 5: launch_trim_layers<5>(a, S, s); break;
+        case 6: launch_trim_layers<6>(a, S, s); break;
+        case 7: launch_trim_layers<7>(a, S, s); break;
+        default: launch_trim_layers<8>(a, S, s); break;
+    }
     return hipGetLastError();
 }
 
