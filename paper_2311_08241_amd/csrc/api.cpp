@@ -1235,26 +1235,32 @@ se_status se_subcycle_adjoint(se_mesh *m, const se_params *p, const void *eta0, 
     fa.c = make_step(p, nsub, dt);
     fa.nblk_v = static_cast<int32_t>((nv + 255) / 256);
     fa.fwd_only = 1;
-    auto fstep = [&](size_t off) -> se_status {
+    // one forward substep from the state (se, sU) into the workspace state at off
+    auto fstep = [&](const void *se, const void *sU, size_t off) -> se_status {
+        fa.eta_src = se;
+        fa.U_src = sU;
         fa.eta = st_eta(off);
         fa.U = st_U(off);
         HIP_TRY(launch_plain_step(f32, fa, s), "adjoint: forward substep");
         return SE_OK;
     };
-    auto copy_state = [&](size_t dst, size_t src) -> se_status {
-        HIP_TRY(hipMemcpyAsync(w + dst, w + src, (nv + 2 * ne) * es, hipMemcpyDeviceToDevice, s),
-                "adjoint: state copy");
-        return SE_OK;
-    };
 
-    // 1. forward sweep storing a checkpoint every k substeps
+    // 1. forward sweep storing a checkpoint every k substeps: state m (m = q k) in
+    // checkpoint slot q, the caller's eta0, U0 standing for slot 0; the states between
+    // checkpoints in the segment slots j = m mod k (no copies: each substep writes its
+    // result into its slot)
     const int32_t k = A.k;
-    HIP_TRY(hipMemcpyAsync(st_eta(A.ckpt), eta0, nv * es, hipMemcpyDeviceToDevice, s), "copy eta0");
-    HIP_TRY(hipMemcpyAsync(st_U(A.ckpt), U0, 2 * ne * es, hipMemcpyDeviceToDevice, s), "copy U0");
-    SE_TRY(copy_state(A.traj, A.ckpt));
-    for (int32_t mm = 0; mm + 1 < nsub; ++mm) {
-        SE_TRY(fstep(A.traj));
-        if ((mm + 1) % k == 0) SE_TRY(copy_state(A.ckpt + st_bytes * ((mm + 1) / k), A.traj));
+    auto ckpt_eta = [&](int32_t q) -> const void * { return q == 0 ? eta0 : st_eta(A.ckpt + st_bytes * q); };
+    auto ckpt_U = [&](int32_t q) -> const void * { return q == 0 ? U0 : st_U(A.ckpt + st_bytes * q); };
+    {
+        const void *ce = eta0, *cU = U0;
+        for (int32_t mm = 0; mm + 1 < nsub; ++mm) {
+            const int32_t n1 = mm + 1;   // index of the state this substep produces
+            const size_t dst = n1 % k == 0 ? A.ckpt + st_bytes * (n1 / k) : A.traj + st_bytes * (n1 % k);
+            SE_TRY(fstep(ce, cU, dst));
+            ce = st_eta(dst);
+            cU = st_U(dst);
+        }
     }
 
     // 2. reverse sweep, segment by segment, recomputing each segment's states
@@ -1279,14 +1285,15 @@ se_status se_subcycle_adjoint(se_mesh *m, const se_params *p, const void *eta0, 
     aa.thrM = p->theta * aa.rM;
     HIP_TRY(launch_adj_init(f32, aa, lam_eta, lam_U, s), "adjoint: init");
     for (int32_t sg = A.nseg - 1; sg >= 0; --sg) {
+        // recompute the segment's states m0 + 1 .. m1 - 1 from its checkpoint
         const int32_t m0 = sg * k, m1 = std::min(nsub, m0 + k);
-        SE_TRY(copy_state(A.traj, A.ckpt + st_bytes * sg));
         for (int32_t j = 1; j < m1 - m0; ++j) {
-            SE_TRY(copy_state(A.traj + st_bytes * j, A.traj + st_bytes * (j - 1)));
-            SE_TRY(fstep(A.traj + st_bytes * j));
+            const void *se = j == 1 ? ckpt_eta(sg) : st_eta(A.traj + st_bytes * (j - 1));
+            const void *sU = j == 1 ? ckpt_U(sg) : st_U(A.traj + st_bytes * (j - 1));
+            SE_TRY(fstep(se, sU, A.traj + st_bytes * j));
         }
         for (int32_t mm = m1 - 1; mm >= m0; --mm) {
-            aa.eta_m = st_eta(A.traj + st_bytes * (mm - m0));
+            aa.eta_m = mm == m0 ? ckpt_eta(sg) : st_eta(A.traj + st_bytes * (mm - m0));
             HIP_TRY(launch_adj_step(f32, aa, s), "adjoint: reverse substep");
         }
     }

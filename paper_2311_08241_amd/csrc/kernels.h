@@ -68,6 +68,9 @@ struct PlainArgs {
     const void *H0, *R, *f, *W, *Av;
     const double *Av64;
     void *eta, *U, *phi, *sum, *U0c;
+    // non-null: the plain step reads the state (eta, U) from here and writes eta and U
+    // (out of place; the source is not modified)
+    const void *eta_src, *U_src;
     double *Uavg, *vol_part;
     uint32_t *faults;
     StepC c;

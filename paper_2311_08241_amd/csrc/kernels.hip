@@ -157,12 +157,12 @@ __global__ void __launch_bounds__(256) k_plain_tri(PlainArgs a) {
     const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (e >= a.ne) return;
     const StepC &c = a.c;
-    const T *eta = static_cast<const T *>(a.eta);
+    const T *eta = static_cast<const T *>(a.eta_src ? a.eta_src : a.eta);
     const T *H0 = static_cast<const T *>(a.H0);
     const T *geom = static_cast<const T *>(a.geom);
     const int32_t va = a.tri[3 * e], vb = a.tri[3 * e + 1], vc = a.tri[3 * e + 2];
     T2 *U = static_cast<T2 *>(a.U);
-    const T2 u = U[e];
+    const T2 u = (a.U_src ? static_cast<const T2 *>(a.U_src) : U)[e];
     const T2 r = static_cast<const T2 *>(a.R)[e];
     const T fc = static_cast<const T *>(a.f)[e];
     T Unx, Uny, pa, pb, pc;
@@ -225,7 +225,7 @@ __global__ void __launch_bounds__(256) k_plain_vtx(PlainArgs a) {
         T acc = T(0);
         const int32_t j1 = a.row_ptr[v + 1];
         for (int32_t j = a.row_ptr[v]; j < j1; ++j) acc += phi[a.pcol[j]];
-        const T eo = eta[v];
+        const T eo = a.eta_src ? static_cast<const T *>(a.eta_src)[v] : eta[v];
         const T wv = a.W ? static_cast<const T *>(a.W)[v] : T(0);
         const T av = static_cast<const T *>(a.Av)[v];
         const T en = F32 ? vtx_update_f32(eo, acc, T(1) / av, wv, cdts<T>(c))
