@@ -87,10 +87,15 @@ def test_checkpoint_interval_does_not_change_the_gradient():
     case = _c5_small()
     mesh, params, d = _setup(case)
     le, lU, lUa = _seeds(mesh, case, 8, None)
+    eta0, U0 = d["eta"].clone(), d["U"].clone()
+    # every checkpoint interval, including one substep per segment, a ragged last
+    # segment (30 = 4 x 7 + 2) and a single segment
     outs = [_gpu_adjoint(mesh, params, d, case, le, lU, lUa, ckpt=k) for k in (1, 5, 7, 30)]
     for o in outs[1:]:
         for a, b in zip(o, outs[0]):
             assert np.array_equal(a, b)
+    # the forward sweep reads the caller's initial state in place and never writes it
+    assert torch.equal(d["eta"], eta0) and torch.equal(d["U"], U0)
 
 
 def test_adjoint_c5_loss_against_central_differences():
