@@ -7,6 +7,7 @@
 #include <string>
 
 #include "consumers.h"
+#include "ensemble.h"
 #include "kernels.h"
 #include "se_internal.h"
 
@@ -1318,6 +1319,11 @@ struct se_batch {
     std::vector<double> atot;            // per member total area
     sesub::DevBuf Av64, Av32, faults, table, lists;
     std::vector<sesub::StepC> table_host;
+    // one-launch epilogue of a call: volume rows of every member, final states that
+    // ended in the workspace copied back (per configuration, host copies to compare)
+    sesub::DevBuf voltab, cpytab;
+    std::vector<sesub::VolMember> voltab_host;
+    std::vector<sesub::CopyRange> cpytab_host;
     std::vector<int32_t> list_off;       // per launch offset into lists (size nlaunch + 1)
     std::unique_ptr<sesub::DevTiles> plan;
     int32_t plan_T = 768, plan_K = 4, plan_block = 512;
@@ -1596,6 +1602,49 @@ se_status se_subcycle_batched(se_batch *b, const se_params *p, se_state *st, con
         b->table_host = tab;
         b->drop_graphs();
     }
+    // epilogue tables: volume rows per member, and the word ranges of the members
+    // whose last chunk wrote the workspace buffers (an odd number of chunks)
+    const size_t es = f32 ? 4 : 8;
+    std::vector<VolMember> vt;
+    int32_t vrows = 0;
+    for (size_t i = 0; i < n; ++i) {
+        const int32_t rows = static_cast<int32_t>(batch_vol_rows(p, nsub, i));
+        VolMember vm{};
+        vm.part_off = L.vol_off[i];
+        vm.out_off = vrows;
+        vm.width = b->mtiles[i];
+        vm.row0 = vrows;
+        vm.add = f32 ? p->eta_ref * b->atot[i] : 0.0;
+        vt.push_back(vm);
+        vrows += rows;
+    }
+    std::vector<CopyRange> ct;
+    int64_t cwords = 0;
+    const int64_t wpe = static_cast<int64_t>(es / 4);   // 32-bit words per value
+    for (size_t i = 0; i < n; ++i) {
+        if (Lm[i] % 2 == 0) continue;
+        CopyRange re{b->voff[i] * wpe, cwords, 0, 0};
+        ct.push_back(re);
+        cwords += b->h[i].nv * wpe;
+        CopyRange ru{2 * b->eoff[i] * wpe, cwords, 1, 0};
+        ct.push_back(ru);
+        cwords += 2 * b->h[i].ne * wpe;
+    }
+    auto differs = [](const auto &x, const auto &y) {
+        return x.size() != y.size() ||
+               (!x.empty() && std::memcmp(x.data(), y.data(), x.size() * sizeof(x[0])) != 0);
+    };
+    if (differs(vt, b->voltab_host) || differs(ct, b->cpytab_host)) {
+        HIP_TRY(hipStreamSynchronize(s), "batched: sync before epilogue table update");
+        b->drop_graphs();
+        SE_TRY(b->voltab.upload(vt.data(), vt.size() * sizeof(VolMember)));
+        if (ct.empty())
+            SE_TRY(b->cpytab.alloc(sizeof(CopyRange)));   // never read (no ranges)
+        else
+            SE_TRY(b->cpytab.upload(ct.data(), ct.size() * sizeof(CopyRange)));
+        b->voltab_host = vt;
+        b->cpytab_host = ct;
+    }
     char *w = static_cast<char *>(ws);
     TileArgs a{};
     a.hdr = P.hdr.as<const TileHdrK>();
@@ -1630,7 +1679,6 @@ se_status se_subcycle_batched(se_batch *b, const se_params *p, se_state *st, con
     a.eta_w = w + L.eta_alt;
     a.U_u = st->U;
     a.U_w = w + L.U_alt;
-    const size_t es = f32 ? 4 : 8;
     const size_t lds = f32 ? P.lds_bytes32 : P.lds_bytes64;
     HIP_TRY(prepare_tile(f32, 0, P.ept, P.block), "batched prepare");
 
@@ -1643,25 +1691,17 @@ se_status se_subcycle_batched(se_batch *b, const se_params *p, se_state *st, con
             a.ntiles = cnt;
             HIP_TRY(launch_tile(f32, 0, P.ept, P.block, a, cnt, lds, s), "batched launch");
         }
-        int64_t vout = 0;
-        for (size_t i = 0; i < n; ++i) {
-            if (Lm[i] % 2 == 1) {   // this member's final state sits in the ping-pong buffers
-                HIP_TRY(hipMemcpyAsync(static_cast<char *>(st->eta) + b->voff[i] * es,
-                                       w + L.eta_alt + b->voff[i] * es, b->h[i].nv * es,
-                                       hipMemcpyDeviceToDevice, s), "batched copy eta");
-                HIP_TRY(hipMemcpyAsync(static_cast<char *>(st->U) + 2 * b->eoff[i] * es,
-                                       w + L.U_alt + 2 * b->eoff[i] * es, 2 * b->h[i].ne * es,
-                                       hipMemcpyDeviceToDevice, s), "batched copy U");
-            }
-            const int64_t rows = batch_vol_rows(p, nsub, i);
-            if (st->volume) {
-                const double add = f32 ? p->eta_ref * b->atot[i] : 0.0;
-                HIP_TRY(launch_vol_reduce(a.vol_part + L.vol_off[i], b->mtiles[i],
-                                          static_cast<int32_t>(rows), add, st->volume + vout, s),
-                        "batched volume");
-            }
-            vout += rows;
-        }
+        HIP_TRY(launch_copy_ranges(reinterpret_cast<const uint32_t *>(w + L.eta_alt),
+                                   static_cast<uint32_t *>(st->eta),
+                                   reinterpret_cast<const uint32_t *>(w + L.U_alt),
+                                   static_cast<uint32_t *>(st->U),
+                                   b->cpytab.as<const CopyRange>(),
+                                   static_cast<int32_t>(b->cpytab_host.size()), cwords, s),
+                "batched copy of final states");
+        if (st->volume)
+            HIP_TRY(launch_vol_reduce_batch(a.vol_part, b->voltab.as<const VolMember>(),
+                                            static_cast<int32_t>(n), vrows, st->volume, s),
+                    "batched volume");
         return SE_OK;
     };
 
