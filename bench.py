@@ -457,8 +457,8 @@ def main():
                     help="time only the trim/z*, forcing and viscous-term kernels (profiling)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only; multi-GPU sharding is designed "
-              "but not implemented, so --gpus must be 1", file=sys.stderr)
+        print("bench.py: the benchmark runs on one GPU only (sharding over GPUs is designed "
+              "but not implemented), so --gpus must be 1", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -54,7 +54,7 @@ typedef enum {
     SE_ERR_CFL = 5,         /* dt_s beyond the stability bound (SE_CHECK_CFL)        */
     SE_ERR_DRY = 6,         /* reserved: reported through se_check_faults            */
     SE_ERR_NONFINITE = 7,   /* reserved: reported through se_check_faults            */
-    SE_ERR_UNSUPPORTED = 8  /* valid request this build does not implement           */
+    SE_ERR_UNSUPPORTED = 8  /* valid request the library does not implement         */
 } se_status;
 
 typedef enum { SE_F64 = 0, SE_F32_MIXED = 1 } se_precision;
