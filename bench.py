@@ -228,10 +228,18 @@ def bench_adjoint(args, log):
                           dt=case["tau"], params=p, workspace=ws)
         fwd()
         msf = _time(fwd, 5)
+        # operations in stream order, each waiting for the previous one: two kernels
+        # per forward substep of the sweep (nsub - 1) and of each segment's recompute,
+        # two per reverse substep, the seed and final kernels, two gradient copies
+        nsub, k = case["nsub"], case["ckpt_every"]
+        segs = [min(k, nsub - m0) for m0 in range(0, nsub, k)]
+        nops = 2 * (nsub - 1) + sum(2 * (L - 1) + 2 * L for L in segs) + 2 + 2
         out[prec] = {"ms_adjoint": ms, "ms_adjoint_graph": ms_graph, "ms_forward": msf,
-                     "adjoint_over_forward": ms / msf}
+                     "adjoint_over_forward": ms / msf, "dependent_launches": nops,
+                     "us_per_launch": 1e3 * ms_graph / nops}
         log(f"[bench] adjoint {prec}: {ms:.3f} ms, graph replay {ms_graph:.3f} ms "
-            f"(forward {msf:.3f} ms)")
+            f"(forward {msf:.3f} ms; {nops} dependent launches, "
+            f"{1e3 * ms_graph / nops:.1f} us each)")
     return out
 
 
