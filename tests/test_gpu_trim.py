@@ -61,9 +61,10 @@ def test_trim_matches_oracle_small(kind, with_w):
         assert _rel(a, b) <= 1e-12
 
 
-@pytest.mark.parametrize("K", [1, 2, 63, 64])
+@pytest.mark.parametrize("K", [1, 2, 9, 20, 27, 45, 55, 63, 64])
 def test_trim_layer_count_limits(K):
-    """One layer (the trim is then U = <<U>>), and the largest column the kernels take."""
+    """One layer (the trim is then U = <<U>>), the largest column the kernels take, and
+    every count of layers per lane (ceil(K / 8) = 1 .. 8, ragged last block)."""
     from paper_2311_08241_amd import Mesh
     case = sesynth.random_case(sesynth.tiny_mesh("chan54"), seed=4, nsub=24)
     om, inp = _inputs(case, K, 3, True)
