@@ -2,7 +2,8 @@
 
 FP64: equal to the oracle's adjoint to 1e-12 relative (same operations in the
 same order); identical for every checkpoint interval; central finite
-differences of the GPU forward agree to 1e-6.  FP32: within 1e-4 of the
+differences of the GPU forward agree to 1e-6; with the depth frozen the
+dot-product identity against the GPU forward holds to 1e-12.  FP32: within 1e-4 of the
 FP64 oracle adjoint.
 """
 import numpy as np
@@ -133,6 +134,43 @@ def test_adjoint_c5_loss_against_central_differences():
         fd = (loss(*xp) - loss(*xm)) / (2 * h)
         an = float(torch.sum(grads[i] * dirn))
         assert abs(fd - an) <= 1e-6 * abs(an), (i, fd, an)
+
+
+@pytest.mark.parametrize("kind", ["jitter76", "sphere86", "c5s"])
+def test_adjoint_dot_product_against_gpu_forward(kind):
+    """With the triangle depth frozen at mean(H0) the subcycle map
+    (eta0, U0, R) -> (eta^M, U^M, <<U>>) is linear, so the adjoint must satisfy
+    <lam, F(d)> = <F^T lam, d> for any direction d and seed lam.  Both sides come
+    from the library (forward on the tile path, adjoint with recompute), so this
+    pins the adjoint to the forward without the oracle."""
+    if kind == "c5s":
+        case = _c5_small()
+        case["linear_h"] = True
+    else:
+        case = sesynth.random_case(sesynth.tiny_mesh(kind), seed=12, nsub=11, linear_h=True)
+        if kind == "sphere86":
+            case["tau"] = 11 * 20.0
+    mesh, params, d = _setup(case)
+    r = sesynth.rng(13)
+    t = lambda a: torch.tensor(a, dtype=torch.float64, device="cuda:0").contiguous()
+    de = t(r.standard_normal(mesh.nv))
+    dU = t(50.0 * r.standard_normal((mesh.ne, 2)))
+    dR = t(0.05 * r.standard_normal((mesh.ne, 2)))
+    eta, U = de.clone(), dU.clone()
+    Uavg = torch.zeros((mesh.ne, 2), dtype=torch.float64, device="cuda:0")
+    mesh.subcycle(eta, U, R=dR, f=d["f"], H0=d["H0"], nsub=case["nsub"], dt=case["tau"],
+                  params=params, Uavg=Uavg)
+    le = t(r.standard_normal(mesh.nv))
+    lU = t(r.standard_normal((mesh.ne, 2)))
+    lUa = t(r.standard_normal((mesh.ne, 2)))
+    ge, gU, gR, _ = mesh.adjoint(de, dU, R=dR, f=d["f"], H0=d["H0"], nsub=case["nsub"],
+                                 dt=case["tau"], params=params, ckpt_every=4,
+                                 lam_eta=le, lam_U=lU, lam_Uavg=lUa)
+    lhs_terms = torch.cat([le * eta, (lU * U).flatten(), (lUa * Uavg).flatten()])
+    rhs_terms = torch.cat([ge * de, (gU * dU).flatten(), (gR * dR).flatten()])
+    lhs, rhs = float(lhs_terms.sum()), float(rhs_terms.sum())
+    scale = float(lhs_terms.abs().sum()) + float(rhs_terms.abs().sum())
+    assert abs(lhs - rhs) <= 1e-12 * scale, (lhs, rhs, scale)
 
 
 def test_adjoint_fp32_within_budget():
