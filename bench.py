@@ -229,11 +229,15 @@ def bench_adjoint(args, log):
         fwd()
         msf = _time(fwd, 5)
         # operations in stream order, each waiting for the previous one: two kernels
-        # per forward substep of the sweep (nsub - 1) and of each segment's recompute,
-        # two per reverse substep, the seed and final kernels, two gradient copies
+        # per forward substep of the sweep (up to the last checkpoint) and of the last
+        # segment's recompute; per segment, two per reverse substep, the recompute of the
+        # previous segment sharing those launches; the seed and final kernels, two
+        # gradient copies
         nsub, k = case["nsub"], case["ckpt_every"]
         segs = [min(k, nsub - m0) for m0 in range(0, nsub, k)]
-        nops = 2 * (nsub - 1) + sum(2 * (L - 1) + 2 * L for L in segs) + 2 + 2
+        nops = (2 * (len(segs) - 1) * k + 2 * (segs[-1] - 1)
+                + sum(2 * max(L, segs[i - 1] - 1 if i > 0 else 0) for i, L in enumerate(segs))
+                + 2 + 2)
         out[prec] = {"ms_adjoint": ms, "ms_adjoint_graph": ms_graph, "ms_forward": msf,
                      "adjoint_over_forward": ms / msf, "dependent_launches": nops,
                      "us_per_launch": 1e3 * ms_graph / nops}

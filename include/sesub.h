@@ -213,7 +213,8 @@ se_status se_subcycle_plain(se_mesh *mesh, const se_params *params, se_state *st
  * (plain sums over array entries) writes dJ/d eta^0, dJ/d U^0, dJ/dR, dJ/dH0.
  * Seeds may be NULL (zero); outputs may be NULL (not computed).  The forward
  * trajectory is recomputed from checkpoints stored every ckpt_every substeps
- * (1 <= ckpt_every <= nsub).  eta0/U0 are the forward inputs and are not
+ * (1 <= ckpt_every <= nsub); each segment's recompute runs in the same launches
+ * as the reverse substeps of the segment after it.  eta0/U0 are the forward inputs and are not
  * modified.  Element types follow params.precision; lam_Uavg is double. */
 se_status se_subcycle_adjoint(se_mesh *mesh, const se_params *params, const void *eta0,
                               const void *U0, const se_forcing *forcing, int32_t nsub,

@@ -302,7 +302,7 @@ Layout fwd_layout(int64_t nv, int64_t ne, bool f32, int32_t nsub, int64_t width,
 }
 
 struct AdjLayout {
-    size_t ckpt, traj, lam_eta, lam_U, psi, gR, gH0, total;
+    size_t ckpt, traj[2], lam_eta, lam_U, psi, gR, gH0, total;
     int32_t nseg, k;
 };
 
@@ -315,7 +315,11 @@ AdjLayout adj_layout(int64_t nv, int64_t ne, bool f32, int32_t nsub, int32_t k, 
     size_t o = base;
     L.ckpt = o;
     o += st * L.nseg;
-    L.traj = o;
+    // two segment buffers: the reverse sweep of one segment reads one while the
+    // recompute of the previous segment writes the other
+    L.traj[0] = o;
+    o += st * k;
+    L.traj[1] = o;
     o += st * k;
     L.lam_eta = o;
     o += al(nv * s);
@@ -1248,23 +1252,36 @@ se_status se_subcycle_adjoint(se_mesh *m, const se_params *p, const void *eta0, 
 
     // 1. forward sweep storing a checkpoint every k substeps: state m (m = q k) in
     // checkpoint slot q, the caller's eta0, U0 standing for slot 0; the states between
-    // checkpoints in the segment slots j = m mod k (no copies: each substep writes its
-    // result into its slot)
+    // checkpoints go to segment buffer 0 (no copies: each substep writes its result into
+    // its slot).  The sweep stops at the last checkpoint: the states after it are
+    // recomputed by the reverse sweep anyway.
     const int32_t k = A.k;
     auto ckpt_eta = [&](int32_t q) -> const void * { return q == 0 ? eta0 : st_eta(A.ckpt + st_bytes * q); };
     auto ckpt_U = [&](int32_t q) -> const void * { return q == 0 ? U0 : st_U(A.ckpt + st_bytes * q); };
+    // state j of segment sg (j = 0: its checkpoint; else segment buffer sg mod 2)
+    auto seg_off = [&](int32_t sg, int32_t j) { return A.traj[sg & 1] + st_bytes * j; };
+    auto seg_eta = [&](int32_t sg, int32_t j) -> const void * {
+        return j == 0 ? ckpt_eta(sg) : st_eta(seg_off(sg, j));
+    };
+    auto seg_U = [&](int32_t sg, int32_t j) -> const void * {
+        return j == 0 ? ckpt_U(sg) : st_U(seg_off(sg, j));
+    };
     {
         const void *ce = eta0, *cU = U0;
-        for (int32_t mm = 0; mm + 1 < nsub; ++mm) {
-            const int32_t n1 = mm + 1;   // index of the state this substep produces
-            const size_t dst = n1 % k == 0 ? A.ckpt + st_bytes * (n1 / k) : A.traj + st_bytes * (n1 % k);
+        const int32_t last_ckpt = (A.nseg - 1) * k;
+        for (int32_t n1 = 1; n1 <= last_ckpt; ++n1) {   // n1: index of the state produced
+            const size_t dst = n1 % k == 0 ? A.ckpt + st_bytes * (n1 / k) : seg_off(0, n1 % k);
             SE_TRY(fstep(ce, cU, dst));
             ce = st_eta(dst);
             cU = st_U(dst);
         }
     }
 
-    // 2. reverse sweep, segment by segment, recomputing each segment's states
+    // 2. reverse sweep, segment by segment.  Segment sg (substeps m0 .. m1 - 1) needs its
+    // states m0 + 1 .. m1 - 1, recomputed from its checkpoint into segment buffer sg mod 2.
+    // The last segment is recomputed alone; every other segment's recompute runs in the
+    // same launches as the reverse substeps of the segment after it (independent work on
+    // disjoint buffers), which halves the chain of dependent launches.
     AdjArgs aa{};
     aa.nv = nv;
     aa.ne = ne;
@@ -1285,17 +1302,30 @@ se_status se_subcycle_adjoint(se_mesh *m, const se_params *p, const void *eta0, 
     aa.rM = 1.0 / static_cast<double>(nsub);
     aa.thrM = p->theta * aa.rM;
     HIP_TRY(launch_adj_init(f32, aa, lam_eta, lam_U, s), "adjoint: init");
+    auto seg_len = [&](int32_t sg) { return std::min(nsub, sg * k + k) - sg * k; };
+    {
+        const int32_t sg = A.nseg - 1;
+        for (int32_t j = 1; j < seg_len(sg); ++j)
+            SE_TRY(fstep(seg_eta(sg, j - 1), seg_U(sg, j - 1), seg_off(sg, j)));
+    }
     for (int32_t sg = A.nseg - 1; sg >= 0; --sg) {
-        // recompute the segment's states m0 + 1 .. m1 - 1 from its checkpoint
-        const int32_t m0 = sg * k, m1 = std::min(nsub, m0 + k);
-        for (int32_t j = 1; j < m1 - m0; ++j) {
-            const void *se = j == 1 ? ckpt_eta(sg) : st_eta(A.traj + st_bytes * (j - 1));
-            const void *sU = j == 1 ? ckpt_U(sg) : st_U(A.traj + st_bytes * (j - 1));
-            SE_TRY(fstep(se, sU, A.traj + st_bytes * j));
-        }
-        for (int32_t mm = m1 - 1; mm >= m0; --mm) {
-            aa.eta_m = mm == m0 ? ckpt_eta(sg) : st_eta(A.traj + st_bytes * (mm - m0));
-            HIP_TRY(launch_adj_step(f32, aa, s), "adjoint: reverse substep");
+        const int32_t nrev = seg_len(sg);                 // reverse substeps of sg
+        const int32_t nrec = sg > 0 ? seg_len(sg - 1) - 1 : 0;   // recompute of sg - 1
+        for (int32_t i = 0; i < std::max(nrev, nrec); ++i) {
+            const bool rev = i < nrev, rec = i < nrec;
+            if (rev) aa.eta_m = seg_eta(sg, nrev - 1 - i);
+            if (rec) {
+                fa.eta_src = seg_eta(sg - 1, i);
+                fa.U_src = seg_U(sg - 1, i);
+                fa.eta = st_eta(seg_off(sg - 1, i + 1));
+                fa.U = st_U(seg_off(sg - 1, i + 1));
+            }
+            if (rev && rec)
+                HIP_TRY(launch_adj_pair(f32, aa, fa, s), "adjoint: reverse substep and recompute");
+            else if (rev)
+                HIP_TRY(launch_adj_step(f32, aa, s), "adjoint: reverse substep");
+            else
+                HIP_TRY(launch_plain_step(f32, fa, s), "adjoint: recompute");
         }
     }
     HIP_TRY(launch_adj_final(f32, aa, s), "adjoint: final");

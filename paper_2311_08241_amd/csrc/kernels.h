@@ -106,6 +106,9 @@ hipError_t launch_plain_step(bool f32, const PlainArgs &a, hipStream_t s);
 hipError_t launch_vol_reduce(const double *part, int64_t width, int32_t rows, double add,
                              double *out, hipStream_t s);
 hipError_t launch_adj_step(bool f32, const AdjArgs &a, hipStream_t s);
+// A reverse substep (rev) and a forward state-only substep (fwd, fwd_only set) of the
+// same mesh in two launches instead of four; the two must touch disjoint arrays.
+hipError_t launch_adj_pair(bool f32, const AdjArgs &rev, const PlainArgs &fwd, hipStream_t s);
 // lam_eta = seed or 0; lam_U = seed + thrM * lam_Uavg; gR = gH0 = 0
 hipError_t launch_adj_init(bool f32, const AdjArgs &a, const void *seed_eta, const void *seed_U,
                            hipStream_t s);

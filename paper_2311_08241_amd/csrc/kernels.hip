@@ -151,10 +151,10 @@ template <bool F32> struct SumT {
 // ---------------------------------------------------------------------------
 // Plain two-kernel path
 // ---------------------------------------------------------------------------
+// Triangle phase of one plain substep for triangle e (any e; out of range returns).
 template <typename T, bool F32>
-__global__ void __launch_bounds__(256) k_plain_tri(PlainArgs a) {
+__device__ __forceinline__ void plain_tri_at(const PlainArgs &a, int64_t e) {
     using T2 = typename Vec2<T>::type;
-    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (e >= a.ne) return;
     const StepC &c = a.c;
     const T *eta = static_cast<const T *>(a.eta_src ? a.eta_src : a.eta);
@@ -212,6 +212,34 @@ __global__ void __launch_bounds__(256) k_plain_tri(PlainArgs a) {
 }
 
 template <typename T, bool F32>
+__global__ void __launch_bounds__(256) k_plain_tri(PlainArgs a) {
+    plain_tri_at<T, F32>(a, static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x);
+}
+
+// Vertex phase of one plain substep for vertex v < nv: the new elevation, and the
+// volume terms A_v eta of the new and old elevation.
+template <typename T, bool F32>
+__device__ __forceinline__ void plain_vtx_at(const PlainArgs &a, int64_t v, double &v_new,
+                                             double &v_old) {
+    const StepC &c = a.c;
+    T *eta = static_cast<T *>(a.eta);
+    const T *phi = static_cast<const T *>(a.phi);
+    T acc = T(0);
+    const int32_t j1 = a.row_ptr[v + 1];
+    for (int32_t j = a.row_ptr[v]; j < j1; ++j) acc += phi[a.pcol[j]];
+    const T eo = a.eta_src ? static_cast<const T *>(a.eta_src)[v] : eta[v];
+    const T wv = a.W ? static_cast<const T *>(a.W)[v] : T(0);
+    const T av = static_cast<const T *>(a.Av)[v];
+    const T en = F32 ? vtx_update_f32(eo, acc, T(1) / av, wv, cdts<T>(c))
+                     : eo - cdts<T>(c) * (acc / av + wv);
+    eta[v] = en;
+    if (!finite_val(en)) set_fault(a.faults, 2u);
+    const double av64 = a.Av64[v];
+    v_new = av64 * (double)en;
+    v_old = av64 * (double)eo;
+}
+
+template <typename T, bool F32>
 __global__ void __launch_bounds__(256) k_plain_vtx(PlainArgs a) {
     __shared__ double red[2][4];
     const int64_t v = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -219,23 +247,7 @@ __global__ void __launch_bounds__(256) k_plain_vtx(PlainArgs a) {
     const bool first = a.m == 0, last = a.m == c.nsub - 1;
     const bool track = (c.flags & KF_TRACK_VOLUME) != 0;
     double v_new = 0.0, v_old = 0.0;
-    if (v < a.nv) {
-        T *eta = static_cast<T *>(a.eta);
-        const T *phi = static_cast<const T *>(a.phi);
-        T acc = T(0);
-        const int32_t j1 = a.row_ptr[v + 1];
-        for (int32_t j = a.row_ptr[v]; j < j1; ++j) acc += phi[a.pcol[j]];
-        const T eo = a.eta_src ? static_cast<const T *>(a.eta_src)[v] : eta[v];
-        const T wv = a.W ? static_cast<const T *>(a.W)[v] : T(0);
-        const T av = static_cast<const T *>(a.Av)[v];
-        const T en = F32 ? vtx_update_f32(eo, acc, T(1) / av, wv, cdts<T>(c))
-                         : eo - cdts<T>(c) * (acc / av + wv);
-        eta[v] = en;
-        if (!finite_val(en)) set_fault(a.faults, 2u);
-        const double av64 = a.Av64[v];
-        v_new = av64 * (double)en;
-        v_old = av64 * (double)eo;
-    }
+    if (v < a.nv) plain_vtx_at<T, F32>(a, v, v_new, v_old);
     if (a.fwd_only || !(track || first || last)) return;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     v_new = wave_sum(v_new);
@@ -1135,10 +1147,10 @@ __global__ void __launch_bounds__(BLOCK) k_tile(TileArgs a) {
 // ---------------------------------------------------------------------------
 // Adjoint of one substep (reverse of the triangle and vertex phases)
 // ---------------------------------------------------------------------------
+// Reverse triangle phase for triangle e (any e; out of range returns).
 template <typename T, bool F32>
-__global__ void __launch_bounds__(256) k_adj_tri(AdjArgs a) {
+__device__ __forceinline__ void adj_tri_at(const AdjArgs &a, int64_t e) {
     using T2 = typename Vec2<T>::type;
-    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (e >= a.ne) return;
     const StepC &c = a.c;
     const T dts = cdts<T>(c), g = cg<T>(c), th = cth<T>(c), opt = copt<T>(c);
@@ -1211,9 +1223,14 @@ __global__ void __launch_bounds__(256) k_adj_tri(AdjArgs a) {
     lU[e] = lo;
 }
 
+template <typename T, bool F32>
+__global__ void __launch_bounds__(256) k_adj_tri(AdjArgs a) {
+    adj_tri_at<T, F32>(a, static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x);
+}
+
+// Reverse vertex phase for vertex v (any v; out of range returns).
 template <typename T>
-__global__ void __launch_bounds__(256) k_adj_vtx(AdjArgs a) {
-    const int64_t v = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void adj_vtx_at(const AdjArgs &a, int64_t v) {
     if (v >= a.nv) return;
     const bool nonlin = !(a.c.flags & KF_LINEAR_H);
     T *le = static_cast<T *>(a.lam_eta);
@@ -1232,6 +1249,39 @@ __global__ void __launch_bounds__(256) k_adj_vtx(AdjArgs a) {
     }
     le[v] = acc;
     gH0[v] = gh;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_adj_vtx(AdjArgs a) {
+    adj_vtx_at<T>(a, static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x);
+}
+
+// A reverse substep of one checkpoint segment and an independent forward substep (state
+// update only) of the recompute of the previous segment in one launch: blocks
+// [0, nb_adj) run the reverse phase, the others the forward phase.  The two parts read
+// and write disjoint arrays (the reverse reads the states of its own segment; the
+// forward writes the other segment buffer, its fluxes and nothing the reverse touches),
+// so their order inside the launch does not matter and each element's arithmetic is
+// that of the separate kernels.
+template <typename T, bool F32>
+__global__ void __launch_bounds__(256) k_pair_tri(AdjArgs aa, PlainArgs fa, int32_t nb_adj) {
+    const int64_t b = blockIdx.x;
+    if (b < nb_adj)
+        adj_tri_at<T, F32>(aa, b * 256 + threadIdx.x);
+    else
+        plain_tri_at<T, F32>(fa, (b - nb_adj) * 256 + threadIdx.x);
+}
+
+template <typename T, bool F32>
+__global__ void __launch_bounds__(256) k_pair_vtx(AdjArgs aa, PlainArgs fa, int32_t nb_adj) {
+    const int64_t b = blockIdx.x;
+    if (b < nb_adj) {
+        adj_vtx_at<T>(aa, b * 256 + threadIdx.x);
+    } else {
+        const int64_t v = (b - nb_adj) * 256 + threadIdx.x;
+        double vn, vo;
+        if (v < fa.nv) plain_vtx_at<T, F32>(fa, v, vn, vo);
+    }
 }
 
 template <typename T>
@@ -1410,6 +1460,19 @@ hipError_t launch_adj_step(bool f32, const AdjArgs &a, hipStream_t s) {
     } else {
         hipLaunchKernelGGL((k_adj_tri<double, false>), dim3(ge), dim3(256), 0, s, a);
         hipLaunchKernelGGL((k_adj_vtx<double>), dim3(gv), dim3(256), 0, s, a);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_pair(bool f32, const AdjArgs &rev, const PlainArgs &fwd, hipStream_t s) {
+    if (rev.nv != fwd.nv || rev.ne != fwd.ne || !fwd.fwd_only) return hipErrorInvalidValue;
+    const int ge = static_cast<int>((rev.ne + 255) / 256), gv = static_cast<int>((rev.nv + 255) / 256);
+    if (f32) {
+        hipLaunchKernelGGL((k_pair_tri<float, true>), dim3(2 * ge), dim3(256), 0, s, rev, fwd, ge);
+        hipLaunchKernelGGL((k_pair_vtx<float, true>), dim3(2 * gv), dim3(256), 0, s, rev, fwd, gv);
+    } else {
+        hipLaunchKernelGGL((k_pair_tri<double, false>), dim3(2 * ge), dim3(256), 0, s, rev, fwd, ge);
+        hipLaunchKernelGGL((k_pair_vtx<double, false>), dim3(2 * gv), dim3(256), 0, s, rev, fwd, gv);
     }
     return hipGetLastError();
 }

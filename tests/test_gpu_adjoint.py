@@ -84,14 +84,17 @@ def test_adjoint_fp64_matches_oracle(kind, linear_h):
         assert _rel(g, r) <= 1e-12
 
 
-def test_checkpoint_interval_does_not_change_the_gradient():
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_checkpoint_interval_does_not_change_the_gradient(precision):
     case = _c5_small()
-    mesh, params, d = _setup(case)
+    mesh, params, d = _setup(case, precision)
     le, lU, lUa = _seeds(mesh, case, 8, None)
     eta0, U0 = d["eta"].clone(), d["U"].clone()
-    # every checkpoint interval, including one substep per segment, a ragged last
-    # segment (30 = 4 x 7 + 2) and a single segment
-    outs = [_gpu_adjoint(mesh, params, d, case, le, lU, lUa, ckpt=k) for k in (1, 5, 7, 30)]
+    # every checkpoint interval, including one substep per segment (no recompute, no
+    # paired launches), ragged last segments (30 = 4 x 7 + 2 and 29 + 1) and a single
+    # segment (recompute only)
+    outs = [_gpu_adjoint(mesh, params, d, case, le, lU, lUa, ckpt=k)
+            for k in (1, 2, 5, 7, 29, 30)]
     for o in outs[1:]:
         for a, b in zip(o, outs[0]):
             assert np.array_equal(a, b)
