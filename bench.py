@@ -197,6 +197,24 @@ def bench_adjoint(args, log):
         ws = mesh.workspace(p, case["nsub"], case["ckpt_every"])
         g = [torch.empty_like(d["eta"]), torch.empty_like(d["U"]), torch.empty_like(d["R"]),
              torch.empty_like(d["H0"])]
+        e, U = d["eta"].clone(), d["U"].clone()
+
+        def fwd():
+            mesh.subcycle(e, U, R=d["R"], f=d["f"], H0=d["H0"], nsub=case["nsub"],
+                          dt=case["tau"], params=p, workspace=ws)
+        # tile plan for this mesh (the forward and the adjoint's checkpoint sweep run on
+        # it): the fastest forward among a few shapes that give 64-512 tiles
+        best = None
+        for plan in ((1024, 4, 512), (512, 4, 512), (256, 4, 256), (256, 2, 256),
+                     (128, 4, 256), (128, 2, 256)):
+            if not mesh.plan_stats(*plan)["ok_f32" if prec == "f32" else "ok_f64"]:
+                continue
+            mesh.set_plan(*plan)
+            fwd()
+            t = _time(fwd, 5)
+            if best is None or t < best[0]:
+                best = (t, plan)
+        mesh.set_plan(*best[1])
 
         def adj():
             mesh.adjoint(d["eta"], d["U"], R=d["R"], f=d["f"], H0=d["H0"], nsub=case["nsub"],
@@ -221,24 +239,21 @@ def bench_adjoint(args, log):
         if not all(torch.equal(a, b) for a, b in zip(g, ref)):
             raise RuntimeError("adjoint graph replay differs from the eager gradients")
         ms_graph = _time(graph.replay, 10)
-        e, U = d["eta"].clone(), d["U"].clone()
-
-        def fwd():
-            mesh.subcycle(e, U, R=d["R"], f=d["f"], H0=d["H0"], nsub=case["nsub"],
-                          dt=case["tau"], params=p, workspace=ws)
         fwd()
         msf = _time(fwd, 5)
-        # operations in stream order, each waiting for the previous one: two kernels
-        # per forward substep of the sweep (up to the last checkpoint) and of the last
-        # segment's recompute; per segment, two per reverse substep, the recompute of the
-        # previous segment sharing those launches; the seed and final kernels, two
-        # gradient copies
+        # operations in stream order, each waiting for the previous one: the sweep up to
+        # the last checkpoint, ceil(k / k_fused) tile launches per segment; two kernels
+        # per forward substep of the last segment's recompute; per segment, two per
+        # reverse substep, the recompute of the previous segment sharing those launches;
+        # the seed and final kernels, two gradient copies
         nsub, k = case["nsub"], case["ckpt_every"]
         segs = [min(k, nsub - m0) for m0 in range(0, nsub, k)]
-        nops = (2 * (len(segs) - 1) * k + 2 * (segs[-1] - 1)
+        nchunk = -(-k // best[1][1])
+        nops = (nchunk * (len(segs) - 1) + 2 * (segs[-1] - 1)
                 + sum(2 * max(L, segs[i - 1] - 1 if i > 0 else 0) for i, L in enumerate(segs))
                 + 2 + 2)
-        out[prec] = {"ms_adjoint": ms, "ms_adjoint_graph": ms_graph, "ms_forward": msf,
+        out[prec] = {"plan": list(best[1]), "ms_adjoint": ms, "ms_adjoint_graph": ms_graph,
+                     "ms_forward": msf,
                      "adjoint_over_forward": ms / msf, "dependent_launches": nops,
                      "us_per_launch": 1e3 * ms_graph / nops}
         log(f"[bench] adjoint {prec}: {ms:.3f} ms, graph replay {ms_graph:.3f} ms "

@@ -252,6 +252,10 @@ se_status make_plan(const std::vector<const HostMesh *> &members, const std::vec
     }
     SE_TRY(p->lav64.upload(a64.data(), nlv * 8));
     SE_TRY(p->lav32.upload(a32.data(), nlv * 4));
+    // raise the LDS limit of the forward-backward tile kernels this plan runs now, so
+    // that a later launch needs no attribute call (the adjoint may be graph-captured)
+    for (int f = 0; f < 2; ++f)
+        p->prepared[f] = p->ok(f == 1, false) && prepare_tile(f == 1, 0, p->ept, p->block) == hipSuccess;
     out = std::move(p);
     return SE_OK;
 }
@@ -731,6 +735,44 @@ static se_status check_state(const se_state *st, const se_forcing *fo, const voi
     return SE_OK;
 }
 
+// Launch arguments of the tile kernel on one mesh: plan tables, forcing, workspace
+// (running sum, U^0 copy, volume partials); K substeps per launch, no average output.
+static TileArgs tile_args(const se_mesh *m, const DevTiles &P, bool f32, const se_forcing *fo,
+                          char *w, const Layout &L, const StepC &c) {
+    TileArgs a{};
+    a.hdr = P.hdr.as<const TileHdrK>();
+    a.nV = P.nV.as<const int32_t>();
+    a.nE = P.nE.as<const int32_t>();
+    a.lv_gid = P.lv_gid.as<const int32_t>();
+    a.le_rec = P.le_rec.as<const uint32_t>();
+    a.cs_row = P.cs_row.as<const uint16_t>();
+    a.lgeo = f32 ? P.geo32.p : P.geo64.p;
+    a.lae = f32 ? P.ae32.p : P.ae64.p;
+    a.lv_av = f32 ? P.lav32.p : P.lav64.p;
+    a.mem = nullptr;
+    a.c0 = c;
+    a.R = fo->R;
+    a.f = fo->f;
+    a.H0 = fo->H0;
+    a.W = fo->W;
+    a.Av = f32 ? m->d.Av32.p : m->d.Av64.p;
+    a.Av64 = m->d.Av64.as<const double>();
+    a.sum = w + L.sum;
+    a.U0c = w + L.U0c;
+    a.Uavg = nullptr;
+    a.vol_part = reinterpret_cast<double *>(w + L.vol);
+    a.faults = m->d.faults.as<uint32_t>();
+    a.K = P.K;
+    a.ksub = P.K;
+    a.ntiles = P.ntiles;
+    a.xcd = 1;
+    a.cap_nv = P.max_nv;
+    a.cap_ne = P.max_ne;
+    a.cap_nvu = P.max_nvu;
+    a.cap_cs = P.max_cs;
+    return a;
+}
+
 se_status se_subcycle(se_mesh *m, const se_params *p, se_state *st, const se_forcing *fo,
                       int32_t nsub, double dt, void *ws, void *stream) {
     SE_TRY(check_params(m, p, nsub, dt));
@@ -779,37 +821,9 @@ se_status se_subcycle(se_mesh *m, const se_params *p, se_state *st, const se_for
     c.ntiles = P.ntiles;
     c.vol_off = 0;
 
-    TileArgs a{};
-    a.hdr = P.hdr.as<const TileHdrK>();
-    a.nV = P.nV.as<const int32_t>();
-    a.nE = P.nE.as<const int32_t>();
-    a.lv_gid = P.lv_gid.as<const int32_t>();
-    a.le_rec = P.le_rec.as<const uint32_t>();
-    a.cs_row = P.cs_row.as<const uint16_t>();
-    a.lgeo = f32 ? P.geo32.p : P.geo64.p;
-    a.lae = f32 ? P.ae32.p : P.ae64.p;
-    a.lv_av = f32 ? P.lav32.p : P.lav64.p;
-    a.mem = nullptr;
-    a.c0 = c;
-    a.R = fo->R;
-    a.f = fo->f;
-    a.H0 = fo->H0;
-    a.W = fo->W;
-    a.Av = f32 ? m->d.Av32.p : m->d.Av64.p;
-    a.Av64 = m->d.Av64.as<const double>();
-    a.sum = w + L.sum;
-    a.U0c = w + L.U0c;
+    TileArgs a = tile_args(m, P, f32, fo, w, L, c);
     a.Uavg = st->Uavg;
-    a.vol_part = reinterpret_cast<double *>(w + L.vol);
-    a.faults = m->d.faults.as<uint32_t>();
-    a.K = P.K;
     a.ksub = visc ? P.K / 2 : P.K;
-    a.ntiles = P.ntiles;
-    a.xcd = 1;
-    a.cap_nv = P.max_nv;
-    a.cap_ne = P.max_ne;
-    a.cap_nvu = P.max_nvu;
-    a.cap_cs = P.max_cs;
     void *eta_u = st->eta, *U_u = st->U;
     void *eta_w = w + L.eta_alt, *U_w = w + L.U_alt;
     const int nlaunch = (nsub + a.ksub - 1) / a.ksub;
@@ -1266,7 +1280,38 @@ se_status se_subcycle_adjoint(se_mesh *m, const se_params *p, const void *eta0, 
     auto seg_U = [&](int32_t sg, int32_t j) -> const void * {
         return j == 0 ? ckpt_U(sg) : st_U(seg_off(sg, j));
     };
-    {
+    const DevTiles *TP = m->plan.get();
+    if (TP && TP->ok(f32, false) && TP->prepared[f32 ? 1 : 0]) {
+        // The mesh has a tile plan for this precision: each segment runs as temporally
+        // blocked launches from checkpoint q to checkpoint q + 1 (the tile path equals
+        // the plain path bit for bit).  A segment is a subcycle of k substeps of this
+        // dt_s; chunk i reads state B_i and writes B_{i+1} (B_0, B_n the checkpoints, the
+        // others alternating between two free slots of the segment buffers).
+        StepC c = fa.c;
+        c.nsub = k;
+        c.flags &= ~KF_TRACK_VOLUME;
+        c.ntiles = TP->ntiles;
+        c.vol_off = 0;
+        TileArgs ta = tile_args(m, *TP, f32, fo, w, L, c);
+        const size_t lds = TP->lds(f32, false);
+        const int32_t nch = (k + TP->K - 1) / TP->K;
+        for (int32_t q = 0; q + 1 < A.nseg; ++q) {
+            for (int32_t i = 0; i < nch; ++i) {
+                void *se = i == 0 ? const_cast<void *>(ckpt_eta(q)) : st_eta(seg_off((i - 1) & 1, 1));
+                void *sU = i == 0 ? const_cast<void *>(ckpt_U(q)) : st_U(seg_off((i - 1) & 1, 1));
+                void *de = i + 1 == nch ? st_eta(A.ckpt + st_bytes * (q + 1)) : st_eta(seg_off(i & 1, 1));
+                void *dU = i + 1 == nch ? st_U(A.ckpt + st_bytes * (q + 1)) : st_U(seg_off(i & 1, 1));
+                // an even chunk reads (eta_u, U_u) and writes (eta_w, U_w); an odd one the reverse
+                ta.eta_u = (i & 1) ? de : se;
+                ta.U_u = (i & 1) ? dU : sU;
+                ta.eta_w = (i & 1) ? se : de;
+                ta.U_w = (i & 1) ? sU : dU;
+                ta.chunk = i;
+                HIP_TRY(launch_tile(f32, 0, TP->ept, TP->block, ta, TP->ntiles, lds, s),
+                        "adjoint: forward sweep");
+            }
+        }
+    } else {
         const void *ce = eta0, *cU = U0;
         const int32_t last_ckpt = (A.nseg - 1) * k;
         for (int32_t n1 = 1; n1 <= last_ckpt; ++n1) {   // n1: index of the state produced

@@ -93,6 +93,9 @@ struct DevTiles {
     bool ok32 = false, ok64 = false;
     size_t lds_sm64 = 0, lds_sm32 = 0;   // AB3-AM4 scheme
     bool ok_sm32 = false, ok_sm64 = false;
+    // forward-backward tile kernel of this plan's shape ready to launch (its LDS limit
+    // raised when the plan was made), indexed by f32
+    bool prepared[2] = {false, false};
     size_t lds(bool f32, bool sm) const {
         return sm ? (f32 ? lds_sm32 : lds_sm64) : (f32 ? lds_bytes32 : lds_bytes64);
     }

@@ -95,6 +95,19 @@ def test_checkpoint_interval_does_not_change_the_gradient(precision):
     # segment (recompute only)
     outs = [_gpu_adjoint(mesh, params, d, case, le, lU, lUa, ckpt=k)
             for k in (1, 2, 5, 7, 29, 30)]
+    # once the mesh has a tile plan the checkpoint sweep runs on the tile kernel (K
+    # substeps per launch: 4 gives two launches per 5-substep segment, 2 three, with
+    # the intermediate states alternating between two scratch slots)
+    tried = 0
+    for plan in ((256, 4, 256), (128, 2, 256)):
+        st = mesh.plan_stats(*plan)
+        if not st["ok_f32" if precision == "f32" else "ok_f64"]:
+            continue
+        tried += 1
+        mesh.set_plan(*plan)
+        outs += [_gpu_adjoint(mesh, params, d, case, le, lU, lUa, ckpt=k)
+                 for k in (1, 2, 5, 7, 29, 30)]
+    assert tried > 0
     for o in outs[1:]:
         for a, b in zip(o, outs[0]):
             assert np.array_equal(a, b)
