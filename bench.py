@@ -245,13 +245,13 @@ def bench_adjoint(args, log):
         # the last checkpoint, ceil(k / k_fused) tile launches per segment; two kernels
         # per forward substep of the last segment's recompute; per segment, two per
         # reverse substep, the recompute of the previous segment sharing those launches;
-        # the seed and final kernels, two gradient copies
+        # the seed and final kernels
         nsub, k = case["nsub"], case["ckpt_every"]
         segs = [min(k, nsub - m0) for m0 in range(0, nsub, k)]
         nchunk = -(-k // best[1][1])
         nops = (nchunk * (len(segs) - 1) + 2 * (segs[-1] - 1)
                 + sum(2 * max(L, segs[i - 1] - 1 if i > 0 else 0) for i, L in enumerate(segs))
-                + 2 + 2)
+                + 2)
         out[prec] = {"plan": list(best[1]), "ms_adjoint": ms, "ms_adjoint_graph": ms_graph,
                      "ms_forward": msf,
                      "adjoint_over_forward": ms / msf, "dependent_launches": nops,

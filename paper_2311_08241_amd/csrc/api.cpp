@@ -1373,11 +1373,7 @@ se_status se_subcycle_adjoint(se_mesh *m, const se_params *p, const void *eta0, 
                 HIP_TRY(launch_plain_step(f32, fa, s), "adjoint: recompute");
         }
     }
-    HIP_TRY(launch_adj_final(f32, aa, s), "adjoint: final");
-    if (g_eta0)
-        HIP_TRY(hipMemcpyAsync(g_eta0, aa.lam_eta, nv * es, hipMemcpyDeviceToDevice, s), "g_eta0");
-    if (g_U0)
-        HIP_TRY(hipMemcpyAsync(g_U0, aa.lam_U, 2 * ne * es, hipMemcpyDeviceToDevice, s), "g_U0");
+    HIP_TRY(launch_adj_final(f32, aa, g_eta0, g_U0, s), "adjoint: final");
     return SE_OK;
 }
 

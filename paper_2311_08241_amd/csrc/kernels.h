@@ -112,8 +112,8 @@ hipError_t launch_adj_pair(bool f32, const AdjArgs &rev, const PlainArgs &fwd, h
 // lam_eta = seed or 0; lam_U = seed + thrM * lam_Uavg; gR = gH0 = 0
 hipError_t launch_adj_init(bool f32, const AdjArgs &a, const void *seed_eta, const void *seed_U,
                            hipStream_t s);
-// lam_U -= thrM * lam_Uavg
-hipError_t launch_adj_final(bool f32, const AdjArgs &a, hipStream_t s);
+// lam_U -= thrM * lam_Uavg; g_eta0 = lam_eta, g_U0 = lam_U where not null
+hipError_t launch_adj_final(bool f32, const AdjArgs &a, void *g_eta0, void *g_U0, hipStream_t s);
 // Raise the dynamic-LDS limit of a tile kernel instantiation (call before any
 // stream capture that launches it).
 hipError_t prepare_tile(bool f32, int mode, int ept, int block);

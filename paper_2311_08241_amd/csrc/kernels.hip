@@ -1299,13 +1299,21 @@ __global__ void __launch_bounds__(256) k_adj_init(AdjArgs a, const T *seed_eta, 
     }
 }
 
+// Endpoint term of the average for U^0, and the gradients with respect to the initial
+// state written out (either output may be null).
 template <typename T>
-__global__ void __launch_bounds__(256) k_adj_final(AdjArgs a) {
+__global__ void __launch_bounds__(256) k_adj_final(AdjArgs a, T *g_eta0, T *g_U0) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i < 2 * a.ne && a.lam_Uavg) {
+    if (i < 2 * a.ne) {
         T *lU = static_cast<T *>(a.lam_U);
-        lU[i] = lU[i] - (T)(a.thrM * a.lam_Uavg[i]);
+        T u = lU[i];
+        if (a.lam_Uavg) {
+            u = u - (T)(a.thrM * a.lam_Uavg[i]);
+            lU[i] = u;
+        }
+        if (g_U0) g_U0[i] = u;
     }
+    if (i < a.nv && g_eta0) g_eta0[i] = static_cast<const T *>(a.lam_eta)[i];
 }
 
 // Deterministic sum of each row of partials: out[r] = add + sum_i part[r*width + i].
@@ -1491,12 +1499,14 @@ hipError_t launch_adj_init(bool f32, const AdjArgs &a, const void *seed_eta, con
     return hipGetLastError();
 }
 
-hipError_t launch_adj_final(bool f32, const AdjArgs &a, hipStream_t s) {
-    const int g = static_cast<int>((2 * a.ne + 255) / 256);
+hipError_t launch_adj_final(bool f32, const AdjArgs &a, void *g_eta0, void *g_U0, hipStream_t s) {
+    const int g = static_cast<int>((std::max<int64_t>(a.nv, 2 * a.ne) + 255) / 256);
     if (f32)
-        hipLaunchKernelGGL((k_adj_final<float>), dim3(g), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((k_adj_final<float>), dim3(g), dim3(256), 0, s, a,
+                           static_cast<float *>(g_eta0), static_cast<float *>(g_U0));
     else
-        hipLaunchKernelGGL((k_adj_final<double>), dim3(g), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((k_adj_final<double>), dim3(g), dim3(256), 0, s, a,
+                           static_cast<double *>(g_eta0), static_cast<double *>(g_U0));
     return hipGetLastError();
 }
 
