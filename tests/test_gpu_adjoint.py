@@ -82,6 +82,14 @@ def test_adjoint_fp64_matches_oracle(kind, linear_h):
     ref = _oracle_adjoint(case, le, lU, lUa, W=W)
     for g, r in zip(got, ref):
         assert _rel(g, r) <= 1e-12
+    # the same with a tile plan on the mesh (checkpoint sweep on the tile kernel, two
+    # launches per 4-substep segment): equal to the plain sweep bit for bit
+    plan = (64, 2, 256)
+    assert mesh.plan_stats(*plan)["ok_f64"]
+    mesh.set_plan(*plan)
+    tiled = _gpu_adjoint(mesh, params, d, case, le, lU, lUa, ckpt=4, W=W)
+    for a, b in zip(tiled, got):
+        assert np.array_equal(a, b)
 
 
 @pytest.mark.parametrize("precision", ["f64", "f32"])
