@@ -203,10 +203,12 @@ def bench_adjoint(args, log):
             mesh.subcycle(e, U, R=d["R"], f=d["f"], H0=d["H0"], nsub=case["nsub"],
                           dt=case["tau"], params=p, workspace=ws)
         # tile plan for this mesh (the forward and the adjoint's checkpoint sweep run on
-        # it): the fastest forward among a few shapes that give 64-512 tiles
+        # it): the fastest forward among a few shapes that give 64-512 tiles, with 2-6
+        # substeps per launch (5 or more run a checkpoint segment in one launch)
         best = None
         for plan in ((1024, 4, 512), (512, 4, 512), (256, 4, 256), (256, 2, 256),
-                     (128, 4, 256), (128, 2, 256)):
+                     (128, 4, 256), (128, 2, 256), (256, 5, 256), (128, 5, 256),
+                     (128, 6, 256)):
             if not mesh.plan_stats(*plan)["ok_f32" if prec == "f32" else "ok_f64"]:
                 continue
             mesh.set_plan(*plan)
