@@ -227,14 +227,19 @@ def test_autograd_function_matches_direct_adjoint():
         assert torch.equal(a, b)
 
 
+@pytest.mark.parametrize("plan", [None, (128, 5, 256)])
 @pytest.mark.parametrize("precision", ["f64", "f32"])
-def test_adjoint_captured_in_a_graph_replays_bitwise(precision):
-    """se_subcycle_adjoint issues only kernels and device-to-device copies on the caller's
-    stream, so a caller can capture it in a graph; every replay (with eager adjoint runs
-    and synchronizations in between) equals the eager gradients bit for bit."""
+def test_adjoint_captured_in_a_graph_replays_bitwise(precision, plan):
+    """se_subcycle_adjoint issues only kernels on the caller's stream, so a caller can
+    capture it in a graph; every replay (with eager adjoint runs and synchronizations in
+    between) equals the eager gradients bit for bit.  With a tile plan on the mesh the
+    checkpoint sweep runs on the tile kernel inside the graph."""
     from paper_2311_08241_amd import Mesh, Params, device_inputs
     case = sesynth.adjoint_c5(n=64)
     mesh = Mesh.from_dict(case, device=0)
+    if plan is not None:
+        assert mesh.plan_stats(*plan)["ok_f32" if precision == "f32" else "ok_f64"]
+        mesh.set_plan(*plan)
     p = Params(precision=precision, eta_ref=case["eta_ref"] if precision == "f32" else 0.0)
     d = device_inputs(mesh, case, p)
     lam = torch.linspace(0.5, 1.5, mesh.nv, dtype=p.dtype, device="cuda:0")
