@@ -7,11 +7,12 @@ volume and averaged transport, followed by the averaged transport.  Inputs are
 seeded and synthetic and resident in HBM before timing starts.
 
 Prints one JSON line with: throughput in vertex-substeps/s, the roofline
-position of the dominant kernel (algorithmic bytes per vertex-substep x
-vertex-substeps per launch / average launch time, against 8 TB/s), the plain
+position of the dominant kernel (its compulsory bytes per launch -- one pass
+over the state, forcing, geometry, connectivity and running sums, 236 B per
+vertex in FP32 -- over the average launch time, against 8 TB/s), the plain
 FP64 GPU path and the FP64 fused path on the same workload, errors of the
-timed configuration against the FP64 oracle after one step, and the oracle
-timed on this host's cores.
+timed configuration against the FP64 oracle after 13 steps (1040 substeps),
+and the oracle timed on this host's cores (all cores, and one thread).
 """
 from __future__ import annotations
 
@@ -29,11 +30,16 @@ sys.path.insert(0, ROOT)
 
 METRIC = ("vertex-substeps/s + HBM GB/s, FP32/batched vs FP64 plain at stated η error")
 HBM_PEAK_GBS = 8000.0
-# Algorithmic bytes per vertex-substep of one streaming pass with no on-chip
-# reuse across substeps (r = triangles per vertex ~ 2):
+# Compulsory bytes per vertex of one streaming pass over everything a substep
+# touches (r = triangles per vertex ~ 2):
 #   vertex: eta r+w, H0, 1/A_v, row pointer; triangle: U r+w, R, f, geometry,
 #   connectivity, running sum r+w, CSR column.
+# The tile kernel makes one such pass per launch of k substeps (the state stays on
+# chip in between), so its compulsory traffic per launch is B_ALG x nv.
 B_ALG = {"f32": 236.0, "f64": 356.0}
+# baroclinic steps (13 x 80 = 1040 substeps) after which the errors of the timed
+# configuration are measured against the oracle
+ERR_STEPS = 13
 
 
 def host_cpu():
@@ -95,9 +101,10 @@ def _time(fn, n, stream=None):
     return e0.elapsed_time(e1) / n
 
 
-def bench_batched(args, log):
+def bench_batched(args, log, with_oracle=True):
     """Ensemble of 64 jittered basins (10k-200k vertices, 20-120 substeps): one graph-captured
-    FP32 batched launch sequence vs a per-member loop of the plain FP64 path."""
+    FP32 batched launch sequence vs a per-member loop of the plain FP64 path; both against
+    the FP64 oracle, member by member."""
     import torch
 
     import sesynth
@@ -158,17 +165,32 @@ def bench_batched(args, log):
                        dt=c["tau"], params=p64, Uavg=ua, workspace=w, plain=True)
     loop64()
     torch.cuda.synchronize()
-    e_max = 0.0
-    u_max = 0.0
+    # errors of one step (M_i substeps per member) against the oracle (all host cores)
+    err = {"eta_max": 0.0, "Uavg_max": 0.0, "fp64_eta_max": 0.0, "fp64_Uavg_max": 0.0}
     vo, eo = batch.vert_offset, batch.elem_offset
+    t0 = time.perf_counter()
+    if with_oracle:
+        import oracle
     for i, (m, c, d, ua, w, e0_, u0_) in enumerate(members64):
-        e64 = d["eta"].cpu().numpy()
-        den = np.abs(e64 - eta_ref).max()
-        e_max = max(e_max, float(np.abs(eta32[vo[i]:vo[i + 1]] - e64).max() / den))
-        ua64 = ua.cpu().numpy()
-        u_max = max(u_max, float(np.abs(ua32[eo[i]:eo[i + 1]] - ua64).max() / np.abs(ua64).max()))
+        e64 = m.v_out(d["eta"].cpu().numpy())
+        ua64 = m.e_out(ua.cpu().numpy())
         d["eta"].copy_(e0_)
         d["U"].copy_(u0_)
+        if not with_oracle:
+            continue
+        ref = oracle.run_case(c, nsteps=1, threads=0)
+        om = ref["mesh"]
+        eta_r, ua_r = om.v_out(ref["eta"]), om.e_out(ref["Uavg"])
+        den, uden = np.abs(eta_r - eta_ref).max(), np.abs(ua_r).max()
+        e32 = m.v_out(eta32[vo[i]:vo[i + 1]])
+        u32 = m.e_out(ua32[eo[i]:eo[i + 1]])
+        err["eta_max"] = max(err["eta_max"], float(np.abs(e32 - eta_r).max() / den))
+        err["Uavg_max"] = max(err["Uavg_max"], float(np.abs(u32 - ua_r).max() / uden))
+        err["fp64_eta_max"] = max(err["fp64_eta_max"], float(np.abs(e64 - eta_r).max() /
+                                                             np.abs(eta_r).max()))
+        err["fp64_Uavg_max"] = max(err["fp64_Uavg_max"], float(np.abs(ua64 - ua_r).max() / uden))
+    if with_oracle:
+        log(f"[bench] ensemble errors vs oracle ({time.perf_counter() - t0:.1f} s): {err}")
     ms64 = _time(loop64, 2)
     log(f"[bench] ensemble FP64 per-member plain loop: {ms64:.2f} ms/step")
     return {"workload": f"{len(cases)} jittered basins, {batch.nv} vertices, substeps "
@@ -177,7 +199,8 @@ def bench_batched(args, log):
             "plan": tune["plan"], "graph": True, "faults": faults,
             "fp64_member_loop": {"value": work / ms64 * 1e3, "ms_per_step": ms64},
             "speedup_vs_fp64_member_loop": ms64 / ms,
-            "eta_max_err_vs_fp64": e_max, "Uavg_max_err_vs_fp64": u_max}
+            "errors_vs_oracle": (dict(err, after="one step (M_i substeps) per member")
+                                 if with_oracle else None)}
 
 
 def bench_adjoint(args, log):
@@ -548,15 +571,20 @@ def main():
             f"cached={tune['cached']})")
     plan = mesh.get_plan()
 
-    # one step from the initial state, for the error report
-    step()
+    # ERR_STEPS chained steps from the initial state at the timed plan, for the error
+    # report against the oracle
+    vol_0 = None
+    for k in range(ERR_STEPS):
+        step()
+        if k == 0:
+            vol_0 = float(vol[0].item())   # volume of the initial state
     torch.cuda.synchronize()
     if mesh.check_faults():
         raise RuntimeError("kernel fault flags set")
-    eta_1 = d["eta"].double().cpu().numpy() + (params.eta_ref if prec == "f32" else 0.0)
-    Uavg_1 = Uavg.cpu().numpy()
-    vol_0 = float(vol[0].item())   # volume of the initial state
-    log(f"[bench] plan tile,k,block={plan}; first step done ({time.time() - t0:.1f}s)")
+    eta_err = d["eta"].double().cpu().numpy() + (params.eta_ref if prec == "f32" else 0.0)
+    Uavg_err = Uavg.cpu().numpy()
+    log(f"[bench] plan tile,k,block={plan}; {ERR_STEPS} steps for the error report done "
+        f"({time.time() - t0:.1f}s)")
 
     for _ in range(args.warmup):
         step()
@@ -576,25 +604,33 @@ def main():
     value = vsub / (ms * 1e-3)
     # volume drift over every step run so far (first, warm-up and timed), FP64 accumulator
     atot = float(mesh.geometry()[0].sum())
-    volume_drift = {"steps": 1 + args.warmup + args.steps,
+    volume_drift = {"steps": ERR_STEPS + args.warmup + args.steps,
                     "rel": abs(float(vol[-1].item()) - vol_0) /
                     (atot * float(np.abs(case["eta0"]).max()))}
     log(f"[bench] timed {args.steps} steps: {ms:.2f} ms, {value:.3e} vertex-substeps/s")
 
-    # roofline of the dominant kernel: the tile kernel runs ceil(nsub/k) launches per step
-    nlaunch = -(-nsub // plan[1]) * args.steps
-    avg_launch_s = ms * 1e-3 / nlaunch
-    units_per_launch = float(mesh.nv) * nsub / -(-nsub // plan[1])
-    achieved = B_ALG[prec] * units_per_launch / avg_launch_s / 1e9
+    # roofline of the dominant kernel: the tile kernel runs ceil(nsub/k) launches per
+    # step, each one compulsory pass (B_ALG bytes per vertex) for k substeps
+    launches_per_step = -(-nsub // plan[1])
+    avg_launch_s = ms * 1e-3 / (launches_per_step * args.steps)
+    units_per_launch = float(mesh.nv)
+    compulsory = B_ALG[prec] * units_per_launch
+    achieved = compulsory / avg_launch_s / 1e9
+    # the same bytes counted once per substep (what a kernel streaming every substep
+    # from HBM would have to move for this rate)
+    effective = compulsory * nsub / launches_per_step / avg_launch_s / 1e9
     traffic = read_traffic(f"{tag}_{prec}", plan)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic, "kernel": "k_tile",
+                "unit_of_work": "vertex (one compulsory pass per launch of k substeps)",
+                "bytes_per_unit": B_ALG[prec], "units_per_launch": units_per_launch,
+                "avg_launch_us": round(avg_launch_s * 1e6, 2),
                 "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                 "hbm_frac_measured": (None if traffic is None else
                                       round(traffic / avg_launch_s / 1e9 / HBM_PEAK_GBS, 4)),
-                "avg_launch_us": round(avg_launch_s * 1e6, 2),
-                "bytes_per_unit": B_ALG[prec], "units_per_launch": units_per_launch}
+                "traffic_ratio": (None if traffic is None else round(traffic / compulsory, 4)),
+                "effective_gbs": round(effective, 1)}
 
     extra = {}
     if not args.no_extra:
@@ -642,38 +678,55 @@ def main():
         t0 = time.time()
         om = oracle.Mesh(case, reordered=True)
         log(f"[bench] oracle mesh {time.time() - t0:.1f}s")
-        H0, f, R = om.v_in(case["H0"]), om.e_in(case["f"]), om.e_in(case["R"])
+        kw = dict(H0=om.v_in(case["H0"]), f=om.e_in(case["f"]), R=om.e_in(case["R"]),
+                  g=case["g"], theta=case["theta"], nsub=nsub, tau=tau, linear_h=False,
+                  volume=True)
         eta, U = om.v_in(case["eta0"]), om.e_in(case["U0"])
-        # three chained baroclinic steps (10-20 s of one core); the first one's result
-        # is the reference for the error report
-        nstep_cpu = 3
-        t0 = time.perf_counter()
-        eta_o, U_o, Uavg_o, _ = om.subcycle(eta, U, H0=H0, f=f, R=R, g=case["g"],
-                                            theta=case["theta"], nsub=nsub, tau=tau,
-                                            linear_h=False, volume=True)
-        e_c, U_c = eta_o, U_o
-        for _ in range(nstep_cpu - 1):
-            e_c, U_c, _, _ = om.subcycle(e_c, U_c, H0=H0, f=f, R=R, g=case["g"],
-                                         theta=case["theta"], nsub=nsub, tau=tau,
-                                         linear_h=False, volume=True)
-        tcpu = time.perf_counter() - t0
-        cpu = {"value": om.nv * nsub * nstep_cpu / tcpu, "unit": "vertex-substeps/s",
-               "cores": 1, "kind": "oracle", "host_cpu": host_cpu(),
-               "host_cpus": os.cpu_count(),
-               "sample": f"{nstep_cpu} chained baroclinic steps ({nstep_cpu * nsub} substeps) "
-                         f"of the same mesh, FP64, 1 thread, {tcpu:.1f} s"}
-        log(f"[bench] oracle: {tcpu:.1f}s, {cpu['value']:.3e} vertex-substeps/s")
-        # errors of the benchmarked configuration after one step
-        eta_g = mesh.v_out(eta_1)
-        eta_r = om.v_out(eta_o)
-        ua_g = mesh.e_out(Uavg_1)
-        ua_r = om.e_out(Uavg_o)
+        # all cores: the ERR_STEPS chained steps of the error report, each timed
+        t_all = []
+        e_c, U_c = eta, U
+        first = None
+        for k in range(ERR_STEPS):
+            t1 = time.perf_counter()
+            e_c, U_c, ua_c, _ = om.subcycle(e_c, U_c, threads=0, **kw)
+            t_all.append(time.perf_counter() - t1)
+            if k == 0:
+                first = (e_c, U_c, ua_c)
+        cores = om.threads_used
+        # one thread: the first step, three times
+        t_one = []
+        for _ in range(3):
+            t1 = time.perf_counter()
+            o1 = om.subcycle(eta, U, **kw)
+            t_one.append(time.perf_counter() - t1)
+        if not all(np.array_equal(a, b) for a, b in zip(o1[:3], first)):
+            raise RuntimeError("threaded oracle differs from the serial oracle")
+        per_step = om.nv * nsub
+        med_all, med_one = float(np.median(t_all)), float(np.median(t_one))
+        cpu = {"value": per_step / med_all, "unit": "vertex-substeps/s", "cores": cores,
+               "kind": "oracle", "host_cpu": host_cpu(), "host_cpus": os.cpu_count(),
+               "sample": f"median of {ERR_STEPS} chained baroclinic steps ({nsub} substeps "
+                         f"each, {sum(t_all):.1f} s in all) of the same mesh, FP64, "
+                         f"{cores} OpenMP threads (the multithreaded form, equal to the "
+                         f"serial oracle bit for bit)",
+               "single_thread": {"value": per_step / med_one, "cores": 1,
+                                 "sample": f"median of 3 runs of the first baroclinic step, "
+                                           f"{sum(t_one):.1f} s in all"},
+               "speedup_all_cores": med_one / med_all}
+        log(f"[bench] oracle: {cores} threads {med_all:.2f} s/step, 1 thread {med_one:.2f} "
+            f"s/step ({cpu['value']:.3e} / {cpu['single_thread']['value']:.3e} "
+            f"vertex-substeps/s)")
+        # errors of the benchmarked configuration after ERR_STEPS steps
+        eta_g = mesh.v_out(eta_err)
+        eta_r = om.v_out(e_c)
+        ua_g = mesh.e_out(Uavg_err)
+        ua_r = om.e_out(ua_c)
         Av = om.v_out(om.Av)
         Ae = om.e_out(om.Ae)
         ref = case["eta_ref"] if prec == "f32" else 0.0
         den = np.abs(eta_r - ref).max()
         errors = {
-            "after_substeps": nsub,
+            "after_substeps": nsub * ERR_STEPS, "plan": list(plan),
             "eta_max": float(np.abs(eta_g - eta_r).max() / den),
             "eta_rms": float(np.sqrt(np.sum(Av * (eta_g - eta_r) ** 2) /
                                      np.sum(Av * (eta_r - ref) ** 2))),
@@ -684,7 +737,7 @@ def main():
         log(f"[bench] errors vs oracle: {errors}")
 
     if not args.no_extra:
-        extra["batched"] = bench_batched(args, log)
+        extra["batched"] = bench_batched(args, log, not args.no_cpu)
         extra["adjoint"] = bench_adjoint(args, log)
 
     out = {

@@ -1,6 +1,6 @@
 """Copy of a known number of bytes, used to calibrate memory counters.
 
-`python -m paper_2311_08241_amd.calib [MiB]` copies a device buffer of the
+`python calib.py [MiB]` copies a device buffer of the
 given size (default 512 MiB) once after a warm-up copy, so a hardware-counter
 run over it (FETCH_SIZE / WRITE_SIZE per dispatch) can be compared with the
 known byte count and the ratio applied to other kernels' counter readings.

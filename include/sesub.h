@@ -346,6 +346,16 @@ se_status se_forcing_assemble(se_mesh *mesh, int32_t K, const int32_t *nlev, con
                      const double *RP, const double *RhV, const double *tau_s, const double *u,
                      double Cd, int32_t precision, void *R, void *stream);
 
+/* The AB3-AM4 (SE_SCHEME_SESM) coefficients of the paper's setting for the
+ * dissipation of the forward-backward scheme with parameter theta (Sec. 2.2,
+ * Sec. 3.2): chi = theta / 2 (eq. (eqdp_4), SE side: 2 chi = theta);
+ * zeta = 0.010 - 0.135 chi and gamma = 0.083 - 0.514 chi (eq. (eqdp_6), second
+ * line); delta = 2 chi + gamma + 2 zeta + 1/2 (eq. (eqdp_4), SESM side); beta as
+ * given, or 0.281105 (the value with the largest stability range, Sec. 3.2) when
+ * beta <= 0.  Host call, no device work.  out[4] receives beta, delta, gamma, zeta
+ * (the order of se_params).  Errors: SE_ERR_ARG (out NULL, theta not finite). */
+se_status se_sesm_coefficients(double theta, double beta, double *out);
+
 /* Thread-local text of the last error. */
 const char *se_last_error(void);
 

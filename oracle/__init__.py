@@ -34,7 +34,7 @@ def build(force: bool = False) -> str:
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math",
-                               "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+                               "-fopenmp", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -162,10 +162,12 @@ class Mesh:
                 _p(_f64(R, (self.ne, 2))), _p(None if W is None else _f64(W)))
 
     def subcycle(self, eta, U, *, H0, f, R, W=None, g, theta, nsub, tau, linear_h=False,
-                 volume=True, visc=None):
+                 volume=True, visc=None, threads=None):
         """One baroclinic step in this mesh's numbering.  Returns (eta, U, Uavg, volume).
         visc = (A0, Cv) adds the barotropic viscous regularization (eq. (eq:viscosity_BT))
-        and subtracts its initial value from R."""
+        and subtracts its initial value from R.  threads = n (0: the OpenMP default) runs
+        the multithreaded form (same eta, U, Uavg bit for bit; volume summed in fixed
+        blocks); the thread count it used is left in self.threads_used."""
         L = _load()
         eta = _f64(eta).copy()
         U = _f64(U, (self.ne, 2)).copy()
@@ -173,7 +175,13 @@ class Mesh:
         vol = np.empty(nsub + 1) if volume else None
         args = self._common(g, theta, linear_h, H0, f, R, W) + (
             ctypes.c_int32(nsub), ctypes.c_double(tau), _p(eta), _p(U), _p(Uavg), _p(vol))
-        if visc is None:
+        if threads is not None:
+            if visc is not None:
+                raise ValueError("oracle: the threaded subcycle has no viscous term")
+            used = ctypes.c_int(0)
+            _check(L.orc_subcycle_threads(*args, ctypes.c_int(threads), ctypes.byref(used)))
+            self.threads_used = used.value
+        elif visc is None:
             _check(L.orc_subcycle(*args))
         else:
             nb, elen, lod = self.visc_geometry()
@@ -279,8 +287,10 @@ class Mesh:
         return g_eta0, g_U0, g_R, g_H0
 
 
-def run_case(case: dict, nsteps: int | None = None, reordered: bool = True, mesh: Mesh = None):
-    """Run a generated workload through the oracle, in the oracle's reordered numbering.
+def run_case(case: dict, nsteps: int | None = None, reordered: bool = True, mesh: Mesh = None,
+             threads=None):
+    """Run a generated workload through the oracle, in the oracle's reordered numbering
+    (threads: see Mesh.subcycle).
 
     Returns dict(mesh, eta, U, Uavg (last step), volume (all substeps), inputs...).
     """
@@ -294,6 +304,7 @@ def run_case(case: dict, nsteps: int | None = None, reordered: bool = True, mesh
     for _ in range(nsteps):
         eta, U, Uavg, vol = m.subcycle(eta, U, H0=H0, f=f, R=R, W=W, g=case["g"],
                                        theta=case["theta"], nsub=case["nsub"],
-                                       tau=case["tau"], linear_h=case["linear_h"])
+                                       tau=case["tau"], linear_h=case["linear_h"],
+                                       threads=threads)
         vols.append(vol if not vols else vol[1:])
     return dict(mesh=m, eta=eta, U=U, Uavg=Uavg, volume=np.concatenate(vols), H0=H0, f=f, R=R)

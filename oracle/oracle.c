@@ -7,7 +7,8 @@
  * baseline of the benchmark may load this file's library.  It shares no code
  * with the GPU library and must stay slow, plain and obviously correct:
  * loops in the order of the definitions, no blocking, no fusion.
- * Build: gcc -O2 -ffp-contract=off -fno-fast-math -shared -fPIC.
+ * Build: gcc -O2 -ffp-contract=off -fno-fast-math -fopenmp -shared -fPIC (OpenMP
+ * only in orc_subcycle_threads, the all-core timing form of the subcycle).
  *
  * What is computed (readings of the paper fixed where it is silent):
  *  - Continuous problem: the barotropic system of Sec. 2.2, eq. (eq4_5):
@@ -41,6 +42,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define ORC_PERIODIC_X 1u
 #define ORC_PERIODIC_Y 2u
@@ -402,6 +406,109 @@ int orc_subcycle_visc(int64_t nv, int64_t ne, const int32_t *tri, const double *
     orc_visc vs = {nb, elen, lod, A0, Cv};
     return subcycle_core(nv, ne, tri, Ae, gN, Av, g, theta, linear_h, H0, f, R, W, nsub, tau,
                          eta, U, Uavg, volume, &vs);
+}
+
+/*
+ * The subcycle of orc_subcycle on several host threads (OpenMP), for timing the
+ * definition on all cores of a machine.  Same operations, same order per output:
+ *  - the triangle loop computes U', F and the three sub-cell fluxes of each
+ *    triangle exactly as above, storing the fluxes instead of adding them;
+ *  - each vertex then adds its fluxes starting from 0.0 in ascending triangle
+ *    index (its incidences listed by a counting pass over the triangles), which
+ *    is the sequence of additions the triangle-order scatter above makes into
+ *    that vertex's sum;
+ * so eta, U and Uavg equal orc_subcycle's bit for bit for any thread count.  The
+ * volume is summed in fixed blocks of 8192 vertices, the block sums then added in
+ * block order: independent of the thread count, equal to the serial sum up to
+ * rounding.  nthreads <= 0 takes the OpenMP default; *used receives the count.
+ * No viscous term.
+ */
+int orc_subcycle_threads(int64_t nv, int64_t ne, const int32_t *tri, const double *Ae,
+                         const double *gN, const double *Av, double g, double theta,
+                         int linear_h, const double *H0, const double *f, const double *R,
+                         const double *W, int32_t nsub, double tau, double *eta, double *U,
+                         double *Uavg, double *volume, int nthreads, int *used)
+{
+    if (nsub <= 0 || nv <= 0 || ne <= 0) return ORC_ERR_ARG;
+    orc_mesh m = {nv, ne, tri, Ae, gN, Av};
+    const double dts = tau / (double)nsub;
+    const int64_t VB = 8192, nb = (nv + VB - 1) / VB;
+    double *Un = (double *)malloc(sizeof(double) * 2 * ne);
+    double *U0 = (double *)malloc(sizeof(double) * 2 * ne);
+    double *sum = (double *)calloc((size_t)(2 * ne), sizeof(double));
+    double *phi = (double *)malloc(sizeof(double) * 3 * ne);
+    double *part = (double *)malloc(sizeof(double) * nb);
+    int64_t *row = (int64_t *)calloc((size_t)(nv + 1), sizeof(int64_t));
+    int64_t *slot = (int64_t *)malloc(sizeof(int64_t) * 3 * ne);
+    int64_t *cur = (int64_t *)malloc(sizeof(int64_t) * nv);
+    if (!Un || !U0 || !sum || !phi || !part || !row || !slot || !cur) {
+        free(Un); free(U0); free(sum); free(phi); free(part); free(row); free(slot); free(cur);
+        return ORC_ERR_OOM;
+    }
+    for (int64_t i = 0; i < 3 * ne; ++i) {
+        if (tri[i] < 0 || tri[i] >= nv) {
+            free(Un); free(U0); free(sum); free(phi); free(part); free(row); free(slot); free(cur);
+            return ORC_ERR_MESH;
+        }
+        row[tri[i] + 1] += 1;
+    }
+    for (int64_t v = 0; v < nv; ++v) row[v + 1] += row[v];
+    for (int64_t v = 0; v < nv; ++v) cur[v] = row[v];
+    for (int64_t i = 0; i < 3 * ne; ++i) slot[cur[tri[i]]++] = i;   /* 3 e + k, e ascending */
+    memcpy(U0, U, sizeof(double) * 2 * ne);
+    int nt = 1;
+#ifdef _OPENMP
+    nt = nthreads > 0 ? nthreads : omp_get_max_threads();
+#endif
+    if (used) *used = nt;
+#pragma omp parallel num_threads(nt)
+    {
+        for (int32_t s = -1; s < nsub; ++s) {
+            if (s >= 0) {
+#pragma omp for schedule(static)
+                for (int64_t e = 0; e < ne; ++e) {
+                    orc_elem q;
+                    double F[2];
+                    elem_quantities(&m, e, eta, H0, f[e], dts, linear_h, &q);
+                    transport_update(&q, g, dts, U + 2 * e, R + 2 * e, Un + 2 * e);
+                    F[0] = (1.0 + theta) * Un[2 * e] - theta * U[2 * e];
+                    F[1] = (1.0 + theta) * Un[2 * e + 1] - theta * U[2 * e + 1];
+                    for (int k = 0; k < 3; ++k) phi[3 * e + k] = slot_flux(&m, e, k, F);
+                }
+#pragma omp for schedule(static)
+                for (int64_t v = 0; v < nv; ++v) {
+                    double div = 0.0;
+                    for (int64_t j = row[v]; j < row[v + 1]; ++j) div += phi[slot[j]];
+                    eta[v] = eta[v] - dts * (div / Av[v] + (W ? W[v] : 0.0));
+                }
+#pragma omp for schedule(static)
+                for (int64_t i = 0; i < 2 * ne; ++i) {
+                    U[i] = Un[i];
+                    sum[i] += Un[i];
+                }
+            }
+            if (volume) {
+#pragma omp for schedule(static)
+                for (int64_t b = 0; b < nb; ++b) {
+                    double V = 0.0;
+                    const int64_t v1 = (b + 1) * VB < nv ? (b + 1) * VB : nv;
+                    for (int64_t v = b * VB; v < v1; ++v) V += Av[v] * eta[v];
+                    part[b] = V;
+                }
+#pragma omp single
+                {
+                    double V = 0.0;
+                    for (int64_t b = 0; b < nb; ++b) V += part[b];
+                    volume[s + 1] = V;
+                }
+            }
+        }
+#pragma omp for schedule(static)
+        for (int64_t i = 0; i < 2 * ne; ++i)
+            Uavg[i] = sum[i] / (double)nsub + theta / (double)nsub * (U[i] - U0[i]);
+    }
+    free(Un); free(U0); free(sum); free(phi); free(part); free(row); free(slot); free(cur);
+    return ORC_OK;
 }
 
 /* ------------------------------------------------------------------------ */

@@ -73,6 +73,7 @@ _lib = None
 
 _SIGS = {
     "se_last_error": (ctypes.c_char_p, []),
+    "se_sesm_coefficients": (c_int32, [c_double, c_double, c_void_p]),
     "se_mesh_create": (c_int32, [ctypes.POINTER(MeshDesc), c_int32, ctypes.POINTER(c_void_p)]),
     "se_mesh_destroy": (None, [c_void_p]),
     "se_mesh_info": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),

@@ -29,15 +29,12 @@ def _stream_ptr(stream=None):
     return ctypes.c_void_p(s.cuda_stream)
 
 
-def sesm_coefficients(theta: float = 0.14, beta: float = 0.281105):
+def sesm_coefficients(theta: float = 0.14, beta: float = 0.0):
     """(beta, delta, gamma, zeta) of the AB3-AM4 scheme at the dissipation of the
-    forward-backward scheme with this theta: 2 chi = theta (eq. (eqdp_4)); beta of
-    the largest stability limit (Sec. 3.2); zeta, gamma from eq. (eqdp_6), second
-    line; delta from 2 chi = delta - gamma - 2 zeta - 1/2 (eq. (eqdp_4))."""
-    chi = 0.5 * theta
-    zeta = 0.010 - 0.135 * chi
-    gamma = 0.083 - 0.514 * chi
-    return beta, 2.0 * chi + gamma + 2.0 * zeta + 0.5, gamma, zeta
+    forward-backward scheme with this theta (se_sesm_coefficients)."""
+    out = (ctypes.c_double * 4)()
+    L.check(L.lib().se_sesm_coefficients(float(theta), float(beta), out))
+    return tuple(out)
 
 
 @dataclass

@@ -531,6 +531,21 @@ extern "C" {
 
 const char *se_last_error(void) { return g_err.c_str(); }
 
+se_status se_sesm_coefficients(double theta, double beta, double *out) {
+    if (!out || !std::isfinite(theta) || !std::isfinite(beta)) {
+        set_error("se_sesm_coefficients: bad argument");
+        return SE_ERR_ARG;
+    }
+    const double chi = 0.5 * theta;            // SE dissipation 2 chi = theta
+    const double zeta = 0.010 - 0.135 * chi;    // eq. (eqdp_6), second line
+    const double gamma = 0.083 - 0.514 * chi;
+    out[0] = beta > 0.0 ? beta : 0.281105;      // largest stability range (Sec. 3.2)
+    out[1] = 2.0 * chi + gamma + 2.0 * zeta + 0.5;   // eq. (eqdp_4)
+    out[2] = gamma;
+    out[3] = zeta;
+    return SE_OK;
+}
+
 se_status se_mesh_create(const se_mesh_desc *desc, int device, se_mesh **out) {
     if (!desc || !out) {
         set_error("se_mesh_create: null argument");
@@ -540,6 +555,7 @@ se_status se_mesh_create(const se_mesh_desc *desc, int device, se_mesh **out) {
     auto m = std::make_unique<se_mesh>();
     m->device = device;
     SE_TRY(build_host_mesh(*desc, m->h));
+    for (double v : m->h.Av) m->h.Av_total += v;
     if (device < 0) {   // host-only mesh: reordering and geometry, no device arrays
         *out = m.release();
         return SE_OK;
@@ -883,9 +899,7 @@ se_status se_subcycle(se_mesh *m, const se_params *p, se_state *st, const se_for
         const int rows = (p->flags & SE_TRACK_VOLUME) ? nsub + 1 : 2;
         double add = 0.0;
         if (f32) {
-            double atot = 0.0;
-            for (double v : m->h.Av) atot += v;
-            add = p->eta_ref * atot;
+            add = p->eta_ref * m->h.Av_total;
         }
         HIP_TRY(launch_vol_reduce(a.vol_part, P.ntiles, rows, add, st->volume, s), "volume");
     }
@@ -976,9 +990,7 @@ se_status se_subcycle_plain(se_mesh *m, const se_params *p, se_state *st, const 
         const int rows = (p->flags & SE_TRACK_VOLUME) ? nsub + 1 : 2;
         double add = 0.0;
         if (f32) {
-            double atot = 0.0;
-            for (double v : m->h.Av) atot += v;
-            add = p->eta_ref * atot;
+            add = p->eta_ref * m->h.Av_total;
         }
         HIP_TRY(launch_vol_reduce(a.vol_part, a.nblk_v, rows, add, st->volume, s), "volume");
     }
@@ -1525,9 +1537,7 @@ se_status se_batch_create(se_mesh *const *members, int32_t n, se_batch **out) {
     std::vector<double> av;
     av.reserve(b->nv);
     for (const auto &m : b->h) {
-        double s = 0.0;
-        for (double v : m.Av) s += v;
-        b->atot.push_back(s);
+        b->atot.push_back(m.Av_total);
         av.insert(av.end(), m.Av.begin(), m.Av.end());
     }
     if (b->device >= 0) {

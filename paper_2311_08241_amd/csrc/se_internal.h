@@ -27,6 +27,7 @@ struct HostMesh {
     std::vector<int32_t> row_ptr, col;   // vertex -> (tri << 2 | slot)
     std::vector<double> x, y;            // reordered coordinates
     std::vector<double> Ae, gN, Av;      // gN [ne][3][2]
+    double Av_total = 0;                 // sum of Av in vertex order (FP32 volume offset)
     double mu_max = 0;                   // Gershgorin bound of -div grad
 };
 

@@ -2,12 +2,14 @@
 benchmark selects (tile plans of the autotuner's shortlist).
 
   lat-lon 2048x1536, 30% land (2.2M vertices): FP64 one step equal to the
-      oracle to 1e-12; FP32 identical across plans, and within 1e-5 of the
+      oracle to 1e-12; FP32 identical across plans (the benchmark's timed plan
+      464,4,512 and the ensemble's 352,4,512 among them), and within 1e-5 of the
       oracle after 1040 substeps
   channel 1024x512 (0.5M vertices): FP32 within 1e-5 after 1020 substeps
   adjoint basin 256x256: FP64 adjoint equal to the oracle's to 1e-12
-  ensemble of 64 basins: FP32 batched within 1e-5 of the FP64 batched run
-      (itself bit-identical to standalone runs) after 10 steps
+  ensemble of 64 basins (10k-200k vertices, 20-120 substeps): every member of
+      the batched run against the oracle after 10 steps, FP64 within 1e-12 and
+      FP32 within 1e-5
   AB3-AM4 (SESM) scheme: lat-lon FP64 one step equal to the oracle to 1e-12;
       channel FP32 within 1e-5 of the oracle after 1020 substeps
   consumers at 40 layers on the lat-lon mesh: vertically integrated forcing within
@@ -54,11 +56,14 @@ def _oracle_steps(om, case, nsteps):
     eta, U = om.v_in(case["eta0"]), om.e_in(case["U0"])
     for _ in range(nsteps):
         eta, U, Uavg, _ = om.subcycle(eta, U, H0=H0, f=f, R=R, g=case["g"], theta=case["theta"],
-                                      nsub=case["nsub"], tau=case["tau"], volume=False)
+                                      nsub=case["nsub"], tau=case["tau"], volume=False,
+                                      threads=0)
     return om.v_out(eta), om.e_out(Uavg)
 
 
-FP32_PLANS = [(768, 6, 512), (512, 8, 512), (768, 5, 512)]
+# the benchmark's timed plan first (its errors are the ones asserted), then other
+# tile shapes, the ensemble's shipped plan among them
+FP32_PLANS = [(464, 4, 512), (768, 6, 512), (512, 8, 512), (768, 5, 512), (352, 4, 512)]
 
 
 def test_c3_fp64_one_step_equals_oracle():
@@ -78,8 +83,11 @@ def test_c3_fp32_identical_across_plans_and_1040_substep_budget():
         assert np.array_equal(o[0], outs[0][0]) and np.array_equal(o[1], outs[0][1])
     eta_r, ua_r = _oracle_steps(om, case, nsteps)
     e_max = np.abs(outs[0][0] - eta_r).max() / np.abs(eta_r - case["eta_ref"]).max()
+    u_max = np.abs(outs[0][1] - ua_r).max() / np.abs(ua_r).max()
+    print(f"lat-lon FP32 after 1040 substeps: eta e_max {e_max:.2e}, <<U>> e_max {u_max:.2e}",
+          flush=True)
     assert e_max <= 1e-5, e_max
-    assert np.abs(outs[0][1] - ua_r).max() <= 1e-4 * np.abs(ua_r).max()
+    assert u_max <= 1e-5, u_max
 
 
 def test_c2_fp32_1020_substep_budget():
@@ -122,20 +130,19 @@ def test_c5_adjoint_full_size_equals_oracle():
         assert np.abs(a - b).max() <= 1e-12 * np.abs(b).max()
 
 
-def test_c4_ensemble_fp32_budget_10_steps():
+def test_c4_ensemble_members_equal_oracle_10_steps():
     from paper_2311_08241_amd import Batch, Mesh, Params, batch_inputs
     cases = sesynth.batch_c4()
     meshes = [Mesh.from_dict(c, device=0) for c in cases]
     batch = Batch(meshes)
     nsub = [c["nsub"] for c in cases]
-    shortlist = [(512, 6, 512), (512, 4, 512), (384, 4, 512), (256, 4, 256), (128, 2, 256)]
-
-    def first_ok(prec):
-        for pl in shortlist:
-            if batch.plan_stats(*pl)["ok_" + prec]:
-                return pl
-        raise AssertionError("no plan fits")
-    plans = {prec: first_ok(prec) for prec in ("f32", "f64")}
+    # FP32 at the ensemble's shipped plan; FP64 at the first plan of a shortlist that fits
+    plans = {"f32": (352, 4, 512)}
+    for pl in [(352, 4, 512), (256, 4, 256), (128, 2, 256)]:
+        if batch.plan_stats(*pl)["ok_f64"]:
+            plans["f64"] = pl
+            break
+    assert batch.plan_stats(*plans["f32"])["ok_f32"] and "f64" in plans
     dts = [c["tau"] for c in cases]
     eta_ref = float(np.mean(np.concatenate([c["eta0"] for c in cases])))
     res = {}
@@ -143,18 +150,33 @@ def test_c4_ensemble_fp32_budget_10_steps():
         batch.set_plan(*plans[prec])
         p = Params(precision=prec, eta_ref=eta_ref if prec == "f32" else 0.0)
         d = batch_inputs(batch, cases, p)
+        Uavg = torch.empty((batch.ne, 2), dtype=torch.float64, device="cuda:0")
         ws = batch.workspace(p, nsub)
         for _ in range(10):
             batch.subcycle(d["eta"], d["U"], R=d["R"], f=d["f"], H0=d["H0"], nsub=nsub, dt=dts,
-                           params=p, workspace=ws)
+                           params=p, Uavg=Uavg, workspace=ws)
         torch.cuda.synchronize()
         assert batch.check_faults() == 0
-        res[prec] = d["eta"].double().cpu().numpy() + p.eta_ref
-    vo = batch.vert_offset
-    for i in range(len(cases)):
-        a, b = res["f32"][vo[i]:vo[i + 1]], res["f64"][vo[i]:vo[i + 1]]
-        e = np.abs(a - b).max() / np.abs(b - eta_ref).max()
+        res[prec] = (d["eta"].double().cpu().numpy() + p.eta_ref, Uavg.cpu().numpy())
+        del d, ws, Uavg
+    vo, eo = batch.vert_offset, batch.elem_offset
+    worst = 0.0
+    for i, (m, c) in enumerate(zip(meshes, cases)):
+        r = oracle.run_case(c, nsteps=10, threads=0)
+        om = r["mesh"]
+        eta_r, ua_r = om.v_out(r["eta"]), om.e_out(r["Uavg"])
+        e64 = m.v_out(res["f64"][0][vo[i]:vo[i + 1]])
+        u64 = m.e_out(res["f64"][1][eo[i]:eo[i + 1]])
+        assert np.abs(e64 - eta_r).max() <= 1e-12 * np.abs(eta_r).max(), i
+        assert np.abs(u64 - ua_r).max() <= 1e-12 * np.abs(ua_r).max(), i
+        e32 = m.v_out(res["f32"][0][vo[i]:vo[i + 1]])
+        u32 = m.e_out(res["f32"][1][eo[i]:eo[i + 1]])
+        e = np.abs(e32 - eta_r).max() / np.abs(eta_r - eta_ref).max()
+        u = np.abs(u32 - ua_r).max() / np.abs(ua_r).max()
+        worst = max(worst, e)
         assert e <= 1e-5, (i, nsub[i] * 10, e)
+        assert u <= 1e-5, (i, nsub[i] * 10, u)
+    print(f"ensemble FP32 worst member eta e_max {worst:.2e}", flush=True)
 
 
 def _sesm_gpu(mesh, case, prec, plan, nsteps):

@@ -49,6 +49,39 @@ def test_reorder_and_geometry_match_oracle_exactly(name, mesh):
     assert np.array_equal(Av, om.Av) and np.array_equal(Ae, om.Ae) and np.array_equal(gN, om.gN)
 
 
+def _full_size():
+    yield "C2", lambda: sesynth.channel_c2(nsteps=1)
+    yield "C3", lambda: sesynth.latlon_c3(nsteps=1)
+    yield "C5", lambda: sesynth.adjoint_c5()
+
+
+@pytest.mark.parametrize("name,make", list(_full_size()), ids=[c[0] for c in _full_size()])
+def test_full_size_reorder_and_geometry_match_oracle_exactly(name, make):
+    """The workloads at their full sizes (0.5M, 2.2M and 65k vertices): permutations,
+    canonical triangles, CSR, A_v, A_e and grad N integer for integer and bit for bit."""
+    mesh = make()
+    m = Mesh.from_dict(mesh, device=-1)
+    om = oracle.Mesh(mesh, reordered=True)
+    assert np.array_equal(m.vperm, om.vperm) and np.array_equal(m.eperm, om.eperm)
+    t2, r2, c2 = m.csr()
+    assert np.array_equal(t2, om.tri) and np.array_equal(r2, om.row_ptr)
+    assert np.array_equal(c2, om.col)
+    Av, Ae, gN = m.geometry()
+    assert np.array_equal(Av, om.Av) and np.array_equal(Ae, om.Ae) and np.array_equal(gN, om.gN)
+
+
+def test_sesm_coefficients_match_the_oracle_settings():
+    """se_sesm_coefficients against the oracle's own reading of eqs. (eqdp_4), (eqdp_6)."""
+    from oracle import analytic
+    from paper_2311_08241_amd.api import sesm_coefficients
+    for theta in (0.0, 0.14, 0.3):
+        assert np.allclose(sesm_coefficients(theta), analytic.sesm_params(theta), rtol=0,
+                           atol=1e-15)
+    assert sesm_coefficients(0.14, 0.2)[0] == 0.2
+    with pytest.raises(L.SeError):
+        sesm_coefficients(float("nan"))
+
+
 @pytest.mark.parametrize("name,mesh", list(_cases())[:6])
 def test_viscous_neighbours_and_edge_geometry_match_oracle_exactly(name, mesh):
     """The library finds neighbours through its CSR rows, the oracle by sorting
