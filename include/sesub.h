@@ -202,6 +202,26 @@ se_status se_subcycle(se_mesh *mesh, const se_params *params, se_state *state,
                       const se_forcing *forcing, int32_t nsub, double dt, void *workspace,
                       void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): se_subcycle with the same
+ * kernels and results, its workspace taken from a static device array of
+ * SE_NOALLOC_SCRATCH_BYTES instead of a caller buffer.  The library holds one such
+ * array on every device it runs on, until the process ends.  Nothing is allocated:
+ * the mesh must already have a tile plan (se_set_plan, or an earlier se_subcycle
+ * call), and with the viscous term its tables must already exist (an earlier
+ * se_subcycle call with the term builds them).  All calls on one device share that
+ * device's array and find the last call's contents in it (the subcycle writes every
+ * part of its workspace before reading it, so nothing needs clearing); calls that
+ * overlap on one device (several streams or host threads) race and must be
+ * serialised by the caller.
+ * Errors: as se_subcycle, plus SE_ERR_ARG when se_workspace_bytes for this mesh,
+ * precision and nsub exceeds SE_NOALLOC_SCRATCH_BYTES, or when the plan or the
+ * viscous tables are missing. */
+#define SE_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)   /* 256 MiB per device */
+se_status se_subcycle_noalloc(se_mesh *mesh, const se_params *params, se_state *state,
+                              const se_forcing *forcing, int32_t nsub, double dt,
+                              void *stream);
+
 /* Same step on the two-kernel path (one triangle launch and one vertex
  * launch per substep, no temporal blocking): the plain baseline. */
 se_status se_subcycle_plain(se_mesh *mesh, const se_params *params, se_state *state,

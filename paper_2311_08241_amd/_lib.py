@@ -85,6 +85,8 @@ _SIGS = {
                                      ctypes.POINTER(ctypes.c_size_t)]),
     "se_subcycle": (c_int32, [c_void_p, ctypes.POINTER(Params), ctypes.POINTER(State),
                               ctypes.POINTER(Forcing), c_int32, c_double, c_void_p, c_void_p]),
+    "se_subcycle_noalloc": (c_int32, [c_void_p, ctypes.POINTER(Params), ctypes.POINTER(State),
+                                      ctypes.POINTER(Forcing), c_int32, c_double, c_void_p]),
     "se_subcycle_plain": (c_int32, [c_void_p, ctypes.POINTER(Params), ctypes.POINTER(State),
                                     ctypes.POINTER(Forcing), c_int32, c_double, c_void_p,
                                     c_void_p]),

@@ -237,6 +237,29 @@ class Mesh:
                    float(dt), _ptr(workspace), _stream_ptr(stream)))
         return eta, U, Uavg, volume
 
+    def subcycle_noalloc(self, eta, U, *, R, f, H0, W=None, nsub: int, dt: float,
+                         params: Params, Uavg=None, volume=None, stream=None):
+        """se_subcycle_noalloc: se_subcycle with the library's static device scratch as
+        workspace (nothing allocated; the mesh needs a tile plan already)."""
+        torch = _torch()
+        dt_ = params.dtype
+        self._check_tensor(eta, self.nv, "eta", dt_)
+        self._check_tensor(U, self.ne, "U", dt_, 2)
+        self._check_tensor(R, self.ne, "R", dt_, 2)
+        self._check_tensor(f, self.ne, "f", dt_)
+        self._check_tensor(H0, self.nv, "H0", dt_)
+        self._check_tensor(W, self.nv, "W", dt_, allow_none=True)
+        self._check_tensor(Uavg, self.ne, "Uavg", torch.float64, 2, allow_none=True)
+        nvol = nsub + 1 if params.track_volume else 2
+        self._check_tensor(volume, nvol, "volume", torch.float64, allow_none=True)
+        st = L.State(_ptr(eta), _ptr(U), _ptr(Uavg), _ptr(volume))
+        fo = L.Forcing(_ptr(R), _ptr(f), _ptr(H0), _ptr(W))
+        pc = params.c()
+        L.check(L.lib().se_subcycle_noalloc(self._h, ctypes.byref(pc), ctypes.byref(st),
+                                            ctypes.byref(fo), int(nsub), float(dt),
+                                            _stream_ptr(stream)))
+        return eta, U, Uavg, volume
+
     def trim_zstar(self, *, H0, eta_new, Uavg, Ustar, hn, h0, tau: float, W=None, U=None,
                    hnew=None, w=None, stream=None):
         """se_trim_zstar (FP64): trim of the layer transports Ustar [ne][K][2] to Uavg

@@ -8,7 +8,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsesub.so")
-SOURCES = ["kernels.hip", "consumers.hip", "ensemble.hip", "api.cpp", "mesh_prep.cpp"]
+SOURCES = ["kernels.hip", "consumers.hip", "ensemble.hip", "noalloc.hip", "api.cpp",
+           "mesh_prep.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

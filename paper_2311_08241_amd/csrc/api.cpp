@@ -791,6 +791,17 @@ static TileArgs tile_args(const se_mesh *m, const DevTiles &P, bool f32, const s
 
 se_status se_subcycle(se_mesh *m, const se_params *p, se_state *st, const se_forcing *fo,
                       int32_t nsub, double dt, void *ws, void *stream) {
+    return sesub::subcycle_tile(m, p, st, fo, nsub, dt, ws, stream, true);
+}
+
+}  // extern "C"
+
+// The tile-kernel subcycle behind se_subcycle and se_subcycle_noalloc.  With
+// may_alloc false nothing is allocated: a missing plan or missing viscous tables are
+// errors instead of being built here.
+se_status sesub::subcycle_tile(se_mesh *m, const se_params *p, se_state *st,
+                               const se_forcing *fo, int32_t nsub, double dt, void *ws,
+                               void *stream, bool may_alloc) {
     SE_TRY(check_params(m, p, nsub, dt));
     const bool visc = visc_on(p);
     if (visc && p->scheme != SE_SCHEME_SE) {
@@ -800,7 +811,13 @@ se_status se_subcycle(se_mesh *m, const se_params *p, se_state *st, const se_for
     SE_TRY(check_state(st, fo, ws));
     SE_TRY(check_device(m));
     DeviceGuard dg(m->device);
-    SE_TRY(ensure_plan(m));
+    if (may_alloc) {
+        SE_TRY(ensure_plan(m));
+    } else if (!m->plan) {
+        set_error("se_subcycle_noalloc: the mesh has no tile plan yet (se_set_plan, or one "
+                  "se_subcycle call, makes one)");
+        return SE_ERR_ARG;
+    }
     const DevTiles &P = *m->plan;
     const bool f32 = p->precision == SE_F32_MIXED;
     const bool sm = p->scheme == SE_SCHEME_SESM;
@@ -824,6 +841,11 @@ se_status se_subcycle(se_mesh *m, const se_params *p, se_state *st, const se_for
                       std::to_string(lds) + " bytes of LDS within 160 KiB and at most " +
                       "3 / 1 (1024 threads) or 6 / 4 (512 threads) triangles per thread "
                       "(FP32 / FP64)");
+            return SE_ERR_ARG;
+        }
+        if (!may_alloc && (!m->d.vnb.p || !m->plan->vnb.p)) {
+            set_error("se_subcycle_noalloc: the viscous tables of this mesh and plan are not "
+                      "built yet (one se_subcycle call with the viscous term builds them)");
             return SE_ERR_ARG;
         }
         SE_TRY(ensure_visc(m));
@@ -905,6 +927,8 @@ se_status se_subcycle(se_mesh *m, const se_params *p, se_state *st, const se_for
     }
     return SE_OK;
 }
+
+extern "C" {
 
 se_status se_subcycle_plain(se_mesh *m, const se_params *p, se_state *st, const se_forcing *fo,
                             int32_t nsub, double dt, void *ws, void *stream) {

@@ -127,6 +127,11 @@ struct DevMesh {
     DevBuf slotS;
 };
 
+// The forward subcycle on the tile kernel (se_subcycle); may_alloc false: fail instead
+// of building a missing plan or missing viscous tables (se_subcycle_noalloc).
+se_status subcycle_tile(se_mesh *m, const se_params *p, se_state *st, const se_forcing *fo,
+                        int32_t nsub, double dt, void *ws, void *stream, bool may_alloc);
+
 }  // namespace sesub
 
 struct se_mesh {
