@@ -136,14 +136,16 @@ se_status plan_host(const std::vector<const HostMesh *> &members, const std::vec
     st.tri_per_thread = ept;
     st.lds_f32 = tile_lds_bytes(true, false, block, K, ht.max_nv, ht.max_ne, ht.max_nvu, ht.max_cs);
     st.lds_f64 = tile_lds_bytes(false, false, block, K, ht.max_nv, ht.max_ne, ht.max_nvu, ht.max_cs);
-    st.ok_f32 = ept_ok(true, ept, block) && st.lds_f32 <= 160 * 1024;
-    st.ok_f64 = ept_ok(false, ept, block) && st.lds_f64 <= 160 * 1024;
+    // owned triangles must fit the slots that carry running sums
+    const bool own_ok = ept > 0 && ht.max_nown <= own_slots(ept) * block;
+    st.ok_f32 = own_ok && ept_ok(true, ept, block) && st.lds_f32 <= 160 * 1024;
+    st.ok_f64 = own_ok && ept_ok(false, ept, block) && st.lds_f64 <= 160 * 1024;
     st.lds_sesm_f32 = tile_lds_bytes(true, true, block, K, ht.max_nv, ht.max_ne, ht.max_nvu,
                                      ht.max_cs);
     st.lds_sesm_f64 = tile_lds_bytes(false, true, block, K, ht.max_nv, ht.max_ne, ht.max_nvu,
                                      ht.max_cs);
-    st.ok_sesm_f32 = ept_ok(true, ept, block, true) && st.lds_sesm_f32 <= 160 * 1024;
-    st.ok_sesm_f64 = ept_ok(false, ept, block, true) && st.lds_sesm_f64 <= 160 * 1024;
+    st.ok_sesm_f32 = own_ok && ept_ok(true, ept, block, true) && st.lds_sesm_f32 <= 160 * 1024;
+    st.ok_sesm_f64 = own_ok && ept_ok(false, ept, block, true) && st.lds_sesm_f64 <= 160 * 1024;
     int64_t nv = 0, ne = 0;
     for (const HostMesh *m : members) {
         nv += m->nv;
@@ -192,6 +194,7 @@ se_status make_plan(const std::vector<const HostMesh *> &members, const std::vec
     p->max_ne = ht.max_ne;
     p->max_nvu = ht.max_nvu;
     p->max_cs = ht.max_cs;
+    p->ell = ht.ell;
     p->lds_bytes64 = st.lds_f64;
     p->lds_bytes32 = st.lds_f32;
     p->ok32 = st.ok_f32;
@@ -786,6 +789,7 @@ static TileArgs tile_args(const se_mesh *m, const DevTiles &P, bool f32, const s
     a.cap_ne = P.max_ne;
     a.cap_nvu = P.max_nvu;
     a.cap_cs = P.max_cs;
+    a.ell = P.ell ? 1 : 0;
     return a;
 }
 
@@ -1780,6 +1784,7 @@ se_status se_subcycle_batched(se_batch *b, const se_params *p, se_state *st, con
     a.cap_ne = P.max_ne;
     a.cap_nvu = P.max_nvu;
     a.cap_cs = P.max_cs;
+    a.ell = P.ell ? 1 : 0;
     a.eta_u = st->eta;
     a.eta_w = w + L.eta_alt;
     a.U_u = st->U;

@@ -21,6 +21,16 @@ struct StepC {
 
 enum : int32_t { KF_LINEAR_H = 1, KF_TRACK_VOLUME = 4 };
 
+// Fixed-width deposit rows of the tile kernel: a vertex with at most this many
+// triangles keeps its sub-cell fluxes at kEllWidth * (local vertex) + rank, the
+// unused entries zero (odd, so that the rows of consecutive vertices fall in
+// distinct LDS banks).
+constexpr int kEllWidth = 7;
+
+// Triangle slots per thread that can hold owned triangles (the first ones of the
+// local order), for EPT slots in all: only these carry running-sum registers.
+__host__ __device__ constexpr int own_slots(int ept) { return ept <= 2 ? ept : ept - 1; }
+
 struct TileHdrK {   // mirror of TileHdr (same layout)
     int32_t vbase, nv0, ebase, nown, lv_off, le_off, cs_off, rw_off, member, mtile, p0, p1;
 };
@@ -49,6 +59,7 @@ struct TileArgs {
     int32_t K, chunk, ntiles, xcd;
     int32_t ksub;               // substeps per launch (K; K / 2 with the viscous term)
     int32_t cap_nv, cap_ne, cap_nvu, cap_cs;
+    int32_t ell;                // deposits in fixed-width rows (kEllWidth per vertex)
     // viscous term only: per local triangle the local neighbours across its three
     // edges (16 bits each, 0xffff: none in the tile) and (l, l/d) of the three edges
     const uint32_t *vnb;

@@ -636,9 +636,15 @@ __global__ void __launch_bounds__(BLOCK) k_tile(TileArgs a) {
         g3[EPT], g4[EPT];
     // SM: U^{-1} and the AB3 transport of the previous substep
     T pUx[SM ? EPT : 1], pUy[SM ? EPT : 1], aUx[SM ? EPT : 1], aUy[SM ? EPT : 1];
-    uint32_t t0[EPT], t1[EPT], t2[EPT];   // local vertices and flux positions, 16 bits each
+    // local vertices and flux positions, 16 bits each (slots past the tile's triangles
+    // hold copies of its last triangle's)
+    uint32_t t0[EPT] = {}, t1[EPT] = {}, t2[EPT] = {};
     int gt[EPT];
-    SumT<F32> sm[EPT];
+    // running sums only in the slots that can hold owned triangles (the plan keeps
+    // every tile's owned triangles within them); osl(r) names slot r's sum
+    constexpr int OS = own_slots(EPT);
+    SumT<F32> sm[OS];
+    auto osl = [](int r) { return r < OS ? r : 0; };
     if (ne_load > 0) {
 #pragma unroll
         for (int r = 0; r < EPT; ++r) {
@@ -667,7 +673,7 @@ __global__ void __launch_bounds__(BLOCK) k_tile(TileArgs a) {
         if (!first && h.nown > 0) {
             // running sums of owned triangles (the tile's contiguous global range)
 #pragma unroll
-            for (int r = 0; r < EPT; ++r) sm[r].load(a.sum, h.ebase + min(tid + r * BLOCK, h.nown - 1));
+            for (int r = 0; r < OS; ++r) sm[r].load(a.sum, h.ebase + min(tid + r * BLOCK, h.nown - 1));
         }
     }
     // FP64 dual-cell areas of owned vertices, for the volume sums of this launch
@@ -792,9 +798,15 @@ __global__ void __launch_bounds__(BLOCK) k_tile(TileArgs a) {
         stage_vertex(i, lv[i]);
     }
     for (int i = tid + BLOCK; i < nrow4; i += BLOCK) reinterpret_cast<uint2 *>(sRow)[i] = crow[i];
+    if (a.ell) {
+        // fixed-width rows: the entries past a vertex's triangles are never written
+        // and must read as zero (adding +0 leaves every row sum unchanged)
+        const int nz = (kEllWidth * nvu * (int)sizeof(T) + 15) / 16;
+        for (int i = tid; i < nz; i += BLOCK) reinterpret_cast<uint4 *>(sAcc)[i] = make_uint4(0, 0, 0, 0);
+    }
     if (first && !SM) {
 #pragma unroll
-        for (int r = 0; r < EPT; ++r) {
+        for (int r = 0; r < OS; ++r) {
             const int le = tid + r * BLOCK;
             if (le < h.nown) {
                 T2 u;
@@ -866,6 +878,17 @@ __global__ void __launch_bounds__(BLOCK) k_tile(TileArgs a) {
 #pragma unroll
             for (int r = 0; r < EPT; ++r) asm volatile("" : "+v"(t0[r]), "+v"(t1[r]));
         }
+        // FP32 forward-backward: the three elevations of every slot read before any
+        // update, so that all slots wait for one LDS round trip
+        float hE[(F32 && MODE == 0) ? 3 * EPT : 1];
+        if constexpr (F32 && MODE == 0) {
+#pragma unroll
+            for (int r = 0; r < EPT; ++r) {
+                hE[3 * r] = sEta[t0[r] & 0xffffu];
+                hE[3 * r + 1] = sEta[t0[r] >> 16];
+                hE[3 * r + 2] = sEta[t1[r] & 0xffffu];
+            }
+        }
         if constexpr (VI) {
             const int ne_u = sLev[9 + lev + 1];
 #pragma unroll
@@ -926,11 +949,11 @@ __global__ void __launch_bounds__(BLOCK) k_tile(TileArgs a) {
                     pUy[r] = Qy;
                     aUx[r] = abx;
                     aUy[r] = aby;
-                    if (le < h.nown) {
+                    if (r < OS && le < h.nown) {
                         if (first && j == 0)
-                            sm[r].init(abx, aby);
+                            sm[osl(r)].init(abx, aby);
                         else
-                            sm[r].add(abx, aby);
+                            sm[osl(r)].add(abx, aby);
                     }
                     continue;
                 }
@@ -970,7 +993,10 @@ __global__ void __launch_bounds__(BLOCK) k_tile(TileArgs a) {
                 }
                 if constexpr (F32) {
                     bool dry;
-                    tri_update_f32(sEta[ia], sEta[ib], sEta[ic], rH[r], g0[r], g1[r], g2[r],
+                    const float ea = MODE == 0 ? hE[MODE == 0 ? 3 * r : 0] : sEta[ia];
+                    const float eb = MODE == 0 ? hE[MODE == 0 ? 3 * r + 1 : 0] : sEta[ib];
+                    const float ec = MODE == 0 ? hE[MODE == 0 ? 3 * r + 2 : 0] : sEta[ic];
+                    tri_update_f32(ea, eb, ec, rH[r], g0[r], g1[r], g2[r],
                                    g3[r], g4[r], rUx[r], rUy[r], rx, ry, rf[r], rk[r],
                                    gd, th, linear_h, Unx, Uny, pa, pb, pc, dry);
                     dry_any |= dry;
@@ -987,19 +1013,48 @@ __global__ void __launch_bounds__(BLOCK) k_tile(TileArgs a) {
                 sAcc[t2[r] >> 16] = pc;
                 rUx[r] = Unx;
                 rUy[r] = Uny;
-                if (le < h.nown) {
+                if (r < OS && le < h.nown) {
                     if (first && j == 0)
-                        sm[r].init(Unx, Uny);
+                        sm[osl(r)].init(Unx, Uny);
                     else
-                        sm[r].add(Unx, Uny);
+                        sm[osl(r)].add(Unx, Uny);
                 }
             }
         }
         __syncthreads();
-        // vertex phase: row sums in entry order, loads issued four (or the last up to
+        // vertex phase.  The update of vertex i from its row sum acc (and its elevation,
+        // area term and W read beforehand)
+        auto finish = [&](int i, T acc, T e_i, T av_i, T w_i) -> T {
+            T en;
+            if constexpr (F32)
+                en = vtx_update_f32(e_i, acc, av_i, w_i, dts);
+            else
+                en = e_i - dts * (acc / av_i + w_i);
+            if constexpr (SM) {
+                const T e1 = sE1[i], e2 = sE2[i];
+                sEA[i] = sesm_am<T>(c, en, e_i, e1, e2);
+                sE2[i] = e1;
+                sE1[i] = e_i;
+            }
+            sEta[i] = en;
+            bad_any |= !finite_val(en);
+            return en;
+        };
+        // fixed-width rows: the row's entries in ascending triangle order, then zeros
+        auto ell_sum = [&](int i) -> T {
+            const T *row = sAcc + kEllWidth * i;
+            T b[kEllWidth];
+#pragma unroll
+            for (int q = 0; q < kEllWidth; ++q) b[q] = row[q];
+            T acc = T(0);
+#pragma unroll
+            for (int q = 0; q < kEllWidth; ++q) acc += b[q];
+            return acc;
+        };
+        // local CSR rows: row sums in entry order, loads issued four (or the last up to
         // three) at a time; reads past a row end stay inside the flux array (its 64
         // scratch slots) and are not summed
-        auto vertex = [&](int i) -> T {
+        auto csr_sum = [&](int i) -> T {
             T acc = T(0);
             int q = sRow[i];
             const int q1 = sRow[i + 1];
@@ -1015,29 +1070,42 @@ __global__ void __launch_bounds__(BLOCK) k_tile(TileArgs a) {
             if (rem > 0) acc += b0;
             if (rem > 1) acc += b1;
             if (rem > 2) acc += b2;
-            T en;
-            if constexpr (F32)
-                en = vtx_update_f32(sEta[i], acc, sAv[i], sW[i], dts);
-            else
-                en = sEta[i] - dts * (acc / sAv[i] + sW[i]);
-            if constexpr (SM) {
-                const T e0 = sEta[i], e1 = sE1[i], e2 = sE2[i];
-                sEA[i] = sesm_am<T>(c, en, e0, e1, e2);
-                sE2[i] = e1;
-                sE1[i] = e0;
-            }
-            sEta[i] = en;
-            bad_any |= !finite_val(en);
-            return en;
+            return acc;
+        };
+        auto vertex = [&](int i) -> T {
+            const T acc = a.ell ? ell_sum(i) : csr_sum(i);
+            return finish(i, acc, sEta[i], sAv[i], sW[i]);
         };
         const bool vol_j = track || (last && j == cnt - 1);
         double vp = 0.0;
+        if (F32 && a.ell) {
+            // every read of the thread's vertex slots issued before any update (slots
+            // past nv_act read a valid row and are not updated)
+            T vacc[VO], ve[VO], vav[VO], vw[VO];
 #pragma unroll
-        for (int k = 0; k < VO; ++k) {
-            const int i = tid + k * BLOCK;
-            if (i < nv_act) {
-                const T en = vertex(i);
-                if (vol_j && i < h.nv0) vp += rAv64[k] * (double)en;
+            for (int k = 0; k < VO; ++k) {
+                const int i = min(tid + k * BLOCK, max(nv_act - 1, 0));
+                vacc[k] = ell_sum(i);
+                ve[k] = sEta[i];
+                vav[k] = sAv[i];
+                vw[k] = sW[i];
+            }
+#pragma unroll
+            for (int k = 0; k < VO; ++k) {
+                const int i = tid + k * BLOCK;
+                if (i < nv_act) {
+                    const T en = finish(i, vacc[k], ve[k], vav[k], vw[k]);
+                    if (vol_j && i < h.nv0) vp += rAv64[k] * (double)en;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < VO; ++k) {
+                const int i = tid + k * BLOCK;
+                if (i < nv_act) {
+                    const T en = vertex(i);
+                    if (vol_j && i < h.nv0) vp += rAv64[k] * (double)en;
+                }
             }
         }
         for (int i = tid + VO * BLOCK; i < nv_act; i += BLOCK) {
@@ -1070,7 +1138,7 @@ __global__ void __launch_bounds__(BLOCK) k_tile(TileArgs a) {
         T2 *u1 = static_cast<T2 *>(a.sm_e[wsel][1]);
         T2 *u2 = static_cast<T2 *>(a.sm_e[wsel][2]);
 #pragma unroll
-        for (int r = 0; r < EPT; ++r) {
+        for (int r = 0; r < OS; ++r) {   // owned triangles lie in the first OS slots
             const int le = tid + r * BLOCK;
             if (le < h.nown) {
                 const int g = h.ebase + le;
@@ -1099,23 +1167,21 @@ __global__ void __launch_bounds__(BLOCK) k_tile(TileArgs a) {
     for (int i = tid; i < h.nv0; i += BLOCK) eta_out[h.vbase + i] = sEta[i];
     T2 *Uout = static_cast<T2 *>(even ? a.U_w : a.U_u);
 #pragma unroll
-    for (int r = 0; r < EPT; ++r) {
+    for (int r = 0; r < OS; ++r) {   // owned triangles lie in the first OS slots
         const int le = tid + r * BLOCK;
-        if (le < ne_load) {
+        if (le < h.nown) {
             const int g = h.ebase + le;
-            if (le < h.nown) {
-                T2 u;
-                u.x = rUx[r];
-                u.y = rUy[r];
-                Uout[g] = u;
-                if (last) {
-                    if (!a.Uavg) continue;
-                    const T2 u0 = static_cast<const T2 *>(a.U0c)[g];
-                    a.Uavg[2 * g] = sm[r].vx() / c.Mdbl + c.thM * ((double)u.x - (double)u0.x);
-                    a.Uavg[2 * g + 1] = sm[r].vy() / c.Mdbl + c.thM * ((double)u.y - (double)u0.y);
-                } else {
-                    sm[r].store(a.sum, g);
-                }
+            T2 u;
+            u.x = rUx[r];
+            u.y = rUy[r];
+            Uout[g] = u;
+            if (last) {
+                if (!a.Uavg) continue;
+                const T2 u0 = static_cast<const T2 *>(a.U0c)[g];
+                a.Uavg[2 * g] = sm[r].vx() / c.Mdbl + c.thM * ((double)u.x - (double)u0.x);
+                a.Uavg[2 * g + 1] = sm[r].vy() / c.Mdbl + c.thM * ((double)u.y - (double)u0.y);
+            } else {
+                sm[r].store(a.sum, g);
             }
         }
     }

@@ -10,6 +10,7 @@
 #include <numeric>
 #include <tuple>
 
+#include "kernels.h"
 #include "se_internal.h"
 
 namespace sesub {
@@ -332,8 +333,8 @@ namespace {
 // Tiles [t0, t1) of member mi appended to `out` (offsets local to `out`).
 se_status build_tile_range(const HostMesh &m, size_t mi, int64_t voff, int64_t eoff,
                            const std::vector<int32_t> &efirst, int64_t t0, int64_t t1, int32_t T,
-                           int32_t K, std::vector<int32_t> &vloc, std::vector<int32_t> &eloc,
-                           HostTiles &out) {
+                           int32_t K, bool ell, std::vector<int32_t> &vloc,
+                           std::vector<int32_t> &eloc, HostTiles &out) {
     const int64_t nv = m.nv;
     std::vector<int32_t> lv, le, fresh, pos;
     for (int64_t t = t0; t < t1; ++t) {
@@ -408,10 +409,12 @@ se_status build_tile_range(const HostMesh &m, size_t mi, int64_t voff, int64_t e
         h.rw_off = static_cast<int32_t>(out.cs_row.size());
         h.member = static_cast<int32_t>(mi);
         h.mtile = static_cast<int32_t>(t);
-        // local CSR of the vertices updated at some inner substep (V_{K-1}); each
-        // incidence (triangle, slot) gets the position of its entry, where the
-        // triangle phase deposits its sub-cell flux.  Incidences of vertices that
-        // are never updated go to one of 64 scratch slots past the entries.
+        // local rows of the vertices updated at some inner substep (V_{K-1}); each
+        // incidence (triangle, slot) gets the position where the triangle phase
+        // deposits its sub-cell flux: the vertex's row in the local CSR, or with
+        // fixed-width rows (ell) entry `rank` of row q at kEllWidth * q + rank, the
+        // incidences in ascending triangle order in both.  Incidences of vertices
+        // that are never updated go to one of 64 scratch slots past the rows.
         const int32_t nvu = nVl[K - 1];
         pos.assign(3 * le.size(), -1);
         int32_t nent = 0;
@@ -420,10 +423,13 @@ se_status build_tile_range(const HostMesh &m, size_t mi, int64_t voff, int64_t e
             const int32_t v = lv[q];
             for (int32_t j = m.row_ptr[v]; j < m.row_ptr[v + 1]; ++j) {
                 const int32_t e = m.col[j] >> 2;
-                pos[3 * eloc[e] + (m.col[j] & 3)] = nent++;
+                const int32_t rank = j - m.row_ptr[v];
+                pos[3 * eloc[e] + (m.col[j] & 3)] = ell ? kEllWidth * q + rank : nent;
+                ++nent;
             }
         }
-        if (nent + 64 > 65535) {
+        const int32_t rows_end = ell ? kEllWidth * nvu : nent;
+        if (rows_end + 64 > 65535) {
             for (int32_t v : lv) vloc[v] = -1;
             for (int32_t e : le) eloc[e] = -1;
             set_error("se_set_plan: tile CSR too large for 16-bit offsets");
@@ -446,7 +452,7 @@ se_status build_tile_range(const HostMesh &m, size_t mi, int64_t voff, int64_t e
             uint32_t p3[3];
             for (int k = 0; k < 3; ++k)
                 p3[k] = pos[3 * q + k] >= 0 ? static_cast<uint32_t>(pos[3 * q + k])
-                                            : static_cast<uint32_t>(nent + (q & 63));
+                                            : static_cast<uint32_t>(rows_end + (q & 63));
             // three local vertices and three flux positions, 16 bits each
             out.le_tri.push_back(a | (b << 16));
             out.le_tri.push_back(c | (p3[0] << 16));
@@ -455,7 +461,8 @@ se_status build_tile_range(const HostMesh &m, size_t mi, int64_t voff, int64_t e
         out.max_nv = std::max(out.max_nv, nVl[K]);
         out.max_ne = std::max(out.max_ne, nEl[K]);
         out.max_nvu = std::max(out.max_nvu, nvu);
-        out.max_cs = std::max(out.max_cs, nent + 64);
+        out.max_cs = std::max(out.max_cs, rows_end + 64);
+        out.max_nown = std::max(out.max_nown, h.nown);
         for (int32_t v : lv) vloc[v] = -1;
         for (int32_t e : le) eloc[e] = -1;
     }
@@ -470,6 +477,13 @@ se_status build_tiles(const std::vector<const HostMesh *> &members,
     out = HostTiles();
     out.T = T;
     out.K = K;
+    // fixed-width rows when no vertex of any member has more than kEllWidth triangles
+    int32_t max_deg = 0;
+    for (const HostMesh *m : members)
+        for (int64_t v = 0; v < m->nv; ++v)
+            max_deg = std::max(max_deg, m->row_ptr[v + 1] - m->row_ptr[v]);
+    out.ell = max_deg <= kEllWidth;
+    const bool ell = out.ell;
     // first triangle whose smallest vertex is >= v, per member
     std::vector<std::vector<int32_t>> efirst(members.size());
     struct Unit {
@@ -509,7 +523,7 @@ se_status build_tiles(const std::vector<const HostMesh *> &members,
             }
             parts[u].K = K;
             st[u] = build_tile_range(m, U.mi, voff[U.mi], eoff[U.mi], efirst[U.mi], U.t0, U.t1, T,
-                                     K, vloc, eloc, parts[u]);
+                                     K, ell, vloc, eloc, parts[u]);
             if (st[u] != SE_OK) {   // stamps may be dirty after an early return
                 cur_member = static_cast<size_t>(-1);
             }
@@ -549,6 +563,7 @@ se_status build_tiles(const std::vector<const HostMesh *> &members,
         out.max_ne = std::max(out.max_ne, p.max_ne);
         out.max_nvu = std::max(out.max_nvu, p.max_nvu);
         out.max_cs = std::max(out.max_cs, p.max_cs);
+        out.max_nown = std::max(out.max_nown, p.max_nown);
     }
     return SE_OK;
 }

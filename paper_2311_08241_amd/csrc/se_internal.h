@@ -68,7 +68,9 @@ struct HostTiles {
     std::vector<uint32_t> le_tri;
     std::vector<uint16_t> cs_row; // per tile: nV[K-1] + 1 row offsets (local), padded to 4
     int64_t n_ent = 0;            // local CSR entries over all tiles
-    int32_t max_nv = 0, max_ne = 0, max_nvu = 0, max_cs = 0;   // max_cs: entries + 64 scratch
+    int32_t max_nv = 0, max_ne = 0, max_nvu = 0, max_cs = 0;   // max_cs: rows + 64 scratch
+    int32_t max_nown = 0;         // most owned triangles of a tile
+    bool ell = false;             // fixed-width rows of kEllWidth deposits per vertex
 };
 
 se_status build_tiles(const std::vector<const HostMesh *> &members,
@@ -89,6 +91,7 @@ struct DevBuf {
 
 struct DevTiles {
     int32_t T = 0, K = 0, block = 256, ept = 0, ntiles = 0;
+    bool ell = false;   // fixed-width deposit rows (HostTiles::ell)
     int32_t max_nv = 0, max_ne = 0, max_nvu = 0, max_cs = 0;
     size_t lds_bytes64 = 0, lds_bytes32 = 0;
     bool ok32 = false, ok64 = false;
