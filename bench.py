@@ -225,13 +225,13 @@ def bench_adjoint(args, log):
         def fwd():
             mesh.subcycle(e, U, R=d["R"], f=d["f"], H0=d["H0"], nsub=case["nsub"],
                           dt=case["tau"], params=p, workspace=ws)
-        # tile plan for this mesh (the forward and the adjoint's checkpoint sweep run on
-        # it): the fastest forward among a few shapes that give 64-512 tiles, with 2-6
-        # substeps per launch (5 or more run a checkpoint segment in one launch)
+        # tile plan for this mesh (the forward and the adjoint run on it): the fastest
+        # forward among a few shapes that give 64-512 tiles, with 2-6 substeps per
+        # launch (5 or more run a checkpoint segment in one launch)
         best = None
-        for plan in ((1024, 4, 512), (512, 4, 512), (256, 4, 256), (256, 2, 256),
-                     (128, 4, 256), (128, 2, 256), (256, 5, 256), (128, 5, 256),
-                     (128, 6, 256)):
+        for plan in ((1024, 4, 512), (512, 4, 512), (256, 4, 256), (128, 4, 256),
+                     (256, 5, 256), (128, 5, 256), (128, 6, 256), (256, 5, 512),
+                     (192, 5, 512), (320, 5, 512), (128, 5, 512)):
             if not mesh.plan_stats(*plan)["ok_f32" if prec == "f32" else "ok_f64"]:
                 continue
             mesh.set_plan(*plan)
@@ -266,17 +266,19 @@ def bench_adjoint(args, log):
         ms_graph = _time(graph.replay, 10)
         fwd()
         msf = _time(fwd, 5)
-        # operations in stream order, each waiting for the previous one: the sweep up to
-        # the last checkpoint, ceil(k / k_fused) tile launches per segment; two kernels
-        # per forward substep of the last segment's recompute; per segment, two per
-        # reverse substep, the recompute of the previous segment sharing those launches;
-        # the seed and final kernels
+        # launches in stream order, each waiting for the previous one (the tile path of
+        # se_subcycle_adjoint): the seed kernel; the sweep up to the last checkpoint,
+        # ceil(k / k_fused) tile launches per segment; the last segment's recompute; per
+        # segment its reverse launches (ceil(len / k_fused)), the recompute of the
+        # segment before it sharing them; the final kernel
         nsub, k = case["nsub"], case["ckpt_every"]
+        K = best[1][1]
         segs = [min(k, nsub - m0) for m0 in range(0, nsub, k)]
-        nchunk = -(-k // best[1][1])
-        nops = (nchunk * (len(segs) - 1) + 2 * (segs[-1] - 1)
-                + sum(2 * max(L, segs[i - 1] - 1 if i > 0 else 0) for i, L in enumerate(segs))
-                + 2)
+        nch = lambda L: -(-L // K)
+        rec = lambda L: nch(L) if L > 1 else 0
+        nops = (1 + nch(k) * (len(segs) - 1) + rec(segs[-1])
+                + sum(max(nch(L), rec(segs[i - 1]) if i > 0 else 0) for i, L in enumerate(segs))
+                + 1)
         out[prec] = {"plan": list(best[1]), "ms_adjoint": ms, "ms_adjoint_graph": ms_graph,
                      "ms_forward": msf,
                      "adjoint_over_forward": ms / msf, "dependent_launches": nops,

@@ -259,6 +259,18 @@ se_status make_plan(const std::vector<const HostMesh *> &members, const std::vec
     // that a later launch needs no attribute call (the adjoint may be graph-captured)
     for (int f = 0; f < 2; ++f)
         p->prepared[f] = p->ok(f == 1, false) && prepare_tile(f == 1, 0, p->ept, p->block) == hipSuccess;
+    // the adjoint on the plan: recompute with trajectory output (mode 3) and the reverse
+    // tile kernel (256- or 512-thread workgroups, up to four triangles per thread, a tile's
+    // owned vertices within two per thread, its LDS within 160 KiB)
+    for (int f = 0; f < 2; ++f) {
+        const bool f32 = f == 1;
+        p->lds_adj[f] = static_cast<size_t>(adj_tile_lds_bytes(f32, block, K, p->max_nv,
+                                                               p->max_nvu, p->max_cs));
+        p->adj_ready[f] = p->prepared[f] && (block == 256 || block == 512) && ept <= 4 &&
+                          T <= 2 * block && p->lds_adj[f] <= 160 * 1024 &&
+                          prepare_tile(f32, 3, ept, block) == hipSuccess &&
+                          prepare_adj_tile(f32, ept, block) == hipSuccess;
+    }
     out = std::move(p);
     return SE_OK;
 }
@@ -310,6 +322,8 @@ Layout fwd_layout(int64_t nv, int64_t ne, bool f32, int32_t nsub, int64_t width,
 
 struct AdjLayout {
     size_t ckpt, traj[2], lam_eta, lam_U, psi, gR, gH0, total;
+    size_t etraj, lam_eta2, lam_U2;   // tile reverse sweep: forward elevations (two
+                                      // segments), second adjoint state
     int32_t nseg, k;
 };
 
@@ -338,6 +352,14 @@ AdjLayout adj_layout(int64_t nv, int64_t ne, bool f32, int32_t nsub, int32_t k, 
     o += al(2 * ne * s);
     L.gH0 = o;
     o += al(nv * s);
+    // the tile reverse sweep: elevations of one segment's substeps (slot m at m nv), the
+    // second buffer of the adjoint state (launches alternate between the two)
+    L.etraj = o;
+    o += 2 * al(static_cast<size_t>(k) * nv * s);
+    L.lam_eta2 = o;
+    o += al(nv * s);
+    L.lam_U2 = o;
+    o += al(2 * ne * s);
     L.total = o;
     return L;
 }
@@ -1362,11 +1384,7 @@ se_status se_subcycle_adjoint(se_mesh *m, const se_params *p, const void *eta0, 
         }
     }
 
-    // 2. reverse sweep, segment by segment.  Segment sg (substeps m0 .. m1 - 1) needs its
-    // states m0 + 1 .. m1 - 1, recomputed from its checkpoint into segment buffer sg mod 2.
-    // The last segment is recomputed alone; every other segment's recompute runs in the
-    // same launches as the reverse substeps of the segment after it (independent work on
-    // disjoint buffers), which halves the chain of dependent launches.
+    auto seg_len = [&](int32_t sg) { return std::min(nsub, sg * k + k) - sg * k; };
     AdjArgs aa{};
     aa.nv = nv;
     aa.ne = ne;
@@ -1387,7 +1405,119 @@ se_status se_subcycle_adjoint(se_mesh *m, const se_params *p, const void *eta0, 
     aa.rM = 1.0 / static_cast<double>(nsub);
     aa.thrM = p->theta * aa.rM;
     HIP_TRY(launch_adj_init(f32, aa, lam_eta, lam_U, s), "adjoint: init");
-    auto seg_len = [&](int32_t sg) { return std::min(nsub, sg * k + k) - sg * k; };
+
+    if (TP && TP->ok(f32, false) && TP->prepared[f32 ? 1 : 0] && TP->adj_ready[f32 ? 1 : 0]) {
+        // 2'. reverse sweep on the tile plan, segment by segment from the last.  A
+        // segment's forward elevations are recomputed from its checkpoint on the tile
+        // kernel (mode 3: each substep's owned elevations to the segment's trajectory
+        // buffer, two buffers alternating by segment), its reverse substeps run up to K
+        // per launch on the reverse tile kernel (the adjoint state alternating between
+        // two buffers).  The recompute of segment sg - 1 shares the launches of the
+        // reverse substeps of segment sg (independent work on disjoint arrays); only
+        // the last segment's recompute runs alone.
+        const DevTiles &P = *TP;
+        StepC c = fa.c;
+        c.flags &= ~KF_TRACK_VOLUME;
+        c.ntiles = P.ntiles;
+        c.vol_off = 0;
+        const size_t traj_bytes = al(static_cast<size_t>(k) * nv * es);
+        auto traj_of = [&](int32_t sg) { return static_cast<void *>(w + A.etraj + (sg & 1) * traj_bytes); };
+        AdjTileArgs ra{};
+        ra.hdr = P.hdr.as<const TileHdrK>();
+        ra.nV = P.nV.as<const int32_t>();
+        ra.nE = P.nE.as<const int32_t>();
+        ra.lv_gid = P.lv_gid.as<const int32_t>();
+        ra.le_rec = P.le_rec.as<const uint32_t>();
+        ra.cs_row = P.cs_row.as<const uint16_t>();
+        ra.lgeo = f32 ? P.geo32.p : P.geo64.p;
+        ra.lae = f32 ? P.ae32.p : P.ae64.p;
+        ra.Av = fa.Av;
+        ra.H0 = fo->H0;
+        ra.f = fo->f;
+        ra.traj_stride = nv;
+        ra.lam_Uavg = lam_Uavg;
+        ra.gR = aa.gR;
+        ra.gH0 = aa.gH0;
+        ra.c = fa.c;
+        ra.rM = aa.rM;
+        ra.K = P.K;
+        ra.ntiles = P.ntiles;
+        ra.xcd = 1;
+        ra.ell = P.ell ? 1 : 0;
+        ra.cap_nv = P.max_nv;
+        ra.cap_ne = P.max_ne;
+        ra.cap_nvu = P.max_nvu;
+        ra.cap_cs = P.max_cs;
+        void *lam_e[2] = {w + A.lam_eta, w + A.lam_eta2};
+        void *lam_u[2] = {w + A.lam_U, w + A.lam_U2};
+        int cur = 0;
+        const size_t lds_f = P.lds(f32, false), lds_r = P.lds_adj[f32 ? 1 : 0];
+        const size_t lds_p = std::max(lds_f, lds_r);
+        // recompute launches of segment sg (none when it has a single substep)
+        auto recompute = [&](int32_t sg) {
+            std::vector<TileArgs> v;
+            const int32_t len = seg_len(sg);
+            if (len <= 1) return v;
+            StepC cs = c;
+            cs.nsub = len;
+            TileArgs ta = tile_args(m, P, f32, fo, w, L, cs);
+            ta.traj = traj_of(sg);
+            ta.traj_stride = nv;
+            const int32_t nch = (len + P.K - 1) / P.K;
+            for (int32_t i = 0; i < nch; ++i) {
+                void *se = i == 0 ? const_cast<void *>(ckpt_eta(sg)) : st_eta(seg_off((i - 1) & 1, 1));
+                void *sU = i == 0 ? const_cast<void *>(ckpt_U(sg)) : st_U(seg_off((i - 1) & 1, 1));
+                void *de = st_eta(seg_off(i & 1, 1));
+                void *dU = st_U(seg_off(i & 1, 1));
+                ta.eta_u = (i & 1) ? de : se;
+                ta.U_u = (i & 1) ? dU : sU;
+                ta.eta_w = (i & 1) ? se : de;
+                ta.U_w = (i & 1) ? sU : dU;
+                ta.chunk = i;
+                v.push_back(ta);
+            }
+            return v;
+        };
+        for (const TileArgs &ta : recompute(A.nseg - 1))
+            HIP_TRY(launch_tile(f32, 3, P.ept, P.block, ta, P.ntiles, lds_f, s),
+                    "adjoint: last segment recompute");
+        for (int32_t sg = A.nseg - 1; sg >= 0; --sg) {
+            const std::vector<TileArgs> rec = sg > 0 ? recompute(sg - 1) : std::vector<TileArgs>();
+            ra.eta_s0 = ckpt_eta(sg);
+            ra.traj = traj_of(sg);
+            size_t i = 0;
+            for (int32_t s_hi = seg_len(sg); s_hi > 0; ++i) {
+                const int32_t cntr = std::min(P.K, s_hi);
+                ra.cnt = cntr;
+                ra.s_hi = s_hi;
+                ra.lam_eta_in = lam_e[cur];
+                ra.lam_U_in = lam_u[cur];
+                ra.lam_eta_out = lam_e[cur ^ 1];
+                ra.lam_U_out = lam_u[cur ^ 1];
+                if (i < rec.size())
+                    HIP_TRY(launch_adj_tile_pair(f32, P.ept, P.block, ra, rec[i], lds_p, s),
+                            "adjoint: reverse substeps and recompute");
+                else
+                    HIP_TRY(launch_adj_tile(f32, P.ept, P.block, ra, lds_r, s),
+                            "adjoint: reverse substeps");
+                cur ^= 1;
+                s_hi -= cntr;
+            }
+            for (; i < rec.size(); ++i)
+                HIP_TRY(launch_tile(f32, 3, P.ept, P.block, rec[i], P.ntiles, lds_f, s),
+                        "adjoint: segment recompute");
+        }
+        aa.lam_eta = lam_e[cur];
+        aa.lam_U = lam_u[cur];
+        HIP_TRY(launch_adj_final(f32, aa, g_eta0, g_U0, s), "adjoint: final");
+        return SE_OK;
+    }
+
+    // 2. reverse sweep, segment by segment.  Segment sg (substeps m0 .. m1 - 1) needs its
+    // states m0 + 1 .. m1 - 1, recomputed from its checkpoint into segment buffer sg mod 2.
+    // The last segment is recomputed alone; every other segment's recompute runs in the
+    // same launches as the reverse substeps of the segment after it (independent work on
+    // disjoint buffers), which halves the chain of dependent launches.
     {
         const int32_t sg = A.nseg - 1;
         for (int32_t j = 1; j < seg_len(sg); ++j)

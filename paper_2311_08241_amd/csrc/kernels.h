@@ -70,6 +70,34 @@ struct TileArgs {
     // set (ch - 1) & 1 (the caller's eta_u / U_u at the member's first chunk)
     void *sm_v[2][4];
     void *sm_e[2][3];
+    // forward-backward only (adjoint recompute): when set, the elevation of the owned
+    // vertices after member substep m (m = 1 .. nsub - 1) is also written to
+    // traj + m * traj_stride (global numbering)
+    void *traj;
+    int64_t traj_stride;
+};
+
+// Reverse (adjoint) substeps of the forward-backward scheme on a tile plan: one launch
+// runs cnt reverse substeps, the substeps of trajectory slots s_hi - 1 down to
+// s_hi - cnt, on a tile and cnt rings of halo (the forward tile kernel's rings).
+struct AdjTileArgs {
+    const TileHdrK *hdr;
+    const int32_t *nV, *nE, *lv_gid;
+    const uint32_t *le_rec;
+    const uint16_t *cs_row;
+    const void *lgeo, *lae;     // per local triangle: gbx gby gcx gcy; A_e
+    const void *Av, *H0, *f;    // global numbering, the precision's type
+    // forward elevation of slot s: s == 0 ? eta_s0 : traj + s * traj_stride
+    const void *eta_s0, *traj;
+    int64_t traj_stride;
+    const void *lam_eta_in, *lam_U_in;   // adjoint state before the launch
+    void *lam_eta_out, *lam_U_out;       // after (owned entries)
+    const double *lam_Uavg;              // seed of <<U>> or nullptr
+    void *gR, *gH0;                      // accumulated gradients (owned entries updated)
+    StepC c;
+    double rM;                           // 1 / M
+    int32_t K, cnt, s_hi, ntiles, xcd, ell;
+    int32_t cap_nv, cap_ne, cap_nvu, cap_cs;
 };
 
 struct PlainArgs {
@@ -128,6 +156,15 @@ hipError_t launch_adj_final(bool f32, const AdjArgs &a, void *g_eta0, void *g_U0
 // Raise the dynamic-LDS limit of a tile kernel instantiation (call before any
 // stream capture that launches it).
 hipError_t prepare_tile(bool f32, int mode, int ept, int block);
+// Reverse tile kernel: LDS bytes, its limit raised (before any capture), launch.
+int adj_tile_lds_bytes(bool f32, int block, int cnt, int cap_nv, int cap_nvu, int cap_cs);
+hipError_t prepare_adj_tile(bool f32, int ept, int block);
+hipError_t launch_adj_tile(bool f32, int ept, int block, const AdjTileArgs &a, size_t lds,
+                           hipStream_t s);
+// The reverse launch a and an independent recompute launch f (mode 3, the same plan) in
+// one launch of a.ntiles + f.ntiles workgroups; lds: the larger of the two kernels' LDS.
+hipError_t launch_adj_tile_pair(bool f32, int ept, int block, const AdjTileArgs &a,
+                                const TileArgs &f, size_t lds, hipStream_t s);
 hipError_t launch_sesm_step(bool f32, const PlainArgs &a, hipStream_t s);
 int tile_lds_bytes(bool f32, bool sm, int block, int K, int cap_nv, int cap_ne, int cap_nvu,
                    int cap_cs);

@@ -516,16 +516,18 @@ __device__ __forceinline__ int align16(int b) { return (b + 15) & ~15; }
 // loading K rings runs K / 2 substeps, each with a velocity phase (u = U / H_e of the
 // triangles one ring beyond those updated) before the triangle phase; R holds
 // R - V(eta^0, U^0) and the triangle phase adds V(eta^m, U^m).
+// MODE 3: MODE 0 that also writes the owned vertices' elevation after every substep to
+// a trajectory (the adjoint's recompute).
+// The body of one tile's launch work for block index b of a grid of G blocks.
 template <typename T, bool F32, int EPT, int BLOCK, int MODE>
-__global__ void __launch_bounds__(BLOCK) k_tile(TileArgs a) {
-    constexpr bool SM = MODE == 1, VI = MODE == 2;
+__device__ __forceinline__ void tile_body(const TileArgs &a, int b, int G) {
+    constexpr bool SM = MODE == 1, VI = MODE == 2, TR = MODE == 3, FB = MODE == 0 || TR;
     using T2 = typename Vec2<T>::type;
     constexpr int NW = BLOCK / 64;
     extern __shared__ __align__(16) unsigned char smem[];
-    int b = blockIdx.x;
     if (a.xcd) {
         // consecutive tiles on the same XCD (blocks are dealt round-robin to 8 XCDs)
-        const int G = gridDim.x, x = b & 7, q = b >> 3;
+        const int x = b & 7, q = b >> 3;
         const int base = G >> 3, rem = G & 7;
         b = x * base + (x < rem ? x : rem) + q;
     }
@@ -880,8 +882,8 @@ __global__ void __launch_bounds__(BLOCK) k_tile(TileArgs a) {
         }
         // FP32 forward-backward: the three elevations of every slot read before any
         // update, so that all slots wait for one LDS round trip
-        float hE[(F32 && MODE == 0) ? 3 * EPT : 1];
-        if constexpr (F32 && MODE == 0) {
+        float hE[(F32 && FB) ? 3 * EPT : 1];
+        if constexpr (F32 && FB) {
 #pragma unroll
             for (int r = 0; r < EPT; ++r) {
                 hE[3 * r] = sEta[t0[r] & 0xffffu];
@@ -993,9 +995,9 @@ __global__ void __launch_bounds__(BLOCK) k_tile(TileArgs a) {
                 }
                 if constexpr (F32) {
                     bool dry;
-                    const float ea = MODE == 0 ? hE[MODE == 0 ? 3 * r : 0] : sEta[ia];
-                    const float eb = MODE == 0 ? hE[MODE == 0 ? 3 * r + 1 : 0] : sEta[ib];
-                    const float ec = MODE == 0 ? hE[MODE == 0 ? 3 * r + 2 : 0] : sEta[ic];
+                    const float ea = FB ? hE[FB ? 3 * r : 0] : sEta[ia];
+                    const float eb = FB ? hE[FB ? 3 * r + 1 : 0] : sEta[ib];
+                    const float ec = FB ? hE[FB ? 3 * r + 2 : 0] : sEta[ic];
                     tri_update_f32(ea, eb, ec, rH[r], g0[r], g1[r], g2[r],
                                    g3[r], g4[r], rUx[r], rUy[r], rx, ry, rf[r], rk[r],
                                    gd, th, linear_h, Unx, Uny, pa, pb, pc, dry);
@@ -1077,6 +1079,11 @@ __global__ void __launch_bounds__(BLOCK) k_tile(TileArgs a) {
             return finish(i, acc, sEta[i], sAv[i], sW[i]);
         };
         const bool vol_j = track || (last && j == cnt - 1);
+        // adjoint recompute: the owned vertices' elevation after member substep
+        // m0 + j + 1 to the trajectory (all but the final state)
+        T *trj = nullptr;
+        if (TR && m0 + j + 1 < c.nsub)
+            trj = static_cast<T *>(a.traj) + (int64_t)(m0 + j + 1) * a.traj_stride + h.vbase;
         double vp = 0.0;
         if (F32 && a.ell) {
             // every read of the thread's vertex slots issued before any update (slots
@@ -1096,6 +1103,7 @@ __global__ void __launch_bounds__(BLOCK) k_tile(TileArgs a) {
                 if (i < nv_act) {
                     const T en = finish(i, vacc[k], ve[k], vav[k], vw[k]);
                     if (vol_j && i < h.nv0) vp += rAv64[k] * (double)en;
+                    if (TR && trj && i < h.nv0) trj[i] = en;
                 }
             }
         } else {
@@ -1105,12 +1113,14 @@ __global__ void __launch_bounds__(BLOCK) k_tile(TileArgs a) {
                 if (i < nv_act) {
                     const T en = vertex(i);
                     if (vol_j && i < h.nv0) vp += rAv64[k] * (double)en;
+                    if (TR && trj && i < h.nv0) trj[i] = en;
                 }
             }
         }
         for (int i = tid + VO * BLOCK; i < nv_act; i += BLOCK) {
             const T en = vertex(i);
             if (vol_j && i < h.nv0) vp += a.Av64[h.vbase + i] * (double)en;
+            if (TR && trj && i < h.nv0) trj[i] = en;
         }
         if (vol_j) {
             vp = wave_sum(vp);
@@ -1210,6 +1220,11 @@ __global__ void __launch_bounds__(BLOCK) k_tile(TileArgs a) {
     }
 }
 
+template <typename T, bool F32, int EPT, int BLOCK, int MODE>
+__global__ void __launch_bounds__(BLOCK) k_tile(TileArgs a) {
+    tile_body<T, F32, EPT, BLOCK, MODE>(a, blockIdx.x, gridDim.x);
+}
+
 // ---------------------------------------------------------------------------
 // Adjoint of one substep (reverse of the triangle and vertex phases)
 // ---------------------------------------------------------------------------
@@ -1227,16 +1242,19 @@ __device__ __forceinline__ void adj_tri_at(const AdjArgs &a, int64_t e) {
     const int32_t v0 = a.tri[3 * e], v1 = a.tri[3 * e + 1], v2 = a.tri[3 * e + 2];
     const T *le = static_cast<const T *>(a.lam_eta);
     const T *Av = static_cast<const T *>(a.Av);
-    // lambda_F = -dt_s sum_k (lambda_eta_k / A_k) S_k,  S_k = -A_e grad N_k
+    // lambda_F = -dt_s sum_k (lambda_eta_k / A_k) S_k,  S_k = -A_e grad N_k; the
+    // adjoint multiplies by reciprocals (1 / A_k, 1 / (1 + a^2), 1 / 3) where the
+    // forward divides: the gradients agree with the CPU adjoint to rounding, and the
+    // per-substep and tile kernels evaluate the same operations
     T lFx = T(0), lFy = T(0);
     {
-        const T w0 = -dts * le[v0] / Av[v0];
+        const T w0 = -dts * le[v0] * (T(1) / Av[v0]);
         lFx += w0 * (-Ae * gax);
         lFy += w0 * (-Ae * gay);
-        const T w1 = -dts * le[v1] / Av[v1];
+        const T w1 = -dts * le[v1] * (T(1) / Av[v1]);
         lFx += w1 * (-Ae * gbx);
         lFy += w1 * (-Ae * gby);
-        const T w2 = -dts * le[v2] / Av[v2];
+        const T w2 = -dts * le[v2] * (T(1) / Av[v2]);
         lFx += w2 * (-Ae * gcx);
         lFy += w2 * (-Ae * gcy);
     }
@@ -1255,19 +1273,20 @@ __device__ __forceinline__ void adj_tri_at(const AdjArgs &a, int64_t e) {
     const T db = eb - ea, dc = ec - ea;
     const T gx = db * gbx + dc * gcx;
     const T gy = db * gby + dc * gcy;
+    const T third = T(1) / T(3);
     T He;
     if (c.flags & KF_LINEAR_H) {
-        He = (H0[v0] + H0[v1] + H0[v2]) / T(3);
+        He = (H0[v0] + H0[v1] + H0[v2]) * third;
     } else if (!F32) {
-        He = ((H0[v0] + ea) + (H0[v1] + eb) + (H0[v2] + ec)) / T(3);
+        He = ((H0[v0] + ea) + (H0[v1] + eb) + (H0[v2] + ec)) * third;
     } else {
-        He = ((H0[v0] + H0[v1] + H0[v2]) + (ea + eb + ec)) / T(3) + c.eta_ref_f;
+        He = ((H0[v0] + H0[v1] + H0[v2]) + (ea + eb + ec)) * third + c.eta_ref_f;
     }
     const T al = T(0.5) * static_cast<const T *>(a.f)[e] * dts;
-    const T den = T(1) + al * al;
+    const T rden = T(1) / (T(1) + al * al);
     // U' = C r with C = (I + aJ)^-1:  lambda_r = C^T lambda_U'
-    const T lrx = (lUnx - al * lUny) / den;
-    const T lry = (lUny + al * lUnx) / den;
+    const T lrx = (lUnx - al * lUny) * rden;
+    const T lry = (lUny + al * lUnx) * rden;
     // r = (I - aJ) U + dt_s(-g H grad eta + R)
     lUox += lrx - al * lry;
     lUoy += lry + al * lrx;
@@ -1282,7 +1301,7 @@ __device__ __forceinline__ void adj_tri_at(const AdjArgs &a, int64_t e) {
     psi[0] = gax * lgx + gay * lgy;
     psi[1] = gbx * lgx + gby * lgy;
     psi[2] = gcx * lgx + gcy * lgy;
-    psi[3] = lHe / T(3);
+    psi[3] = lHe * third;
     T2 lo;
     lo.x = lUox;
     lo.y = lUoy;
@@ -1382,6 +1401,329 @@ __global__ void __launch_bounds__(256) k_adj_final(AdjArgs a, T *g_eta0, T *g_U0
     if (i < a.nv && g_eta0) g_eta0[i] = static_cast<const T *>(a.lam_eta)[i];
 }
 
+// ---------------------------------------------------------------------------
+// Reverse substeps on a tile plan
+// ---------------------------------------------------------------------------
+// cnt reverse substeps per launch on a tile and cnt rings of halo (the rings of the
+// forward tile kernel: the reverse substep has the forward one's stencil, a triangle
+// reading its three vertices and a vertex summing over its triangles), with the
+// arithmetic of adj_tri_at / adj_vtx_at operation for operation, so the gradients equal
+// those of the per-substep kernels bit for bit.  Inner step j runs the reverse of the
+// forward substep of trajectory slot s_hi - 1 - j; triangles E_lev and vertices
+// V_lev-1 are updated at level lev = cnt - j.  LDS holds the adjoint elevation, H0, A_v,
+// the forward elevations of the launch's slots and the deposits (three slot terms and
+// lambda_H / 3 per triangle, at the forward kernel's flux positions); registers hold
+// the adjoint transport, the R gradient of owned triangles and the H0 gradient of owned
+// vertices (the plan keeps a tile's owned vertices within two slots per thread).
+template <typename T, bool F32, int EPT, int BLOCK>
+__device__ __forceinline__ void adj_tile_body(const AdjTileArgs &a, int b, int G) {
+    using T2 = typename Vec2<T>::type;
+    constexpr int NVO = 2;   // owned-vertex slots per thread
+    extern __shared__ __align__(16) unsigned char smem[];
+    if (a.xcd) {
+        const int x = b & 7, q = b >> 3;
+        const int base = G >> 3, rem = G & 7;
+        b = x * base + (x < rem ? x : rem) + q;
+    }
+    if (b >= a.ntiles) return;
+    const TileHdrK h = a.hdr[b];
+    const StepC c = a.c;
+    const int K = a.K, cnt = a.cnt;
+    const int *nV = a.nV + b * (K + 1);
+    const int *nE = a.nE + b * (K + 1);
+    const int nv_load = nV[cnt], ne_load = nE[cnt], nvu = nV[cnt - 1];
+    const int tid = threadIdx.x;
+    const bool nonlin = !(c.flags & KF_LINEAR_H);
+    const bool linear_h = !nonlin;
+
+    int off = 0;
+    T *sLe = reinterpret_cast<T *>(smem + off);
+    off = align16(off + (int)sizeof(T) * a.cap_nv);
+    T *sH = reinterpret_cast<T *>(smem + off);
+    off = align16(off + (int)sizeof(T) * a.cap_nv);
+    T *sAv = reinterpret_cast<T *>(smem + off);
+    off = align16(off + (int)sizeof(T) * a.cap_nv);
+    T *sEm = reinterpret_cast<T *>(smem + off);   // [cnt][cap_nv] forward elevations
+    off = align16(off + (int)sizeof(T) * a.cap_nv * cnt);
+    int *sLev = reinterpret_cast<int *>(smem + off);   // V_0..V_8, E_0..E_8
+    off = align16(off + 4 * 18);
+    T *sPsi = reinterpret_cast<T *>(smem + off);
+    off = align16(off + (int)sizeof(T) * a.cap_cs);
+    T *sChi = reinterpret_cast<T *>(smem + off);
+    off = align16(off + (int)sizeof(T) * a.cap_cs);
+    uint16_t *sRow = reinterpret_cast<uint16_t *>(smem + off);
+
+    // ---- load phase: (A) contiguous per-tile data and owned gradients, (B) gathers
+    const int32_t *lv = a.lv_gid + h.lv_off;
+    const uint4 *lrec = reinterpret_cast<const uint4 *>(a.le_rec) + h.le_off;
+    const T *lgeo = static_cast<const T *>(a.lgeo) + 4 * (int64_t)h.le_off;
+    const T *lae = static_cast<const T *>(a.lae) + h.le_off;
+    constexpr int OS = own_slots(EPT);
+    // den: 1 / (1 + a^2)
+    T g0[EPT], g1[EPT], g2[EPT], g3[EPT], g4[EPT], lUx[EPT], lUy[EPT], al[EPT], den[EPT];
+    T sux[EPT], suy[EPT];
+    T grx[OS], gry[OS];
+    uint32_t t0[EPT] = {}, t1[EPT] = {}, t2[EPT] = {};
+    int gt[EPT] = {};
+    if (ne_load > 0) {
+#pragma unroll
+        for (int r = 0; r < EPT; ++r) {
+            const int lc = min(tid + r * BLOCK, ne_load - 1);
+            const uint4 rec = lrec[lc];
+            gt[r] = (int)rec.x;
+            t0[r] = rec.y;
+            t1[r] = rec.z;
+            t2[r] = rec.w;
+            if constexpr (F32) {
+                const float4 gg = reinterpret_cast<const float4 *>(lgeo)[lc];
+                g0[r] = gg.x;
+                g1[r] = gg.y;
+                g2[r] = gg.z;
+                g3[r] = gg.w;
+            } else {
+                const double2 ga = reinterpret_cast<const double2 *>(lgeo)[2 * lc];
+                const double2 gb = reinterpret_cast<const double2 *>(lgeo)[2 * lc + 1];
+                g0[r] = ga.x;
+                g1[r] = ga.y;
+                g2[r] = gb.x;
+                g3[r] = gb.y;
+            }
+            g4[r] = lae[lc];
+        }
+    }
+    const T2 *gRg = static_cast<const T2 *>(a.gR);
+#pragma unroll
+    for (int r = 0; r < OS; ++r) {
+        grx[r] = T(0);
+        gry[r] = T(0);
+    }
+    if (h.nown > 0) {   // a tile may own no triangle (then ebase may equal ne)
+#pragma unroll
+        for (int r = 0; r < OS; ++r) {
+            const T2 v = gRg[h.ebase + min(tid + r * BLOCK, h.nown - 1)];
+            grx[r] = v.x;
+            gry[r] = v.y;
+        }
+    }
+    T gh[NVO];
+    const T *gHg = static_cast<const T *>(a.gH0);
+#pragma unroll
+    for (int k = 0; k < NVO; ++k) gh[k] = gHg[h.vbase + min(tid + k * BLOCK, h.nv0 - 1)];
+    const uint2 *crow = reinterpret_cast<const uint2 *>(a.cs_row + h.rw_off);
+    const int nrow4 = (nvu + 1 + 3) >> 2;
+    const int lev_cnt = tid <= K ? nV[tid] : 0;
+    const int lev_cnt_e = tid <= K ? nE[tid] : 0;
+    __builtin_amdgcn_s_waitcnt(0);   // round A complete
+
+    const T *lein = static_cast<const T *>(a.lam_eta_in);
+    const T *H0g = static_cast<const T *>(a.H0);
+    const T *Avg = static_cast<const T *>(a.Av);
+    for (int i = tid; i < nv_load; i += BLOCK) {
+        const int g = lv[i];
+        sLe[i] = lein[g];
+        sH[i] = H0g[g];
+        sAv[i] = T(1) / Avg[g];   // reciprocal area
+        for (int j = 0; j < cnt; ++j) {
+            const int sl = a.s_hi - 1 - j;
+            const T *es = sl == 0 ? static_cast<const T *>(a.eta_s0)
+                                  : static_cast<const T *>(a.traj) + (int64_t)sl * a.traj_stride;
+            sEm[j * a.cap_nv + i] = es[g];
+        }
+    }
+    const T dts = cdts<T>(c);
+    if (ne_load > 0) {
+        const T2 *lUin = static_cast<const T2 *>(a.lam_U_in);
+        const T *fg = static_cast<const T *>(a.f);
+#pragma unroll
+        for (int r = 0; r < EPT; ++r) {
+            const int g = gt[r];
+            const T2 u = lUin[g];
+            lUx[r] = u.x;
+            lUy[r] = u.y;
+            al[r] = T(0.5) * fg[g] * dts;
+            den[r] = T(1) / (T(1) + al[r] * al[r]);   // reciprocal
+            if (a.lam_Uavg) {   // U^{m+1} enters the running sum with weight 1/M
+                sux[r] = (T)(a.rM * a.lam_Uavg[2 * (int64_t)g]);
+                suy[r] = (T)(a.rM * a.lam_Uavg[2 * (int64_t)g + 1]);
+            } else {
+                sux[r] = T(0);
+                suy[r] = T(0);
+            }
+        }
+    }
+    for (int i = tid; i < nrow4; i += BLOCK) reinterpret_cast<uint2 *>(sRow)[i] = crow[i];
+    if (tid <= K) {
+        sLev[tid] = lev_cnt;
+        sLev[9 + tid] = lev_cnt_e;
+    }
+    if (a.ell) {   // fixed-width rows: unused entries read as zero
+        const int nz = (kEllWidth * nvu * (int)sizeof(T) + 15) / 16;
+        for (int i = tid; i < nz; i += BLOCK) {
+            reinterpret_cast<uint4 *>(sPsi)[i] = make_uint4(0, 0, 0, 0);
+            reinterpret_cast<uint4 *>(sChi)[i] = make_uint4(0, 0, 0, 0);
+        }
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+
+    const T g = cg<T>(c), th = cth<T>(c), opt = copt<T>(c);
+    const bool seeded = a.lam_Uavg != nullptr;
+    for (int j = 0; j < cnt; ++j) {
+        const int lev = cnt - j;
+        const int ne_act = sLev[9 + lev], nv_act = sLev[lev - 1];
+        const T *em = sEm + j * a.cap_nv;
+        // the packed indices and the geometry pass through an empty asm once per substep,
+        // so that values derived from them are recomputed instead of held in registers
+        // across the loop
+#pragma unroll
+        for (int r = 0; r < EPT; ++r) {
+            asm volatile("" : "+v"(t0[r]), "+v"(t1[r]), "+v"(t2[r]));
+            asm volatile("" : "+v"(g0[r]), "+v"(g1[r]), "+v"(g2[r]), "+v"(g3[r]), "+v"(g4[r]));
+        }
+#pragma unroll
+        for (int r = 0; r < EPT; ++r) {
+            const int le = tid + r * BLOCK;
+            if (le >= ne_act) continue;
+            const int ia = t0[r] & 0xffffu, ib = t0[r] >> 16, ic = t1[r] & 0xffffu;
+            const T gbx = g0[r], gby = g1[r], gcx = g2[r], gcy = g3[r], Ae = g4[r];
+            const T gax = -(gbx + gcx), gay = -(gby + gcy);
+            // lambda_F = -dt_s sum_k (lambda_eta_k / A_k) S_k,  S_k = -A_e grad N_k
+            T lFx = T(0), lFy = T(0);
+            {
+                const T w0 = -dts * sLe[ia] * sAv[ia];
+                lFx += w0 * (-Ae * gax);
+                lFy += w0 * (-Ae * gay);
+                const T w1 = -dts * sLe[ib] * sAv[ib];
+                lFx += w1 * (-Ae * gbx);
+                lFy += w1 * (-Ae * gby);
+                const T w2 = -dts * sLe[ic] * sAv[ic];
+                lFx += w2 * (-Ae * gcx);
+                lFy += w2 * (-Ae * gcy);
+            }
+            T lux = lUx[r], luy = lUy[r];
+            if (seeded) {
+                lux = lux + sux[r];
+                luy = luy + suy[r];
+            }
+            const T lUnx = lux + opt * lFx, lUny = luy + opt * lFy;
+            T lUox = -th * lFx, lUoy = -th * lFy;
+            const T ea = em[ia], eb = em[ib], ec = em[ic];
+            const T db = eb - ea, dc = ec - ea;
+            const T gx = db * gbx + dc * gcx;
+            const T gy = db * gby + dc * gcy;
+            const T third = T(1) / T(3);
+            T He;
+            if (linear_h) {
+                He = (sH[ia] + sH[ib] + sH[ic]) * third;
+            } else if (!F32) {
+                He = ((sH[ia] + ea) + (sH[ib] + eb) + (sH[ic] + ec)) * third;
+            } else {
+                He = ((sH[ia] + sH[ib] + sH[ic]) + (ea + eb + ec)) * third + c.eta_ref_f;
+            }
+            const T lrx = (lUnx - al[r] * lUny) * den[r];
+            const T lry = (lUny + al[r] * lUnx) * den[r];
+            lUox += lrx - al[r] * lry;
+            lUoy += lry + al[r] * lrx;
+            if (r < OS) {
+                grx[r < OS ? r : 0] += dts * lrx;
+                gry[r < OS ? r : 0] += dts * lry;
+            }
+            const T lgx = -dts * g * He * lrx, lgy = -dts * g * He * lry;
+            const T lHe = -dts * g * (gx * lrx + gy * lry);
+            const T chi = lHe * third;
+            const int p0 = t1[r] >> 16, p1 = t2[r] & 0xffffu, p2 = t2[r] >> 16;
+            sPsi[p0] = gax * lgx + gay * lgy;
+            sPsi[p1] = gbx * lgx + gby * lgy;
+            sPsi[p2] = gcx * lgx + gcy * lgy;
+            sChi[p0] = chi;
+            sChi[p1] = chi;
+            sChi[p2] = chi;
+            lUx[r] = lUox;
+            lUy[r] = lUoy;
+        }
+        __syncthreads();
+        // vertex phase: lambda_eta += sum over the vertex's triangles (ascending) of
+        // the slot term and lambda_H / 3; the H0 gradient of owned vertices
+        auto vsum = [&](int i, T &ghv, bool own) {
+            T acc = sLe[i];
+            if (a.ell) {
+                const int q0 = kEllWidth * i;
+#pragma unroll
+                for (int q = 0; q < kEllWidth; ++q) {
+                    acc += sPsi[q0 + q];
+                    const T ch = sChi[q0 + q];
+                    if (nonlin) acc += ch;
+                    if (own) ghv += ch;
+                }
+            } else {
+                const int q1 = sRow[i + 1];
+                for (int q = sRow[i]; q < q1; ++q) {
+                    acc += sPsi[q];
+                    const T ch = sChi[q];
+                    if (nonlin) acc += ch;
+                    if (own) ghv += ch;
+                }
+            }
+            sLe[i] = acc;
+        };
+#pragma unroll
+        for (int k = 0; k < NVO; ++k) {
+            const int i = tid + k * BLOCK;
+            if (i < nv_act) vsum(i, gh[k], i < h.nv0);
+        }
+        for (int i = tid + NVO * BLOCK; i < nv_act; i += BLOCK) {
+            T dummy = T(0);
+            vsum(i, dummy, false);
+        }
+        __syncthreads();
+    }
+
+    // write back the owned entries
+    T *leout = static_cast<T *>(a.lam_eta_out) + h.vbase;
+    T *gHo = static_cast<T *>(a.gH0) + h.vbase;
+#pragma unroll
+    for (int k = 0; k < NVO; ++k) {
+        const int i = tid + k * BLOCK;
+        if (i < h.nv0) {
+            leout[i] = sLe[i];
+            gHo[i] = gh[k];
+        }
+    }
+    T2 *lUout = static_cast<T2 *>(a.lam_U_out);
+    T2 *gRo = static_cast<T2 *>(a.gR);
+#pragma unroll
+    for (int r = 0; r < OS; ++r) {
+        const int le = tid + r * BLOCK;
+        if (le < h.nown) {
+            T2 u;
+            u.x = lUx[r];
+            u.y = lUy[r];
+            lUout[h.ebase + le] = u;
+            u.x = grx[r];
+            u.y = gry[r];
+            gRo[h.ebase + le] = u;
+        }
+    }
+}
+
+template <typename T, bool F32, int EPT, int BLOCK>
+__global__ void __launch_bounds__(BLOCK) k_adj_tile(AdjTileArgs a) {
+    adj_tile_body<T, F32, EPT, BLOCK>(a, blockIdx.x, gridDim.x);
+}
+
+// The reverse substeps of one checkpoint segment (blocks [0, nrev)) and the recompute,
+// with trajectory output, of the segment before it (the other blocks) in one launch:
+// the two read and write disjoint arrays (the reverse reads its own segment's
+// trajectory buffer, the recompute writes the other one), so their order does not
+// matter and each part's arithmetic is that of its own kernel.
+template <typename T, bool F32, int EPT, int BLOCK>
+__global__ void __launch_bounds__(BLOCK) k_adj_tile_pair(AdjTileArgs ra, TileArgs fa, int nrev) {
+    if ((int)blockIdx.x < nrev)
+        adj_tile_body<T, F32, EPT, BLOCK>(ra, blockIdx.x, nrev);
+    else
+        tile_body<T, F32, EPT, BLOCK, 3>(fa, blockIdx.x - nrev, gridDim.x - nrev);
+}
+
 // Deterministic sum of each row of partials: out[r] = add + sum_i part[r*width + i].
 __global__ void __launch_bounds__(256) k_vol_reduce(const double *part, int64_t width,
                                                     double add, double *out) {
@@ -1456,6 +1798,7 @@ hipError_t launch_tile_any(bool f32, int mode, int ept, int block, const TileArg
         case 0: return launch_tile_sm<0>(f32, ept, block, a, grid, lds, s);
         case 1: return launch_tile_sm<1>(f32, ept, block, a, grid, lds, s);
         case 2: return launch_tile_sm<2>(f32, ept, block, a, grid, lds, s);
+        case 3: return launch_tile_sm<3>(f32, ept, block, a, grid, lds, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -1489,6 +1832,91 @@ hipError_t prepare_tile(bool f32, int mode, int ept, int block) {
 hipError_t launch_tile(bool f32, int mode, int ept, int block, const TileArgs &a, int grid,
                        size_t lds, hipStream_t s) {
     return launch_tile_any(f32, mode, ept, block, &a, grid, lds, s);
+}
+
+namespace {
+template <typename T, bool F32, int EPT, int BLOCK>
+hipError_t launch_adj_tile_t(const AdjTileArgs *a, size_t lds, hipStream_t s) {
+    auto *kern = k_adj_tile<T, F32, EPT, BLOCK>;
+    if (!a)   // prepare only
+        return hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    hipLaunchKernelGGL(kern, dim3(a->ntiles), dim3(BLOCK), lds, s, *a);
+    return hipGetLastError();
+}
+
+template <typename T, bool F32, int EPT, int BLOCK>
+hipError_t launch_adj_pair_t(const AdjTileArgs *a, const TileArgs *f, size_t lds, hipStream_t s) {
+    auto *kern = k_adj_tile_pair<T, F32, EPT, BLOCK>;
+    if (!a)   // prepare only
+        return hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    hipLaunchKernelGGL(kern, dim3(a->ntiles + f->ntiles), dim3(BLOCK), lds, s, *a, *f,
+                       a->ntiles);
+    return hipGetLastError();
+}
+
+// f null: the reverse kernel alone; else the reverse paired with a recompute launch
+template <typename T, bool F32, int BLOCK>
+hipError_t launch_adj_tile_ept(int ept, const AdjTileArgs *a, const TileArgs *f, size_t lds,
+                               hipStream_t s, bool pair) {
+    switch (ept) {
+        case 1: return pair ? launch_adj_pair_t<T, F32, 1, BLOCK>(a, f, lds, s)
+                            : launch_adj_tile_t<T, F32, 1, BLOCK>(a, lds, s);
+        case 2: return pair ? launch_adj_pair_t<T, F32, 2, BLOCK>(a, f, lds, s)
+                            : launch_adj_tile_t<T, F32, 2, BLOCK>(a, lds, s);
+        case 3: return pair ? launch_adj_pair_t<T, F32, 3, BLOCK>(a, f, lds, s)
+                            : launch_adj_tile_t<T, F32, 3, BLOCK>(a, lds, s);
+        case 4: return pair ? launch_adj_pair_t<T, F32, 4, BLOCK>(a, f, lds, s)
+                            : launch_adj_tile_t<T, F32, 4, BLOCK>(a, lds, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+// reverse tile kernels exist for 256- and 512-thread workgroups, up to four triangles
+// per thread
+hipError_t launch_adj_tile_any(bool f32, int ept, int block, const AdjTileArgs *a,
+                               const TileArgs *f, size_t lds, hipStream_t s, bool pair) {
+    if (block == 256)
+        return f32 ? launch_adj_tile_ept<float, true, 256>(ept, a, f, lds, s, pair)
+                   : launch_adj_tile_ept<double, false, 256>(ept, a, f, lds, s, pair);
+    if (block == 512)
+        return f32 ? launch_adj_tile_ept<float, true, 512>(ept, a, f, lds, s, pair)
+                   : launch_adj_tile_ept<double, false, 512>(ept, a, f, lds, s, pair);
+    return hipErrorInvalidValue;
+}
+}  // namespace
+
+int adj_tile_lds_bytes(bool f32, int block, int cnt, int cap_nv, int cap_nvu, int cap_cs) {
+    (void)block;
+    const int ts = f32 ? 4 : 8;
+    int off = 0;
+    auto al = [](int b) { return (b + 15) & ~15; };
+    off = al(off + ts * cap_nv);
+    off = al(off + ts * cap_nv);
+    off = al(off + ts * cap_nv);
+    off = al(off + ts * cap_nv * cnt);
+    off = al(off + 4 * 18);
+    off = al(off + ts * cap_cs);
+    off = al(off + ts * cap_cs);
+    off = al(off + 2 * (cap_nvu + 4));
+    return off;
+}
+
+hipError_t prepare_adj_tile(bool f32, int ept, int block) {
+    const hipError_t e = launch_adj_tile_any(f32, ept, block, nullptr, nullptr, 0, nullptr, false);
+    if (e != hipSuccess) return e;
+    return launch_adj_tile_any(f32, ept, block, nullptr, nullptr, 0, nullptr, true);
+}
+
+hipError_t launch_adj_tile(bool f32, int ept, int block, const AdjTileArgs &a, size_t lds,
+                           hipStream_t s) {
+    return launch_adj_tile_any(f32, ept, block, &a, nullptr, lds, s, false);
+}
+
+hipError_t launch_adj_tile_pair(bool f32, int ept, int block, const AdjTileArgs &a,
+                                const TileArgs &f, size_t lds, hipStream_t s) {
+    return launch_adj_tile_any(f32, ept, block, &a, &f, lds, s, true);
 }
 
 hipError_t launch_plain_step(bool f32, const PlainArgs &a, hipStream_t s) {

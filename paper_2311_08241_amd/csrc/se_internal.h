@@ -100,6 +100,9 @@ struct DevTiles {
     // forward-backward tile kernel of this plan's shape ready to launch (its LDS limit
     // raised when the plan was made), indexed by f32
     bool prepared[2] = {false, false};
+    // the adjoint's tile path ready (recompute and reverse kernels prepared), its LDS
+    bool adj_ready[2] = {false, false};
+    size_t lds_adj[2] = {0, 0};
     size_t lds(bool f32, bool sm) const {
         return sm ? (f32 ? lds_sm32 : lds_sm64) : (f32 ? lds_bytes32 : lds_bytes64);
     }
