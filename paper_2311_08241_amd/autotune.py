@@ -16,7 +16,7 @@ import time
 
 import numpy as np
 
-TILES = (256, 320, 352, 384, 416, 448, 464, 512, 576, 640, 768, 1024)
+TILES = (256, 288, 304, 320, 352, 384, 416, 448, 464, 512, 576, 640, 768, 1024)
 KS = (2, 3, 4, 5, 6)
 VISC_KS = (2, 4, 6, 8)
 BLOCKS = (256, 512, 1024)
@@ -57,10 +57,16 @@ def _tier_ok(precision: str, ept: int, block: int) -> bool:
     return ept <= ((3 if sm else 4) if prec == "f32" else 1)
 
 
+# VGPRs of the FP64 tile kernel per register tier, from the compiler's resource report
+# (the per-triangle indices and geometry are re-materialised every substep)
+_F64_VGPRS = {1: 82, 2: 101, 3: 127, 4: 157, 6: 215, 8: 256}
+
+
 def _vgprs(precision: str, ept: int) -> int:
     """Approximate VGPRs of the tile kernel per register tier (measured from the
-    compiler's resource report: about 24 per triangle slot in FP32, 45 in FP64;
-    26 and 51 with the two extra transports of the AB3-AM4 scheme)."""
+    compiler's resource report: about 24 per triangle slot in FP32, 26 with the two
+    extra transports of the AB3-AM4 scheme, 51 in FP64 AB3-AM4; FP64 forward-backward
+    tiers tabulated)."""
     prec, sm = _split(precision)
     if _visc(precision):   # viscous form: about 26 (FP32) and 50 (FP64) per slot; the
         # compiler fits the FP64 tiers it allows into 256 registers
@@ -68,7 +74,7 @@ def _vgprs(precision: str, ept: int) -> int:
     elif prec == "f32":
         v = 37 + 26 * ept if sm else 32 + 24 * ept
     else:
-        v = 52 + 51 * ept if sm else 44 + 45 * ept
+        v = 52 + 51 * ept if sm else _F64_VGPRS[ept]
     return -(-v // 8) * 8
 
 

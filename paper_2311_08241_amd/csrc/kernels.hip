@@ -880,6 +880,16 @@ __device__ __forceinline__ void tile_body(const TileArgs &a, int b, int G) {
 #pragma unroll
             for (int r = 0; r < EPT; ++r) asm volatile("" : "+v"(t0[r]), "+v"(t1[r]));
         }
+        // FP64 forward-backward: likewise the packed indices and the geometry (the FP64
+        // values derived from them would otherwise double the registers held per
+        // triangle; three triangles per thread then fit two 512-thread tiles per CU)
+        if constexpr (!F32 && FB) {
+#pragma unroll
+            for (int r = 0; r < EPT; ++r) {
+                asm volatile("" : "+v"(t0[r]), "+v"(t1[r]), "+v"(t2[r]));
+                asm volatile("" : "+v"(g0[r]), "+v"(g1[r]), "+v"(g2[r]), "+v"(g3[r]), "+v"(g4[r]));
+            }
+        }
         // FP32 forward-backward: the three elevations of every slot read before any
         // update, so that all slots wait for one LDS round trip
         float hE[(F32 && FB) ? 3 * EPT : 1];
