@@ -509,6 +509,10 @@ def main():
                     help="time the plan candidates even if a tuned plan is cached or shipped")
     ap.add_argument("--consumers-only", action="store_true",
                     help="time only the trim/z*, forcing and viscous-term kernels (profiling)")
+    ap.add_argument("--scheme", default="se", choices=["se", "sesm"],
+                    help="scheme of the timed step (profiling the AB3-AM4 tile kernel)")
+    ap.add_argument("--visc", default="",
+                    help="A0,Cv: time the step with the barotropic viscous term (profiling)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: the benchmark runs on one GPU only (sharding over GPUs is designed "
@@ -545,8 +549,20 @@ def main():
     t0 = time.time()
     nsub, tau = case["nsub"], case["tau"]
     prec = args.precision
+    if args.scheme != "se" or args.visc:
+        # profiling runs of the other tile-kernel forms: the timed step only
+        args.no_cpu = args.no_extra = True
+    variant = {}
+    tune_key = prec
+    if args.scheme == "sesm":
+        variant["scheme"] = "sesm"
+        tune_key = prec + "-sesm"
+    if args.visc:
+        variant["visc"] = tuple(float(v) for v in args.visc.split(","))
+        tune_key = prec + "-visc"
     params = Params(g=case["g"], theta=case["theta"], precision=prec,
-                    eta_ref=case["eta_ref"] if prec == "f32" else 0.0, track_volume=True)
+                    eta_ref=case["eta_ref"] if prec == "f32" else 0.0, track_volume=True,
+                    **variant)
     d = device_inputs(mesh, case, params)
     Uavg = torch.empty((mesh.ne, 2), dtype=torch.float64, device=dev)
     vol = torch.empty(nsub + 1, dtype=torch.float64, device=dev)
@@ -566,7 +582,7 @@ def main():
         def reset():
             scratch["eta"].copy_(d["eta"])
             scratch["U"].copy_(d["U"])
-        tune = autotune(mesh, lambda: step(scratch), prec, nsub, log=log, reset=reset,
+        tune = autotune(mesh, lambda: step(scratch), tune_key, nsub, log=log, reset=reset,
                         use_cache=not args.retune)
         del scratch
         log(f"[bench] autotuned plan {tune['plan']} ({tune['ms']:.3f} ms/step, "
@@ -613,7 +629,7 @@ def main():
 
     # roofline of the dominant kernel: the tile kernel runs ceil(nsub/k) launches per
     # step, each one compulsory pass (B_ALG bytes per vertex) for k substeps
-    launches_per_step = -(-nsub // plan[1])
+    launches_per_step = -(-nsub // (plan[1] // 2 if args.visc else plan[1]))
     avg_launch_s = ms * 1e-3 / (launches_per_step * args.steps)
     units_per_launch = float(mesh.nv)
     compulsory = B_ALG[prec] * units_per_launch
@@ -621,7 +637,7 @@ def main():
     # the same bytes counted once per substep (what a kernel streaming every substep
     # from HBM would have to move for this rate)
     effective = compulsory * nsub / launches_per_step / avg_launch_s / 1e9
-    traffic = read_traffic(f"{tag}_{prec}", plan)
+    traffic = None if variant else read_traffic(f"{tag}_{prec}", plan)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic, "kernel": "k_tile",
@@ -751,7 +767,11 @@ def main():
                    "nv": mesh.nv, "ne": mesh.ne, "substeps_per_step": nsub,
                    "precision": ("FP32 bulk, FP64 volume and averaged transport"
                                  if prec == "f32" else "FP64"),
-                   "plan": {"tile": plan[0], "k_fused": plan[1], "block": plan[2]}},
+                   "plan": {"tile": plan[0], "k_fused": plan[1], "block": plan[2]},
+                   **({"variant": {"scheme": args.scheme, "visc": args.visc or None},
+                       "note": "profiling run of another tile-kernel form; the roofline "
+                               "bytes are those of the forward-backward scheme"}
+                      if variant else {})},
         "roofline": roofline, "cpu_baseline": cpu, "errors": errors,
         "volume_drift": volume_drift, "hbm_gbs_algorithmic": round(achieved, 1),
     }
