@@ -241,8 +241,8 @@ se_status make_plan(const std::vector<const HostMesh *> &members, const std::vec
     SE_TRY(p->geo32.upload(g32.data(), g32.size() * 4));
     SE_TRY(p->ae64.upload(a64e.data(), a64e.size() * 8));
     SE_TRY(p->ae32.upload(a32e.data(), a32e.size() * 4));
-    // dual-cell areas per local vertex (contiguous per tile: no index round trip);
-    // FP32 holds the reciprocal of the FP32-rounded area, rounded once
+    // reciprocal dual-cell areas per local vertex (contiguous per tile: no index round
+    // trip); FP32: of the FP32-rounded area, rounded once
     const int64_t nlv = static_cast<int64_t>(ht.lv_gid.size());
     std::vector<double> a64(nlv);
     std::vector<float> a32(nlv);
@@ -250,7 +250,7 @@ se_status make_plan(const std::vector<const HostMesh *> &members, const std::vec
         const int64_t gv = ht.lv_gid[i];
         size_t mi = std::upper_bound(voff.begin(), voff.end(), gv) - voff.begin() - 1;
         const double av = members[mi]->Av[gv - voff[mi]];
-        a64[i] = av;
+        a64[i] = 1.0 / av;
         a32[i] = 1.0f / static_cast<float>(av);
     }
     SE_TRY(p->lav64.upload(a64.data(), nlv * 8));

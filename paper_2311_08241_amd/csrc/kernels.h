@@ -43,7 +43,7 @@ struct TileArgs {
     const uint16_t *cs_row;
     const void *lgeo;           // per local triangle: gbx, gby, gcx, gcy (4 values)
     const void *lae;            // per local triangle: A_e
-    const void *lv_av;          // per local vertex: A_v (FP64) or 1 / A_v (FP32)
+    const void *lv_av;          // per local vertex: 1 / A_v
     const StepC *mem;           // per-member constants (batches); nullptr: use c0
     StepC c0;
     void *eta_u, *eta_w;        // ping-pong pair: member chunk ch reads (ch even ? u : w)

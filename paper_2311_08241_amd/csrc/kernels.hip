@@ -41,32 +41,36 @@ template <> __device__ __forceinline__ double copt<double>(const StepC &c) { ret
 template <> __device__ __forceinline__ float copt<float>(const StepC &c) { return c.opt_f; }
 
 // Per-triangle update.  ea..ec: eta at the vertices (FP64: absolute; FP32:
-// deviation from eta_ref), ha..hc: H0.  Returns U' and the three sub-cell
-// fluxes; dry is set when the triangle's total depth is not positive.
+// deviation from eta_ref), ha..hc: H0, al = f dt_s / 2 (0.5 f first, then dt_s).
+// Returns U' and the three sub-cell fluxes; dry is set when the triangle's total depth
+// is not positive.  The CPU definition's divisions by 3 and by 1 + a^2 are
+// multiplications by reciprocals here (one FP64 division per triangle and substep
+// instead of three; agreement with the definition to rounding), the same in every
+// path and plan.
 template <typename T, bool F32>
 __device__ __forceinline__ void tri_update(T ea, T eb, T ec, T ha, T hb, T hc, T gbx, T gby,
-                                           T gcx, T gcy, T Ae, T Ux, T Uy, T Rx, T Ry, T fc,
+                                           T gcx, T gcy, T Ae, T Ux, T Uy, T Rx, T Ry, T al,
                                            const StepC &c, bool linear_h, T &Unx, T &Uny,
                                            T &pa, T &pb, T &pc, bool &dry) {
     const T dts = cdts<T>(c), g = cg<T>(c), th = cth<T>(c), opt = copt<T>(c);
     const T db = eb - ea, dc = ec - ea;
     const T gx = db * gbx + dc * gcx;
     const T gy = db * gby + dc * gcy;
+    const T third = T(1) / T(3);
     T He;
     if (linear_h) {
-        He = (ha + hb + hc) / T(3);
+        He = (ha + hb + hc) * third;
     } else if (!F32) {
-        He = ((ha + ea) + (hb + eb) + (hc + ec)) / T(3);
+        He = ((ha + ea) + (hb + eb) + (hc + ec)) * third;
     } else {
-        He = ((ha + hb + hc) + (ea + eb + ec)) / T(3) + c.eta_ref_f;
+        He = ((ha + hb + hc) + (ea + eb + ec)) * third + c.eta_ref_f;
     }
     dry = !(He > T(0));
-    const T al = T(0.5) * fc * dts;
     const T rx = Ux + al * Uy + dts * (-g * He * gx + Rx);
     const T ry = Uy - al * Ux + dts * (-g * He * gy + Ry);
-    const T den = T(1) + al * al;
-    Unx = (rx + al * ry) / den;
-    Uny = (ry - al * rx) / den;
+    const T rden = T(1) / (T(1) + al * al);
+    Unx = (rx + al * ry) * rden;
+    Uny = (ry - al * rx) * rden;
     const T Fx = opt * Unx - th * Ux;
     const T Fy = opt * Uny - th * Uy;
     const T gax = -(gbx + gcx), gay = -(gby + gcy);
@@ -179,8 +183,8 @@ __device__ __forceinline__ void plain_tri_at(const PlainArgs &a, int64_t e) {
     } else {
         tri_update<T, F32>(eta[va], eta[vb], eta[vc], H0[va], H0[vb], H0[vc], geom[e],
                            geom[a.ne + e], geom[2 * a.ne + e], geom[3 * a.ne + e],
-                           geom[4 * a.ne + e], u.x, u.y, r.x, r.y, fc, c, linear_h, Unx, Uny,
-                           pa, pb, pc, dry);
+                           geom[4 * a.ne + e], u.x, u.y, r.x, r.y, T(0.5) * fc * cdts<T>(c), c,
+                           linear_h, Unx, Uny, pa, pb, pc, dry);
     }
     if (dry) set_fault(a.faults, 1u);
     T *phi = static_cast<T *>(a.phi);
@@ -231,7 +235,7 @@ __device__ __forceinline__ void plain_vtx_at(const PlainArgs &a, int64_t v, doub
     const T wv = a.W ? static_cast<const T *>(a.W)[v] : T(0);
     const T av = static_cast<const T *>(a.Av)[v];
     const T en = F32 ? vtx_update_f32(eo, acc, T(1) / av, wv, cdts<T>(c))
-                     : eo - cdts<T>(c) * (acc / av + wv);
+                     : eo - cdts<T>(c) * (acc * (T(1) / av) + wv);
     eta[v] = en;
     if (!finite_val(en)) set_fault(a.faults, 2u);
     const double av64 = a.Av64[v];
@@ -395,7 +399,7 @@ __global__ void __launch_bounds__(256) k_sesm_vtx(PlainArgs a) {
         const T wv = a.W ? static_cast<const T *>(a.W)[v] : T(0);
         const T av = static_cast<const T *>(a.Av)[v];
         const T en = F32 ? vtx_update_f32(eo, acc, T(1) / av, wv, cdts<T>(c))
-                         : eo - cdts<T>(c) * (acc / av + wv);
+                         : eo - cdts<T>(c) * (acc * (T(1) / av) + wv);
         static_cast<T *>(a.etaA)[v] = sesm_am<T>(c, en, eo, e1, e2);
         eta2[v] = e1;
         eta1[v] = eo;
@@ -584,7 +588,7 @@ __device__ __forceinline__ void tile_body(const TileArgs &a, int b, int G) {
     }
     T *sH = reinterpret_cast<T *>(smem + off);
     off = align16(off + (int)sizeof(T) * a.cap_nv);
-    T *sAv = reinterpret_cast<T *>(smem + off);   // FP64: A_v; FP32: 1 / A_v
+    T *sAv = reinterpret_cast<T *>(smem + off);   // 1 / A_v
     off = align16(off + (int)sizeof(T) * a.cap_nvu);
     T *sW = reinterpret_cast<T *>(smem + off);
     off = align16(off + (int)sizeof(T) * a.cap_nvu);
@@ -615,7 +619,7 @@ __device__ __forceinline__ void tile_body(const TileArgs &a, int b, int G) {
     const T *eA_in = SM ? static_cast<const T *>(a.sm_v[rs][3]) : nullptr;
     const T *H0 = static_cast<const T *>(a.H0);
     const T *Wt = static_cast<const T *>(a.W);
-    const T *lav = static_cast<const T *>(a.lv_av) + h.lv_off;   // FP64: A_v; FP32: 1/A_v
+    const T *lav = static_cast<const T *>(a.lv_av) + h.lv_off;   // 1 / A_v
     const int32_t *lv = a.lv_gid + h.lv_off;
     // vertex slots per thread staged in the rounds (the rest, for large tiles on
     // small workgroups, in a loop afterwards)
@@ -841,6 +845,10 @@ __device__ __forceinline__ void tile_body(const TileArgs &a, int b, int G) {
                 g4[r] = -g4[r];
             }
         }
+    } else if constexpr (!SM) {
+        // FP64 forward-backward: a = f dt_s / 2 of the launch in place of f
+#pragma unroll
+        for (int r = 0; r < EPT; ++r) rf[r] = T(0.5) * rf[r] * dts;
     }
     T rH[F32 ? EPT : 1];
     if constexpr (F32) {
@@ -1041,7 +1049,7 @@ __device__ __forceinline__ void tile_body(const TileArgs &a, int b, int G) {
             if constexpr (F32)
                 en = vtx_update_f32(e_i, acc, av_i, w_i, dts);
             else
-                en = e_i - dts * (acc / av_i + w_i);
+                en = e_i - dts * (acc * av_i + w_i);
             if constexpr (SM) {
                 const T e1 = sE1[i], e2 = sE2[i];
                 sEA[i] = sesm_am<T>(c, en, e_i, e1, e2);

@@ -110,7 +110,7 @@ struct DevTiles {
     std::vector<TileHdr> hdr_host;
     DevBuf hdr, nV, nE, lv_gid, le_rec, cs_row;
     DevBuf geo64, geo32, ae64, ae32;   // per local triangle: 4 gradient values; A_e
-    DevBuf lav64, lav32;          // per local vertex: A_v (FP64), 1 / A_v (FP32)
+    DevBuf lav64, lav32;          // per local vertex: 1 / A_v (FP64, FP32)
     // host copies for tables built on first use: global id of each local triangle,
     // level counts [ntiles][K+1]
     std::vector<int32_t> le_gid_host, nE_host;
