@@ -54,23 +54,26 @@ def _tier_ok(precision: str, ept: int, block: int) -> bool:
         return ept <= (8 if prec == "f32" else 6)
     if block == 512:
         return ept <= (8 if prec == "f32" else 4)
-    return ept <= ((3 if sm else 4) if prec == "f32" else 1)
+    return ept <= ((3 if sm else 4) if prec == "f32" else (1 if sm else 3))
 
 
 # VGPRs of the FP64 tile kernel per register tier, from the compiler's resource report
 # (the per-triangle indices and geometry are re-materialised every substep)
 _F64_VGPRS = {1: 82, 2: 101, 3: 127, 4: 157, 6: 215, 8: 256}
+# the same for the viscous form (FP32 up to three slots: the edge geometry held in
+# registers; the tiers the library refuses are never timed)
+_VISC_VGPRS = {"f32": {1: 72, 2: 102, 3: 127, 4: 141, 6: 189, 8: 239},
+               "f64": {1: 109, 2: 141, 3: 165, 4: 197, 6: 256, 8: 256}}
 
 
 def _vgprs(precision: str, ept: int) -> int:
     """Approximate VGPRs of the tile kernel per register tier (measured from the
     compiler's resource report: about 24 per triangle slot in FP32, 26 with the two
     extra transports of the AB3-AM4 scheme, 51 in FP64 AB3-AM4; FP64 forward-backward
-    tiers tabulated)."""
+    and viscous tiers tabulated)."""
     prec, sm = _split(precision)
-    if _visc(precision):   # viscous form: about 26 (FP32) and 50 (FP64) per slot; the
-        # compiler fits the FP64 tiers it allows into 256 registers
-        v = 44 + 26 * ept if prec == "f32" else min(256, 75 + 50 * ept)
+    if _visc(precision):
+        v = _VISC_VGPRS[prec][ept]
     elif prec == "f32":
         v = 37 + 26 * ept if sm else 32 + 24 * ept
     else:

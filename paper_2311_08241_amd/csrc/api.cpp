@@ -116,7 +116,7 @@ bool ept_ok(bool f32, int ept, int block, bool sm = false) {
     if (block == 256) return f32 ? ept <= 8 : ept <= 6;
     if (block == 512) return f32 ? ept <= 8 : ept <= 4;
     // 1024 threads: at most 128 VGPRs (the AB3-AM4 form holds two more transports)
-    return f32 ? ept <= (sm ? 3 : 4) : ept <= 1;
+    return f32 ? ept <= (sm ? 3 : 4) : ept <= (sm ? 1 : 3);
 }
 
 // Host-side construction and statistics of a plan (no device memory).
@@ -260,13 +260,13 @@ se_status make_plan(const std::vector<const HostMesh *> &members, const std::vec
     for (int f = 0; f < 2; ++f)
         p->prepared[f] = p->ok(f == 1, false) && prepare_tile(f == 1, 0, p->ept, p->block) == hipSuccess;
     // the adjoint on the plan: recompute with trajectory output (mode 3) and the reverse
-    // tile kernel (256- or 512-thread workgroups, up to four triangles per thread, a tile's
-    // owned vertices within two per thread, its LDS within 160 KiB)
+    // tile kernel (up to four triangles per thread, two in FP64 with 1024-thread
+    // workgroups; a tile's owned vertices within two per thread, its LDS within 160 KiB)
     for (int f = 0; f < 2; ++f) {
         const bool f32 = f == 1;
         p->lds_adj[f] = static_cast<size_t>(adj_tile_lds_bytes(f32, block, K, p->max_nv,
                                                                p->max_nvu, p->max_cs));
-        p->adj_ready[f] = p->prepared[f] && (block == 256 || block == 512) && ept <= 4 &&
+        p->adj_ready[f] = p->prepared[f] && ept <= 4 &&
                           T <= 2 * block && p->lds_adj[f] <= 160 * 1024 &&
                           prepare_tile(f32, 3, ept, block) == hipSuccess &&
                           prepare_adj_tile(f32, ept, block) == hipSuccess;
@@ -855,8 +855,10 @@ se_status sesub::subcycle_tile(se_mesh *m, const se_params *p, se_state *st,
     const size_t es = f32 ? 4 : 8;
     size_t lds = P.lds(f32, sm);
     if (visc) {
-        // two rings per substep; the velocities u = U / H_e of the tile's triangles in LDS
-        lds += 2 * es * static_cast<size_t>(P.max_ne);
+        // two rings per substep; the velocities u = U / H_e of the tile's triangles and
+        // their edge-neighbour ids in LDS
+        lds = ((lds + 2 * es * static_cast<size_t>(P.max_ne) + 15) & ~static_cast<size_t>(15)) +
+              8 * static_cast<size_t>(P.max_ne);
         // register budget of the viscous form (no spills): 1024-thread workgroups up to
         // three triangles per thread (FP32; FP64 one), 512-thread ones up to six (FP32)
         // or four (FP64)

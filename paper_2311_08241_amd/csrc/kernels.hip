@@ -599,8 +599,11 @@ __device__ __forceinline__ void tile_body(const TileArgs &a, int b, int G) {
     T *sAcc = reinterpret_cast<T *>(smem + off);   // sub-cell fluxes in local CSR order
     off = align16(off + (int)sizeof(T) * a.cap_cs);
     uint16_t *sRow = reinterpret_cast<uint16_t *>(smem + off);
-    // VI: u = U / H_e per local triangle (after the row offsets)
-    T *sUb = reinterpret_cast<T *>(smem + align16(off + 2 * (a.cap_nvu + 4)));
+    // VI: u = U / H_e per local triangle (after the row offsets), then the triangles'
+    // local edge-neighbour ids (three 16-bit ids in a uint2)
+    const int ub_off = align16(off + 2 * (a.cap_nvu + 4));
+    T *sUb = reinterpret_cast<T *>(smem + ub_off);
+    uint2 *sNb = reinterpret_cast<uint2 *>(smem + align16(ub_off + 2 * (int)sizeof(T) * a.cap_ne));
 
     // ---- load phase in two rounds of independent loads: (A) index and static data
     // (local vertex ids, triangle records, geometry, row offsets, running sums), one
@@ -651,6 +654,12 @@ __device__ __forceinline__ void tile_body(const TileArgs &a, int b, int G) {
     constexpr int OS = own_slots(EPT);
     SumT<F32> sm[OS];
     auto osl = [](int r) { return r < OS ? r : 0; };
+    // VI: the edge geometry of the first HV slots held in registers for the whole launch
+    // (the other slots read it from memory at every substep).  Measured on the lat-lon
+    // workload: faster with FP32 and up to three triangles per thread in 256- and
+    // 512-thread workgroups (the same register tier), slower elsewhere
+    constexpr int HV = (VI && F32 && BLOCK <= 512 && EPT <= 3) ? EPT : 0;
+    T vgh[HV > 0 ? 6 * HV : 1];
     if (ne_load > 0) {
 #pragma unroll
         for (int r = 0; r < EPT; ++r) {
@@ -675,6 +684,19 @@ __device__ __forceinline__ void tile_body(const TileArgs &a, int b, int G) {
                 g3[r] = gb.y;
             }
             g4[r] = lae[lc];
+        }
+        if constexpr (HV > 0) {
+#pragma unroll
+            for (int r = 0; r < HV; ++r) {
+                const int lc = min(tid + r * BLOCK, ne_load - 1);
+                const T2 *vg = reinterpret_cast<const T2 *>(a.vgeo) + 3 * (int64_t)(h.le_off + lc);
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    const T2 v = vg[q];
+                    vgh[6 * r + 2 * q] = v.x;
+                    vgh[6 * r + 2 * q + 1] = v.y;
+                }
+            }
         }
         if (!first && h.nown > 0) {
             // running sums of owned triangles (the tile's contiguous global range)
@@ -804,6 +826,10 @@ __device__ __forceinline__ void tile_body(const TileArgs &a, int b, int G) {
         stage_vertex(i, lv[i]);
     }
     for (int i = tid + BLOCK; i < nrow4; i += BLOCK) reinterpret_cast<uint2 *>(sRow)[i] = crow[i];
+    if constexpr (VI) {
+        const uint2 *nbt = reinterpret_cast<const uint2 *>(a.vnb) + h.le_off;
+        for (int i = tid; i < ne_load; i += BLOCK) sNb[i] = nbt[i];
+    }
     if (a.ell) {
         // fixed-width rows: the entries past a vertex's triangles are never written
         // and must read as zero (adding +0 leaves every row sum unchanged)
@@ -879,14 +905,17 @@ __device__ __forceinline__ void tile_body(const TileArgs &a, int b, int G) {
         // needs the velocities of ring lev + 1
         const int lev = VI ? 2 * (cnt - j) - 1 : cnt - j;
         const int ne_act = sLev[9 + lev], nv_act = sLev[lev - 1];
-        // VI: the thread index and the packed local indices pass through an empty asm
-        // once per substep, so addresses and indices derived from them are recomputed
-        // instead of held in registers for every triangle across the loop
+        // VI: the thread index, the packed local indices and the geometry pass through an
+        // empty asm once per substep, so addresses, indices and values derived from them
+        // are recomputed instead of held in registers for every triangle across the loop
         int tidv = tid;
         if constexpr (VI) {
             asm volatile("" : "+v"(tidv));
 #pragma unroll
-            for (int r = 0; r < EPT; ++r) asm volatile("" : "+v"(t0[r]), "+v"(t1[r]));
+            for (int r = 0; r < EPT; ++r) {
+                asm volatile("" : "+v"(t0[r]), "+v"(t1[r]), "+v"(t2[r]));
+                asm volatile("" : "+v"(g0[r]), "+v"(g1[r]), "+v"(g2[r]), "+v"(g3[r]), "+v"(g4[r]));
+            }
         }
         // FP64 forward-backward: likewise the packed indices and the geometry (the FP64
         // values derived from them would otherwise double the registers held per
@@ -981,9 +1010,10 @@ __device__ __forceinline__ void tile_body(const TileArgs &a, int b, int G) {
                 T rx = rRx[r], ry = rRy[r];
                 if constexpr (VI) {
                     // V(eta^m, U^m): edges to local neighbours (0xffff: coast)
+                    const uint2 nbp = sNb[le];
                     const int lq = h.le_off + tidv + r * BLOCK;   // = h.le_off + le
-                    const uint2 nbp = reinterpret_cast<const uint2 *>(a.vnb)[lq];
-                    const T *vg = static_cast<const T *>(a.vgeo) + 6 * (int64_t)lq;
+                    const T *vg = r < HV ? vgh + 6 * (r < HV ? r : 0)
+                                         : static_cast<const T *>(a.vgeo) + 6 * (int64_t)lq;
                     const int nbs[3] = {static_cast<int>(nbp.x & 0xffffu),
                                         static_cast<int>(nbp.x >> 16),
                                         static_cast<int>(nbp.y & 0xffffu)};
@@ -1778,8 +1808,8 @@ hipError_t launch_tile_ept(int ept, const TileArgs *a, int grid, size_t lds, hip
     }
 }
 
-// 1024-thread workgroups must fit 128 VGPRs: FP32 up to 4 triangles per thread,
-// FP64 one.
+// 1024-thread workgroups must fit 128 VGPRs: FP32 up to 4 triangles per thread; FP64
+// forward-backward (modes 0 and 3) up to 3, the other FP64 modes one.
 template <typename T, bool F32, int SM>
 hipError_t launch_tile_1024(int ept, const TileArgs *a, int grid, size_t lds, hipStream_t s) {
     if constexpr (F32) {
@@ -1788,6 +1818,13 @@ hipError_t launch_tile_1024(int ept, const TileArgs *a, int grid, size_t lds, hi
             case 2: return launch_tile_t<T, F32, 2, 1024, SM>(a, grid, lds, s);
             case 3: return launch_tile_t<T, F32, 3, 1024, SM>(a, grid, lds, s);
             case 4: return launch_tile_t<T, F32, 4, 1024, SM>(a, grid, lds, s);
+            default: return hipErrorInvalidValue;
+        }
+    } else if constexpr (SM == 0 || SM == 3) {
+        switch (ept) {
+            case 1: return launch_tile_t<T, F32, 1, 1024, SM>(a, grid, lds, s);
+            case 2: return launch_tile_t<T, F32, 2, 1024, SM>(a, grid, lds, s);
+            case 3: return launch_tile_t<T, F32, 3, 1024, SM>(a, grid, lds, s);
             default: return hipErrorInvalidValue;
         }
     } else {
@@ -1891,10 +1928,35 @@ hipError_t launch_adj_tile_ept(int ept, const AdjTileArgs *a, const TileArgs *f,
     }
 }
 
-// reverse tile kernels exist for 256- and 512-thread workgroups, up to four triangles
-// per thread
+// 1024-thread workgroups (128 VGPRs): FP32 up to four triangles per thread, FP64 two
+template <typename T, bool F32>
+hipError_t launch_adj_tile_1024(int ept, const AdjTileArgs *a, const TileArgs *f, size_t lds,
+                                hipStream_t s, bool pair) {
+    if (ept > (F32 ? 4 : 2)) return hipErrorInvalidValue;
+    switch (ept) {
+        case 1: return pair ? launch_adj_pair_t<T, F32, 1, 1024>(a, f, lds, s)
+                            : launch_adj_tile_t<T, F32, 1, 1024>(a, lds, s);
+        case 2: return pair ? launch_adj_pair_t<T, F32, 2, 1024>(a, f, lds, s)
+                            : launch_adj_tile_t<T, F32, 2, 1024>(a, lds, s);
+        default:
+            if constexpr (F32) {
+                if (ept == 3)
+                    return pair ? launch_adj_pair_t<T, F32, 3, 1024>(a, f, lds, s)
+                                : launch_adj_tile_t<T, F32, 3, 1024>(a, lds, s);
+                return pair ? launch_adj_pair_t<T, F32, 4, 1024>(a, f, lds, s)
+                            : launch_adj_tile_t<T, F32, 4, 1024>(a, lds, s);
+            }
+            return hipErrorInvalidValue;
+    }
+}
+
+// reverse tile kernels exist for 256-, 512- and 1024-thread workgroups, up to four
+// triangles per thread (two in FP64 at 1024 threads)
 hipError_t launch_adj_tile_any(bool f32, int ept, int block, const AdjTileArgs *a,
                                const TileArgs *f, size_t lds, hipStream_t s, bool pair) {
+    if (block == 1024)
+        return f32 ? launch_adj_tile_1024<float, true>(ept, a, f, lds, s, pair)
+                   : launch_adj_tile_1024<double, false>(ept, a, f, lds, s, pair);
     if (block == 256)
         return f32 ? launch_adj_tile_ept<float, true, 256>(ept, a, f, lds, s, pair)
                    : launch_adj_tile_ept<double, false, 256>(ept, a, f, lds, s, pair);

@@ -105,9 +105,10 @@ def test_checkpoint_interval_does_not_change_the_gradient(precision):
             for k in (1, 2, 5, 7, 29, 30)]
     # once the mesh has a tile plan the checkpoint sweep runs on the tile kernel (K
     # substeps per launch: 4 gives two launches per 5-substep segment, 2 three, with
-    # the intermediate states alternating between two scratch slots)
+    # the intermediate states alternating between two scratch slots; 256,5,1024 runs
+    # each segment's reverse substeps in one launch with 1024-thread workgroups)
     tried = 0
-    for plan in ((256, 4, 256), (128, 2, 256)):
+    for plan in ((256, 4, 256), (128, 2, 256), (256, 5, 1024)):
         st = mesh.plan_stats(*plan)
         if not st["ok_f32" if precision == "f32" else "ok_f64"]:
             continue

@@ -96,7 +96,8 @@ def _case(name):
     return CASES[name]
 
 
-PLANS = [(64, 1, 256), (64, 3, 256), (128, 4, 256), (256, 2, 512), (96, 8, 256)]
+PLANS = [(64, 1, 256), (64, 3, 256), (128, 4, 256), (256, 2, 512), (96, 8, 256),
+         (512, 4, 1024), (640, 3, 1024)]   # 1024 threads: two and three triangles each
 
 
 @pytest.mark.parametrize("name", ["jitter76", "chan54", "sphere86", "torus43", "grid45", "fan100"])

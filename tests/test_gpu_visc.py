@@ -227,7 +227,9 @@ def test_viscous_tile_fp32_identical_to_plain():
     mesh = Mesh.from_dict(case, device=0)
     p = _params(case, "f32", visc)
     ref = _run_gpu(case, mesh, p, 2)
-    for pl in VPLANS:
+    # and the FP32 register tiers of the viscous form: three triangles per thread with
+    # 1024- and 512-thread workgroups
+    for pl in VPLANS + [(512, 6, 1024), (256, 4, 512)]:
         if not mesh.plan_stats(*pl)["ok_f32"]:
             continue
         out = _run_tile(case, mesh, p, 2, pl)
