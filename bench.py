@@ -217,34 +217,43 @@ def bench_adjoint(args, log):
         p = Params(precision=prec, eta_ref=case["eta_ref"] if prec == "f32" else 0.0)
         d = device_inputs(mesh, case, p)
         lam = torch.ones(mesh.nv, dtype=p.dtype, device="cuda:0")
-        ws = mesh.workspace(p, case["nsub"], case["ckpt_every"])
         g = [torch.empty_like(d["eta"]), torch.empty_like(d["U"]), torch.empty_like(d["R"]),
              torch.empty_like(d["H0"])]
         e, U = d["eta"].clone(), d["U"].clone()
+        ws = None
 
         def fwd():
             mesh.subcycle(e, U, R=d["R"], f=d["f"], H0=d["H0"], nsub=case["nsub"],
                           dt=case["tau"], params=p, workspace=ws)
-        # tile plan for this mesh (the forward and the adjoint run on it): the fastest
-        # forward among a few shapes that give 64-512 tiles, with 2-6 substeps per
-        # launch (5 or more run a checkpoint segment in one launch)
-        best = None
-        for plan in ((1024, 4, 512), (512, 4, 512), (256, 4, 256), (128, 4, 256),
-                     (256, 5, 256), (128, 5, 256), (128, 6, 256), (256, 5, 512),
-                     (192, 5, 512), (320, 5, 512), (128, 5, 512)):
-            if not mesh.plan_stats(*plan)["ok_f32" if prec == "f32" else "ok_f64"]:
-                continue
-            mesh.set_plan(*plan)
-            fwd()
-            t = _time(fwd, 5)
-            if best is None or t < best[0]:
-                best = (t, plan)
-        mesh.set_plan(*best[1])
 
         def adj():
             mesh.adjoint(d["eta"], d["U"], R=d["R"], f=d["f"], H0=d["H0"], nsub=case["nsub"],
                          dt=case["tau"], params=p, ckpt_every=case["ckpt_every"], lam_eta=lam,
                          g_eta0=g[0], g_U0=g[1], g_R=g[2], g_H0=g[3], workspace=ws)
+
+        def use(plan):
+            nonlocal ws
+            mesh.set_plan(*plan)
+            ws = mesh.workspace(p, case["nsub"], case["ckpt_every"])
+        # tile plans for this mesh (shapes that give 64-512 tiles, with 2-6 substeps per
+        # launch; 5 or more run a checkpoint segment in one launch): the forward and the
+        # adjoint are each timed on every plan and each is reported at its fastest
+        bestf = besta = None
+        for plan in ((1024, 4, 512), (512, 4, 512), (256, 4, 256), (128, 4, 256),
+                     (256, 5, 256), (128, 5, 256), (128, 6, 256), (256, 5, 512),
+                     (192, 5, 512), (320, 5, 512), (128, 5, 512), (256, 5, 1024)):
+            if not mesh.plan_stats(*plan)["ok_f32" if prec == "f32" else "ok_f64"]:
+                continue
+            use(plan)
+            fwd()
+            t = _time(fwd, 5)
+            if bestf is None or t < bestf[0]:
+                bestf = (t, plan)
+            adj()
+            t = _time(adj, 5)
+            if besta is None or t < besta[0]:
+                besta = (t, plan)
+        use(besta[1])
         adj()
         torch.cuda.synchronize()
         ms = _time(adj, 5)
@@ -264,27 +273,28 @@ def bench_adjoint(args, log):
         if not all(torch.equal(a, b) for a, b in zip(g, ref)):
             raise RuntimeError("adjoint graph replay differs from the eager gradients")
         ms_graph = _time(graph.replay, 10)
+        use(bestf[1])
         fwd()
         msf = _time(fwd, 5)
         # launches in stream order, each waiting for the previous one (the tile path of
-        # se_subcycle_adjoint): the seed kernel; the sweep up to the last checkpoint,
-        # ceil(k / k_fused) tile launches per segment; the last segment's recompute; per
-        # segment its reverse launches (ceil(len / k_fused)), the recompute of the
-        # segment before it sharing them; the final kernel
+        # se_subcycle_adjoint): the sweep up to the last checkpoint, ceil(k / k_fused)
+        # tile launches per segment; the last segment's recompute; per segment its
+        # reverse launches (ceil(len / k_fused)), the recompute of the segment before it
+        # sharing them (the first reverse launch starts from the seeds, the last one
+        # writes the gradients of the initial state)
         nsub, k = case["nsub"], case["ckpt_every"]
-        K = best[1][1]
+        K = besta[1][1]
         segs = [min(k, nsub - m0) for m0 in range(0, nsub, k)]
         nch = lambda L: -(-L // K)
         rec = lambda L: nch(L) if L > 1 else 0
-        nops = (1 + nch(k) * (len(segs) - 1) + rec(segs[-1])
-                + sum(max(nch(L), rec(segs[i - 1]) if i > 0 else 0) for i, L in enumerate(segs))
-                + 1)
-        out[prec] = {"plan": list(best[1]), "ms_adjoint": ms, "ms_adjoint_graph": ms_graph,
-                     "ms_forward": msf,
+        nops = (nch(k) * (len(segs) - 1) + rec(segs[-1])
+                + sum(max(nch(L), rec(segs[i - 1]) if i > 0 else 0) for i, L in enumerate(segs)))
+        out[prec] = {"plan": list(besta[1]), "forward_plan": list(bestf[1]),
+                     "ms_adjoint": ms, "ms_adjoint_graph": ms_graph, "ms_forward": msf,
                      "adjoint_over_forward": ms / msf, "dependent_launches": nops,
                      "us_per_launch": 1e3 * ms_graph / nops}
-        log(f"[bench] adjoint {prec}: {ms:.3f} ms, graph replay {ms_graph:.3f} ms "
-            f"(forward {msf:.3f} ms; {nops} dependent launches, "
+        log(f"[bench] adjoint {prec}: {ms:.3f} ms at {besta[1]}, graph replay {ms_graph:.3f} ms "
+            f"(forward {msf:.3f} ms at {bestf[1]}; {nops} dependent launches, "
             f"{1e3 * ms_graph / nops:.1f} us each)")
     return out
 
@@ -509,6 +519,8 @@ def main():
                     help="time the plan candidates even if a tuned plan is cached or shipped")
     ap.add_argument("--consumers-only", action="store_true",
                     help="time only the trim/z*, forcing and viscous-term kernels (profiling)")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="time only the adjoint on the 256x256 basin (profiling)")
     ap.add_argument("--scheme", default="se", choices=["se", "sesm"],
                     help="scheme of the timed step (profiling the AB3-AM4 tile kernel)")
     ap.add_argument("--visc", default="",
@@ -526,6 +538,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+    if args.adjoint_only:
+        print(json.dumps({"adjoint": bench_adjoint(args, log)}), flush=True)
+        return
     t0 = time.time()
     if args.small:
         case = sesynth.latlon_c3(nlon=512, nlat=384, nsteps=args.steps)

@@ -260,8 +260,9 @@ se_status make_plan(const std::vector<const HostMesh *> &members, const std::vec
     for (int f = 0; f < 2; ++f)
         p->prepared[f] = p->ok(f == 1, false) && prepare_tile(f == 1, 0, p->ept, p->block) == hipSuccess;
     // the adjoint on the plan: recompute with trajectory output (mode 3) and the reverse
-    // tile kernel (up to four triangles per thread, two in FP64 with 1024-thread
-    // workgroups; a tile's owned vertices within two per thread, its LDS within 160 KiB)
+    // tile kernel (up to four triangles per thread, with 1024-thread workgroups three in
+    // FP32 and two in FP64; a tile's owned vertices within two per thread, its LDS within
+    // 160 KiB)
     for (int f = 0; f < 2; ++f) {
         const bool f32 = f == 1;
         p->lds_adj[f] = static_cast<size_t>(adj_tile_lds_bytes(f32, block, K, p->max_nv,
@@ -1406,7 +1407,6 @@ se_status se_subcycle_adjoint(se_mesh *m, const se_params *p, const void *eta0, 
     aa.c = fa.c;
     aa.rM = 1.0 / static_cast<double>(nsub);
     aa.thrM = p->theta * aa.rM;
-    HIP_TRY(launch_adj_init(f32, aa, lam_eta, lam_U, s), "adjoint: init");
 
     if (TP && TP->ok(f32, false) && TP->prepared[f32 ? 1 : 0] && TP->adj_ready[f32 ? 1 : 0]) {
         // 2'. reverse sweep on the tile plan, segment by segment from the last.  A
@@ -1416,7 +1416,9 @@ se_status se_subcycle_adjoint(se_mesh *m, const se_params *p, const void *eta0, 
         // per launch on the reverse tile kernel (the adjoint state alternating between
         // two buffers).  The recompute of segment sg - 1 shares the launches of the
         // reverse substeps of segment sg (independent work on disjoint arrays); only
-        // the last segment's recompute runs alone.
+        // the last segment's recompute runs alone.  The sweep's first launch starts from
+        // the seeds and its last one writes the gradients of the initial state (the
+        // seed and final kernels of the per-substep path folded in).
         const DevTiles &P = *TP;
         StepC c = fa.c;
         c.flags &= ~KF_TRACK_VOLUME;
@@ -1442,6 +1444,7 @@ se_status se_subcycle_adjoint(se_mesh *m, const se_params *p, const void *eta0, 
         ra.gH0 = aa.gH0;
         ra.c = fa.c;
         ra.rM = aa.rM;
+        ra.thrM = aa.thrM;
         ra.K = P.K;
         ra.ntiles = P.ntiles;
         ra.xcd = 1;
@@ -1490,12 +1493,17 @@ se_status se_subcycle_adjoint(se_mesh *m, const se_params *p, const void *eta0, 
             size_t i = 0;
             for (int32_t s_hi = seg_len(sg); s_hi > 0; ++i) {
                 const int32_t cntr = std::min(P.K, s_hi);
+                const bool first = sg == A.nseg - 1 && i == 0, last = sg == 0 && s_hi == cntr;
                 ra.cnt = cntr;
                 ra.s_hi = s_hi;
-                ra.lam_eta_in = lam_e[cur];
-                ra.lam_U_in = lam_u[cur];
+                ra.seed = first ? 1 : 0;
+                ra.lam_eta_in = first ? lam_eta : lam_e[cur];
+                ra.lam_U_in = first ? lam_U : lam_u[cur];
                 ra.lam_eta_out = lam_e[cur ^ 1];
                 ra.lam_U_out = lam_u[cur ^ 1];
+                ra.fin = last ? 1 : 0;
+                ra.g_eta0 = last ? g_eta0 : nullptr;
+                ra.g_U0 = last ? g_U0 : nullptr;
                 if (i < rec.size())
                     HIP_TRY(launch_adj_tile_pair(f32, P.ept, P.block, ra, rec[i], lds_p, s),
                             "adjoint: reverse substeps and recompute");
@@ -1509,11 +1517,9 @@ se_status se_subcycle_adjoint(se_mesh *m, const se_params *p, const void *eta0, 
                 HIP_TRY(launch_tile(f32, 3, P.ept, P.block, rec[i], P.ntiles, lds_f, s),
                         "adjoint: segment recompute");
         }
-        aa.lam_eta = lam_e[cur];
-        aa.lam_U = lam_u[cur];
-        HIP_TRY(launch_adj_final(f32, aa, g_eta0, g_U0, s), "adjoint: final");
         return SE_OK;
     }
+    HIP_TRY(launch_adj_init(f32, aa, lam_eta, lam_U, s), "adjoint: init");
 
     // 2. reverse sweep, segment by segment.  Segment sg (substeps m0 .. m1 - 1) needs its
     // states m0 + 1 .. m1 - 1, recomputed from its checkpoint into segment buffer sg mod 2.

@@ -96,6 +96,14 @@ struct AdjTileArgs {
     void *gR, *gH0;                      // accumulated gradients (owned entries updated)
     StepC c;
     double rM;                           // 1 / M
+    // seed != 0 (the sweep's first launch): the state before it is the seed itself —
+    // lam_eta_in / lam_U_in are the caller's seeds or null for zero, the transport's
+    // plus thrM <<U>>-seed — and the gradients start from zero.  fin != 0 (the last
+    // launch): the transport's final value minus thrM <<U>>-seed, written to lam_U_out
+    // and g_U0, the elevation's also to g_eta0 (either may be null)
+    double thrM;                         // theta / M
+    void *g_eta0, *g_U0;
+    int32_t seed, fin;
     int32_t K, cnt, s_hi, ntiles, xcd, ell;
     int32_t cap_nv, cap_ne, cap_nvu, cap_cs;
 };

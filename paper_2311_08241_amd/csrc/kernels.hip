@@ -1545,7 +1545,7 @@ __device__ __forceinline__ void adj_tile_body(const AdjTileArgs &a, int b, int G
         grx[r] = T(0);
         gry[r] = T(0);
     }
-    if (h.nown > 0) {   // a tile may own no triangle (then ebase may equal ne)
+    if (h.nown > 0 && !a.seed) {   // a tile may own no triangle (then ebase may equal ne)
 #pragma unroll
         for (int r = 0; r < OS; ++r) {
             const T2 v = gRg[h.ebase + min(tid + r * BLOCK, h.nown - 1)];
@@ -1556,7 +1556,7 @@ __device__ __forceinline__ void adj_tile_body(const AdjTileArgs &a, int b, int G
     T gh[NVO];
     const T *gHg = static_cast<const T *>(a.gH0);
 #pragma unroll
-    for (int k = 0; k < NVO; ++k) gh[k] = gHg[h.vbase + min(tid + k * BLOCK, h.nv0 - 1)];
+    for (int k = 0; k < NVO; ++k) gh[k] = a.seed ? T(0) : gHg[h.vbase + min(tid + k * BLOCK, h.nv0 - 1)];
     const uint2 *crow = reinterpret_cast<const uint2 *>(a.cs_row + h.rw_off);
     const int nrow4 = (nvu + 1 + 3) >> 2;
     const int lev_cnt = tid <= K ? nV[tid] : 0;
@@ -1568,7 +1568,7 @@ __device__ __forceinline__ void adj_tile_body(const AdjTileArgs &a, int b, int G
     const T *Avg = static_cast<const T *>(a.Av);
     for (int i = tid; i < nv_load; i += BLOCK) {
         const int g = lv[i];
-        sLe[i] = lein[g];
+        sLe[i] = lein ? lein[g] : T(0);   // null only for a zero seed
         sH[i] = H0g[g];
         sAv[i] = T(1) / Avg[g];   // reciprocal area
         for (int j = 0; j < cnt; ++j) {
@@ -1585,7 +1585,17 @@ __device__ __forceinline__ void adj_tile_body(const AdjTileArgs &a, int b, int G
 #pragma unroll
         for (int r = 0; r < EPT; ++r) {
             const int g = gt[r];
-            const T2 u = lUin[g];
+            T2 u;
+            if (lUin) {
+                u = lUin[g];
+            } else {   // zero seed
+                u.x = T(0);
+                u.y = T(0);
+            }
+            if (a.seed && a.lam_Uavg) {   // the endpoint term of <<U>> for U^M
+                u.x = u.x + (T)(a.thrM * a.lam_Uavg[2 * (int64_t)g]);
+                u.y = u.y + (T)(a.thrM * a.lam_Uavg[2 * (int64_t)g + 1]);
+            }
             lUx[r] = u.x;
             lUy[r] = u.y;
             al[r] = T(0.5) * fg[g] * dts;
@@ -1726,30 +1736,39 @@ __device__ __forceinline__ void adj_tile_body(const AdjTileArgs &a, int b, int G
         __syncthreads();
     }
 
-    // write back the owned entries
+    // write back the owned entries (the last launch: with the final step's work)
     T *leout = static_cast<T *>(a.lam_eta_out) + h.vbase;
     T *gHo = static_cast<T *>(a.gH0) + h.vbase;
+    T *ge0 = (a.fin && a.g_eta0) ? static_cast<T *>(a.g_eta0) + h.vbase : nullptr;
 #pragma unroll
     for (int k = 0; k < NVO; ++k) {
         const int i = tid + k * BLOCK;
         if (i < h.nv0) {
             leout[i] = sLe[i];
             gHo[i] = gh[k];
+            if (ge0) ge0[i] = sLe[i];
         }
     }
     T2 *lUout = static_cast<T2 *>(a.lam_U_out);
     T2 *gRo = static_cast<T2 *>(a.gR);
+    T2 *gU0 = (a.fin && a.g_U0) ? static_cast<T2 *>(a.g_U0) : nullptr;
 #pragma unroll
     for (int r = 0; r < OS; ++r) {
         const int le = tid + r * BLOCK;
         if (le < h.nown) {
+            const int64_t e = h.ebase + le;
             T2 u;
             u.x = lUx[r];
             u.y = lUy[r];
-            lUout[h.ebase + le] = u;
+            if (a.fin && a.lam_Uavg) {   // the endpoint term of <<U>> for U^0
+                u.x = u.x - (T)(a.thrM * a.lam_Uavg[2 * e]);
+                u.y = u.y - (T)(a.thrM * a.lam_Uavg[2 * e + 1]);
+            }
+            lUout[e] = u;
+            if (gU0) gU0[e] = u;
             u.x = grx[r];
             u.y = gry[r];
-            gRo[h.ebase + le] = u;
+            gRo[e] = u;
         }
     }
 }
@@ -1928,30 +1947,27 @@ hipError_t launch_adj_tile_ept(int ept, const AdjTileArgs *a, const TileArgs *f,
     }
 }
 
-// 1024-thread workgroups (128 VGPRs): FP32 up to four triangles per thread, FP64 two
+// 1024-thread workgroups (128 VGPRs without spills): FP32 up to three triangles per
+// thread, FP64 two
 template <typename T, bool F32>
 hipError_t launch_adj_tile_1024(int ept, const AdjTileArgs *a, const TileArgs *f, size_t lds,
                                 hipStream_t s, bool pair) {
-    if (ept > (F32 ? 4 : 2)) return hipErrorInvalidValue;
+    if (ept > (F32 ? 3 : 2)) return hipErrorInvalidValue;
     switch (ept) {
         case 1: return pair ? launch_adj_pair_t<T, F32, 1, 1024>(a, f, lds, s)
                             : launch_adj_tile_t<T, F32, 1, 1024>(a, lds, s);
         case 2: return pair ? launch_adj_pair_t<T, F32, 2, 1024>(a, f, lds, s)
                             : launch_adj_tile_t<T, F32, 2, 1024>(a, lds, s);
         default:
-            if constexpr (F32) {
-                if (ept == 3)
-                    return pair ? launch_adj_pair_t<T, F32, 3, 1024>(a, f, lds, s)
-                                : launch_adj_tile_t<T, F32, 3, 1024>(a, lds, s);
-                return pair ? launch_adj_pair_t<T, F32, 4, 1024>(a, f, lds, s)
-                            : launch_adj_tile_t<T, F32, 4, 1024>(a, lds, s);
-            }
+            if constexpr (F32)
+                return pair ? launch_adj_pair_t<T, F32, 3, 1024>(a, f, lds, s)
+                            : launch_adj_tile_t<T, F32, 3, 1024>(a, lds, s);
             return hipErrorInvalidValue;
     }
 }
 
 // reverse tile kernels exist for 256-, 512- and 1024-thread workgroups, up to four
-// triangles per thread (two in FP64 at 1024 threads)
+// triangles per thread (three in FP32 and two in FP64 at 1024 threads)
 hipError_t launch_adj_tile_any(bool f32, int ept, int block, const AdjTileArgs *a,
                                const TileArgs *f, size_t lds, hipStream_t s, bool pair) {
     if (block == 1024)
