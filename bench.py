@@ -299,6 +299,52 @@ def bench_adjoint(args, log):
     return out
 
 
+def bench_share(args, log, mesh, case, value_full, nparts=8):
+    """One GPU's share of the lat-lon workload at its real size: a contiguous 1/nparts
+    range of the library's Hilbert vertex order (the middle one), as a mesh of its own
+    whose cut edge is a coast instead of a halo, FP32, the fastest of a few tile plans.
+    What it leaves out: the halo exchange every k_fused substeps and the volume
+    all-reduce of a multi-GPU run."""
+    import torch
+
+    import sesynth
+    from paper_2311_08241_amd import Mesh, Params, device_inputs
+    k = nparts // 2
+    lo, hi = k * mesh.nv // nparts, (k + 1) * mesh.nv // nparts
+    sub = sesynth.vertex_subset(case, mesh.vperm[lo:hi], name=f"{case['name']}-share{k}of{nparts}")
+    m = Mesh.from_dict(sub, device=0)
+    nsub, tau = sub["nsub"], sub["tau"]
+    p = Params(g=sub["g"], theta=sub["theta"], precision="f32", eta_ref=sub["eta_ref"],
+               track_volume=True)
+    d = device_inputs(m, sub, p)
+    Uavg = torch.empty((m.ne, 2), dtype=torch.float64, device="cuda:0")
+    vol = torch.empty(nsub + 1, dtype=torch.float64, device="cuda:0")
+    best = None
+    for plan in ((464, 4, 512), (384, 4, 512), (304, 4, 512), (256, 4, 512), (192, 4, 512),
+                 (320, 2, 256), (256, 3, 512)):
+        if not m.plan_stats(*plan)["ok_f32"]:
+            continue
+        m.set_plan(*plan)
+        ws = m.workspace(p, nsub)
+
+        def step():
+            m.subcycle(d["eta"], d["U"], R=d["R"], f=d["f"], H0=d["H0"], nsub=nsub, dt=tau,
+                       params=p, Uavg=Uavg, volume=vol, workspace=ws)
+        step()
+        t = _time(step, 10)
+        if best is None or t < best[0]:
+            best = (t, plan, m.plan_stats(*plan)["ntiles"])
+    assert m.check_faults() == 0
+    ms, plan, ntiles = best
+    rate = m.nv * nsub / ms * 1e3
+    log(f"[bench] share {k + 1}/{nparts}: {m.nv} vertices, {ms:.3f} ms/step at {plan} "
+        f"({ntiles} tiles), {rate:.3e} vertex-substeps/s ({rate / value_full:.2f} of the whole mesh's)")
+    return {"workload": f"vertices {lo}..{hi - 1} of the Hilbert order ({m.nv} vertices, {m.ne} "
+                        f"triangles), FP32, {nsub} substeps per step",
+            "plan": list(plan), "tiles": ntiles, "ms_per_step": ms, "value": rate,
+            "of_whole_mesh_rate": rate / value_full}
+
+
 def bench_sesm(args, log, mesh, case, stream, with_oracle):
     """The AB3-AM4 scheme (eqs. (eq4_7)-(eq4_8)) on the same lat-lon workload: FP32
     on the tile kernel (autotuned), FP64 on the plain three-kernel path, FP32 error
@@ -703,6 +749,8 @@ def main():
         extra["trim_zstar"] = bench_trim(args, log, mesh, case, stream)
         extra["forcing"] = bench_forcing(args, log, mesh, case, stream)
         extra["visc"] = bench_visc(args, log, mesh, case, stream)
+        if not args.small:
+            extra["share_1_of_8"] = bench_share(args, log, mesh, case, value)
 
     cpu = None
     errors = None

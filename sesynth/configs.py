@@ -183,6 +183,24 @@ def latlon_c3(seed: int = 0, nlon: int = 2048, nlat: int = 1536, nsteps: int = 2
                  name=f"C3-latlon-{nlon}x{nlat}")
 
 
+def vertex_subset(case: dict, vertices: np.ndarray, name: str | None = None):
+    """The workload restricted to a set of its vertices (input numbering): the triangles
+    with all three vertices in the set, their vertices, and every field on them.  With a
+    contiguous range of a space-filling-curve order this is one GPU's share of the mesh
+    (its edge becomes a coast instead of a halo)."""
+    keep = np.zeros(case["x"].size, bool)
+    keep[np.asarray(vertices)] = True
+    keep_t = keep[case["tri"]].all(axis=1)
+    mesh, old = M.keep_vertices(case, keep)
+    d = dict(case)
+    d.update(x=mesh["x"], y=mesh["y"], tri=mesh["tri"], H0=case["H0"][old].copy(),
+             eta0=case["eta0"][old].copy(), f=case["f"][keep_t].copy(),
+             R=case["R"][keep_t].copy(), U0=case["U0"][keep_t].copy(),
+             W=None if case.get("W") is None else case["W"][old].copy(),
+             name=name or case["name"] + "-subset")
+    return d
+
+
 def adjoint_c5(seed: int = 0, n: int = 256, delta: float = 4000.0):
     """256x256 jittered closed basin with a seeded elevation target."""
     r = M.rng(500 + seed)
