@@ -777,11 +777,21 @@ static se_status check_state(const se_state *st, const se_forcing *fo, const voi
     return SE_OK;
 }
 
+// Access policy of the tile kernels for nv vertices: stream each tile's own tables and
+// the write-back past the caches when one launch moves more than half of the 256 MiB
+// last-level cache (about 236 B per vertex in FP32, 356 in FP64); smaller working sets
+// stay cached from launch to launch and keep ordinary accesses (lat-lon workload, 2.2M
+// vertices: 150 -> 136 us per launch with it; the 65k-vertex adjoint basin 10% slower).
+static int32_t stream_policy(int64_t nv, bool f32) {
+    return (f32 ? 236.0 : 356.0) * static_cast<double>(nv) > 128.0 * 1024 * 1024 ? 1 : 0;
+}
+
 // Launch arguments of the tile kernel on one mesh: plan tables, forcing, workspace
 // (running sum, U^0 copy, volume partials); K substeps per launch, no average output.
 static TileArgs tile_args(const se_mesh *m, const DevTiles &P, bool f32, const se_forcing *fo,
                           char *w, const Layout &L, const StepC &c) {
     TileArgs a{};
+    a.nt = stream_policy(m->h.nv, f32);
     a.hdr = P.hdr.as<const TileHdrK>();
     a.nV = P.nV.as<const int32_t>();
     a.nE = P.nE.as<const int32_t>();
@@ -1894,6 +1904,7 @@ se_status se_subcycle_batched(se_batch *b, const se_params *p, se_state *st, con
     }
     char *w = static_cast<char *>(ws);
     TileArgs a{};
+    a.nt = stream_policy(b->nv, f32);
     a.hdr = P.hdr.as<const TileHdrK>();
     a.nV = P.nV.as<const int32_t>();
     a.nE = P.nE.as<const int32_t>();

@@ -75,6 +75,10 @@ struct TileArgs {
     // traj + m * traj_stride (global numbering)
     void *traj;
     int64_t traj_stride;
+    // access policy: non-zero selects the kernel that streams the tile's own tables and
+    // the write-back past the caches (meshes whose launch traffic exceeds what the
+    // caches keep between launches)
+    int32_t nt;
 };
 
 // Reverse (adjoint) substeps of the forward-backward scheme on a tile plan: one launch

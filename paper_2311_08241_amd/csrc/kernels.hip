@@ -153,6 +153,10 @@ __device__ __forceinline__ float4 ld_nt(const float4 *p) {
     const nt_f4 v = __builtin_nontemporal_load(reinterpret_cast<const nt_f4 *>(p));
     return make_float4(v.x, v.y, v.z, v.w);
 }
+__device__ __forceinline__ float2 ld_nt(const float2 *p) {
+    const nt_f2 v = __builtin_nontemporal_load(reinterpret_cast<const nt_f2 *>(p));
+    return make_float2(v.x, v.y);
+}
 __device__ __forceinline__ double2 ld_nt(const double2 *p) {
     const nt_d2 v = __builtin_nontemporal_load(reinterpret_cast<const nt_d2 *>(p));
     return make_double2(v.x, v.y);
@@ -164,6 +168,34 @@ template <typename T> __device__ __forceinline__ void st_nt2(void *p, int64_t i,
     using V = typename NtVec2<T>::type;
     const V v = {x, y};
     __builtin_nontemporal_store(v, static_cast<V *>(p) + i);
+}
+// The same accesses under a launch-wide policy (a template parameter of the tile
+// kernel, so that no access carries a branch): non-temporal when the launch streams
+// more than the last-level cache can keep between launches (large meshes), ordinary
+// when the whole working set stays cached from one launch to the next (small meshes,
+// where bypassing the caches would turn hits into device-memory reads).
+template <bool NT, typename V> __device__ __forceinline__ V ldp(const V *p) {
+    if constexpr (NT)
+        return ld_nt(p);
+    else
+        return *p;
+}
+template <bool NT, typename T> __device__ __forceinline__ void st2(void *p, int64_t i, T x, T y) {
+    if constexpr (NT) {
+        st_nt2<T>(p, i, x, y);
+    } else {
+        using T2 = typename Vec2<T>::type;
+        T2 v;
+        v.x = x;
+        v.y = y;
+        static_cast<T2 *>(p)[i] = v;
+    }
+}
+template <bool NT, typename T> __device__ __forceinline__ void st1(T v, T *p) {
+    if constexpr (NT)
+        __builtin_nontemporal_store(v, p);
+    else
+        *p = v;
 }
 
 // Running sum of the substep transports, always accumulated in FP64 (the FP32 path
@@ -184,9 +216,12 @@ template <bool F32> struct SumT {
         x = v.x;
         y = v.y;
     }
-    __device__ __forceinline__ void store(void *p, int64_t i) const {   // non-temporal
+    template <bool NT = false> __device__ __forceinline__ void store(void *p, int64_t i) const {
         const nt_d2 v = {x, y};
-        __builtin_nontemporal_store(v, static_cast<nt_d2 *>(p) + i);
+        if constexpr (NT)
+            __builtin_nontemporal_store(v, static_cast<nt_d2 *>(p) + i);
+        else
+            static_cast<nt_d2 *>(p)[i] = v;
     }
     __device__ __forceinline__ double vx() const { return x; }
     __device__ __forceinline__ double vy() const { return y; }
@@ -564,7 +599,9 @@ __device__ __forceinline__ int align16(int b) { return (b + 15) & ~15; }
 // MODE 3: MODE 0 that also writes the owned vertices' elevation after every substep to
 // a trajectory (the adjoint's recompute).
 // The body of one tile's launch work for block index b of a grid of G blocks.
-template <typename T, bool F32, int EPT, int BLOCK, int MODE>
+// NT: the access policy of the launch (non-temporal accesses of the tile's own tables
+// and of the write-back; see ldp), chosen by the host per mesh size.
+template <typename T, bool F32, int EPT, int BLOCK, int MODE, bool NT = false>
 __device__ __forceinline__ void tile_body(const TileArgs &a, int b, int G) {
     constexpr bool SM = MODE == 1, VI = MODE == 2, TR = MODE == 3, FB = MODE == 0 || TR;
     using T2 = typename Vec2<T>::type;
@@ -579,6 +616,7 @@ __device__ __forceinline__ void tile_body(const TileArgs &a, int b, int G) {
     if (b >= a.ntiles) return;
     if (a.tile_list) b = a.tile_list[b];
     const TileHdrK h = a.hdr[b];
+    constexpr bool nt = NT;   // access policy of the launch (ldp, st1, st2)
     // step constants: the member's table row (batches) or the launch's own copy,
     // moved word by word so that both sources stay in scalar registers
     StepC c;
@@ -705,26 +743,26 @@ __device__ __forceinline__ void tile_body(const TileArgs &a, int b, int G) {
 #pragma unroll
         for (int r = 0; r < EPT; ++r) {
             const int lc = min(tid + r * BLOCK, ne_load - 1);
-            const uint4 rec = ld_nt(lrec + lc);
+            const uint4 rec = ldp<nt>(lrec + lc);
             gt[r] = (int)rec.x;
             t0[r] = rec.y;
             t1[r] = rec.z;
             t2[r] = rec.w;
             if constexpr (F32) {
-                const float4 gg = ld_nt(reinterpret_cast<const float4 *>(lgeo) + lc);
+                const float4 gg = ldp<nt>(reinterpret_cast<const float4 *>(lgeo) + lc);
                 g0[r] = gg.x;
                 g1[r] = gg.y;
                 g2[r] = gg.z;
                 g3[r] = gg.w;
             } else {
-                const double2 ga = ld_nt(reinterpret_cast<const double2 *>(lgeo) + 2 * lc);
-                const double2 gb = ld_nt(reinterpret_cast<const double2 *>(lgeo) + 2 * lc + 1);
+                const double2 ga = ldp<nt>(reinterpret_cast<const double2 *>(lgeo) + 2 * lc);
+                const double2 gb = ldp<nt>(reinterpret_cast<const double2 *>(lgeo) + 2 * lc + 1);
                 g0[r] = ga.x;
                 g1[r] = ga.y;
                 g2[r] = gb.x;
                 g3[r] = gb.y;
             }
-            g4[r] = ld_nt(lae + lc);
+            g4[r] = ldp<nt>(lae + lc);
         }
         if constexpr (HV > 0) {
 #pragma unroll
@@ -732,7 +770,7 @@ __device__ __forceinline__ void tile_body(const TileArgs &a, int b, int G) {
                 const int lc = min(tid + r * BLOCK, ne_load - 1);
                 const T *vg = static_cast<const T *>(a.vgeo) + 6 * (int64_t)(h.le_off + lc);
 #pragma unroll
-                for (int q = 0; q < 6; ++q) vgh[6 * r + q] = ld_nt(vg + q);
+                for (int q = 0; q < 6; ++q) vgh[6 * r + q] = ldp<nt>(vg + q);
             }
         }
         if (!first && h.nown > 0) {
@@ -749,7 +787,7 @@ __device__ __forceinline__ void tile_body(const TileArgs &a, int b, int G) {
 #pragma unroll
         for (int k = 0; k < VO; ++k) {
             const double *pa = a.Av64 + h.vbase + min(tid + k * BLOCK, h.nv0 - 1);
-            rAv64[k] = F32 ? *pa : ld_nt(pa);
+            rAv64[k] = F32 ? *pa : ldp<nt>(pa);
         }
     }
     // level counts for the substep loop
@@ -758,12 +796,12 @@ __device__ __forceinline__ void tile_body(const TileArgs &a, int b, int G) {
     // local CSR row offsets (chunks padded to multiples of 4 entries)
     const uint2 *crow = reinterpret_cast<const uint2 *>(a.cs_row + h.rw_off);
     const int nrow4 = (nvu + 1 + 3) >> 2;
-    const uint2 row0 = F32 ? crow[min(tid, nrow4 - 1)] : ld_nt(crow + min(tid, nrow4 - 1));
+    const uint2 row0 = F32 ? crow[min(tid, nrow4 - 1)] : ldp<nt>(crow + min(tid, nrow4 - 1));
     __builtin_amdgcn_s_waitcnt(0);   // round A complete
 
     auto stage_vertex = [&](int i, int g) {   // register path
         const T ve = eta_in[g], vh = H0[g];
-        const T va = i < nvu ? ld_nt(lav + i) : T(0);
+        const T va = i < nvu ? ldp<nt>(lav + i) : T(0);
         const T vw = (i < nvu && hasW) ? Wt[g] : T(0);
         if constexpr (SM) {
             const T v1 = e1_in[g], v2 = e2_in[g];
@@ -865,10 +903,10 @@ __device__ __forceinline__ void tile_body(const TileArgs &a, int b, int G) {
         }
         stage_vertex(i, lv[i]);
     }
-    for (int i = tid + BLOCK; i < nrow4; i += BLOCK) reinterpret_cast<uint2 *>(sRow)[i] = ld_nt(crow + i);
+    for (int i = tid + BLOCK; i < nrow4; i += BLOCK) reinterpret_cast<uint2 *>(sRow)[i] = ldp<nt>(crow + i);
     if constexpr (VI) {
         const uint2 *nbt = reinterpret_cast<const uint2 *>(a.vnb) + h.le_off;
-        for (int i = tid; i < ne_load; i += BLOCK) sNb[i] = ld_nt(nbt + i);
+        for (int i = tid; i < ne_load; i += BLOCK) sNb[i] = ldp<nt>(nbt + i);
     }
     if (a.ell) {
         // fixed-width rows: the entries past a vertex's triangles are never written
@@ -884,7 +922,7 @@ __device__ __forceinline__ void tile_body(const TileArgs &a, int b, int G) {
                 T2 u;
                 u.x = rUx[r];
                 u.y = rUy[r];
-                st_nt2<T>(a.U0c, h.ebase + le, u.x, u.y);
+                st2<nt, T>(a.U0c, h.ebase + le, u.x, u.y);
             }
         }
     }
@@ -1227,10 +1265,10 @@ __device__ __forceinline__ void tile_body(const TileArgs &a, int b, int G) {
         T *o2 = static_cast<T *>(a.sm_v[wsel][2]) + h.vbase;
         T *o3 = static_cast<T *>(a.sm_v[wsel][3]) + h.vbase;
         for (int i = tid; i < h.nv0; i += BLOCK) {
-            __builtin_nontemporal_store(sEta[i], o0 + i);
-            __builtin_nontemporal_store(sE1[i], o1 + i);
-            __builtin_nontemporal_store(sE2[i], o2 + i);
-            __builtin_nontemporal_store(sEA[i], o3 + i);
+            st1<nt>(sEta[i], o0 + i);
+            st1<nt>(sE1[i], o1 + i);
+            st1<nt>(sE2[i], o2 + i);
+            st1<nt>(sEA[i], o3 + i);
         }
         T2 *u0 = static_cast<T2 *>(a.sm_e[wsel][0]);
         T2 *u1 = static_cast<T2 *>(a.sm_e[wsel][1]);
@@ -1240,21 +1278,21 @@ __device__ __forceinline__ void tile_body(const TileArgs &a, int b, int G) {
             const int le = tid + r * BLOCK;
             if (le < h.nown) {
                 const int g = h.ebase + le;
-                st_nt2<T>(u0, g, rUx[r], rUy[r]);
-                st_nt2<T>(u1, g, pUx[r], pUy[r]);
-                st_nt2<T>(u2, g, aUx[r], aUy[r]);
+                st2<nt, T>(u0, g, rUx[r], rUy[r]);
+                st2<nt, T>(u1, g, pUx[r], pUy[r]);
+                st2<nt, T>(u2, g, aUx[r], aUy[r]);
                 if (last) {
                     if (a.Uavg) {
-                        st_nt2<double>(a.Uavg, g, sm[r].vx() / c.Mdbl, sm[r].vy() / c.Mdbl);
+                        st2<nt, double>(a.Uavg, g, sm[r].vx() / c.Mdbl, sm[r].vy() / c.Mdbl);
                     }
                 } else {
-                    sm[r].store(a.sum, g);
+                    sm[r].template store<nt>(a.sum, g);
                 }
             }
         }
     } else {
     T *eta_out = static_cast<T *>(even ? a.eta_w : a.eta_u);
-    for (int i = tid; i < h.nv0; i += BLOCK) __builtin_nontemporal_store(sEta[i], eta_out + h.vbase + i);
+    for (int i = tid; i < h.nv0; i += BLOCK) st1<nt>(sEta[i], eta_out + h.vbase + i);
     T2 *Uout = static_cast<T2 *>(even ? a.U_w : a.U_u);
 #pragma unroll
     for (int r = 0; r < OS; ++r) {   // owned triangles lie in the first OS slots
@@ -1264,15 +1302,14 @@ __device__ __forceinline__ void tile_body(const TileArgs &a, int b, int G) {
             T2 u;
             u.x = rUx[r];
             u.y = rUy[r];
-            st_nt2<T>(Uout, g, u.x, u.y);
+            st2<nt, T>(Uout, g, u.x, u.y);
             if (last) {
                 if (!a.Uavg) continue;
-                const typename NtVec2<T>::type u0 = __builtin_nontemporal_load(
-                    static_cast<const typename NtVec2<T>::type *>(a.U0c) + g);
-                st_nt2<double>(a.Uavg, g, sm[r].vx() / c.Mdbl + c.thM * ((double)u.x - (double)u0.x),
+                const T2 u0 = ldp<nt>(static_cast<const T2 *>(a.U0c) + g);
+                st2<nt, double>(a.Uavg, g, sm[r].vx() / c.Mdbl + c.thM * ((double)u.x - (double)u0.x),
                                sm[r].vy() / c.Mdbl + c.thM * ((double)u.y - (double)u0.y));
             } else {
-                sm[r].store(a.sum, g);
+                sm[r].template store<nt>(a.sum, g);
             }
         }
     }
@@ -1301,9 +1338,9 @@ __device__ __forceinline__ void tile_body(const TileArgs &a, int b, int G) {
     }
 }
 
-template <typename T, bool F32, int EPT, int BLOCK, int MODE>
+template <typename T, bool F32, int EPT, int BLOCK, int MODE, bool NT>
 __global__ void __launch_bounds__(BLOCK) k_tile(TileArgs a) {
-    tile_body<T, F32, EPT, BLOCK, MODE>(a, blockIdx.x, gridDim.x);
+    tile_body<T, F32, EPT, BLOCK, MODE, NT>(a, blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1508,6 +1545,9 @@ __device__ __forceinline__ void adj_tile_body(const AdjTileArgs &a, int b, int G
     }
     if (b >= a.ntiles) return;
     const TileHdrK h = a.hdr[b];
+    // ordinary accesses: the adjoint's workloads are small enough to stay cached from
+    // launch to launch (non-temporal loads cost the 65k-vertex basin about 10%)
+    constexpr bool nt = false;
     const StepC c = a.c;
     const int K = a.K, cnt = a.cnt;
     const int *nV = a.nV + b * (K + 1);
@@ -1550,26 +1590,26 @@ __device__ __forceinline__ void adj_tile_body(const AdjTileArgs &a, int b, int G
 #pragma unroll
         for (int r = 0; r < EPT; ++r) {
             const int lc = min(tid + r * BLOCK, ne_load - 1);
-            const uint4 rec = ld_nt(lrec + lc);
+            const uint4 rec = ldp<nt>(lrec + lc);
             gt[r] = (int)rec.x;
             t0[r] = rec.y;
             t1[r] = rec.z;
             t2[r] = rec.w;
             if constexpr (F32) {
-                const float4 gg = ld_nt(reinterpret_cast<const float4 *>(lgeo) + lc);
+                const float4 gg = ldp<nt>(reinterpret_cast<const float4 *>(lgeo) + lc);
                 g0[r] = gg.x;
                 g1[r] = gg.y;
                 g2[r] = gg.z;
                 g3[r] = gg.w;
             } else {
-                const double2 ga = ld_nt(reinterpret_cast<const double2 *>(lgeo) + 2 * lc);
-                const double2 gb = ld_nt(reinterpret_cast<const double2 *>(lgeo) + 2 * lc + 1);
+                const double2 ga = ldp<nt>(reinterpret_cast<const double2 *>(lgeo) + 2 * lc);
+                const double2 gb = ldp<nt>(reinterpret_cast<const double2 *>(lgeo) + 2 * lc + 1);
                 g0[r] = ga.x;
                 g1[r] = ga.y;
                 g2[r] = gb.x;
                 g3[r] = gb.y;
             }
-            g4[r] = ld_nt(lae + lc);
+            g4[r] = ldp<nt>(lae + lc);
         }
     }
     const T2 *gRg = static_cast<const T2 *>(a.gR);
@@ -1600,7 +1640,7 @@ __device__ __forceinline__ void adj_tile_body(const AdjTileArgs &a, int b, int G
     const T *H0g = static_cast<const T *>(a.H0);
     const T *Avg = static_cast<const T *>(a.Av);
     for (int i = tid; i < nv_load; i += BLOCK) {
-        const int g = ld_nt(lv + i);
+        const int g = ldp<nt>(lv + i);
         sLe[i] = lein ? lein[g] : T(0);   // null only for a zero seed
         sH[i] = H0g[g];
         sAv[i] = T(1) / Avg[g];   // reciprocal area
@@ -1642,7 +1682,7 @@ __device__ __forceinline__ void adj_tile_body(const AdjTileArgs &a, int b, int G
             }
         }
     }
-    for (int i = tid; i < nrow4; i += BLOCK) reinterpret_cast<uint2 *>(sRow)[i] = ld_nt(crow + i);
+    for (int i = tid; i < nrow4; i += BLOCK) reinterpret_cast<uint2 *>(sRow)[i] = ldp<nt>(crow + i);
     if (tid <= K) {
         sLev[tid] = lev_cnt;
         sLev[9 + tid] = lev_cnt_e;
@@ -1839,11 +1879,17 @@ __global__ void __launch_bounds__(256) k_vol_reduce(const double *part, int64_t 
 
 template <typename T, bool F32, int EPT, int BLOCK, int SM>
 hipError_t launch_tile_t(const TileArgs *a, int grid, size_t lds, hipStream_t s) {
-    auto *kern = k_tile<T, F32, EPT, BLOCK, SM>;
-    if (!a)   // prepare only
-        return hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+    auto *kern = k_tile<T, F32, EPT, BLOCK, SM, false>;
+    auto *kern_nt = k_tile<T, F32, EPT, BLOCK, SM, true>;
+    if (!a) {   // prepare only: both access policies
+        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                 160 * 1024);
+        if (e != hipSuccess) return e;
+        return hipFuncSetAttribute(reinterpret_cast<const void *>(kern_nt),
                                    hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(BLOCK), lds, s, *a);
+    }
+    hipLaunchKernelGGL(a->nt ? kern_nt : kern, dim3(grid), dim3(BLOCK), lds, s, *a);
     return hipGetLastError();
 }
 
