@@ -250,9 +250,10 @@ def bench_adjoint(args, log):
             if bestf is None or t < bestf[0]:
                 bestf = (t, plan)
             adj()
-            t = _time(adj, 5)
-            if besta is None or t < besta[0]:
-                besta = (t, plan)
+            ta = _time(adj, 5)
+            log(f"[bench] adjoint {prec} plan {plan}: forward {t:.3f} ms, adjoint {ta:.3f} ms")
+            if besta is None or ta < besta[0]:
+                besta = (ta, plan)
         use(besta[1])
         adj()
         torch.cuda.synchronize()

@@ -117,17 +117,22 @@ def test_c5_adjoint_full_size_equals_oracle():
     Av = torch.tensor(mesh.geometry()[0], dtype=torch.float64, device="cuda:0")
     tgt = torch.tensor(mesh.v_in(case["eta_target"]), dtype=torch.float64, device="cuda:0")
     lam = 2 * Av * (eta - tgt)
-    g = mesh.adjoint(d["eta"], d["U"], R=d["R"], f=d["f"], H0=d["H0"], nsub=case["nsub"],
-                     dt=case["tau"], params=p, ckpt_every=case["ckpt_every"], lam_eta=lam)
     lam_o = om.v_in(mesh.v_out(lam.cpu().numpy()))
     ref = om.adjoint(om.v_in(case["eta0"]), om.e_in(case["U0"]), lam_o, H0=om.v_in(case["H0"]),
                      f=om.e_in(case["f"]), R=om.e_in(case["R"]), g=case["g"],
                      theta=case["theta"], nsub=case["nsub"], tau=case["tau"])
-    outs = [mesh.v_out(g[0].cpu().numpy()), mesh.e_out(g[1].cpu().numpy()),
-            mesh.e_out(g[2].cpu().numpy()), mesh.v_out(g[3].cpu().numpy())]
     refs = [om.v_out(ref[0]), om.e_out(ref[1]), om.e_out(ref[2]), om.v_out(ref[3])]
-    for a, b in zip(outs, refs):
-        assert np.abs(a - b).max() <= 1e-12 * np.abs(b).max()
+    # the mesh's default plan, then 256,5,512 (three triangles per thread in FP64)
+    for plan in (None, (256, 5, 512)):
+        if plan is not None:
+            assert mesh.plan_stats(*plan)["tri_per_thread"] == 3
+            mesh.set_plan(*plan)
+        g = mesh.adjoint(d["eta"], d["U"], R=d["R"], f=d["f"], H0=d["H0"], nsub=case["nsub"],
+                         dt=case["tau"], params=p, ckpt_every=case["ckpt_every"], lam_eta=lam)
+        outs = [mesh.v_out(g[0].cpu().numpy()), mesh.e_out(g[1].cpu().numpy()),
+                mesh.e_out(g[2].cpu().numpy()), mesh.v_out(g[3].cpu().numpy())]
+        for a, b in zip(outs, refs):
+            assert np.abs(a - b).max() <= 1e-12 * np.abs(b).max(), plan
 
 
 def test_c4_ensemble_members_equal_oracle_10_steps():
