@@ -310,9 +310,15 @@ se_status se_check_faults(void *mesh_or_batch, int32_t kind, void *stream,
  * come from the same subcycle (eq. (eq4_11)).  Device arrays, mesh numbering:
  * H0, eta_new [nv] (absolute eta), Uavg [ne][2], Ustar and U [ne][K][2] (U may
  * alias Ustar; no other output may alias an input), hn, h0, hnew [nv][K], W [nv] or
- * NULL, w [nv][K+1] (also scratch between the kernels of the call).  The first call
- * on a mesh builds a table of its sub-cell flux vectors on the host and uploads
- * it synchronously (48 bytes per triangle, device memory owned by the mesh).
+ * NULL, w [nv][K+1].  The first call on a mesh builds a table of its sub-cell flux
+ * vectors on the host and uploads it synchronously (48 bytes per triangle, device
+ * memory owned by the mesh).  With U distinct from Ustar the call is one launch over
+ * tiles (runs of consecutive vertices with every triangle of their rows, at most 256,
+ * 128, 96 or 64 triangles for K <= 16, <= 32, <= 40, <= 64); the first such call for
+ * a class of K builds the mesh's tile tables, likewise synchronously (about 20 bytes
+ * per triangle).  With U = Ustar, or when one vertex's row exceeds a tile, the call
+ * runs as three launches, w serving as scratch between them; both forms give the
+ * same bits.
  * Results equal the FP64 CPU definition to rounding: the sums over layers are
  * tree reductions and the vertical recursion a parallel suffix sum.
  * Errors: SE_ERR_ARG (NULL array, K outside 1..64, tau <= 0, host-only mesh). */

@@ -1104,6 +1104,34 @@ se_status se_trim_zstar(se_mesh *m, int32_t K, const double *H0, const double *e
             for (int q = 0; q < 6; ++q) S[6 * e + q] = -h.Ae[e] * h.gN[6 * e + q];
         SE_TRY(m->d.slotS.upload(S.data(), S.size() * 8));
     }
+    // the tile form (one launch), unless U is Ustar itself (a tile would overwrite
+    // transports that a later tile still reads) or one vertex's row exceeds a tile
+    const int cap_e = trim_tile_cap_e(K), cap_v = trim_tile_cap_v(K);
+    if (U != Ustar && m->d.tt_cap_e != cap_e && m->d.tt_cap_e != -cap_e) {
+        TrimTiles tt;
+        m->d.tt_cap_e = 0;
+        if (build_trim_tiles(m->h, cap_e, kTrimTileOwn, cap_v, tt)) {
+            SE_TRY(m->d.tt_hdr.upload(tt.hdr.data(), tt.hdr.size() * 4));
+            SE_TRY(m->d.tt_lv.upload(tt.lv.data(), tt.lv.size() * 4));
+            SE_TRY(m->d.tt_le.upload(tt.le.data(), tt.le.size() * 4));
+            SE_TRY(m->d.tt_rloc.upload(tt.rloc.data(), tt.rloc.size() * 2));
+            m->d.tt_ntiles = tt.ntiles;
+            m->d.tt_cap_v = cap_v;
+            m->d.tt_cap_e = cap_e;
+        } else {
+            m->d.tt_cap_e = -cap_e;
+        }
+    }
+    if (U != Ustar && m->d.tt_cap_e == cap_e) {
+        a.tt_hdr = m->d.tt_hdr.as<const int32_t>();
+        a.tt_lv = m->d.tt_lv.as<const int32_t>();
+        a.tt_le = m->d.tt_le.as<const int2>();
+        a.tt_rloc = m->d.tt_rloc.as<const uint16_t>();
+        a.tt_ntiles = m->d.tt_ntiles;
+        a.tt_cap_v = m->d.tt_cap_v;
+        HIP_TRY(launch_trim_tile(a, m->d.slotS.as<const double>(), s), "se_trim_zstar launch");
+        return SE_OK;
+    }
     HIP_TRY(launch_trim(a, m->d.slotS.as<const double>(), s), "se_trim_zstar launch");
     return SE_OK;
 }

@@ -19,9 +19,20 @@ struct TrimArgs {
     const double *Av;
     const double *H0, *eta_new, *Uavg, *Ustar, *hn, *h0, *W;
     double *U, *hnew, *w;
+    // tile form only (the mesh's trim tiles): headers [ntiles][8], halo vertices, local
+    // triangle records, local triangle of each CSR entry; local vertex capacity
+    const int32_t *tt_hdr, *tt_lv;
+    const int2 *tt_le;
+    const uint16_t *tt_rloc;
+    int32_t tt_ntiles, tt_cap_v;
 };
 // S: per-triangle sub-cell flux vectors [ne][3][2], S_k = -A_e grad N_k
 hipError_t launch_trim(const TrimArgs &a, const double *S, hipStream_t s);
+// Tile form: triangles (local ones) per tile and local vertices per tile for K layers
+int trim_tile_cap_e(int K);
+int trim_tile_cap_v(int K);
+constexpr int kTrimTileOwn = 64;   // own vertices per tile
+hipError_t launch_trim_tile(const TrimArgs &a, const double *S, hipStream_t s);
 
 // Barotropic viscous term: V = div(H A grad(U / H)) per triangle (two-point fluxes
 // through edges shared with a neighbour); out = base + sign V (base may be null).

@@ -19,7 +19,9 @@ namespace {
 // ---------------------------------------------------------------------------
 // Consumer of the averaged transport (FP64): z* target h0 (H / H0), mid thickness
 // on triangles, trim of the layer transports to <<U>>, layer divergences in
-// ascending triangle order, and the diasurface velocity from the bottom up.
+// ascending triangle order, and the diasurface velocity from the bottom up.  One
+// launch of k_trim_tile (below) when U is distinct from U* and every row fits a tile;
+// otherwise three launches:
 //   k_zstar_h       h^{n+1} = h0 (H0 + eta) / H0, one thread per vertex-layer; also
 //                   hn + h^{n+1}, parked in w until k_zstar_w overwrites it
 //   k_trim          8 lanes per triangle, 8 triangles per wavefront iteration;
@@ -269,6 +271,185 @@ __global__ void __launch_bounds__(256) k_zstar_w(TrimArgs a, const double *S) {
 }
 
 // ---------------------------------------------------------------------------
+// Tile form of the consumer, one launch.  A workgroup (32 groups of 8 lanes, lane g of
+// a group holding layers g, g + 8, ...) takes one run of consecutive vertices with
+// every triangle of their CSR rows (TrimTiles):
+//   1. hn + hnew of the tile's vertices to LDS; its own vertices also write hnew and
+//      keep (hnew - hn) / tau; the rows' local triangle and flux vector per entry
+//   2. the trim of each local triangle (TPG per group) into registers, stored to U
+//      when the tile owns the triangle (a triangle of an earlier run's vertex is trimmed
+//      there too, from the same inputs, to the same bits)
+//   3. per block of 8 layers: the trimmed transports to LDS, then each own vertex's
+//      layer divergences over its row in CSR order
+//   4. w by group suffix sums, bottom up
+// The arithmetic of k_zstar_h + k_trim + k_zstar_w in the same order (the same bits),
+// without the parked sums and the second pass over U.  U* is read with ordinary loads
+// (the tiles after it find the shared triangles in L2); U, hnew and w are written once.
+// ---------------------------------------------------------------------------
+constexpr int TT_VPG = kTrimTileOwn / 32;   // own vertices per group
+
+template <int L> constexpr int trim_tpg() { return L <= 2 ? 8 : L <= 4 ? 4 : L <= 5 ? 3 : 2; }
+
+template <int L, int TPG>
+__global__ void __launch_bounds__(256) k_trim_tile(TrimArgs a, const double *S) {
+    extern __shared__ __align__(16) double tsm[];
+    const int tid = threadIdx.x, g = tid & 7, grp = tid >> 3;
+    const int K = a.K;
+    const int32_t *hd = a.tt_hdr + 8 * xcd_block();
+    const int32_t v0 = hd[0], nvo = hd[1], nvl = hd[2], nel = hd[3], neo = hd[4];
+    const int32_t lv_off = hd[5], le_off = hd[6], nent = hd[7];
+    constexpr int CE = 32 * TPG;
+    double *sP = tsm;                                                     // [cap_v][K]
+    d2v *sU = reinterpret_cast<d2v *>(tsm + static_cast<size_t>(a.tt_cap_v) * K);   // [CE][8]
+    d2v *sS = sU + CE * 8;                                               // [3 CE]
+    uint16_t *sL = reinterpret_cast<uint16_t *>(sS + 3 * CE);             // [3 CE]
+    const double inv_tau = 1.0 / a.tau;
+    // the loads of steps 2 and 3 that do not wait for LDS, issued first: the local
+    // triangles' records, transports U* and <<U>> (past the tile's last triangle a group
+    // repeats it and stores nothing), the own vertices' row bounds
+    d2v Ut[TPG][L];
+    int64_t ge[TPG];
+    int pk[TPG];
+    double uax[TPG], uay[TPG];
+#pragma unroll
+    for (int q = 0; q < TPG; ++q) {
+        const int2 rec = a.tt_le[le_off + min(grp + 32 * q, nel - 1)];
+        ge[q] = rec.x;
+        pk[q] = rec.y;
+#pragma unroll
+        for (int l = 0; l < L; ++l) {
+            const int k = 8 * l + g;
+            Ut[q][l] = k < K ? *reinterpret_cast<const d2v *>(a.Ustar + 2 * (ge[q] * K + k))
+                             : d2v{0.0, 0.0};
+        }
+        uax[q] = a.Uavg[2 * ge[q]];
+        uay[q] = a.Uavg[2 * ge[q] + 1];
+    }
+    const int32_t jb = a.row_ptr[v0];
+    int j0[TT_VPG], j1[TT_VPG];
+#pragma unroll
+    for (int q = 0; q < TT_VPG; ++q) {
+        const int lv = grp + 32 * q;
+        const int64_t v = v0 + min(lv, nvo - 1);
+        j0[q] = a.row_ptr[v];
+        j1[q] = lv < nvo ? a.row_ptr[v + 1] : j0[q];
+    }
+    // 1. vertex columns
+    double dh[TT_VPG][L];
+#pragma unroll
+    for (int q = 0; q < TT_VPG; ++q) {
+        const int lv = grp + 32 * q;
+#pragma unroll
+        for (int l = 0; l < L; ++l) dh[q][l] = 0.0;
+        if (lv < nvo) {
+            const int64_t v = v0 + lv;
+            const double sc = (a.H0[v] + a.eta_new[v]) / a.H0[v];
+#pragma unroll
+            for (int l = 0; l < L; ++l) {
+                const int k = 8 * l + g;
+                if (k < K) {
+                    const double hn = a.hn[v * K + k];
+                    const double h = a.h0[v * K + k] * sc;
+                    a.hnew[v * K + k] = h;
+                    sP[lv * K + k] = hn + h;
+                    dh[q][l] = (h - hn) * inv_tau;
+                }
+            }
+        }
+    }
+    for (int lv = nvo + grp; lv < nvl; lv += 32) {
+        const int64_t v = a.tt_lv[lv_off + lv - nvo];
+        const double sc = (a.H0[v] + a.eta_new[v]) / a.H0[v];
+#pragma unroll
+        for (int l = 0; l < L; ++l) {
+            const int k = 8 * l + g;
+            if (k < K) {
+                const double h = a.h0[v * K + k] * sc;
+                sP[lv * K + k] = a.hn[v * K + k] + h;
+            }
+        }
+    }
+    const d2v *S2 = reinterpret_cast<const d2v *>(S);
+    for (int i = tid; i < nent; i += 256) {
+        sL[i] = a.tt_rloc[jb + i];
+        sS[i] = S2[a.pcol[jb + i]];
+    }
+    __syncthreads();
+    // 2. trim
+#pragma unroll
+    for (int q = 0; q < TPG; ++q) {
+        const int la = pk[q] & 1023, lb = (pk[q] >> 10) & 1023, lc = pk[q] >> 20;
+        double hh[L];
+        double hs = 0.0, sx = 0.0, sy = 0.0;
+#pragma unroll
+        for (int l = 0; l < L; ++l) {
+            const int k = 8 * l + g;
+            hh[l] = k < K ? (sP[la * K + k] + sP[lb * K + k]) + sP[lc * K + k] : 0.0;
+            hs += hh[l];
+            sx += Ut[q][l].x;
+            sy += Ut[q][l].y;
+        }
+        hs = grp_sum(hs);
+        const double ex = grp_sum(sx) - uax[q];
+        const double ey = grp_sum(sy) - uay[q];
+        const double rh = 1.0 / hs;
+        const bool own = grp + 32 * q < neo;
+#pragma unroll
+        for (int l = 0; l < L; ++l) {
+            const int k = 8 * l + g;
+            const double qh = hh[l] * rh;
+            d2v r;
+            r.x = Ut[q][l].x - qh * ex;
+            r.y = Ut[q][l].y - qh * ey;
+            Ut[q][l] = r;
+            if (own && k < K) st_stream(a.U + 2 * (ge[q] * K + k), r);
+        }
+    }
+    // 3. layer divergences of the own vertices, one block of 8 layers at a time
+    double div[TT_VPG][L];
+#pragma unroll
+    for (int q = 0; q < TT_VPG; ++q)
+#pragma unroll
+        for (int l = 0; l < L; ++l) div[q][l] = 0.0;
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+#pragma unroll
+        for (int q = 0; q < TPG; ++q)
+            if (grp + 32 * q < nel) sU[(grp + 32 * q) * 8 + g] = Ut[q][l];
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < TT_VPG; ++q)
+            for (int jj = j0[q] - jb; jj < j1[q] - jb; ++jj) {
+                const d2v sv = sS[jj];
+                const d2v F = sU[sL[jj] * 8 + g];
+                div[q][l] += F.x * sv.x + F.y * sv.y;
+            }
+        __syncthreads();
+    }
+    // 4. w from the bottom up
+#pragma unroll
+    for (int q = 0; q < TT_VPG; ++q) {
+        const int lv = grp + 32 * q;
+        if (lv >= nvo) continue;
+        const int64_t v = v0 + lv;
+        const double rA = 1.0 / a.Av[v];
+        const double Wv = a.W ? a.W[v] : 0.0;
+        double *w = a.w + v * (K + 1);
+        double run = 0.0;
+#pragma unroll
+        for (int l = L - 1; l >= 0; --l) {
+            const int k = 8 * l + g;
+            const double t = k < K ? dh[q][l] + div[q][l] * rA + (k == 0 ? Wv : 0.0) : 0.0;
+            double tot;
+            const double sfx = grp_suffix(t, g, tot);
+            if (k < K) w[k] = -(sfx + run);
+            run += tot;
+        }
+        if (g == 0) w[K] = 0.0;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Barotropic viscous regularization: one thread per triangle.  k_visc_u stores the
 // velocity U / H_e of every triangle; k_visc sums the two-point fluxes
 // H_j A_j (l/d)_j (u_n - u_e) over the triangle's edges shared with a neighbour,
@@ -432,6 +613,40 @@ hipError_t launch_forcing(const ForcingArgs &a, hipStream_t s) {
 template <int L> void launch_trim_layers(const TrimArgs &a, const double *S, hipStream_t s) {
     if (a.ne > 0) hipLaunchKernelGGL(k_trim<L>, dim3(256 * 4), dim3(256), 0, s, a);
     if (a.nv > 0) hipLaunchKernelGGL(k_zstar_w<L>, dim3(256 * 3), dim3(256), 0, s, a, S);
+}
+
+int trim_tile_cap_e(int K) {
+    const int L = (K + 7) / 8;
+    return 32 * (L <= 2 ? trim_tpg<2>() : L <= 4 ? trim_tpg<4>() : L <= 5 ? trim_tpg<5>()
+                                                                          : trim_tpg<8>());
+}
+int trim_tile_cap_v(int K) { return trim_tile_cap_e(K); }
+
+template <int L> hipError_t launch_trim_tile_l(const TrimArgs &a, const double *S, hipStream_t s) {
+    constexpr int TPG = trim_tpg<L>();
+    constexpr int CE = 32 * TPG;
+    const size_t lds = static_cast<size_t>(a.tt_cap_v) * a.K * 8 + CE * (8 * 16 + 3 * 16 + 3 * 2);
+    hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void *>(k_trim_tile<L, TPG>),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         static_cast<int>(lds));
+    if (err != hipSuccess) return err;
+    hipLaunchKernelGGL((k_trim_tile<L, TPG>), dim3(a.tt_ntiles), dim3(256), lds, s, a, S);
+    return hipGetLastError();
+}
+
+hipError_t launch_trim_tile(const TrimArgs &a, const double *S, hipStream_t s) {
+    if (a.K < 1 || a.K > 64 || a.tt_cap_v != trim_tile_cap_v(a.K)) return hipErrorInvalidValue;
+    if (a.tt_ntiles <= 0) return hipSuccess;
+    switch ((a.K + 7) / 8) {
+        case 1: return launch_trim_tile_l<1>(a, S, s);
+        case 2: return launch_trim_tile_l<2>(a, S, s);
+        case 3: return launch_trim_tile_l<3>(a, S, s);
+        case 4: return launch_trim_tile_l<4>(a, S, s);
+        case 5: return launch_trim_tile_l<5>(a, S, s);
+        case 6: return launch_trim_tile_l<6>(a, S, s);
+        case 7: return launch_trim_tile_l<7>(a, S, s);
+        default: return launch_trim_tile_l<8>(a, S, s);
+    }
 }
 
 hipError_t launch_trim(const TrimArgs &a, const double *S, hipStream_t s) {

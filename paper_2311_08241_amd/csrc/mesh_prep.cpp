@@ -328,6 +328,84 @@ se_status build_visc_tables(const HostMesh &m, std::vector<int32_t> &nb4,
     return SE_OK;
 }
 
+bool build_trim_tiles(const HostMesh &m, int cap_e, int cap_o, int cap_v, TrimTiles &out) {
+    const int64_t nv = m.nv, ne = m.ne;
+    out = TrimTiles{};
+    out.rloc.assign(3 * static_cast<size_t>(ne), 0);
+    std::vector<int32_t> estamp(ne, -1), vstamp(nv, -1), eloc(ne, 0), vloc(nv, 0);
+    std::vector<int32_t> te, tv, add_e, add_v;   // this tile's triangles / vertices
+    int32_t t = 0;
+    for (int64_t v0 = 0; v0 < nv; ++t) {
+        te.clear();
+        tv.clear();
+        int64_t v1 = v0;
+        // grow the range while its rows' triangles and their vertices fit
+        for (; v1 < nv && v1 - v0 < cap_o; ++v1) {
+            add_e.clear();
+            add_v.clear();
+            for (int32_t j = m.row_ptr[v1]; j < m.row_ptr[v1 + 1]; ++j) {
+                const int32_t e = m.col[j] >> 2;
+                if (estamp[e] == t) continue;
+                estamp[e] = t;
+                add_e.push_back(e);
+                for (int q = 0; q < 3; ++q) {
+                    const int32_t u = m.tri[3 * static_cast<int64_t>(e) + q];
+                    if (vstamp[u] != t) {
+                        vstamp[u] = t;
+                        add_v.push_back(u);
+                    }
+                }
+            }
+            if (te.size() + add_e.size() > static_cast<size_t>(cap_e) ||
+                tv.size() + add_v.size() > static_cast<size_t>(cap_v)) {
+                for (int32_t e : add_e) estamp[e] = -1;
+                for (int32_t u : add_v) vstamp[u] = -1;
+                break;
+            }
+            te.insert(te.end(), add_e.begin(), add_e.end());
+            tv.insert(tv.end(), add_v.begin(), add_v.end());
+        }
+        if (v1 == v0) return false;   // one vertex's row alone exceeds the capacity
+        // local order: owned triangles (smallest vertex in the range: one contiguous run
+        // of the mesh order) then the others, each ascending; owned vertices v0 .. v1 - 1,
+        // then the others ascending
+        std::sort(te.begin(), te.end());
+        std::stable_partition(te.begin(), te.end(), [&](int32_t e) {
+            return m.tri[3 * static_cast<int64_t>(e)] >= v0;
+        });
+        int32_t neo = 0;
+        while (neo < static_cast<int32_t>(te.size()) && m.tri[3 * static_cast<int64_t>(te[neo])] >= v0)
+            ++neo;
+        std::sort(tv.begin(), tv.end());
+        const int32_t nvo = static_cast<int32_t>(v1 - v0);
+        for (int32_t i = 0; i < nvo; ++i) vloc[v0 + i] = i;
+        const int32_t lv_off = static_cast<int32_t>(out.lv.size());
+        int32_t nh = 0;
+        for (int32_t u : tv)
+            if (u < v0 || u >= v1) {
+                vloc[u] = nvo + nh++;
+                out.lv.push_back(u);
+            }
+        const int32_t le_off = static_cast<int32_t>(out.le.size() / 2);
+        for (int32_t i = 0; i < static_cast<int32_t>(te.size()); ++i) {
+            const int32_t e = te[i];
+            eloc[e] = i;
+            const int32_t *tr = &m.tri[3 * static_cast<int64_t>(e)];
+            out.le.push_back(e);
+            out.le.push_back(vloc[tr[0]] | vloc[tr[1]] << 10 | vloc[tr[2]] << 20);
+        }
+        for (int32_t j = m.row_ptr[v0]; j < m.row_ptr[v1]; ++j)
+            out.rloc[j] = static_cast<uint16_t>(eloc[m.col[j] >> 2]);
+        const int32_t h[8] = {static_cast<int32_t>(v0), nvo, nvo + nh,
+                              static_cast<int32_t>(te.size()), neo, lv_off, le_off,
+                              m.row_ptr[v1] - m.row_ptr[v0]};
+        out.hdr.insert(out.hdr.end(), h, h + 8);
+        v0 = v1;
+    }
+    out.ntiles = t;
+    return true;
+}
+
 namespace {
 
 // Tiles [t0, t1) of member mi appended to `out` (offsets local to `out`).

@@ -39,6 +39,22 @@ se_status build_host_mesh(const se_mesh_desc &d, HostMesh &m);
 se_status build_visc_tables(const HostMesh &m, std::vector<int32_t> &nb4,
                             std::vector<double> &vg);
 
+// Tiles of the trim/z* consumer: runs of consecutive vertices, each with every triangle
+// of its vertices' CSR rows (at most cap_e), the vertices of those triangles (at most
+// cap_v) and at most cap_o vertices of its own.  hdr [ntiles][8]: first vertex v0, own
+// vertices nvo, local vertices nvl (own first, then the others ascending: lv), local
+// triangles nel, owned triangles neo (smallest vertex in the run; the first neo local
+// triangles, ascending), offset into lv, offset into le, CSR entries of the run's rows.
+// le [2 per local triangle]: global id, local vertices a | b << 10 | c << 20.  rloc [3 ne]
+// (CSR order): local index of the entry's triangle in the tile owning the row.  Returns
+// false when one vertex's row alone exceeds a capacity.
+struct TrimTiles {
+    int32_t ntiles = 0;
+    std::vector<int32_t> hdr, lv, le;
+    std::vector<uint16_t> rloc;
+};
+bool build_trim_tiles(const HostMesh &m, int cap_e, int cap_o, int cap_v, TrimTiles &out);
+
 // ---------------------------------------------------------------------------
 // Tile plan of the temporally blocked kernel (one mesh or a disjoint union).
 // Tile t owns vertices [vbase, vbase + nv0) and the triangles whose smallest
@@ -129,8 +145,12 @@ struct DevMesh {
     // barotropic viscous term, built on first use: neighbours int32 [ne][4],
     // edge (l, l/d) [ne][3][2] in FP64 and FP32
     DevBuf vnb, vgeo64, vgeo32;
-    // trim/z* consumer, built on first use: sub-cell flux vectors [ne][3][2] FP64
+    // trim/z* consumer, built on first use: sub-cell flux vectors [ne][3][2] FP64; the
+    // tile tables (TrimTiles) for the triangle capacity tt_cap_e (0: not built, -1: the
+    // mesh has a row beyond it) and local vertex capacity tt_cap_v
     DevBuf slotS;
+    DevBuf tt_hdr, tt_lv, tt_le, tt_rloc;
+    int32_t tt_cap_e = 0, tt_cap_v = 0, tt_ntiles = 0;
 };
 
 // The forward subcycle on the tile kernel (se_subcycle); may_alloc false: fail instead

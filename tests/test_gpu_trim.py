@@ -81,12 +81,14 @@ def test_trim_layer_count_limits(K):
         assert _rel(out[0][:, 0], inp["Uavg"]) <= 1e-14
 
 
-def test_trim_long_csr_row():
+@pytest.mark.parametrize("K", [24, 40])
+def test_trim_long_csr_row(K):
     """A vertex shared by 100 triangles: its CSR row spans more than one window of
-    columns."""
+    columns.  With 24 layers its row fits one tile of the one-launch form (128 local
+    triangles); with 40 (96 per tile) it does not, and the three-launch form runs."""
     from paper_2311_08241_amd import Mesh
     case = sesynth.random_case(sesynth.tiny_mesh("fan100"), seed=4, nsub=24, tau=4.0)
-    om, inp = _inputs(case, 40, 1, True)
+    om, inp = _inputs(case, K, 1, True)
     mesh = Mesh.from_dict(case, device=0)
     ref = om.trim_zstar(**inp)
     out = _gpu(mesh, inp)
@@ -94,17 +96,36 @@ def test_trim_long_csr_row():
         assert _rel(a, b) <= 1e-12
 
 
-def test_trim_c2_forty_layers_inplace_and_closure():
+def test_trim_c2_forty_layers_both_forms_and_closure():
+    """The channel workload at 40 layers: out of place (the one-launch tile form) and in
+    place (U = Ustar: the three-launch form) against the oracle, and against each other
+    bit for bit (the same operations in the same order)."""
     from paper_2311_08241_amd import Mesh
     case = sesynth.channel_c2(nsteps=1)
     om, inp = _inputs(case, 40, 2, True)
     mesh = Mesh.from_dict(case, device=0)
     ref = om.trim_zstar(**inp)
+    tiled = _gpu(mesh, inp)
     out = _gpu(mesh, inp, inplace=True)
-    for a, b in zip(out, ref):
+    for a, b, c in zip(out, ref, tiled):
         assert _rel(a, b) <= 1e-12
+        assert np.array_equal(a, c)
     # column closure at the surface (eq. (eq4_11)-(eq4_13))
     assert np.abs(out[2][:, 0]).max() <= 1e-12 * inp["H0"].max() / inp["tau"]
+
+
+@pytest.mark.parametrize("K", [1, 8, 9, 17, 33, 40, 41, 49, 64])
+def test_trim_tile_form_equals_three_launch_form_bitwise(K):
+    """Every layer count class of the tile form (triangles per tile 256, 128, 96, 64) on
+    a mesh of many tiles, bit for bit against the three-launch form (in place)."""
+    from paper_2311_08241_amd import Mesh
+    case = sesynth.channel_c2(nx=96, ny=40, nsteps=1)
+    om, inp = _inputs(case, K, 5, True)
+    mesh = Mesh.from_dict(case, device=0)
+    tiled = _gpu(mesh, inp)
+    out = _gpu(mesh, inp, inplace=True)
+    for a, c in zip(out, tiled):
+        assert np.array_equal(a, c)
 
 
 def test_trim_rejects_bad_arguments():
