@@ -16,7 +16,8 @@ import time
 
 import numpy as np
 
-TILES = (256, 288, 304, 320, 352, 384, 416, 448, 464, 512, 576, 640, 768, 1024)
+TILES = (256, 288, 304, 320, 336, 352, 384, 416, 448, 464, 480, 496, 512, 520, 576, 640, 768,
+         1024)
 KS = (2, 3, 4, 5, 6)
 VISC_KS = (2, 4, 6, 8)
 BLOCKS = (256, 512, 1024)

@@ -128,6 +128,26 @@ se_status plan_host(const std::vector<const HostMesh *> &members, const std::vec
         return SE_ERR_ARG;
     }
     SE_TRY(build_tiles(members, voff, eoff, T, K, ht));
+    // a few tiles with more local triangles than the rest (a long coast, a fold of the
+    // curve) set the register tier of all: when at most one tile in 50 exceeds the tier
+    // below, those tiles are halved instead
+    {
+        const int e0 = pick_ept((ht.max_ne + block - 1) / block);
+        int lower = 0;
+        for (int e : kEpts)
+            if (e < e0) lower = e;
+        if (e0 > 0 && lower > 0) {
+            const int32_t cap = lower * block;
+            const size_t nt = ht.hdr.size();
+            size_t over = 0;
+            for (size_t t = 0; t < nt; ++t) over += ht.nE[t * (K + 1) + K] > cap;
+            if (over > 0 && over * 50 <= nt) {
+                HostTiles hs;
+                SE_TRY(build_tiles(members, voff, eoff, T, K, hs, cap));
+                if (hs.max_ne <= cap) ht = std::move(hs);
+            }
+        }
+    }
     st = se_plan_stats_t{};
     const int ept = pick_ept((ht.max_ne + block - 1) / block);
     st.ntiles = static_cast<int32_t>(ht.hdr.size());

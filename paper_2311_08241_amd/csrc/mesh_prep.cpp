@@ -410,14 +410,14 @@ namespace {
 
 // Tiles [t0, t1) of member mi appended to `out` (offsets local to `out`).
 se_status build_tile_range(const HostMesh &m, size_t mi, int64_t voff, int64_t eoff,
-                           const std::vector<int32_t> &efirst, int64_t t0, int64_t t1, int32_t T,
-                           int32_t K, bool ell, std::vector<int32_t> &vloc,
-                           std::vector<int32_t> &eloc, HostTiles &out) {
-    const int64_t nv = m.nv;
+                           const std::vector<int32_t> &efirst, const std::vector<int32_t> &vstart,
+                           int64_t t0, int64_t t1, int32_t K, bool ell,
+                           std::vector<int32_t> &vloc, std::vector<int32_t> &eloc,
+                           HostTiles &out) {
     std::vector<int32_t> lv, le, fresh, pos;
     for (int64_t t = t0; t < t1; ++t) {
-        const int32_t vb = static_cast<int32_t>(t * T);
-        const int32_t nv0 = static_cast<int32_t>(std::min<int64_t>(T, nv - vb));
+        const int32_t vb = vstart[t];
+        const int32_t nv0 = vstart[t + 1] - vb;
         const int32_t eb = efirst[vb], ee = efirst[vb + nv0];
         lv.clear();
         le.clear();
@@ -549,21 +549,14 @@ se_status build_tile_range(const HostMesh &m, size_t mi, int64_t voff, int64_t e
 
 }  // namespace
 
-se_status build_tiles(const std::vector<const HostMesh *> &members,
-                      const std::vector<int64_t> &voff, const std::vector<int64_t> &eoff,
-                      int32_t T, int32_t K, HostTiles &out) {
-    out = HostTiles();
-    out.T = T;
-    out.K = K;
-    // fixed-width rows when no vertex of any member has more than kEllWidth triangles
-    int32_t max_deg = 0;
-    for (const HostMesh *m : members)
-        for (int64_t v = 0; v < m->nv; ++v)
-            max_deg = std::max(max_deg, m->row_ptr[v + 1] - m->row_ptr[v]);
-    out.ell = max_deg <= kEllWidth;
-    const bool ell = out.ell;
-    // first triangle whose smallest vertex is >= v, per member
-    std::vector<std::vector<int32_t>> efirst(members.size());
+// One pass over the given tile ranges (vstart[mi]: first vertex of each tile of member
+// mi, then the member's vertex count), in parallel over runs of tiles.
+static se_status build_tiles_pass(const std::vector<const HostMesh *> &members,
+                                  const std::vector<int64_t> &voff,
+                                  const std::vector<int64_t> &eoff,
+                                  const std::vector<std::vector<int32_t>> &vstart,
+                                  const std::vector<std::vector<int32_t>> &efirst, int32_t K,
+                                  bool ell, HostTiles &out) {
     struct Unit {
         size_t mi;
         int64_t t0, t1;
@@ -571,16 +564,10 @@ se_status build_tiles(const std::vector<const HostMesh *> &members,
     std::vector<Unit> units;
     unsigned nthreads = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
     int64_t total_tiles = 0;
-    for (size_t mi = 0; mi < members.size(); ++mi)
-        total_tiles += (members[mi]->nv + T - 1) / T;
+    for (size_t mi = 0; mi < members.size(); ++mi) total_tiles += vstart[mi].size() - 1;
     const int64_t chunk = std::max<int64_t>(1, total_tiles / (8 * nthreads));
     for (size_t mi = 0; mi < members.size(); ++mi) {
-        const HostMesh &m = *members[mi];
-        std::vector<int32_t> &ef = efirst[mi];
-        ef.assign(m.nv + 1, static_cast<int32_t>(m.ne));
-        for (int64_t e = m.ne - 1; e >= 0; --e) ef[m.tri[3 * e]] = static_cast<int32_t>(e);
-        for (int64_t v = m.nv - 1; v >= 0; --v) ef[v] = std::min(ef[v], ef[v + 1]);
-        const int64_t nt = (m.nv + T - 1) / T;
+        const int64_t nt = static_cast<int64_t>(vstart[mi].size()) - 1;
         for (int64_t t = 0; t < nt; t += chunk) units.push_back({mi, t, std::min(nt, t + chunk)});
     }
     std::vector<HostTiles> parts(units.size());
@@ -600,8 +587,8 @@ se_status build_tiles(const std::vector<const HostMesh *> &members,
                 cur_member = U.mi;
             }
             parts[u].K = K;
-            st[u] = build_tile_range(m, U.mi, voff[U.mi], eoff[U.mi], efirst[U.mi], U.t0, U.t1, T,
-                                     K, ell, vloc, eloc, parts[u]);
+            st[u] = build_tile_range(m, U.mi, voff[U.mi], eoff[U.mi], efirst[U.mi],
+                                     vstart[U.mi], U.t0, U.t1, K, ell, vloc, eloc, parts[u]);
             if (st[u] != SE_OK) {   // stamps may be dirty after an early return
                 cur_member = static_cast<size_t>(-1);
             }
@@ -642,6 +629,61 @@ se_status build_tiles(const std::vector<const HostMesh *> &members,
         out.max_nvu = std::max(out.max_nvu, p.max_nvu);
         out.max_cs = std::max(out.max_cs, p.max_cs);
         out.max_nown = std::max(out.max_nown, p.max_nown);
+    }
+    return SE_OK;
+}
+
+se_status build_tiles(const std::vector<const HostMesh *> &members,
+                      const std::vector<int64_t> &voff, const std::vector<int64_t> &eoff,
+                      int32_t T, int32_t K, HostTiles &out, int32_t split_cap) {
+    out = HostTiles();
+    out.T = T;
+    out.K = K;
+    // fixed-width rows when no vertex of any member has more than kEllWidth triangles
+    int32_t max_deg = 0;
+    for (const HostMesh *m : members)
+        for (int64_t v = 0; v < m->nv; ++v)
+            max_deg = std::max(max_deg, m->row_ptr[v + 1] - m->row_ptr[v]);
+    out.ell = max_deg <= kEllWidth;
+    // first triangle whose smallest vertex is >= v, per member; T vertices per tile
+    std::vector<std::vector<int32_t>> efirst(members.size()), vstart(members.size());
+    for (size_t mi = 0; mi < members.size(); ++mi) {
+        const HostMesh &m = *members[mi];
+        std::vector<int32_t> &ef = efirst[mi];
+        ef.assign(m.nv + 1, static_cast<int32_t>(m.ne));
+        for (int64_t e = m.ne - 1; e >= 0; --e) ef[m.tri[3 * e]] = static_cast<int32_t>(e);
+        for (int64_t v = m.nv - 1; v >= 0; --v) ef[v] = std::min(ef[v], ef[v + 1]);
+        for (int64_t v = 0; v < m.nv; v += T) vstart[mi].push_back(static_cast<int32_t>(v));
+        vstart[mi].push_back(static_cast<int32_t>(m.nv));
+    }
+    se_status rc = build_tiles_pass(members, voff, eoff, vstart, efirst, K, out.ell, out);
+    if (rc != SE_OK) return rc;
+    // split_cap > 0: halve every tile with more local triangles than split_cap (its
+    // halves again, up to four times), keeping the tiles in vertex order
+    for (int round = 0; split_cap > 0 && round < 4 && out.max_ne > split_cap; ++round) {
+        std::vector<std::vector<int32_t>> vs(members.size());
+        size_t t = 0;
+        bool any = false;
+        for (size_t mi = 0; mi < members.size(); ++mi) {
+            for (size_t i = 0; i + 1 < vstart[mi].size(); ++i, ++t) {
+                const int32_t vb = vstart[mi][i], n = vstart[mi][i + 1] - vb;
+                vs[mi].push_back(vb);
+                if (out.nE[t * (K + 1) + K] > split_cap && n >= 2) {
+                    vs[mi].push_back(vb + n / 2);
+                    any = true;
+                }
+            }
+            vs[mi].push_back(vstart[mi].back());
+        }
+        if (!any) break;
+        vstart.swap(vs);
+        HostTiles next;
+        next.T = T;
+        next.K = K;
+        next.ell = out.ell;
+        rc = build_tiles_pass(members, voff, eoff, vstart, efirst, K, next.ell, next);
+        if (rc != SE_OK) return rc;
+        out = std::move(next);
     }
     return SE_OK;
 }

@@ -89,9 +89,11 @@ struct HostTiles {
     bool ell = false;             // fixed-width rows of kEllWidth deposits per vertex
 };
 
+// T vertices per tile (the last tile of a member the rest); split_cap > 0: tiles with
+// more local triangles than split_cap are halved (repeatedly, at most four times).
 se_status build_tiles(const std::vector<const HostMesh *> &members,
                       const std::vector<int64_t> &voff, const std::vector<int64_t> &eoff,
-                      int32_t T, int32_t K, HostTiles &out);
+                      int32_t T, int32_t K, HostTiles &out, int32_t split_cap = 0);
 
 // ---------------------------------------------------------------------------
 // Device-side arrays

@@ -97,7 +97,9 @@ def _case(name):
 
 
 PLANS = [(64, 1, 256), (64, 3, 256), (128, 4, 256), (256, 2, 512), (96, 8, 256),
-         (512, 4, 1024), (640, 3, 1024)]   # 1024 threads: two and three triangles each
+         (512, 4, 1024), (640, 3, 1024),   # 1024 threads: two and three triangles each
+         (464, 4, 512)]   # on the 256 x 128 channel one of its tiles is halved (so is
+                          # one in 64 at 128,4,256)
 
 
 @pytest.mark.parametrize("name", ["jitter76", "chan54", "sphere86", "torus43", "grid45", "fan100"])

@@ -188,6 +188,23 @@ def test_workspace_size_grows_with_substeps():
     assert b > a > c > 0 and a % 256 == 0
 
 
+def test_plan_halves_the_few_tiles_above_the_next_lower_tier():
+    """Tiles of T consecutive vertices, except that when at most one tile in 50 holds more
+    local triangles than the register tier below the one the largest tile needs, those
+    tiles are halved (here: one of 71 at 464,4,512, four of 256 at 128,4,256 on the
+    256 x 128 channel), so the plan keeps the smaller tier; where more tiles exceed it the
+    tiles stay uniform."""
+    case = sesynth.channel_c2(nx=256, ny=128, nsteps=1)
+    mesh = Mesh.from_dict(case, device=-1)
+    nv = mesh.nv
+    for plan, ntiles, tier in (((464, 4, 512), 72, 4), ((128, 4, 256), 260, 3)):
+        st = mesh.plan_stats(*plan)
+        assert st["ntiles"] == ntiles > -(-nv // plan[0])
+        assert st["tri_per_thread"] == tier and st["max_tri"] <= tier * plan[2]
+    st = mesh.plan_stats(576, 4, 512)      # many tiles above 3 x 512: uniform
+    assert st["ntiles"] == -(-nv // 576)
+
+
 def test_autotune_candidates_and_signature_on_a_host_mesh():
     """The tuner's host side: plan ranking for both schemes and the cache key."""
     from paper_2311_08241_amd import Mesh
