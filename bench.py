@@ -321,8 +321,8 @@ def bench_share(args, log, mesh, case, value_full, nparts=8):
     Uavg = torch.empty((m.ne, 2), dtype=torch.float64, device="cuda:0")
     vol = torch.empty(nsub + 1, dtype=torch.float64, device="cuda:0")
     best = None
-    for plan in ((464, 4, 512), (384, 4, 512), (304, 4, 512), (256, 4, 512), (192, 4, 512),
-                 (320, 2, 256), (256, 3, 512)):
+    for plan in ((520, 4, 512), (464, 4, 512), (384, 4, 512), (304, 4, 512), (256, 4, 512),
+                 (192, 4, 512), (320, 2, 256), (256, 3, 512)):
         if not m.plan_stats(*plan)["ok_f32"]:
             continue
         m.set_plan(*plan)

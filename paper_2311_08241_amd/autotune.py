@@ -99,8 +99,8 @@ def candidates(mesh, precision: str, nsub: int, top: int = 30):
     proportional to its triangles per thread; tiles resident per CU follow from
     the register tier (VGPRs per wave) and the LDS size.  The estimate
     (tile time) / (vertex-substeps per tile x resident tiles) orders the plans;
-    the shortlist is then timed.  One se_plan_stats call per (tile, k) gives the
-    largest triangle count and the LDS size.
+    the shortlist is then timed.  One se_plan_stats call per (tile, k, block) gives
+    the largest triangle count and the LDS size.
     """
     prec, sm = _split(precision)
     visc = _visc(precision)
@@ -114,14 +114,16 @@ def candidates(mesh, precision: str, nsub: int, top: int = 30):
             continue
         waste = (-(-nsub // ks) * ks) / nsub     # short last chunk of the launch sequence
         for T in TILES:
-            try:
-                st = mesh.plan_stats(T, K, 256)
-            except Exception:
-                continue
-            lds = st[lkey] + (2 * es * st["max_tri"] if visc else 0)
-            if lds > LDS_MAX:
-                continue
             for B in BLOCKS:
+                # per block size: the plan halves its few oversized tiles against the
+                # register tiers of that block size
+                try:
+                    st = mesh.plan_stats(T, K, B)
+                except Exception:
+                    continue
+                lds = st[lkey] + (2 * es * st["max_tri"] if visc else 0)
+                if lds > LDS_MAX:
+                    continue
                 need = -(-st["max_tri"] // B)
                 ept = next((e for e in EPT_TIERS if e >= need), None)
                 if ept is None or not _tier_ok(precision, ept, B):

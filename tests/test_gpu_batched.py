@@ -157,7 +157,8 @@ def _parity_members():
     return _C4_PARITY["cases"]
 
 
-@pytest.mark.parametrize("precision,plan", [("f64", (352, 4, 512)), ("f32", (352, 4, 512))])
+@pytest.mark.parametrize("precision,plan", [("f64", (352, 4, 512)), ("f32", (352, 4, 512)),
+                                            ("f32", (448, 4, 512))])
 def test_batched_members_equal_oracle_after_1000_substeps(precision, plan):
     from paper_2311_08241_amd import Batch, Mesh, Params, batch_inputs
     cases = _parity_members()
