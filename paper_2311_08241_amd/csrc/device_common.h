@@ -18,6 +18,32 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+// A double moved between lanes by one DPP control (both halves; rows outside ROWMASK
+// receive 0).
+template <int CTRL, int ROWMASK = 0xf>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(b), CTRL, ROWMASK, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(b >> 32), CTRL, ROWMASK, 0xf,
+                                               false);
+    return __builtin_bit_cast(double, (static_cast<uint64_t>(static_cast<uint32_t>(hi)) << 32) |
+                                          static_cast<uint32_t>(lo));
+}
+
+// Sum over the wavefront (every lane active) in a fixed order without LDS: within each
+// row of 16 lanes by quad permutations and mirrors, then row 0 into row 1 and row 2
+// into row 3 (broadcast of lane 15), then rows 0-1 into row 3 (broadcast of lane 31).
+// The total is in lane 63.
+__device__ __forceinline__ double wave_sum_last(double v) {
+    v += dpp_f64<0xB1>(v);          // quad_perm [1, 0, 3, 2]
+    v += dpp_f64<0x4E>(v);          // quad_perm [2, 3, 0, 1]
+    v += dpp_f64<0x141>(v);         // row_half_mirror
+    v += dpp_f64<0x140>(v);         // row_mirror
+    v += dpp_f64<0x142, 0xa>(v);    // row_bcast:15 into rows 1 and 3
+    v += dpp_f64<0x143, 0xc>(v);    // row_bcast:31 into rows 2 and 3
+    return v;
+}
+
 __device__ __forceinline__ void set_fault(uint32_t *faults, uint32_t bit) {
     atomicOr(faults, bit);
 }

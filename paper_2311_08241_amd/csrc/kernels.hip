@@ -1248,9 +1248,9 @@ __device__ __forceinline__ void tile_body(const TileArgs &a, int b, int G) {
             if (vol_j && i < h.nv0) vp += a.Av64[h.vbase + i] * (double)en;
             if (TR && trj && i < h.nv0) trj[i] = en;
         }
-        if (vol_j) {
-            vp = wave_sum(vp);
-            if ((tid & 63) == 0) red[j * NW + (tid >> 6)] = vp;
+        if (vol_j) {   // by DPP: no LDS round trips before the barrier
+            vp = wave_sum_last(vp);
+            if ((tid & 63) == 63) red[j * NW + (tid >> 6)] = vp;
         }
         __syncthreads();
     }
@@ -1316,8 +1316,8 @@ __device__ __forceinline__ void tile_body(const TileArgs &a, int b, int G) {
     }
     // volume partials of this tile
     if (first) {
-        v0 = wave_sum(v0);
-        if ((tid & 63) == 0) red[8 * NW + (tid >> 6)] = v0;
+        v0 = wave_sum_last(v0);
+        if ((tid & 63) == 63) red[8 * NW + (tid >> 6)] = v0;
     }
     __syncthreads();
     if (tid == 0) {
