@@ -314,7 +314,7 @@ se_status se_check_faults(void *mesh_or_batch, int32_t kind, void *stream,
  * vectors on the host and uploads it synchronously (48 bytes per triangle, device
  * memory owned by the mesh).  With U distinct from Ustar the call is one launch over
  * tiles (runs of consecutive vertices with every triangle of their rows, at most 256,
- * 128, 96 or 64 triangles for K <= 16, <= 32, <= 40, <= 64); the first such call for
+ * 128, 96 or 64 triangles for K <= 8, <= 24, <= 32, <= 64); the first such call for
  * a class of K builds the mesh's tile tables, likewise synchronously (about 20 bytes
  * per triangle).  With U = Ustar, or when one vertex's row exceeds a tile, the call
  * runs as three launches, w serving as scratch between them; both forms give the

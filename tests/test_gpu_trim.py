@@ -85,7 +85,7 @@ def test_trim_layer_count_limits(K):
 def test_trim_long_csr_row(K):
     """A vertex shared by 100 triangles: its CSR row spans more than one window of
     columns.  With 24 layers its row fits one tile of the one-launch form (128 local
-    triangles); with 40 (96 per tile) it does not, and the three-launch form runs."""
+    triangles); with 40 (64 per tile) it does not, and the three-launch form runs."""
     from paper_2311_08241_amd import Mesh
     case = sesynth.random_case(sesynth.tiny_mesh("fan100"), seed=4, nsub=24, tau=4.0)
     om, inp = _inputs(case, K, 1, True)
@@ -114,7 +114,7 @@ def test_trim_c2_forty_layers_both_forms_and_closure():
     assert np.abs(out[2][:, 0]).max() <= 1e-12 * inp["H0"].max() / inp["tau"]
 
 
-@pytest.mark.parametrize("K", [1, 8, 9, 17, 33, 40, 41, 49, 64])
+@pytest.mark.parametrize("K", [1, 8, 9, 17, 24, 25, 33, 40, 41, 49, 64])
 def test_trim_tile_form_equals_three_launch_form_bitwise(K):
     """Every layer count class of the tile form (triangles per tile 256, 128, 96, 64) on
     a mesh of many tiles, bit for bit against the three-launch form (in place)."""
